@@ -1,0 +1,168 @@
+/*
+ * gfield — Whittle-Matern Gaussian random fields on closed surfaces by isogeometric
+ * finite elements and sinc quadrature of the Balakrishnan integral, on one AMD MI355X.
+ *
+ * C ABI of the solver library (libgfield.so).  The operations follow Harbrecht,
+ * Sonderegger and von Rickenbach, "Simulation of Gaussian random fields on surfaces
+ * using the isogeometric finite element method" (arXiv 2605.24882):
+ *
+ *   surface      Gamma = union of six patches F_m: [0,1]^2 -> Gamma_m      (Sec. 2.2)
+ *   space        S^0_{j,p}: continuous, patchwise tensor B-splines of degree p on
+ *                2^j x 2^j elements per patch                              (Sec. 2.3)
+ *   matrices     M_ij = <phi_j, phi_i>, S_ij = <grad phi_j, grad phi_i>     (Sec. 3.1, eq. FEM;
+ *                pulled back to the reference square, Sec. 3.2, eq. mass / eq. stiffness)
+ *   load         b ~ N(0, M), the discrete white noise                      (Sec. 3.3)
+ *   field        u ~ (M^-1 A)^-beta M^-1 b, A = kappa^2 M + S, by the split beta = n + beta',
+ *                n integer solves and the sinc rule for beta'               (Sec. 3.4, eq. beta-approx)
+ *
+ * Conventions shared by all calls
+ *   - Every call returns a gf_status; on failure gf_last_error() gives a message
+ *     (thread-local).  No C++ exception crosses this boundary.
+ *   - Handles are created and destroyed by the caller; a space keeps its geometry alive.
+ *     The library keeps no caller pointer after a call returns.
+ *   - `mem` says where caller arrays live: GF_HOST (host memory; the library copies) or
+ *     GF_DEVICE (device memory of the context's GPU).  All work is queued on the context's
+ *     HIP stream; every call returns after that work has finished.
+ *   - Vectors of unknowns are float64 in the global numbering of the space, several
+ *     vectors stored one after the other: array[v * N + i] is unknown i of vector v.
+ *   - Global numbering: patches 0..5, then coefficient row iy, then column ix (ix fastest),
+ *     each coefficient whose surface point has not been seen yet gets the next number.
+ *   - Arguments are validated on the host before any device work: GF_EINVAL for bad sizes,
+ *     null pointers, non-finite or out-of-range parameters.
+ */
+#ifndef GFIELD_H
+#define GFIELD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GF_ABI_VERSION 1
+
+typedef enum {
+  GF_OK = 0,
+  GF_EINVAL = 1,        /* invalid argument */
+  GF_ENOMEM = 2,        /* device or host allocation failed */
+  GF_EDEVICE = 3,       /* HIP runtime error, or no usable gfx950 device */
+  GF_ENOCONV = 4,       /* some system did not reach rtol within max_iter; outputs hold the last iterate */
+  GF_EBREAKDOWN = 5,    /* conjugate gradients broke down (p^T A p <= 0 or not finite) */
+  GF_EUNSUPPORTED = 6   /* a valid but unsupported request */
+} gf_status;
+
+enum { GF_HOST = 0, GF_DEVICE = 1 };
+
+/* Message of the last failure on this thread ("" if none). */
+const char *gf_last_error(void);
+/* GF_ABI_VERSION of the loaded library. */
+int gf_abi_version(void);
+
+typedef struct gf_context gf_context;
+typedef struct gf_geometry gf_geometry;
+typedef struct gf_space gf_space;
+typedef struct gf_tape gf_tape;
+
+/* One GPU and one HIP stream: the caller's hipStream_t (which must outlive the context), or the
+ * device's null stream when hip_stream is NULL (torch's default stream is the null stream).
+ * GF_EDEVICE if the device does not exist or is not gfx950. */
+gf_status gf_context_create(int32_t device, void *hip_stream, gf_context **out);
+void gf_context_destroy(gf_context *ctx);
+
+/* The closed surface as six patches (Sec. 2.2): the radial projection of the faces of the
+ * cube [-1,1]^3 with a = 2s-1, b = 2t-1,
+ *   patch 0: ( 1, a, b)  1: (-1, b, a)  2: ( b, 1, a)  3: ( a,-1, b)  4: ( a, b, 1)  5: ( b, a,-1),
+ * F_m = v/|v| (perturbed = 0, the unit sphere of Sec. 4.1), or F_m = r(xh) xh with xh = v/|v|
+ * and r(x, y, z) = 1 + 0.15 sin(3x) sin(2y) cos(z) (perturbed = 1).  The geometry holds no device
+ * data; ctx may be NULL. */
+gf_status gf_geometry_sphere(gf_context *ctx, int32_t perturbed, gf_geometry **out);
+void gf_geometry_destroy(gf_geometry *geom);
+
+/* Patch index and parameters of surface points, by the radial inverse of the maps above
+ * (the coordinate of largest modulus picks the face).  xyz[npts][3], patch[npts],
+ * st[npts][2], host arrays. */
+gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, int32_t *patch, double *st);
+
+/* S^0_{level,degree} on the geometry (Sec. 2.3): 1 <= degree <= 5, 0 <= level <= 12.
+ * coarse_level (-1: automatic) is the coarsest level of the multigrid hierarchy, 0 <= coarse_level
+ * <= level.  Builds the metric terms m = w a, G = w a K^-1 at the (p+1)^2 Gauss points of every
+ * element (Sec. 3.2), the patch operators and the level hierarchy.  GF_EINVAL out of range. */
+gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degree, int32_t level,
+                          int32_t coarse_level, gf_space **out);
+void gf_space_destroy(gf_space *space);
+/* Number N of unique unknowns: 6(n-2)^2 + 12(n-2) + 8 with n = 2^level + degree. */
+int64_t gf_space_ndofs(const gf_space *space);
+/* Length of one white-noise vector z for gf_white_noise: 6 * 4^level * (degree+1)^2. */
+int64_t gf_space_noise_length(const gf_space *space);
+/* Global number of each patch coefficient: local_to_global[(m*n + iy)*n + ix], n = 2^level + degree,
+ * host array of 6 n^2 entries. */
+gf_status gf_space_dofmap(const gf_space *space, int32_t *local_to_global);
+
+/* Operator kinds of gf_space_apply. */
+enum { GF_APPLY_STENCIL = 0, GF_APPLY_SUMFACT = 1 };
+/* y = (sigma M + s_scale S) x for nvec vectors (eq. FEM, Sec. 3.2).  kind GF_APPLY_SUMFACT evaluates
+ * the element integrals at the quadrature points on the fly (matrix-free, sum-factorised);
+ * GF_APPLY_STENCIL uses the per-patch (2p+1)^2 coefficient stencils assembled from the same
+ * integrals at space creation.  x, y: [nvec][N]. */
+gf_status gf_space_apply(const gf_space *space, double sigma, double s_scale, int32_t nvec, const double *x,
+                         double *y, int32_t mem, int32_t kind);
+
+/* Discrete white noise b = sum_e R_e^T L_e z_e with M_e = L_e L_e^T the lower Cholesky factor of the
+ * element mass matrix, so that b ~ N(0, M) when z ~ N(0, I) (Sec. 3.3).  z: [nsamp][noise_length],
+ * elements in the order patch, ey, ex (ex fastest), each block of (p+1)^2 entries in element-local
+ * order (b, a) with a (along s) fastest.  b: [nsamp][N]. */
+gf_status gf_white_noise(const gf_space *space, int32_t nsamp, const double *z, double *b, int32_t mem);
+
+/* Sinc rule of eq. (beta-approx) with step h and nodes y_k = k h, k = -k_minus..k_plus:
+ * t_k = exp(-2 y_k), shifted systems (t_k M + kappa^2 M + S) x_k = r, weights
+ * omega_k = (2 h sin(pi beta')/pi) t_k^(1-beta').  The paper's rule is h = 1/sqrt(K),
+ * k_minus = k_plus = K. */
+typedef struct {
+  double h;
+  int32_t k_minus, k_plus;
+} gf_quad_rule;
+
+enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
+/* Solver options.  precision GF_PREC_FP64: everything in float64.  GF_PREC_MIXED: the multigrid
+ * V-cycle and its operator applications in float32; the outer CG (its operator application,
+ * residuals, inner products), the coarsest-level Cholesky solve, the metric terms and the
+ * quadrature sum in float64.  rtol: stop a system when |r| <= rtol |b| (Euclidean, global unknowns).
+ * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction (0: default).
+ * apply_kind: GF_APPLY_STENCIL or GF_APPLY_SUMFACT for every operator application in the solver. */
+typedef struct {
+  int32_t precision;
+  double rtol;
+  int32_t max_iter;
+  int32_t cheb_degree;
+  int32_t apply_kind;
+  int32_t flags;
+} gf_solve_opts;
+
+/* Statistics of the last solve (all fields written by the library). */
+typedef struct {
+  int32_t n_systems;       /* shifted systems solved (chain + nodes) x samples */
+  int32_t max_iters;       /* largest CG iteration count over the systems */
+  double max_rel_resid;    /* largest final |r|/|b| */
+  double setup_ms;         /* plan setup (Chebyshev bounds, coarse factors) of this call */
+  double solve_ms;         /* device time of the solves, conversions and the quadrature sum */
+  double apply_ms;         /* with GF_FLAG_TIME_APPLY: summed duration of the outer operator applications */
+  int32_t apply_launches;  /* with GF_FLAG_TIME_APPLY: number of those launches */
+  int32_t apply_cols;      /* with GF_FLAG_TIME_APPLY: columns (systems incl. padding) of each such launch */
+} gf_solve_stats;
+
+/* flags */
+#define GF_FLAG_TIME_APPLY 1 /* bracket each outer-CG operator application with HIP events */
+
+/* Field samples u for loads b (Sec. 3.4): n = floor(beta) integer solves A w_1 = b, A w_i = M w_{i-1},
+ * then the sinc rule applied to r = M w_n (r = b if n = 0), u = sum_k omega_k x_k summed in ascending k.
+ * Each shifted system is solved by multigrid-preconditioned CG; all nodes x samples of the
+ * fractional part are solved as one batch.  kappa > 0, beta > 0, nsamp >= 1.  b, u: [nsamp][N]. */
+gf_status gf_sample(gf_space *space, double kappa, double beta, const gf_quad_rule *rule,
+                    const gf_solve_opts *opts, int32_t nsamp, const double *b, double *u, int32_t mem,
+                    gf_solve_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GFIELD_H */

@@ -1,0 +1,163 @@
+// Internal declarations of the gfield library: space/level data, device buffers,
+// kernel launchers.  Not part of the public ABI (see include/gfield.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/gfield.h"
+
+namespace gf {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  gf_status code;
+  std::string msg;
+};
+void set_error(const std::string &msg);
+[[noreturn]] void fail(gf_status code, const std::string &msg);
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define HIPCHK(x) ::gf::hip_check((x), #x, __FILE__, __LINE__)
+
+// ------------------------------------------------------------------ device buffer
+template <typename T>
+struct DBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf &operator=(DBuf &&o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  // (re)allocate n elements, zero-filled once at allocation
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count == 0) return;
+    HIPCHK(hipMalloc((void **)&p, count * sizeof(T)));
+    HIPCHK(hipMemset(p, 0, count * sizeof(T)));
+    // the fill runs on the null stream: finish it before any other stream touches the buffer
+    HIPCHK(hipDeviceSynchronize());
+    n = count;
+  }
+  // copy from (pageable) host memory; returns once the copy has completed
+  void upload(const T *h, size_t count, hipStream_t s) {
+    alloc(count);
+    HIPCHK(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  void upload(const std::vector<T> &h, hipStream_t s) { upload(h.data(), h.size(), s); }
+};
+
+// ------------------------------------------------------------------ host spline helpers
+struct PatchFrame {
+  int fixed_axis, fixed_sign, a_axis, b_axis;
+};
+extern const PatchFrame kPatchFrames[6];
+void gauss_legendre(int q, std::vector<double> &x, std::vector<double> &w);
+void element_basis(int p, int nel, int e, double u, double *val, double *der);
+std::vector<double> refinement_matrix(int p, int lc);
+void glue_patches(int p, int lev, std::vector<int> &l2g, int &N);
+
+// ------------------------------------------------------------------ per-level data
+// Vectors of a level live in the padded patch-local layout: patch m, coefficient (iy, ix)
+// (0 <= iy, ix < n1) sits at row m*W*W + (iy+p)*W + (ix+p), W = n1 + 2p; the p ghost rows
+// and columns around every patch grid are zero.  A batch of vectors is stored row-major
+// with the column (system) index fastest: element (row, c) at row*ldb + c.
+struct Level {
+  int p = 0, lev = 0, nel = 0, n1 = 0, W = 0, q = 0, S = 0;  // S = 2p+1 stencil width
+  int64_t R = 0;  // padded rows 6*W*W
+  int N = 0;      // unique unknowns
+  std::vector<int> l2g;             // host: local (m, iy, ix) -> global id
+  std::vector<int> owner_row_h;     // host: global id -> owner row
+  DBuf<double> metric;              // [6][nel][nel][q][q][4]: m, G11, G12, G22 (weights folded in)
+  DBuf<double> basis;               // [nel][2][q][p+1]: values, then s-derivatives
+  DBuf<float> metric32, basis32;    // FP32 copies for the FP32 matrix-free apply
+  DBuf<double> stM, stS;            // [R][S*S] patch stencils (FP64)
+  DBuf<float> stM32, stS32;         // same, FP32
+  DBuf<double> dM, dS;              // interface-summed diagonals [R]
+  DBuf<float> dM32, dS32;
+  DBuf<uint8_t> owner;              // [R] 1 on the owner copy of each unknown
+  DBuf<int> grp_ptr, grp_rows;      // shared unknowns: CSR list of their rows
+  int ngroups = 0;
+  DBuf<int> owner_row;              // [N] row of the owner copy
+  DBuf<int> row_gid;                // [R] global id of a row (-1 on ghosts)
+  // prolongation from the next coarser level into this level (empty on level 0 of the space)
+  int pw = 0, rw = 0;               // band widths of P rows / P columns
+  DBuf<int> pro_start, res_start;   // per fine index: first coarse index; per coarse index: first fine index
+  DBuf<double> pro_c, res_c;        // [n1f][pw], [n1c][rw]
+  DBuf<float> pro_c32, res_c32;
+};
+
+}  // namespace gf
+
+// ------------------------------------------------------------------ public handles
+struct gf_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+};
+
+struct gf_geometry {
+  gf_context *ctx = nullptr;
+  int perturbed = 0;
+  int refs = 1;
+};
+
+namespace gf {
+struct Plan;
+}
+
+struct gf_space {
+  gf_context *ctx = nullptr;
+  gf_geometry *geom = nullptr;
+  int p = 0, j = 0, q = 0, lc = 0;
+  std::vector<std::unique_ptr<gf::Level>> lev;  // lev[i] holds refinement level lc + i
+  // dense coarse matrices (global numbering of level lc), FP64 on device
+  gf::DBuf<double> M0, S0;
+  int N0 = 0;
+  std::map<std::string, std::unique_ptr<gf::Plan>> plans;
+  gf::Level &fine() { return *lev.back(); }
+  int nlev() const { return (int)lev.size(); }
+};
+
+namespace gf {
+
+// ------------------------------------------------------------------ kernel launchers
+// Column tiles are 64 systems wide; `active` (may be null) marks tiles still iterating.
+constexpr int CT = 64;
+
+// setup kernels (k_setup.hip)
+void launch_metric(const Level &L, int perturbed, const double *gx, const double *gw, hipStream_t s);
+template <typename T>
+void launch_sumfact_apply(const Level &L, const T *x, T *y, const T *ca, const T *cb, int ldb, int ntiles,
+                          const int *active, hipStream_t s);
+void launch_probe_vectors(const Level &L, double *x, int ldb, hipStream_t s);
+void launch_extract_stencil(const Level &L, const double *y, int ldb, double *stM, double *stS, hipStream_t s);
+void launch_stencil_diag(const Level &L, hipStream_t s);
+
+void launch_coarse_factor(const double *M0, const double *S0, int N0, const double *sig, int nnode, double *Lf,
+                          int *info, hipStream_t s);
+
+// solver kernels (k_solve.hip)
+template <typename T>
+void launch_stencil_apply(const Level &L, const T *stM, const T *stS, const T *x, T *y, const T *ca, const T *cb,
+                          int ldb, int ntiles, const int *active, hipStream_t s);
+template <typename T>
+void launch_interface_sum(const Level &L, T *y, int ldb, int ntiles, const int *active, hipStream_t s);
+
+}  // namespace gf

@@ -1,0 +1,1041 @@
+// Host orchestration and C ABI of the gfield library.
+//
+// Space set-up (Sec. 2.3, 3.2): per refinement level of the multigrid hierarchy the metric
+// terms at the Gauss points, the patch operators (as (2p+1)^2 stencils obtained by probing
+// the matrix-free operator), interface gluing and knot-insertion transfers.
+// Sampling (Sec. 3.4): integer chain and one batch of all sinc nodes x samples, each system
+// solved by CG preconditioned with a multigrid V-cycle (Chebyshev-Jacobi smoothing,
+// knot-insertion transfers, dense Cholesky on the coarsest level).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+
+#include "gf_internal.h"
+#include "k_solve.h"
+
+namespace gf {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+struct GfFailure {
+  gf_status code;
+  std::string msg;
+};
+void set_error(const std::string &msg) { g_last_error = msg; }
+void fail(gf_status code, const std::string &msg) { throw GfFailure{code, msg}; }
+void hip_check(hipError_t e, const char *what, const char *file, int line) {
+  if (e == hipSuccess) return;
+  std::ostringstream os;
+  os << "HIP error " << hipGetErrorName(e) << " (" << hipGetErrorString(e) << ") in " << what << " at " << file
+     << ":" << line;
+  fail(e == hipErrorOutOfMemory ? GF_ENOMEM : GF_EDEVICE, os.str());
+}
+
+template <class F>
+static gf_status guarded(F &&f) {
+  try {
+    f();
+    g_last_error.clear();
+    return GF_OK;
+  } catch (const GfFailure &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return GF_ENOMEM;
+  } catch (const std::exception &e) {
+    g_last_error = e.what();
+    return GF_EDEVICE;
+  }
+}
+
+static inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// ------------------------------------------------------------------ level construction
+static void build_level_host(Level &L, int p, int lev) {
+  L.p = p;
+  L.lev = lev;
+  L.nel = 1 << lev;
+  L.n1 = L.nel + p;
+  L.W = L.n1 + 2 * p;
+  L.q = p + 1;
+  L.S = 2 * p + 1;
+  L.R = (int64_t)6 * L.W * L.W;
+  glue_patches(p, lev, L.l2g, L.N);
+}
+
+static void build_level_device(gf_space *sp, Level &L, int perturbed) {
+  hipStream_t s = sp->ctx->stream;
+  const int p = L.p, n1 = L.n1, W = L.W, nel = L.nel, q = L.q;
+  // Gauss rule and per-element basis tables [nel][2][q][p+1]
+  std::vector<double> gx, gw;
+  gauss_legendre(q, gx, gw);
+  std::vector<double> bt((size_t)nel * 2 * q * (p + 1));
+  for (int e = 0; e < nel; ++e)
+    for (int k = 0; k < q; ++k) {
+      double val[8], der[8];
+      element_basis(p, nel, e, gx[k], val, der);
+      for (int a = 0; a <= p; ++a) {
+        bt[(((size_t)e * 2 + 0) * q + k) * (p + 1) + a] = val[a];
+        bt[(((size_t)e * 2 + 1) * q + k) * (p + 1) + a] = der[a];
+      }
+    }
+  L.basis.upload(bt, s);
+  DBuf<double> dgx, dgw;
+  dgx.upload(gx, s);
+  dgw.upload(gw, s);
+  L.metric.alloc((size_t)6 * nel * nel * q * q * 4);
+  launch_metric(L, perturbed, dgx.p, dgw.p, s);
+  L.metric32.alloc(L.metric.n);
+  launch_to_f32(L.metric.p, L.metric32.p, (int64_t)L.metric.n, s);
+  L.basis32.alloc(L.basis.n);
+  launch_to_f32(L.basis.p, L.basis32.p, (int64_t)L.basis.n, s);
+
+  // rows, owners, shared groups
+  std::vector<int> row_gid((size_t)L.R, -1), owner_row(L.N, -1);
+  std::vector<uint8_t> owner((size_t)L.R, 0);
+  std::vector<std::vector<int>> copies(L.N);
+  for (int m = 0; m < 6; ++m)
+    for (int iy = 0; iy < n1; ++iy)
+      for (int ix = 0; ix < n1; ++ix) {
+        const int g = L.l2g[((size_t)m * n1 + iy) * n1 + ix];
+        const int64_t r = (int64_t)m * W * W + (int64_t)(iy + p) * W + (ix + p);
+        row_gid[r] = g;
+        copies[g].push_back((int)r);
+        if (owner_row[g] < 0) {
+          owner_row[g] = (int)r;
+          owner[r] = 1;
+        }
+      }
+  std::vector<int> gp{0}, gr;
+  for (int g = 0; g < L.N; ++g)
+    if (copies[g].size() > 1) {
+      for (int r : copies[g]) gr.push_back(r);
+      gp.push_back((int)gr.size());
+    }
+  L.ngroups = (int)gp.size() - 1;
+  L.owner_row_h = owner_row;
+  L.row_gid.upload(row_gid, s);
+  L.owner_row.upload(owner_row, s);
+  L.owner.upload(owner, s);
+  if (L.ngroups > 0) {
+    L.grp_ptr.upload(gp, s);
+    L.grp_rows.upload(gr, s);
+  }
+
+  // patch stencils by probing the matrix-free operator: 2 S^2 probe columns (M then S)
+  const int ldb = round_up(2 * L.S * L.S, CT);
+  DBuf<double> X, Y, ca, cb;
+  X.alloc((size_t)L.R * ldb);
+  Y.alloc((size_t)L.R * ldb);
+  std::vector<double> hca(ldb, 0.0), hcb(ldb, 0.0);
+  for (int c = 0; c < L.S * L.S; ++c) hca[c] = 1.0;
+  for (int c = L.S * L.S; c < 2 * L.S * L.S; ++c) hcb[c] = 1.0;
+  ca.upload(hca, s);
+  cb.upload(hcb, s);
+  launch_probe_vectors(L, X.p, ldb, s);
+  launch_sumfact_apply<double>(L, X.p, Y.p, ca.p, cb.p, ldb, ldb / CT, nullptr, s);
+  const size_t nst = (size_t)L.R * L.S * L.S;
+  L.stM.alloc(nst);
+  L.stS.alloc(nst);
+  launch_extract_stencil(L, Y.p, ldb, L.stM.p, L.stS.p, s);
+  L.stM32.alloc(nst);
+  L.stS32.alloc(nst);
+  launch_to_f32(L.stM.p, L.stM32.p, (int64_t)nst, s);
+  launch_to_f32(L.stS.p, L.stS32.p, (int64_t)nst, s);
+  L.dM.alloc((size_t)L.R);
+  L.dS.alloc((size_t)L.R);
+  launch_stencil_diag(L, s);
+  L.dM32.alloc((size_t)L.R);
+  L.dS32.alloc((size_t)L.R);
+  launch_to_f32(L.dM.p, L.dM32.p, L.R, s);
+  launch_to_f32(L.dS.p, L.dS32.p, L.R, s);
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// knot-insertion transfer bands from level C into level F (= C + 1)
+static void build_transfer(gf_space *sp, Level &F, const Level &C) {
+  hipStream_t s = sp->ctx->stream;
+  const int nf = F.n1, nc = C.n1;
+  std::vector<double> P = refinement_matrix(F.p, C.lev);
+  // rows of P: fine index -> band of coarse indices
+  int pw = 0, rw = 0;
+  std::vector<int> f_lo(nf), f_hi(nf), c_lo(nc, nf), c_hi(nc, -1);
+  for (int i = 0; i < nf; ++i) {
+    int lo = nc, hi = -1;
+    for (int c = 0; c < nc; ++c)
+      if (P[(size_t)i * nc + c] != 0.0) {
+        lo = std::min(lo, c);
+        hi = std::max(hi, c);
+        c_lo[c] = std::min(c_lo[c], i);
+        c_hi[c] = std::max(c_hi[c], i);
+      }
+    f_lo[i] = lo;
+    f_hi[i] = hi;
+    pw = std::max(pw, hi - lo + 1);
+  }
+  for (int c = 0; c < nc; ++c) rw = std::max(rw, c_hi[c] - c_lo[c] + 1);
+  std::vector<int> ps(nf), rs(nc);
+  std::vector<double> pc((size_t)nf * pw, 0.0), rc((size_t)nc * rw, 0.0);
+  for (int i = 0; i < nf; ++i) {
+    int st = std::min(f_lo[i], nc - pw);
+    ps[i] = st;
+    for (int k = 0; k < pw; ++k) pc[(size_t)i * pw + k] = P[(size_t)i * nc + st + k];
+  }
+  for (int c = 0; c < nc; ++c) {
+    int st = std::min(c_lo[c], nf - rw);
+    rs[c] = st;
+    for (int k = 0; k < rw; ++k) rc[(size_t)c * rw + k] = P[(size_t)(st + k) * nc + c];
+  }
+  F.pw = pw;
+  F.rw = rw;
+  F.pro_start.upload(ps, s);
+  F.res_start.upload(rs, s);
+  F.pro_c.upload(pc, s);
+  F.res_c.upload(rc, s);
+  std::vector<float> pcf(pc.begin(), pc.end()), rcf(rc.begin(), rc.end());
+  F.pro_c32.upload(pcf, s);
+  F.res_c32.upload(rcf, s);
+}
+
+// dense global matrices of the coarsest level from its patch stencils
+static void build_coarse_dense(gf_space *sp) {
+  Level &C = *sp->lev[0];
+  hipStream_t s = sp->ctx->stream;
+  const size_t nst = (size_t)C.R * C.S * C.S;
+  std::vector<double> hm(nst), hs(nst);
+  HIPCHK(hipMemcpyAsync(hm.data(), C.stM.p, nst * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hs.data(), C.stS.p, nst * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int N0 = C.N, p = C.p, W = C.W, n1 = C.n1, S = C.S;
+  std::vector<double> M0((size_t)N0 * N0, 0.0), S0((size_t)N0 * N0, 0.0);
+  for (int m = 0; m < 6; ++m)
+    for (int iy = 0; iy < n1; ++iy)
+      for (int ix = 0; ix < n1; ++ix) {
+        const int64_t r = (int64_t)m * W * W + (int64_t)(iy + p) * W + (ix + p);
+        const int gi = C.l2g[((size_t)m * n1 + iy) * n1 + ix];
+        for (int dy = -p; dy <= p; ++dy)
+          for (int dx = -p; dx <= p; ++dx) {
+            const int jy = iy + dy, jx = ix + dx;
+            if (jy < 0 || jy >= n1 || jx < 0 || jx >= n1) continue;
+            const int gj = C.l2g[((size_t)m * n1 + jy) * n1 + jx];
+            const int d = (dy + p) * S + (dx + p);
+            M0[(size_t)gi * N0 + gj] += hm[(size_t)r * S * S + d];
+            S0[(size_t)gi * N0 + gj] += hs[(size_t)r * S * S + d];
+          }
+      }
+  sp->N0 = N0;
+  sp->M0.upload(M0, s);
+  sp->S0.upload(S0, s);
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ plans and workspaces
+struct Plan {
+  std::vector<double> sig;                // distinct shifts (nodes)
+  std::vector<std::vector<double>> invb;  // [level index][node] 1/(upper spectral bound of D^-1 A)
+  DBuf<double> Lf;                        // [node][N0][N0] coarse Cholesky factors
+  double setup_ms = 0.0;
+};
+
+struct LevelWork {
+  DBuf<double> r64, z64, d64, a64;  // V-cycle vectors (FP64 mode)
+  DBuf<float> r32, z32, d32, a32;   // V-cycle vectors (mixed mode)
+  DBuf<double> invb64;
+  DBuf<float> invb32;
+};
+
+struct Workspace {
+  int ldb = 0, ntiles = 0, prec = 0;
+  DBuf<double> x, r, z, p, q;  // outer CG (FP64); z unused in mixed mode (z32 of the finest level)
+  std::vector<LevelWork> lw;
+  DBuf<double> sig64, one64, zero64;
+  DBuf<float> sig32, one32;
+  DBuf<int> node, active;
+  DBuf<ColState> cs;
+  DBuf<double> partial;
+  DBuf<int> counter;
+  std::vector<int> active_h;
+  Scratch scratch() { return Scratch{partial.p, counter.p}; }
+};
+
+}  // namespace gf
+
+struct gf_workspaces {
+  std::map<std::pair<int, int>, std::unique_ptr<gf::Workspace>> m;
+};
+
+namespace gf {
+
+static std::map<const gf_space *, std::unique_ptr<gf_workspaces>> &ws_registry() {
+  static std::map<const gf_space *, std::unique_ptr<gf_workspaces>> r;
+  return r;
+}
+
+static Workspace &get_workspace(gf_space *sp, int ldb, int prec) {
+  auto &reg = ws_registry()[sp];
+  if (!reg) reg.reset(new gf_workspaces());
+  auto key = std::make_pair(ldb, prec);
+  auto it = reg->m.find(key);
+  if (it != reg->m.end()) return *it->second;
+  std::unique_ptr<Workspace> w(new Workspace());
+  w->ldb = ldb;
+  w->ntiles = ldb / CT;
+  w->prec = prec;
+  const Level &F = sp->fine();
+  const size_t nf = (size_t)F.R * ldb;
+  w->x.alloc(nf);
+  w->r.alloc(nf);
+  w->p.alloc(nf);
+  w->q.alloc(nf);
+  if (prec == GF_PREC_FP64) w->z.alloc(nf);
+  w->lw.resize(sp->nlev());
+  for (int li = 0; li < sp->nlev(); ++li) {
+    const Level &L = *sp->lev[li];
+    const size_t n = (size_t)L.R * ldb;
+    LevelWork &v = w->lw[li];
+    const bool finest = (li == sp->nlev() - 1);
+    if (prec == GF_PREC_FP64) {
+      if (!finest) {
+        v.r64.alloc(n);
+        v.z64.alloc(n);
+      }
+      v.d64.alloc(n);
+      v.a64.alloc(n);
+    } else {
+      v.r32.alloc(n);
+      v.z32.alloc(n);
+      v.d32.alloc(n);
+      v.a32.alloc(n);
+    }
+    v.invb64.alloc(ldb);
+    v.invb32.alloc(ldb);
+  }
+  w->sig64.alloc(ldb);
+  w->one64.alloc(ldb);
+  w->zero64.alloc(ldb);
+  w->sig32.alloc(ldb);
+  w->one32.alloc(ldb);
+  w->node.alloc(ldb);
+  w->active.alloc(w->ntiles);
+  w->cs.alloc(ldb);
+  w->partial.alloc((size_t)2 * kMaxRowBlocks * ldb);
+  w->counter.alloc(w->ntiles);
+  std::vector<double> ones(ldb, 1.0);
+  std::vector<float> onesf(ldb, 1.0f);
+  w->one64.upload(ones, sp->ctx->stream);
+  w->one32.upload(onesf, sp->ctx->stream);
+  w->active_h.assign(w->ntiles, 0);
+  HIPCHK(hipStreamSynchronize(sp->ctx->stream));
+  Workspace &ref = *w;
+  reg->m[key] = std::move(w);
+  return ref;
+}
+
+// y = (ca M + cb S) x with interface sum, for one level and the chosen operator kind
+template <typename T>
+static void apply_level(const Level &L, int kind, const T *x, T *y, const T *ca, const T *cb, int ldb, int ntiles,
+                        const int *active, hipStream_t s);
+template <>
+void apply_level<double>(const Level &L, int kind, const double *x, double *y, const double *ca, const double *cb,
+                         int ldb, int ntiles, const int *active, hipStream_t s) {
+  if (kind == GF_APPLY_SUMFACT)
+    launch_sumfact_apply<double>(L, x, y, ca, cb, ldb, ntiles, active, s);
+  else
+    launch_stencil_apply<double>(L, L.stM.p, L.stS.p, x, y, ca, cb, ldb, ntiles, active, s);
+  launch_interface_sum<double>(L, y, ldb, ntiles, active, s);
+}
+template <>
+void apply_level<float>(const Level &L, int kind, const float *x, float *y, const float *ca, const float *cb,
+                        int ldb, int ntiles, const int *active, hipStream_t s) {
+  if (kind == GF_APPLY_SUMFACT)
+    launch_sumfact_apply<float>(L, x, y, ca, cb, ldb, ntiles, active, s);
+  else
+    launch_stencil_apply<float>(L, L.stM32.p, L.stS32.p, x, y, ca, cb, ldb, ntiles, active, s);
+  launch_interface_sum<float>(L, y, ldb, ntiles, active, s);
+}
+
+// Chebyshev interval [b/alpha, b] with b = 1.1 x the estimated largest eigenvalue of D^-1 A
+constexpr double kChebAlpha = 8.0;
+constexpr double kChebSafety = 1.1;
+constexpr int kPowerIters = 16;
+
+static std::string plan_key(const std::vector<double> &sig) {
+  std::ostringstream os;
+  os.precision(17);
+  for (double v : sig) os << v << ",";
+  return os.str();
+}
+
+static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
+  const std::string key = plan_key(sig);
+  auto it = sp->plans.find(key);
+  if (it != sp->plans.end()) return *it->second;
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = sp->ctx->stream;
+  std::unique_ptr<Plan> pl(new Plan());
+  pl->sig = sig;
+  const int nn = (int)sig.size();
+  const int ldb = round_up(nn, CT), nt = ldb / CT;
+  DBuf<double> dsig, one, v, w, v2, out;
+  std::vector<double> hsig(ldb, 1.0), ones(ldb, 1.0);
+  for (int k = 0; k < nn; ++k) hsig[k] = sig[k];
+  dsig.upload(hsig, s);
+  one.upload(ones, s);
+  DBuf<double> partial;
+  DBuf<int> counter;
+  partial.alloc((size_t)2 * kMaxRowBlocks * ldb);
+  counter.alloc(nt);
+  out.alloc((size_t)2 * ldb);
+  Scratch sc{partial.p, counter.p};
+  pl->invb.assign(sp->nlev(), std::vector<double>(nn, 0.0));
+  for (int li = 1; li < sp->nlev(); ++li) {
+    const Level &L = *sp->lev[li];
+    const size_t n = (size_t)L.R * ldb;
+    v.alloc(n);
+    w.alloc(n);
+    v2.alloc(n);
+    hash_fill(L, v.p, ldb, nt, s);
+    for (int itp = 0; itp < kPowerIters; ++itp) {
+      apply_level<double>(L, GF_APPLY_STENCIL, v.p, w.p, dsig.p, one.p, ldb, nt, nullptr, s);
+      div_diag(L, v2.p, w.p, dsig.p, ldb, nt, s);
+      if (itp + 1 < kPowerIters) std::swap(v.p, v2.p);
+    }
+    // lambda ~ (w . v_{k+1}) / (w . v_k) with w = A v_k, v_{k+1} = D^-1 w
+    reduce_dot2<double, double, double>(L, v.p, w.p, v2.p, sc, ldb, nt, nullptr, nullptr, OP_STORE, 0.0, 0,
+                                        out.p, s);
+    std::vector<double> ho(2 * ldb);
+    HIPCHK(hipMemcpyAsync(ho.data(), out.p, 2 * ldb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int k = 0; k < nn; ++k) {
+      const double lam = ho[ldb + k] / ho[k];
+      if (!(lam > 0.0) || !std::isfinite(lam)) fail(GF_EDEVICE, "spectral bound estimate failed");
+      pl->invb[li][k] = 1.0 / (kChebSafety * lam);
+    }
+    v.release();
+    w.release();
+    v2.release();
+  }
+  // coarse factors
+  DBuf<double> sn;
+  sn.upload(sig, s);
+  pl->Lf.alloc((size_t)nn * sp->N0 * sp->N0);
+  DBuf<int> info;
+  info.alloc(nn);
+  launch_coarse_factor(sp->M0.p, sp->S0.p, sp->N0, sn.p, nn, pl->Lf.p, info.p, s);
+  std::vector<int> hinfo(nn);
+  HIPCHK(hipMemcpyAsync(hinfo.data(), info.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < nn; ++k)
+    if (hinfo[k] != 0) fail(GF_EINVAL, "coarse matrix not positive definite (shift too small)");
+  pl->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  Plan &ref = *pl;
+  sp->plans[key] = std::move(pl);
+  return ref;
+}
+
+// ------------------------------------------------------------------ batched MG-PCG
+struct SolveSpec {
+  int ncols = 0;                 // real systems (columns 0..ncols-1)
+  std::vector<double> col_sig;   // shift per column
+  std::vector<int> col_node;     // plan node per column
+  const Plan *plan = nullptr;
+  int prec = GF_PREC_FP64;
+  int kind = GF_APPLY_STENCIL;
+  int cheb = 2;
+  double rtol = 1e-10;
+  int max_iter = 500;
+  int flags = 0;
+};
+
+struct SolveResult {
+  int max_it = 0;
+  double max_rel = 0.0;
+  int flags = 0;
+  double apply_ms = 0.0;
+  int apply_launches = 0;
+};
+
+template <typename T>
+struct VT;
+template <>
+struct VT<double> {
+  static double *r(LevelWork &l) { return l.r64.p; }
+  static double *z(LevelWork &l) { return l.z64.p; }
+  static double *d(LevelWork &l) { return l.d64.p; }
+  static double *a(LevelWork &l) { return l.a64.p; }
+  static double *inv(LevelWork &l) { return l.invb64.p; }
+  static const double *dM(const Level &L) { return L.dM.p; }
+  static const double *dS(const Level &L) { return L.dS.p; }
+  static double *sig(Workspace &w) { return w.sig64.p; }
+  static double *one(Workspace &w) { return w.one64.p; }
+};
+template <>
+struct VT<float> {
+  static float *r(LevelWork &l) { return l.r32.p; }
+  static float *z(LevelWork &l) { return l.z32.p; }
+  static float *d(LevelWork &l) { return l.d32.p; }
+  static float *a(LevelWork &l) { return l.a32.p; }
+  static float *inv(LevelWork &l) { return l.invb32.p; }
+  static const float *dM(const Level &L) { return L.dM32.p; }
+  static const float *dS(const Level &L) { return L.dS32.p; }
+  static float *sig(Workspace &w) { return w.sig32.p; }
+  static float *one(Workspace &w) { return w.one32.p; }
+};
+
+// Chebyshev recurrence coefficients for interval [b/alpha, b], in units of 1/b
+static void cheb_coeffs(int deg, std::vector<double> &c1, std::vector<double> &c2) {
+  const double ia = 1.0 / kChebAlpha;
+  const double theta = (1.0 + ia) / 2.0, delta = (1.0 - ia) / 2.0, sigma1 = theta / delta;
+  c1.assign(deg, 0.0);
+  c2.assign(deg, 0.0);
+  double rho_prev = 1.0 / sigma1;
+  c2[0] = 1.0 / theta;
+  for (int k = 1; k < deg; ++k) {
+    const double rho = 1.0 / (2.0 * sigma1 - rho_prev);
+    c1[k] = rho * rho_prev;
+    c2[k] = 2.0 * rho / delta;
+    rho_prev = rho;
+  }
+}
+
+template <typename T>
+static void vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, T *r, T *z, hipStream_t s) {
+  const Level &L = *sp->lev[li];
+  const int ldb = w.ldb, nt = w.ntiles;
+  const int *act = w.active.p;
+  if (li == 0) {
+    coarse_solve<T>(L, sp->N0, z, r, spec.plan->Lf.p, w.node.p, ldb, nt, act, s);
+    return;
+  }
+  LevelWork &lw = w.lw[li];
+  T *d = VT<T>::d(lw), *Az = VT<T>::a(lw), *inv = VT<T>::inv(lw);
+  const T *dM = VT<T>::dM(L), *dS = VT<T>::dS(L), *sig = VT<T>::sig(w), *one = VT<T>::one(w);
+  std::vector<double> c1, c2;
+  cheb_coeffs(spec.cheb, c1, c2);
+  // pre-smoothing from z = 0
+  cheb_step<T>(L, z, d, r, nullptr, dM, dS, sig, inv, (T)0, (T)c2[0], 1, ldb, nt, act, s);
+  for (int k = 1; k < spec.cheb; ++k) {
+    apply_level<T>(L, spec.kind, z, Az, sig, one, ldb, nt, act, s);
+    cheb_step<T>(L, z, d, r, Az, dM, dS, sig, inv, (T)c1[k], (T)c2[k], 0, ldb, nt, act, s);
+  }
+  // coarse correction
+  apply_level<T>(L, spec.kind, z, Az, sig, one, ldb, nt, act, s);
+  const Level &C = *sp->lev[li - 1];
+  LevelWork &cw = w.lw[li - 1];
+  T *rc = VT<T>::r(cw), *zc = VT<T>::z(cw);
+  restrict_residual<T>(L, C, rc, r, Az, ldb, nt, act, s);
+  launch_interface_sum<T>(C, rc, ldb, nt, act, s);
+  vcycle<T>(sp, w, spec, li - 1, rc, zc, s);
+  prolong_add<T>(L, C, z, zc, ldb, nt, act, s);
+  // post-smoothing
+  for (int k = 0; k < spec.cheb; ++k) {
+    apply_level<T>(L, spec.kind, z, Az, sig, one, ldb, nt, act, s);
+    cheb_step<T>(L, z, d, r, Az, dM, dS, sig, inv, (T)c1[k], (T)c2[k], 0, ldb, nt, act, s);
+  }
+}
+
+// z = B r (multigrid preconditioner) for the outer FP64 residual r
+static void precondition(gf_space *sp, Workspace &w, const SolveSpec &spec, hipStream_t s) {
+  const int fi = sp->nlev() - 1;
+  const Level &F = sp->fine();
+  if (spec.prec == GF_PREC_FP64) {
+    vcycle<double>(sp, w, spec, fi, w.r.p, w.z.p, s);
+  } else {
+    LevelWork &fw = w.lw[fi];
+    convert_rows<double, float>(F, w.r.p, fw.r32.p, w.ldb, w.ntiles, w.active.p, s);
+    vcycle<float>(sp, w, spec, fi, fw.r32.p, fw.z32.p, s);
+  }
+}
+
+// Solves (sigma_c M + S) x_c = r_c for all columns c; on entry w.r holds the right-hand sides
+// (assembled, patch-local layout), on exit w.x holds the solutions.
+static SolveResult solve_batch(gf_space *sp, Workspace &w, const SolveSpec &spec) {
+  hipStream_t s = sp->ctx->stream;
+  const Level &F = sp->fine();
+  const int ldb = w.ldb, nt = w.ntiles, fi = sp->nlev() - 1;
+  // per-column data
+  std::vector<double> sig(ldb, 1.0);
+  std::vector<float> sigf(ldb, 1.0f);
+  std::vector<int> node(ldb, 0);
+  std::vector<ColState> cs(ldb);
+  for (int c = 0; c < ldb; ++c) {
+    cs[c] = ColState{};
+    cs[c].done = (c < spec.ncols) ? 0 : 1;
+    if (c < spec.ncols) {
+      sig[c] = spec.col_sig[c];
+      node[c] = spec.col_node[c];
+    }
+    sigf[c] = (float)sig[c];
+  }
+  std::fill(w.active_h.begin(), w.active_h.end(), 0);
+  for (int c = 0; c < spec.ncols; ++c) w.active_h[c / CT] = 1;
+  w.sig64.upload(sig, s);
+  w.sig32.upload(sigf, s);
+  w.node.upload(node, s);
+  w.cs.upload(cs, s);
+  w.active.upload(w.active_h, s);
+  for (int li = 1; li < sp->nlev(); ++li) {
+    std::vector<double> ib(ldb, 1.0);
+    for (int c = 0; c < spec.ncols; ++c) ib[c] = spec.plan->invb[li][node[c]];
+    std::vector<float> ibf(ib.begin(), ib.end());
+    w.lw[li].invb64.upload(ib, s);
+    w.lw[li].invb32.upload(ibf, s);
+  }
+  HIPCHK(hipMemsetAsync(w.x.p, 0, (size_t)F.R * ldb * sizeof(double), s));
+  Scratch sc = w.scratch();
+  const double tol2 = spec.rtol * spec.rtol;
+  const bool mixed = spec.prec == GF_PREC_MIXED;
+  const double *zd = mixed ? nullptr : w.z.p;
+  const float *zf = mixed ? w.lw[fi].z32.p : nullptr;
+  SolveResult res;
+  std::vector<hipEvent_t> evs;
+  auto timed_apply = [&]() {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (spec.flags & GF_FLAG_TIME_APPLY) {
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      HIPCHK(hipEventRecord(e0, s));
+    }
+    if (spec.kind == GF_APPLY_SUMFACT)
+      launch_sumfact_apply<double>(F, w.p.p, w.q.p, w.sig64.p, w.one64.p, ldb, nt, w.active.p, s);
+    else
+      launch_stencil_apply<double>(F, F.stM.p, F.stS.p, w.p.p, w.q.p, w.sig64.p, w.one64.p, ldb, nt, w.active.p, s);
+    if (spec.flags & GF_FLAG_TIME_APPLY) {
+      HIPCHK(hipEventRecord(e1, s));
+      evs.push_back(e0);
+      evs.push_back(e1);
+    }
+    launch_interface_sum<double>(F, w.q.p, ldb, nt, w.active.p, s);
+  };
+  // r = b - A 0 = b;  bb = |b|^2
+  reduce_dot<double, double>(F, w.r.p, w.r.p, sc, ldb, nt, w.cs.p, w.active.p, OP_BB, tol2, spec.max_iter, nullptr,
+                             s);
+  precondition(sp, w, spec, s);
+  if (mixed) {
+    reduce_dot<double, float>(F, w.r.p, zf, sc, ldb, nt, w.cs.p, w.active.p, OP_RZ0, tol2, spec.max_iter, nullptr,
+                              s);
+    convert_rows<float, double>(F, zf, w.p.p, ldb, nt, w.active.p, s);
+  } else {
+    reduce_dot<double, double>(F, w.r.p, zd, sc, ldb, nt, w.cs.p, w.active.p, OP_RZ0, tol2, spec.max_iter, nullptr,
+                               s);
+    convert_rows<double, double>(F, zd, w.p.p, ldb, nt, w.active.p, s);
+  }
+  const int check_every = 1;
+  for (int it = 0; it < spec.max_iter; ++it) {
+    timed_apply();
+    reduce_dot<double, double>(F, w.p.p, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, OP_ALPHA, tol2, spec.max_iter,
+                               nullptr, s);
+    update_xr(F, w.x.p, w.r.p, w.p.p, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, tol2, spec.max_iter, s);
+    if ((it + 1) % check_every == 0) {
+      HIPCHK(hipMemcpyAsync(w.active_h.data(), w.active.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bool any = false;
+      for (int t = 0; t < nt; ++t) any = any || w.active_h[t];
+      if (!any) break;
+    }
+    precondition(sp, w, spec, s);
+    if (mixed) {
+      reduce_dot2<double, float, double>(F, w.r.p, zf, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, OP_BETA_FLEX, tol2,
+                                         spec.max_iter, nullptr, s);
+      update_p<float>(F, w.p.p, zf, w.cs.p, ldb, nt, w.active.p, s);
+    } else {
+      reduce_dot<double, double>(F, w.r.p, zd, sc, ldb, nt, w.cs.p, w.active.p, OP_BETA, tol2, spec.max_iter,
+                                 nullptr, s);
+      update_p<double>(F, w.p.p, zd, w.cs.p, ldb, nt, w.active.p, s);
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+    res.apply_ms += ms;
+    res.apply_launches += 1;
+    (void)hipEventDestroy(evs[i]);
+    (void)hipEventDestroy(evs[i + 1]);
+  }
+  std::vector<ColState> out(ldb);
+  HIPCHK(hipMemcpy(out.data(), w.cs.p, ldb * sizeof(ColState), hipMemcpyDeviceToHost));
+  for (int c = 0; c < spec.ncols; ++c) {
+    res.max_it = std::max(res.max_it, out[c].it);
+    const double rel = out[c].bb > 0 ? std::sqrt(out[c].rr / out[c].bb) : 0.0;
+    res.max_rel = std::max(res.max_rel, rel);
+    res.flags |= out[c].flag;
+    if (!out[c].done) res.flags |= 1;
+  }
+  return res;
+}
+
+}  // namespace gf
+
+using namespace gf;
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *gf_last_error(void) { return g_last_error.c_str(); }
+int gf_abi_version(void) { return GF_ABI_VERSION; }
+
+gf_status gf_context_create(int32_t device, void *hip_stream, gf_context **out) {
+  return guarded([&] {
+    if (!out) fail(GF_EINVAL, "out is null");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) fail(GF_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= n) fail(GF_EDEVICE, "device index out of range");
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      fail(GF_EDEVICE, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+    HIPCHK(hipSetDevice(device));
+    std::unique_ptr<gf_context> c(new gf_context());
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;  // NULL: the device's null stream
+    *out = c.release();
+  });
+}
+
+void gf_context_destroy(gf_context *ctx) {
+  if (!ctx) return;
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+gf_status gf_geometry_sphere(gf_context *ctx, int32_t perturbed, gf_geometry **out) {
+  return guarded([&] {
+    if (!out) fail(GF_EINVAL, "null argument");
+    if (perturbed != 0 && perturbed != 1) fail(GF_EINVAL, "perturbed must be 0 or 1");
+    gf_geometry *g = new gf_geometry();
+    g->ctx = ctx;
+    g->perturbed = perturbed;
+    *out = g;
+  });
+}
+
+void gf_geometry_destroy(gf_geometry *g) {
+  if (!g) return;
+  if (--g->refs == 0) delete g;
+}
+
+gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, int32_t *patch, double *st) {
+  return guarded([&] {
+    if (!geom || (npts > 0 && (!xyz || !patch || !st)) || npts < 0) fail(GF_EINVAL, "bad arguments");
+    for (int i = 0; i < npts; ++i) {
+      const double X[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+      int ax = 0;
+      for (int k = 1; k < 3; ++k)
+        if (std::fabs(X[k]) > std::fabs(X[ax])) ax = k;
+      const double den = std::fabs(X[ax]);
+      if (!(den > 0.0) || !std::isfinite(den)) fail(GF_EINVAL, "point at the origin or not finite");
+      const int sign = X[ax] > 0 ? 1 : -1;
+      int m = -1;
+      for (int k = 0; k < 6; ++k)
+        if (kPatchFrames[k].fixed_axis == ax && kPatchFrames[k].fixed_sign == sign) m = k;
+      const PatchFrame &f = kPatchFrames[m];
+      const double a = X[f.a_axis] / den, b = X[f.b_axis] / den;
+      patch[i] = m;
+      st[2 * i] = (a + 1.0) / 2.0;
+      st[2 * i + 1] = (b + 1.0) / 2.0;
+    }
+  });
+}
+
+gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degree, int32_t level,
+                          int32_t coarse_level, gf_space **out) {
+  return guarded([&] {
+    if (!ctx || !geom || !out) fail(GF_EINVAL, "null argument");
+    *out = nullptr;
+    if (degree < 1 || degree > 5) fail(GF_EINVAL, "degree must be in 1..5");
+    if (level < 0 || level > 12) fail(GF_EINVAL, "level must be in 0..12");
+    if (coarse_level > level) fail(GF_EINVAL, "coarse_level must not exceed level");
+    int lc = coarse_level;
+    if (lc < 0) lc = 0;
+    HIPCHK(hipSetDevice(ctx->device));
+    std::unique_ptr<gf_space> sp(new gf_space());
+    sp->ctx = ctx;
+    sp->geom = const_cast<gf_geometry *>(geom);
+    sp->p = degree;
+    sp->j = level;
+    sp->q = degree + 1;
+    sp->lc = lc;
+    for (int l = lc; l <= level; ++l) {
+      std::unique_ptr<Level> L(new Level());
+      build_level_host(*L, degree, l);
+      build_level_device(sp.get(), *L, geom->perturbed);
+      sp->lev.push_back(std::move(L));
+    }
+    for (int i = 1; i < sp->nlev(); ++i) build_transfer(sp.get(), *sp->lev[i], *sp->lev[i - 1]);
+    build_coarse_dense(sp.get());
+    sp->geom->refs++;
+    *out = sp.release();
+  });
+}
+
+void gf_space_destroy(gf_space *sp) {
+  if (!sp) return;
+  ws_registry().erase(sp);
+  gf_geometry_destroy(sp->geom);
+  delete sp;
+}
+
+int64_t gf_space_ndofs(const gf_space *sp) { return sp ? (int64_t)sp->lev.back()->N : -1; }
+
+int64_t gf_space_noise_length(const gf_space *sp) {
+  if (!sp) return -1;
+  return (int64_t)6 * (int64_t)(1 << sp->j) * (int64_t)(1 << sp->j) * (sp->p + 1) * (sp->p + 1);
+}
+
+gf_status gf_space_dofmap(const gf_space *sp, int32_t *l2g) {
+  return guarded([&] {
+    if (!sp || !l2g) fail(GF_EINVAL, "null argument");
+    const Level &F = *sp->lev.back();
+    std::memcpy(l2g, F.l2g.data(), F.l2g.size() * sizeof(int32_t));
+  });
+}
+
+// device copy of a caller array (or the caller's device pointer itself)
+struct InArray {
+  const double *p = nullptr;
+  DBuf<double> own;
+};
+static void stage_in(InArray &a, const double *src, size_t n, int mem, hipStream_t s) {
+  if (mem == GF_DEVICE) {
+    a.p = src;
+  } else {
+    a.own.upload(src, n, s);
+    a.p = a.own.p;
+  }
+}
+struct OutArray {
+  double *p = nullptr;
+  double *host = nullptr;
+  size_t n = 0;
+  DBuf<double> own;
+};
+static void stage_out(OutArray &a, double *dst, size_t n, int mem) {
+  a.n = n;
+  if (mem == GF_DEVICE) {
+    a.p = dst;
+  } else {
+    a.own.alloc(n);
+    a.p = a.own.p;
+    a.host = dst;
+  }
+}
+static void finish_out(OutArray &a, hipStream_t s) {
+  if (a.host) HIPCHK(hipMemcpyAsync(a.host, a.p, a.n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+gf_status gf_space_apply(const gf_space *csp, double sigma, double s_scale, int32_t nvec, const double *x, double *y,
+                         int32_t mem, int32_t kind) {
+  return guarded([&] {
+    gf_space *sp = const_cast<gf_space *>(csp);
+    if (!sp || !x || !y) fail(GF_EINVAL, "null argument");
+    if (nvec < 1) fail(GF_EINVAL, "nvec must be >= 1");
+    if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
+    if (kind != GF_APPLY_STENCIL && kind != GF_APPLY_SUMFACT) fail(GF_EINVAL, "unknown operator kind");
+    if (!std::isfinite(sigma) || !std::isfinite(s_scale)) fail(GF_EINVAL, "sigma and s_scale must be finite");
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    hipStream_t s = sp->ctx->stream;
+    const Level &F = sp->fine();
+    const size_t n = (size_t)nvec * F.N;
+    InArray xin;
+    stage_in(xin, x, n, mem, s);
+    OutArray yout;
+    stage_out(yout, y, n, mem);
+    const int ldb = round_up(nvec, CT), nt = ldb / CT;
+    DBuf<double> X, Y, ca, cb;
+    X.alloc((size_t)F.R * ldb);
+    Y.alloc((size_t)F.R * ldb);
+    ca.upload(std::vector<double>(ldb, sigma), s);
+    cb.upload(std::vector<double>(ldb, s_scale), s);
+    global_to_local(F, X.p, xin.p, nvec, ldb, s);
+    apply_level<double>(F, kind, X.p, Y.p, ca.p, cb.p, ldb, nt, nullptr, s);
+    local_to_global(F, yout.p, Y.p, nvec, 0, ldb, s);
+    finish_out(yout, s);
+  });
+}
+
+gf_status gf_white_noise(const gf_space *csp, int32_t nsamp, const double *z, double *b, int32_t mem) {
+  return guarded([&] {
+    gf_space *sp = const_cast<gf_space *>(csp);
+    if (!sp || !z || !b) fail(GF_EINVAL, "null argument");
+    if (nsamp < 1) fail(GF_EINVAL, "nsamp must be >= 1");
+    if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    hipStream_t s = sp->ctx->stream;
+    const Level &F = sp->fine();
+    const size_t nz = (size_t)nsamp * gf_space_noise_length(sp);
+    InArray zin;
+    stage_in(zin, z, nz, mem, s);
+    OutArray bout;
+    stage_out(bout, b, (size_t)nsamp * F.N, mem);
+    DBuf<double> ye, BL;
+    ye.alloc(nz);
+    const int ldb = round_up(nsamp, CT);
+    BL.alloc((size_t)F.R * ldb);
+    launch_white_noise(F, zin.p, nsamp, ye.p, BL.p, ldb, s);
+    // interface sum of the per-patch contributions, then owner copies out
+    launch_interface_sum<double>(F, BL.p, ldb, ldb / CT, nullptr, s);
+    local_to_global(F, bout.p, BL.p, nsamp, 0, ldb, s);
+    finish_out(bout, s);
+  });
+}
+
+static void check_common(gf_space *sp, double kappa, double beta, const gf_quad_rule *rule,
+                         const gf_solve_opts *opts, int32_t nsamp, int32_t mem) {
+  if (!sp || !rule || !opts) fail(GF_EINVAL, "null argument");
+  if (!(kappa > 0.0) || !std::isfinite(kappa)) fail(GF_EINVAL, "kappa must be positive and finite");
+  if (!(beta > 0.0) || !std::isfinite(beta) || beta > 64.0) fail(GF_EINVAL, "beta must be in (0, 64]");
+  if (!(rule->h > 0.0) || !std::isfinite(rule->h) || rule->k_minus < 0 || rule->k_plus < 0)
+    fail(GF_EINVAL, "quadrature rule needs h > 0 and k_minus, k_plus >= 0");
+  if (opts->precision != GF_PREC_FP64 && opts->precision != GF_PREC_MIXED) fail(GF_EINVAL, "unknown precision");
+  if (!(opts->rtol > 0.0) || !(opts->rtol < 1.0)) fail(GF_EINVAL, "rtol must be in (0, 1)");
+  if (opts->max_iter < 1) fail(GF_EINVAL, "max_iter must be >= 1");
+  if (opts->cheb_degree < 0 || opts->cheb_degree > 16) fail(GF_EINVAL, "cheb_degree must be in 0..16");
+  if (opts->apply_kind != GF_APPLY_STENCIL && opts->apply_kind != GF_APPLY_SUMFACT)
+    fail(GF_EINVAL, "unknown apply_kind");
+  if (nsamp < 1) fail(GF_EINVAL, "nsamp must be >= 1");
+  if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
+}
+
+gf_status gf_sample(gf_space *sp, double kappa, double beta, const gf_quad_rule *rule, const gf_solve_opts *opts,
+                    int32_t nsamp, const double *b, double *u, int32_t mem, gf_solve_stats *stats) {
+  return guarded([&] {
+    check_common(sp, kappa, beta, rule, opts, nsamp, mem);
+    if (!b || !u) fail(GF_EINVAL, "null argument");
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    hipStream_t s = sp->ctx->stream;
+    const Level &F = sp->fine();
+    const int n = (int)std::floor(beta);
+    const double bf = beta - n;
+    const int K = rule->k_minus + rule->k_plus + 1;
+    if (bf > 0.0 && (int64_t)K * nsamp > (int64_t)1 << 20) fail(GF_EINVAL, "too many systems in one batch");
+    const size_t nv = (size_t)nsamp * F.N;
+    InArray bin;
+    stage_in(bin, b, nv, mem, s);
+    OutArray uout;
+    stage_out(uout, u, nv, mem);
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    SolveSpec base;
+    base.prec = opts->precision;
+    base.kind = opts->apply_kind;
+    base.cheb = opts->cheb_degree > 0 ? opts->cheb_degree : 2;
+    base.rtol = opts->rtol;
+    base.max_iter = opts->max_iter;
+    base.flags = opts->flags;
+    double setup_ms = 0.0;
+    int max_it = 0, flags = 0, nsys = 0;
+    double max_rel = 0.0, apply_ms = 0.0;
+    int apply_launches = 0, apply_cols = 0;
+    auto account = [&](const SolveResult &r, int ncols, int ldb) {
+      max_it = std::max(max_it, r.max_it);
+      max_rel = std::max(max_rel, r.max_rel);
+      flags |= r.flags;
+      nsys += ncols;
+      apply_ms += r.apply_ms;
+      apply_launches += r.apply_launches;
+      if (r.apply_launches) apply_cols = ldb;
+    };
+    // plans first (their set-up is reported separately from the solve time)
+    const Plan *chain_plan = nullptr, *frac_plan = nullptr;
+    std::vector<double> node_sig;
+    std::vector<double> omega;
+    {
+      const size_t np = sp->plans.size();
+      auto c0 = std::chrono::steady_clock::now();
+      if (n > 0) chain_plan = &get_plan(sp, std::vector<double>{kappa * kappa});
+      if (bf > 0.0) {
+        for (int k = -rule->k_minus; k <= rule->k_plus; ++k) {
+          const double t = std::exp(-2.0 * k * rule->h);
+          node_sig.push_back(kappa * kappa + t);
+          omega.push_back(2.0 * rule->h * std::sin(M_PI * bf) / M_PI * std::pow(t, 1.0 - bf));
+        }
+        frac_plan = &get_plan(sp, node_sig);
+      }
+      if (sp->plans.size() != np)
+        setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+    }
+    HIPCHK(hipEventRecord(t0, s));
+    const int ldc = round_up(nsamp, CT);
+    // ---- integer chain: A w_1 = b, A w_i = M w_{i-1}
+    DBuf<double> rloc;  // right-hand side of the fractional part, [R][ldc]
+    if (n > 0) {
+      Workspace &w = get_workspace(sp, ldc, base.prec);
+      global_to_local(F, w.r.p, bin.p, nsamp, ldc, s);
+      SolveSpec spec = base;
+      spec.ncols = nsamp;
+      spec.col_sig.assign(nsamp, kappa * kappa);
+      spec.col_node.assign(nsamp, 0);
+      spec.plan = chain_plan;
+      for (int i = 1; i <= n; ++i) {
+        SolveResult r = solve_batch(sp, w, spec);
+        account(r, nsamp, ldc);
+        if (i < n || bf > 0.0) {
+          // next right-hand side M w_i (assembled)
+          apply_level<double>(F, GF_APPLY_STENCIL, w.x.p, w.r.p, w.one64.p, w.zero64.p, ldc, ldc / CT, nullptr, s);
+        }
+      }
+      if (bf == 0.0) {
+        local_to_global(F, uout.p, w.x.p, nsamp, 0, ldc, s);
+      } else {
+        rloc.alloc((size_t)F.R * ldc);
+        HIPCHK(hipMemcpyAsync(rloc.p, w.r.p, (size_t)F.R * ldc * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
+    } else {
+      rloc.alloc((size_t)F.R * ldc);
+      global_to_local(F, rloc.p, bin.p, nsamp, ldc, s);
+    }
+    // ---- fractional part: all nodes x samples in one batch
+    if (bf > 0.0) {
+      const int ncols = K * nsamp;
+      const int ldf = round_up(ncols, CT);
+      Workspace &w = get_workspace(sp, ldf, base.prec);
+      replicate_cols(F, w.r.p, ldf, rloc.p, ldc, nsamp, K, s);
+      SolveSpec spec = base;
+      spec.ncols = ncols;
+      spec.col_sig.resize(ncols);
+      spec.col_node.resize(ncols);
+      for (int k = 0; k < K; ++k)
+        for (int sm = 0; sm < nsamp; ++sm) {
+          spec.col_sig[k * nsamp + sm] = node_sig[k];
+          spec.col_node[k * nsamp + sm] = k;
+        }
+      spec.plan = frac_plan;
+      SolveResult r = solve_batch(sp, w, spec);
+      account(r, ncols, ldf);
+      DBuf<double> om;
+      om.upload(omega, s);
+      quadrature_sum(F, uout.p, w.x.p, om.p, K, nsamp, ldf, s);
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    HIPCHK(hipEventRecord(t1, s));
+    finish_out(uout, s);
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (stats) {
+      stats->n_systems = nsys;
+      stats->max_iters = max_it;
+      stats->max_rel_resid = max_rel;
+      stats->setup_ms = setup_ms;
+      stats->solve_ms = ms;
+      stats->apply_ms = apply_ms;
+      stats->apply_launches = apply_launches;
+      stats->apply_cols = apply_cols;
+    }
+    if (flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
+    if (flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,195 @@
+// Host-side construction of the spline space tables used by the device kernels:
+// Gauss-Legendre rules, B-spline values/derivatives on the dyadic knot vectors,
+// the knot-insertion (prolongation) matrix between consecutive levels, and the
+// interface gluing of the six cube-sphere patches.
+//
+// Sec. 2.1 (p-open knot vectors, B-spline recursion), Sec. 2.3 (dyadic knot
+// vectors Xi_{j,p}, the continuous space S^0_{j,p}), Sec. 3.2 (quadrature of the
+// pulled-back forms; the rule is Gauss-Legendre with p+1 points per direction).
+#include "gf_internal.h"
+
+#include <cmath>
+#include <map>
+#include <stdexcept>
+#include <tuple>
+
+namespace gf {
+
+// q-point Gauss-Legendre rule on [0,1]: Newton iteration on the three-term
+// Legendre recurrence, started from the Chebyshev-like guess cos(pi (i-1/4)/(q+1/2)).
+void gauss_legendre(int q, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= q; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (q == 1) { p1 = z; p0 = 1.0; }
+      dp = q * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // recompute derivative at the converged root
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= q; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (q == 1) { p1 = z; p0 = 1.0; }
+    dp = q * (z * p1 - p0) / (z * z - 1.0);
+    // map [-1,1] -> [0,1], ascending order
+    x[q - 1 - i] = 0.5 * (z + 1.0);
+    w[q - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);  // 2/((1-z^2)P'^2) scaled by 1/2
+  }
+}
+
+// Knot k of the p-open dyadic knot vector with nel elements, in units of 1/nel.
+static inline int knot_int(int k, int p, int nel) {
+  int v = k - p;
+  return v < 0 ? 0 : (v > nel ? nel : v);
+}
+
+// Values and first derivatives of the p+1 B-splines that are non-zero on element e
+// (indices e..e+p) at the local abscissa u in [0,1] of that element.  The recursion
+// raises the degree one step at a time on the knots around the element; a term with
+// a vanishing knot difference is dropped.
+void element_basis(int p, int nel, int e, double u, double *val, double *der) {
+  const double x = (e + u) / nel;
+  auto kn = [&](int k) { return (double)knot_int(k, p, nel) / nel; };
+  // basis functions of degree d non-zero on span [kn(e+p), kn(e+p+1)): indices e+p-d .. e+p
+  // N[d][r] holds function index e+p-d+r
+  double N[8][8] = {{0}};
+  N[0][0] = 1.0;
+  for (int d = 1; d <= p; ++d) {
+    for (int r = 0; r <= d; ++r) {
+      int l = e + p - d + r;  // global index at degree d
+      double v = 0.0;
+      // left term: (x - xi_l)/(xi_{l+d} - xi_l) * b_l^{d-1}; b_l^{d-1} = N[d-1][r-1]
+      if (r - 1 >= 0) {
+        double den = kn(l + d) - kn(l);
+        if (den > 0.0) v += (x - kn(l)) / den * N[d - 1][r - 1];
+      }
+      // right term: (xi_{l+d+1} - x)/(xi_{l+d+1} - xi_{l+1}) * b_{l+1}^{d-1}; = N[d-1][r]
+      if (r <= d - 1) {
+        double den = kn(l + d + 1) - kn(l + 1);
+        if (den > 0.0) v += (kn(l + d + 1) - x) / den * N[d - 1][r];
+      }
+      N[d][r] = v;
+    }
+  }
+  for (int r = 0; r <= p; ++r) val[r] = N[p][r];
+  if (p == 0) {
+    der[0] = 0.0;
+    return;
+  }
+  // derivative: p/(xi_{l+p}-xi_l) b_l^{p-1} - p/(xi_{l+p+1}-xi_{l+1}) b_{l+1}^{p-1}
+  for (int r = 0; r <= p; ++r) {
+    int l = e + r;
+    double dv = 0.0;
+    if (r - 1 >= 0) {
+      double den = kn(l + p) - kn(l);
+      if (den > 0.0) dv += p / den * N[p - 1][r - 1];
+    }
+    if (r <= p - 1) {
+      double den = kn(l + p + 1) - kn(l + 1);
+      if (den > 0.0) dv -= p / den * N[p - 1][r];
+    }
+    der[r] = dv;
+  }
+}
+
+// Knot-insertion matrix from level lc to lc+1 (dense, row-major (n1f x n1c)), built by
+// inserting the midpoints of all coarse spans one at a time (Boehm's algorithm).  Each
+// row holds one control point of the refined representation as a combination of the
+// coarse control points.
+std::vector<double> refinement_matrix(int p, int lc) {
+  int nel = 1 << lc;
+  std::vector<double> U;  // current knot vector in units of 1/(2 nel)
+  for (int k = 0; k < nel + 2 * p + 1; ++k) U.push_back(2.0 * knot_int(k, p, nel));
+  int nc = nel + p;
+  // rows: current control points, each a combination of nc coarse points
+  std::vector<std::vector<double>> Q(nc, std::vector<double>(nc, 0.0));
+  for (int i = 0; i < nc; ++i) Q[i][i] = 1.0;
+  for (int e = 0; e < nel; ++e) {
+    double ubar = 2.0 * e + 1.0;  // midpoint of coarse span e
+    // span index k with U[k] <= ubar < U[k+1]
+    int k = -1;
+    for (int i = 0; i + 1 < (int)U.size(); ++i)
+      if (U[i] <= ubar && ubar < U[i + 1]) { k = i; break; }
+    if (k < 0) throw std::runtime_error("knot insertion: span not found");
+    int n = (int)Q.size();
+    std::vector<std::vector<double>> R(n + 1, std::vector<double>(nc, 0.0));
+    for (int i = 0; i <= n; ++i) {
+      if (i <= k - p) {
+        R[i] = Q[i];
+      } else if (i >= k + 1) {
+        R[i] = Q[i - 1];
+      } else {
+        double a = (ubar - U[i]) / (U[i + p] - U[i]);
+        for (int c = 0; c < nc; ++c) R[i][c] = a * Q[i][c] + (1.0 - a) * Q[i - 1][c];
+      }
+    }
+    Q.swap(R);
+    U.insert(U.begin() + k + 1, ubar);
+  }
+  int nf = (int)Q.size();
+  if (nf != 2 * nel + p) throw std::runtime_error("knot insertion: wrong fine size");
+  std::vector<double> P((size_t)nf * nc);
+  for (int i = 0; i < nf; ++i)
+    for (int c = 0; c < nc; ++c) P[(size_t)i * nc + c] = Q[i][c];
+  return P;
+}
+
+// Cube-face placement of the six patches: v = (coords) with a = 2s-1, b = 2t-1.
+//   0: ( 1, a, b)  1: (-1, b, a)  2: ( b, 1, a)  3: ( a,-1, b)  4: ( a, b, 1)  5: ( b, a,-1)
+// fixed_axis/fixed_sign give the constant coordinate, a_axis/b_axis where a and b go.
+const PatchFrame kPatchFrames[6] = {
+    {0, +1, 1, 2}, {0, -1, 2, 1}, {1, +1, 2, 0}, {1, -1, 0, 2}, {2, +1, 0, 1}, {2, -1, 1, 0}};
+
+// Interface gluing on one level: local (m, iy, ix) -> global id.  Each coefficient is
+// attached to the cube-surface point of its Greville abscissae, which has integer
+// coordinates in units of 1/(p nel); equal points on different faces are the same
+// unknown.  Numbering: patches 0..5, then iy, then ix, next id to every new point.
+void glue_patches(int p, int lev, std::vector<int> &l2g, int &N) {
+  int nel = 1 << lev, n1 = nel + p;
+  std::vector<int> G(n1);  // p*nel*greville(i)
+  for (int i = 0; i < n1; ++i) {
+    int s = 0;
+    for (int k = 1; k <= p; ++k) s += knot_int(i + k, p, nel);
+    G[i] = (p == 0) ? 0 : s;
+  }
+  const int span = p * nel;
+  std::map<std::tuple<int, int, int>, int> seen;
+  l2g.assign((size_t)6 * n1 * n1, -1);
+  N = 0;
+  for (int m = 0; m < 6; ++m) {
+    const PatchFrame &f = kPatchFrames[m];
+    for (int iy = 0; iy < n1; ++iy)
+      for (int ix = 0; ix < n1; ++ix) {
+        int c[3];
+        c[f.fixed_axis] = f.fixed_sign * span;
+        c[f.a_axis] = 2 * G[ix] - span;
+        c[f.b_axis] = 2 * G[iy] - span;
+        auto key = std::make_tuple(c[0], c[1], c[2]);
+        auto it = seen.find(key);
+        int g;
+        if (it == seen.end()) {
+          g = N++;
+          seen.emplace(key, g);
+        } else {
+          g = it->second;
+        }
+        l2g[((size_t)m * n1 + iy) * n1 + ix] = g;
+      }
+  }
+}
+
+}  // namespace gf

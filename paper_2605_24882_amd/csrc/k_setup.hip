@@ -1,0 +1,442 @@
+// Setup kernels: metric terms at the Gauss points, the matrix-free sum-factorised
+// operator application, stencil extraction by probing, diagonals, the element-wise
+// white-noise load and the coarse-level Cholesky factors.
+#include "gf_internal.h"
+
+namespace gf {
+
+// cube-face frames of the six patches (same table as the host's kPatchFrames)
+__constant__ int c_frames[6][4] = {{0, 1, 1, 2}, {0, -1, 2, 1}, {1, 1, 2, 0},
+                                   {1, -1, 0, 2}, {2, 1, 0, 1}, {2, -1, 1, 0}};
+
+// Surface point and its parameter derivatives for patch m at (s, t) (Sec. 2.2 maps).
+// xh = v/|v| has d xh = (dv - xh (xh . dv))/|v|; the perturbed surface r(xh) xh has
+// d(r xh) = (grad r . d xh) xh + r d xh.
+__device__ void surface_derivs(int m, double s, double t, int perturbed, double Fs[3], double Ft[3]) {
+  const int fa = c_frames[m][0], fs = c_frames[m][1], aa = c_frames[m][2], ba = c_frames[m][3];
+  double v[3], vs[3] = {0, 0, 0}, vt[3] = {0, 0, 0};
+  v[fa] = (double)fs;
+  v[aa] = 2.0 * s - 1.0;
+  v[ba] = 2.0 * t - 1.0;
+  vs[aa] = 2.0;
+  vt[ba] = 2.0;
+  const double nv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  double xh[3], xs[3], xt[3];
+  for (int i = 0; i < 3; ++i) xh[i] = v[i] / nv;
+  const double ps = xh[0] * vs[0] + xh[1] * vs[1] + xh[2] * vs[2];
+  const double pt = xh[0] * vt[0] + xh[1] * vt[1] + xh[2] * vt[2];
+  for (int i = 0; i < 3; ++i) {
+    xs[i] = (vs[i] - xh[i] * ps) / nv;
+    xt[i] = (vt[i] - xh[i] * pt) / nv;
+  }
+  if (!perturbed) {
+    for (int i = 0; i < 3; ++i) { Fs[i] = xs[i]; Ft[i] = xt[i]; }
+    return;
+  }
+  const double X = xh[0], Y = xh[1], Z = xh[2];
+  const double r = 1.0 + 0.15 * sin(3.0 * X) * sin(2.0 * Y) * cos(Z);
+  const double gr[3] = {0.45 * cos(3.0 * X) * sin(2.0 * Y) * cos(Z), 0.30 * sin(3.0 * X) * cos(2.0 * Y) * cos(Z),
+                        -0.15 * sin(3.0 * X) * sin(2.0 * Y) * sin(Z)};
+  const double rs = gr[0] * xs[0] + gr[1] * xs[1] + gr[2] * xs[2];
+  const double rt = gr[0] * xt[0] + gr[1] * xt[1] + gr[2] * xt[2];
+  for (int i = 0; i < 3; ++i) {
+    Fs[i] = rs * xh[i] + r * xs[i];
+    Ft[i] = rt * xh[i] + r * xt[i];
+  }
+}
+
+// m = w a, G = w a K^-1 at every Gauss point (Sec. 3.2: K first fundamental form,
+// a = sqrt(det K)); w is the tensor Gauss weight of the element (area 1/nel^2).
+__global__ void k_metric(double *metric, int nel, int q, int perturbed, const double *gx, const double *gw) {
+  const int64_t total = (int64_t)6 * nel * nel * q * q;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= total) return;
+  int64_t t = id;
+  const int qx = t % q; t /= q;
+  const int qy = t % q; t /= q;
+  const int ex = t % nel; t /= nel;
+  const int ey = t % nel; t /= nel;
+  const int m = (int)t;
+  const double s = (ex + gx[qx]) / nel, tt = (ey + gx[qy]) / nel;
+  double Fs[3], Ft[3];
+  surface_derivs(m, s, tt, perturbed, Fs, Ft);
+  const double k11 = Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2];
+  const double k12 = Fs[0] * Ft[0] + Fs[1] * Ft[1] + Fs[2] * Ft[2];
+  const double k22 = Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2];
+  const double det = k11 * k22 - k12 * k12;
+  const double a = sqrt(det);
+  const double w = gw[qx] * gw[qy] / ((double)nel * nel);
+  double *o = metric + id * 4;
+  o[0] = w * a;
+  o[1] = w * a * k22 / det;
+  o[2] = -w * a * k12 / det;
+  o[3] = w * a * k11 / det;
+}
+
+void launch_metric(const Level &L, int perturbed, const double *gx, const double *gw, hipStream_t s) {
+  const int64_t total = (int64_t)6 * L.nel * L.nel * L.q * L.q;
+  hipLaunchKernelGGL(k_metric, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, L.metric.p, L.nel, L.q,
+                     perturbed, gx, gw);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ matrix-free apply
+// y = (ca M + cb S) x per column, patch by patch (no interface sum), evaluating the
+// element integrals of eq. mass / eq. stiffness at the q x q Gauss points on the fly.
+// One wavefront per block; lane = column of a 64-wide column tile.  A block owns a
+// TT x TT tile of output coefficients and visits every element touching it.  Per element
+// (sum factorisation, q = p+1):
+//   U0[b][qx] = sum_a c[b][a] Bx[qx][a],  U1[b][qx] = sum_a c[b][a] Dx[qx][a]
+//   u = sum_b U0 By, us = sum_b U1 By, ut = sum_b U0 Dy                     (at each qy, qx)
+//   v = ca m u,  gs = cb (G11 us + G12 ut),  gt = cb (G12 us + G22 ut)
+//   V0[b][qx] = sum_qy v By + gt Dy,  V1[b][qx] = sum_qy gs By
+//   y[b][a] += sum_qx V0 Bx + V1 Dx
+// Basis tables and metric terms are uniform over the wavefront.  Accumulators live in
+// LDS, one column per lane, so no barrier is needed.
+template <typename T, int P, int TT>
+__global__ __launch_bounds__(64) void k_sumfact(const T *__restrict__ metric, const T *__restrict__ basis,
+                                                const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ ca,
+                                                const T *__restrict__ cb, int nel, int n1, int W, int ldb,
+                                                const int *__restrict__ active, int ntx) {
+  constexpr int Q = P + 1, NB = P + 1;
+  const int ct = blockIdx.y;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x;
+  const int col = ct * CT + lane;
+  const int tile = blockIdx.x;
+  const int tx = tile % ntx;
+  const int ty = (tile / ntx) % ntx;
+  const int m = tile / (ntx * ntx);
+  const int x0 = tx * TT, y0 = ty * TT;
+  __shared__ T acc[TT * TT][CT];
+#pragma unroll
+  for (int i = 0; i < TT * TT; ++i) acc[i][lane] = T(0);
+  const T sig = ca[col], ss = cb[col];
+  const int64_t prow = (int64_t)m * W * W;
+  const int ey0 = max(0, y0 - P), ey1 = min(nel - 1, y0 + TT - 1);
+  const int ex0 = max(0, x0 - P), ex1 = min(nel - 1, x0 + TT - 1);
+  for (int ey = ey0; ey <= ey1; ++ey) {
+    const T *By = basis + (size_t)ey * 2 * Q * NB;
+    const T *Dy = By + Q * NB;
+    for (int ex = ex0; ex <= ex1; ++ex) {
+      const T *Bx = basis + (size_t)ex * 2 * Q * NB;
+      const T *Dx = Bx + Q * NB;
+      T c[NB][NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+          c[b][a] = x[(prow + (int64_t)(ey + b + P) * W + (ex + a + P)) * ldb + col];
+      T U0[NB][Q], U1[NB][Q];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) {
+          T s0 = 0, s1 = 0;
+#pragma unroll
+          for (int a = 0; a < NB; ++a) {
+            s0 += c[b][a] * Bx[qx * NB + a];
+            s1 += c[b][a] * Dx[qx * NB + a];
+          }
+          U0[b][qx] = s0;
+          U1[b][qx] = s1;
+        }
+      const T *mt = metric + ((((size_t)m * nel + ey) * nel + ex) * Q * Q) * 4;
+      T V0[NB][Q], V1[NB][Q];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) { V0[b][qx] = 0; V1[b][qx] = 0; }
+#pragma unroll
+      for (int qy = 0; qy < Q; ++qy)
+#pragma unroll
+        for (int qx = 0; qx < Q; ++qx) {
+          T u = 0, us = 0, ut = 0;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            u += U0[b][qx] * By[qy * NB + b];
+            us += U1[b][qx] * By[qy * NB + b];
+            ut += U0[b][qx] * Dy[qy * NB + b];
+          }
+          const T *g = mt + (qy * Q + qx) * 4;
+          const T v = sig * g[0] * u;
+          const T gs = ss * (g[1] * us + g[2] * ut);
+          const T gt = ss * (g[2] * us + g[3] * ut);
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            V0[b][qx] += v * By[qy * NB + b] + gt * Dy[qy * NB + b];
+            V1[b][qx] += gs * By[qy * NB + b];
+          }
+        }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int iy = ey + b - y0;
+        if (iy < 0 || iy >= TT) continue;
+#pragma unroll
+        for (int a = 0; a < NB; ++a) {
+          const int ix = ex + a - x0;
+          if (ix < 0 || ix >= TT) continue;
+          T r = 0;
+#pragma unroll
+          for (int qx = 0; qx < Q; ++qx) r += V0[b][qx] * Bx[qx * NB + a] + V1[b][qx] * Dx[qx * NB + a];
+          acc[iy * TT + ix][lane] += r;
+        }
+      }
+    }
+  }
+  for (int iy = 0; iy < TT; ++iy) {
+    if (y0 + iy >= n1) break;
+    for (int ix = 0; ix < TT; ++ix) {
+      if (x0 + ix >= n1) break;
+      y[(prow + (int64_t)(y0 + iy + P) * W + (x0 + ix + P)) * ldb + col] = acc[iy * TT + ix][lane];
+    }
+  }
+}
+
+template <typename T>
+static const T *metric_of(const Level &L);
+template <>
+const double *metric_of<double>(const Level &L) { return L.metric.p; }
+template <>
+const float *metric_of<float>(const Level &L) { return L.metric32.p; }
+template <typename T>
+static const T *basis_of(const Level &L);
+template <>
+const double *basis_of<double>(const Level &L) { return L.basis.p; }
+template <>
+const float *basis_of<float>(const Level &L) { return L.basis32.p; }
+
+template <typename T>
+void launch_sumfact_apply(const Level &L, const T *x, T *y, const T *ca, const T *cb, int ldb, int ntiles,
+                          const int *active, hipStream_t s) {
+  constexpr int TT = 8;
+  const int ntx = (L.n1 + TT - 1) / TT;
+  dim3 grid(6 * ntx * ntx, ntiles), block(CT);
+  const T *mt = metric_of<T>(L), *bs = basis_of<T>(L);
+  switch (L.p) {
+#define GF_SF(PP)                                                                                              \
+  case PP:                                                                                                     \
+    hipLaunchKernelGGL((k_sumfact<T, PP, TT>), grid, block, 0, s, mt, bs, x, y, ca, cb, L.nel, L.n1, L.W, ldb, \
+                       active, ntx);                                                                           \
+    break;
+    GF_SF(1) GF_SF(2) GF_SF(3) GF_SF(4) GF_SF(5)
+#undef GF_SF
+    default: fail(GF_EUNSUPPORTED, "degree out of range");
+  }
+  HIPCHK(hipGetLastError());
+}
+template void launch_sumfact_apply<double>(const Level &, const double *, double *, const double *, const double *,
+                                           int, int, const int *, hipStream_t);
+template void launch_sumfact_apply<float>(const Level &, const float *, float *, const float *, const float *, int,
+                                          int, const int *, hipStream_t);
+
+// ------------------------------------------------------------------ stencil by probing
+// Column c < S*S probes colour c = (iy mod S)*S + (ix mod S) for M, column S*S + c the same
+// colour for S.  Within the (2p+1)^2 window of any coefficient each colour occurs exactly
+// once, so (A x_c)[row] is the single stencil entry of that colour.
+__global__ void k_probe(double *x, int ldb, int n1, int W, int P, int Sw) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (r >= (int64_t)6 * W * W) return;
+  const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P;
+  const bool inside = lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
+  const int colour = inside ? (ly % Sw) * Sw + (lx % Sw) : -1;
+  for (int c = threadIdx.x; c < ldb; c += blockDim.x) {
+    const double v = (inside && c < 2 * Sw * Sw && c % (Sw * Sw) == colour) ? 1.0 : 0.0;
+    x[r * ldb + c] = v;
+  }
+}
+
+void launch_probe_vectors(const Level &L, double *x, int ldb, hipStream_t s) {
+  dim3 block(64, 4);
+  dim3 grid((unsigned)((L.R + block.y - 1) / block.y));
+  hipLaunchKernelGGL(k_probe, grid, block, 0, s, x, ldb, L.n1, L.W, L.p, L.S);
+  HIPCHK(hipGetLastError());
+}
+
+__global__ void k_extract(const double *y, int ldb, double *stM, double *stS, int n1, int W, int P, int Sw) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)6 * W * W) return;
+  const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P;
+  const bool inside = lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
+  for (int dy = -P; dy <= P; ++dy)
+    for (int dx = -P; dx <= P; ++dx) {
+      const int d = (dy + P) * Sw + (dx + P);
+      const int nx = lx + dx, ny = ly + dy;
+      double vm = 0.0, vs = 0.0;
+      if (inside && nx >= 0 && nx < n1 && ny >= 0 && ny < n1) {
+        const int colour = (ny % Sw) * Sw + (nx % Sw);
+        vm = y[r * ldb + colour];
+        vs = y[r * ldb + Sw * Sw + colour];
+      }
+      stM[r * Sw * Sw + d] = vm;
+      stS[r * Sw * Sw + d] = vs;
+    }
+}
+
+void launch_extract_stencil(const Level &L, const double *y, int ldb, double *stM, double *stS, hipStream_t s) {
+  hipLaunchKernelGGL(k_extract, dim3((unsigned)((L.R + 255) / 256)), dim3(256), 0, s, y, ldb, stM, stS, L.n1, L.W,
+                     L.p, L.S);
+  HIPCHK(hipGetLastError());
+}
+
+// diagonals: the stencil centre of every copy, then summed over the copies of shared unknowns
+__global__ void k_diag_centre(const double *stM, const double *stS, double *dM, double *dS, int64_t R, int c) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  dM[r] = stM[r * (2 * c + 1) * (2 * c + 1) + c * (2 * c + 1) + c];
+  dS[r] = stS[r * (2 * c + 1) * (2 * c + 1) + c * (2 * c + 1) + c];
+}
+__global__ void k_diag_sum(double *dM, double *dS, const int *gp, const int *gr, int ng) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  double sm = 0, ss = 0;
+  for (int k = gp[g]; k < gp[g + 1]; ++k) { sm += dM[gr[k]]; ss += dS[gr[k]]; }
+  for (int k = gp[g]; k < gp[g + 1]; ++k) { dM[gr[k]] = sm; dS[gr[k]] = ss; }
+}
+__global__ void k_to_f32(const double *a, float *b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+void launch_stencil_diag(const Level &L, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_centre, dim3((unsigned)((L.R + 255) / 256)), dim3(256), 0, s, L.stM.p, L.stS.p, L.dM.p,
+                     L.dS.p, L.R, L.p);
+  if (L.ngroups > 0)
+    hipLaunchKernelGGL(k_diag_sum, dim3((L.ngroups + 255) / 256), dim3(256), 0, s, L.dM.p, L.dS.p, L.grp_ptr.p,
+                       L.grp_rows.p, L.ngroups);
+  HIPCHK(hipGetLastError());
+}
+
+void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ white noise (Sec. 3.3)
+// Pass 1, one thread per element: element mass matrix M_e = sum_q m_q phi_i phi_j, its lower
+// Cholesky factor, and y_e = L_e z_e for every sample.
+template <int P>
+__global__ void k_noise_elements(const double *metric, const double *basis, const double *z, double *ye, int nel,
+                                 int nsamp) {
+  constexpr int Q = P + 1, NB = P + 1, NL = NB * NB;
+  const int64_t ne_tot = (int64_t)6 * nel * nel;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne_tot) return;
+  const int ex = (int)(e % nel), ey = (int)((e / nel) % nel);
+  const double *Bx = basis + (size_t)ex * 2 * Q * NB;
+  const double *By = basis + (size_t)ey * 2 * Q * NB;
+  const double *mt = metric + e * Q * Q * 4;
+  double A[NL][NL];
+  for (int i = 0; i < NL; ++i)
+    for (int j = 0; j < NL; ++j) A[i][j] = 0.0;
+  for (int qy = 0; qy < Q; ++qy)
+    for (int qx = 0; qx < Q; ++qx) {
+      const double w = mt[(qy * Q + qx) * 4];
+      double phi[NL];
+      for (int b = 0; b < NB; ++b)
+        for (int a = 0; a < NB; ++a) phi[b * NB + a] = By[qy * NB + b] * Bx[qx * NB + a];
+      for (int i = 0; i < NL; ++i)
+        for (int j = 0; j < NL; ++j) A[i][j] += w * phi[i] * phi[j];
+    }
+  // in-place lower Cholesky
+  for (int j = 0; j < NL; ++j) {
+    double d = A[j][j];
+    for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
+    d = sqrt(d);
+    A[j][j] = d;
+    for (int i = j + 1; i < NL; ++i) {
+      double v = A[i][j];
+      for (int k = 0; k < j; ++k) v -= A[i][k] * A[j][k];
+      A[i][j] = v / d;
+    }
+  }
+  for (int s = 0; s < nsamp; ++s) {
+    const double *zs = z + ((size_t)s * ne_tot + e) * NL;
+    double *ys = ye + ((size_t)s * ne_tot + e) * NL;
+    for (int i = 0; i < NL; ++i) {
+      double v = 0.0;
+      for (int k = 0; k <= i; ++k) v += A[i][k] * zs[k];
+      ys[i] = v;
+    }
+  }
+}
+
+// Pass 2, one thread per (coefficient row, sample): gather the element contributions of all
+// elements containing the coefficient (patch-local, before the interface sum).
+__global__ void k_noise_gather(const double *ye, double *bl, int nel, int n1, int W, int P, int nsamp, int64_t R,
+                               int ldb) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= R * nsamp) return;
+  const int64_t r = id / nsamp;
+  const int s = (int)(id % nsamp);
+  const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P, m = (int)(r / ((int64_t)W * W));
+  if (lx < 0 || lx >= n1 || ly < 0 || ly >= n1) return;
+  const int NB = P + 1, NL = NB * NB;
+  const int64_t ne_tot = (int64_t)6 * nel * nel;
+  double v = 0.0;
+  for (int b = 0; b < NB; ++b) {
+    const int ey = ly - b;
+    if (ey < 0 || ey >= nel) continue;
+    for (int a = 0; a < NB; ++a) {
+      const int ex = lx - a;
+      if (ex < 0 || ex >= nel) continue;
+      const int64_t e = ((int64_t)m * nel + ey) * nel + ex;
+      v += ye[((size_t)s * ne_tot + e) * NL + b * NB + a];
+    }
+  }
+  bl[r * ldb + s] = v;
+}
+
+void launch_white_noise(const Level &L, const double *z, int nsamp, double *ye, double *bl, int ldb, hipStream_t s) {
+  const int64_t ne_tot = (int64_t)6 * L.nel * L.nel;
+  dim3 g1((unsigned)((ne_tot + 63) / 64)), b1(64);
+  switch (L.p) {
+    case 1: hipLaunchKernelGGL(k_noise_elements<1>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
+    case 2: hipLaunchKernelGGL(k_noise_elements<2>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
+    case 3: hipLaunchKernelGGL(k_noise_elements<3>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
+    case 4: hipLaunchKernelGGL(k_noise_elements<4>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
+    case 5: hipLaunchKernelGGL(k_noise_elements<5>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
+    default: fail(GF_EUNSUPPORTED, "degree out of range");
+  }
+  HIPCHK(hipGetLastError());
+  const int64_t tot = L.R * nsamp;
+  hipLaunchKernelGGL(k_noise_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ye, bl, L.nel, L.n1, L.W,
+                     L.p, nsamp, L.R, ldb);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ coarse Cholesky
+// One thread per node: A = sigma M0 + S0 (dense, global numbering of the coarsest level),
+// lower Cholesky factor in place.  info = 0 on success, k+1 if pivot k is not positive.
+__global__ void k_coarse_factor(const double *M0, const double *S0, int n, const double *sig, int nnode, double *Lf,
+                                int *info) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnode) return;
+  double *A = Lf + (size_t)k * n * n;
+  const double sg = sig[k];
+  for (int i = 0; i < n * n; ++i) A[i] = sg * M0[i] + S0[i];
+  int bad = 0;
+  for (int j = 0; j < n && !bad; ++j) {
+    double d = A[j * n + j];
+    for (int t = 0; t < j; ++t) d -= A[j * n + t] * A[j * n + t];
+    if (!(d > 0.0)) { bad = j + 1; break; }
+    d = sqrt(d);
+    A[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i * n + j];
+      for (int t = 0; t < j; ++t) v -= A[i * n + t] * A[j * n + t];
+      A[i * n + j] = v / d;
+    }
+    for (int i = 0; i < j; ++i) A[i * n + j] = 0.0;  // clear the upper triangle
+  }
+  info[k] = bad;
+}
+
+void launch_coarse_factor(const double *M0, const double *S0, int N0, const double *sig, int nnode, double *Lf,
+                          int *info, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_factor, dim3((nnode + 63) / 64), dim3(64), 0, s, M0, S0, N0, sig, nnode, Lf, info);
+  HIPCHK(hipGetLastError());
+}
+
+}  // namespace gf

@@ -1,0 +1,670 @@
+// Solver kernels: stencil operator application, interface sums, wavefront-reduction
+// inner products with per-system CG scalar updates, CG vector updates, Chebyshev-Jacobi
+// smoothing, knot-insertion transfers, the coarsest-level Cholesky solve, and the
+// conversions between the caller's global numbering and the patch-local batch layout.
+//
+// Batch layout (all kernels): rows of the padded patch-local grid, 64-column tiles of
+// systems; one wavefront covers one row of one tile, lane = system, so per-row data
+// (stencils, diagonals, masks) is uniform over the wavefront and every vector access is
+// a contiguous 256 B (FP32) or 512 B (FP64) transaction.
+#include "gf_internal.h"
+#include "k_solve.h"
+
+namespace gf {
+
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ bool row_interior(int64_t r, int W, int P, int n1) {
+  const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P;
+  return lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
+}
+
+// ------------------------------------------------------------------ stencil apply
+// y = ca (M x) + cb (S x) with the per-patch (2p+1)^2 stencils (rows of the patch matrices
+// of eq. mass / eq. stiffness).  A wavefront walks a strip of TX coefficients along ix at
+// fixed (patch, iy), keeping a (2p+1) x (2p+1) window of x in registers: one new x value per
+// stencil row and step.  Ghost padding makes every window load valid.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_stencil(const T *__restrict__ stM, const T *__restrict__ stS,
+                                                 const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ ca,
+                                                 const T *__restrict__ cb, int W, int n1, int ldb, int nseg, int TX,
+                                                 const int *__restrict__ active) {
+  constexpr int S = 2 * P + 1;
+  const int ct = blockIdx.y;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x;
+  const int col = ct * CT + lane;
+  const int strip = wave_uniform(blockIdx.x * 4 + threadIdx.y);
+  if (strip >= 6 * nseg * n1) return;
+  const int iy = strip % n1;
+  const int seg = (strip / n1) % nseg;
+  const int m = strip / (n1 * nseg);
+  const int x0 = seg * TX;
+  const int x1 = min(x0 + TX, n1);
+  const T a = ca[col], b = cb[col];
+  const int64_t rowbase = (int64_t)m * W * W + (int64_t)(iy + P) * W + P;
+  const T *xc = x + col;
+  T win[S][S];
+#pragma unroll
+  for (int dy = 0; dy < S; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < S - 1; ++dx)
+      win[dy][dx + 1] = xc[(rowbase + (int64_t)(dy - P) * W + (x0 - P + dx)) * ldb];
+  for (int ix = x0; ix < x1; ++ix) {
+#pragma unroll
+    for (int dy = 0; dy < S; ++dy) {
+#pragma unroll
+      for (int dx = 0; dx < S - 1; ++dx) win[dy][dx] = win[dy][dx + 1];
+      win[dy][S - 1] = xc[(rowbase + (int64_t)(dy - P) * W + (ix + P)) * ldb];
+    }
+    const int64_t row = rowbase + ix;
+    const T *cm = stM + row * (S * S);
+    const T *cs = stS + row * (S * S);
+    T am = 0, as = 0;
+#pragma unroll
+    for (int dy = 0; dy < S; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < S; ++dx) {
+        am = fma(cm[dy * S + dx], win[dy][dx], am);
+        as = fma(cs[dy * S + dx], win[dy][dx], as);
+      }
+    y[row * ldb + col] = a * am + b * as;
+  }
+}
+
+template <typename T>
+void launch_stencil_apply(const Level &L, const T *stM, const T *stS, const T *x, T *y, const T *ca, const T *cb,
+                          int ldb, int ntiles, const int *active, hipStream_t s) {
+  const int txmax = 32;
+  const int nseg = (L.n1 + txmax - 1) / txmax;
+  const int TX = (L.n1 + nseg - 1) / nseg;
+  const int nstrip = 6 * nseg * L.n1;
+  dim3 grid((nstrip + 3) / 4, ntiles), block(CT, 4);
+  switch (L.p) {
+#define GF_ST(PP)                                                                                                  \
+  case PP:                                                                                                         \
+    hipLaunchKernelGGL((k_stencil<T, PP>), grid, block, 0, s, stM, stS, x, y, ca, cb, L.W, L.n1, ldb, nseg, TX, \
+                       active);                                                                                    \
+    break;
+    GF_ST(1) GF_ST(2) GF_ST(3) GF_ST(4) GF_ST(5)
+#undef GF_ST
+    default: fail(GF_EUNSUPPORTED, "degree out of range");
+  }
+  HIPCHK(hipGetLastError());
+}
+template void launch_stencil_apply<double>(const Level &, const double *, const double *, const double *, double *,
+                                           const double *, const double *, int, int, const int *, hipStream_t);
+template void launch_stencil_apply<float>(const Level &, const float *, const float *, const float *, float *,
+                                          const float *, const float *, int, int, const int *, hipStream_t);
+
+// ------------------------------------------------------------------ interface sum
+// Copies of one unknown on neighbouring patches (2 on edges, 3 at cube corners) receive the
+// sum of their patch contributions: this turns patch-local results into the assembled
+// global operator (Sec. 2.3, continuity across interfaces).
+template <typename T>
+__global__ __launch_bounds__(256) void k_iface(T *y, int ldb, const int *__restrict__ gp, const int *__restrict__ gr,
+                                               int ng, const int *__restrict__ active) {
+  const int ct = blockIdx.y;
+  if (active && !active[ct]) return;
+  const int g = wave_uniform(blockIdx.x * 4 + threadIdx.y);
+  if (g >= ng) return;
+  const int col = ct * CT + threadIdx.x;
+  const int k0 = gp[g], k1 = gp[g + 1];
+  T s = 0;
+  for (int k = k0; k < k1; ++k) s += y[(int64_t)gr[k] * ldb + col];
+  for (int k = k0; k < k1; ++k) y[(int64_t)gr[k] * ldb + col] = s;
+}
+
+template <typename T>
+void launch_interface_sum(const Level &L, T *y, int ldb, int ntiles, const int *active, hipStream_t s) {
+  if (L.ngroups == 0) return;
+  hipLaunchKernelGGL(k_iface<T>, dim3((L.ngroups + 3) / 4, ntiles), dim3(CT, 4), 0, s, y, ldb, L.grp_ptr.p,
+                     L.grp_rows.p, L.ngroups, active);
+  HIPCHK(hipGetLastError());
+}
+template void launch_interface_sum<double>(const Level &, double *, int, int, const int *, hipStream_t);
+template void launch_interface_sum<float>(const Level &, float *, int, int, const int *, hipStream_t);
+
+// ------------------------------------------------------------------ reductions
+// Row-loop kernels with an inner-product epilogue.  Each block reduces its rows for the 64
+// columns of its tile through LDS, writes one partial per column, and the last block of the
+// tile to finish (device-scope counter) sums the partials in block order -- a fixed order,
+// so results are bitwise reproducible -- and applies the per-system scalar step `op`.
+struct RowCtx {
+  int64_t R;
+  int W, P, n1, ldb;
+  const uint8_t *owner;
+};
+
+__device__ void finalize_op(int op, int col, const double *tot, ColState *cs, double tol2, int maxit, double *out,
+                            int ldb) {
+  if (op == OP_STORE) {
+    out[col] = tot[0];
+    out[ldb + col] = tot[1];
+    return;
+  }
+  ColState &c = cs[col];
+  switch (op) {
+    case OP_BB:
+      c.bb = tot[0];
+      c.rr = tot[0];
+      c.it = 0;
+      c.flag = 0;
+      c.alpha = 0;
+      c.beta = 0;
+      c.done = (c.done || !(tot[0] > 0.0)) ? 1 : 0;
+      break;
+    case OP_RZ0:
+      c.rz = tot[0];
+      break;
+    case OP_ALPHA:
+      if (c.done) {
+        c.alpha = 0.0;
+      } else if (!(tot[0] > 0.0) || !isfinite(tot[0]) || !isfinite(c.rz)) {
+        c.flag |= 2;
+        c.done = 1;
+        c.alpha = 0.0;
+      } else {
+        c.alpha = c.rz / tot[0];
+      }
+      break;
+    case OP_CHECK:
+      c.rr = tot[0];
+      if (!c.done) {
+        c.it += 1;
+        if (!isfinite(tot[0])) {
+          c.flag |= 2;
+          c.done = 1;
+        } else if (tot[0] <= tol2 * c.bb) {
+          c.done = 1;
+        } else if (c.it >= maxit) {
+          c.flag |= 1;
+          c.done = 1;
+        }
+      }
+      break;
+    case OP_BETA:
+      c.beta = c.done ? 0.0 : tot[0] / c.rz;
+      c.rz = tot[0];
+      break;
+    case OP_BETA_FLEX:
+      // Polak-Ribiere: beta = z_new^T (r_new - r_old) / rz_old with r_new - r_old = -alpha q
+      c.beta = c.done ? 0.0 : -c.alpha * tot[1] / c.rz;
+      c.rz = tot[0];
+      break;
+    default:
+      break;
+  }
+}
+
+template <class F, int ND>
+__global__ __launch_bounds__(256) void k_rowreduce(F f, RowCtx rc, double *partial, int *counter, ColState *cs,
+                                                   int *active, int op, double tol2, int maxit, double *out) {
+  const int ct = blockIdx.y;
+  const bool was_active = !active || active[ct];
+  const int lane = threadIdx.x;
+  const int col = ct * CT + lane;
+  const int wave = wave_uniform(threadIdx.y);
+  double acc[ND > 0 ? ND : 1];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) acc[k] = 0.0;
+  if (was_active) {
+    for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < rc.R; r += (int64_t)gridDim.x * 4) {
+      if (!row_interior(r, rc.W, rc.P, rc.n1)) continue;
+      f(r, col, rc.owner[r] != 0, acc);
+    }
+  }
+  if (ND == 0) return;
+  __shared__ double red[4][ND > 0 ? ND : 1][CT];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) red[threadIdx.y][k][lane] = acc[k];
+  __syncthreads();
+  __shared__ int last;
+  if (threadIdx.y == 0) {
+    const int nrb = gridDim.x;
+    const int ldb = rc.ldb;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      const double v = red[0][k][lane] + red[1][k][lane] + red[2][k][lane] + red[3][k][lane];
+      partial[((int64_t)k * nrb + blockIdx.x) * ldb + col] = v;
+    }
+    __threadfence();
+    if (lane == 0) {
+      const int prev = atomicAdd(&counter[ct], 1);
+      last = (prev == nrb - 1);
+    }
+  }
+  __syncthreads();
+  if (!last || threadIdx.y != 0) return;
+  __threadfence();
+  const int nrb = gridDim.x;
+  double tot[2] = {0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    double s = 0.0;
+    for (int b = 0; b < nrb; ++b) s += partial[((int64_t)k * nrb + b) * rc.ldb + col];
+    tot[k] = s;
+  }
+  if (lane == 0) counter[ct] = 0;
+  if (!was_active && op != OP_STORE) return;
+  finalize_op(op, col, tot, cs, tol2, maxit, out, rc.ldb);
+  if (op == OP_CHECK && active) {
+    const bool alive = !cs[col].done;
+    const unsigned long long any = __ballot(alive);
+    if (lane == 0) active[ct] = any ? 1 : 0;
+  }
+}
+
+// row functors ------------------------------------------------------
+template <typename TA, typename TB>
+struct FDot {
+  const TA *a;
+  const TB *b;
+  int ldb;
+  __device__ void operator()(int64_t r, int col, bool own, double *acc) const {
+    if (own) acc[0] += (double)a[r * ldb + col] * (double)b[r * ldb + col];
+  }
+};
+template <typename TA, typename TB, typename TC>
+struct FDot2 {  // acc0 = a.b, acc1 = b.c
+  const TA *a;
+  const TB *b;
+  const TC *c;
+  int ldb;
+  __device__ void operator()(int64_t r, int col, bool own, double *acc) const {
+    if (own) {
+      const double bv = (double)b[r * ldb + col];
+      acc[0] += (double)a[r * ldb + col] * bv;
+      acc[1] += bv * (double)c[r * ldb + col];
+    }
+  }
+};
+struct FUpdateXR {  // x += alpha p, r -= alpha q, acc = r.r
+  double *x, *r;
+  const double *p, *q;
+  const ColState *cs;
+  int ldb;
+  __device__ void operator()(int64_t row, int col, bool own, double *acc) const {
+    const double al = cs[col].alpha;
+    const int64_t i = row * ldb + col;
+    const double rn = r[i] - al * q[i];
+    x[i] += al * p[i];
+    r[i] = rn;
+    if (own) acc[0] += rn * rn;
+  }
+};
+
+static RowCtx rowctx(const Level &L, int ldb) { return RowCtx{L.R, L.W, L.p, L.n1, ldb, L.owner.p}; }
+
+static int row_blocks(const Level &L, int ntiles) {
+  const int64_t waves_rows = (L.R + 3) / 4;
+  int nrb = (int)std::min<int64_t>(waves_rows, std::max<int64_t>(1, 4096 / std::max(1, ntiles)));
+  return std::max(1, std::min(nrb, kMaxRowBlocks));
+}
+
+template <class F, int ND>
+static void run_reduce(const Level &L, F f, Scratch &sc, int ldb, int ntiles, ColState *cs, int *active, int op,
+                       double tol2, int maxit, double *out, hipStream_t s) {
+  const int nrb = row_blocks(L, ntiles);
+  hipLaunchKernelGGL((k_rowreduce<F, ND>), dim3(nrb, ntiles), dim3(CT, 4), 0, s, f, rowctx(L, ldb), sc.partial,
+                     sc.counter, cs, active, op, tol2, maxit, out);
+  HIPCHK(hipGetLastError());
+}
+
+template <typename TA, typename TB>
+void reduce_dot(const Level &L, const TA *a, const TB *b, Scratch &sc, int ldb, int ntiles, ColState *cs,
+                int *active, int op, double tol2, int maxit, double *out, hipStream_t s) {
+  run_reduce<FDot<TA, TB>, 1>(L, FDot<TA, TB>{a, b, ldb}, sc, ldb, ntiles, cs, active, op, tol2, maxit, out, s);
+}
+template void reduce_dot<double, double>(const Level &, const double *, const double *, Scratch &, int, int,
+                                         ColState *, int *, int, double, int, double *, hipStream_t);
+template void reduce_dot<double, float>(const Level &, const double *, const float *, Scratch &, int, int,
+                                        ColState *, int *, int, double, int, double *, hipStream_t);
+
+template <typename TA, typename TB, typename TC>
+void reduce_dot2(const Level &L, const TA *a, const TB *b, const TC *c, Scratch &sc, int ldb, int ntiles,
+                 ColState *cs, int *active, int op, double tol2, int maxit, double *out, hipStream_t s) {
+  run_reduce<FDot2<TA, TB, TC>, 2>(L, FDot2<TA, TB, TC>{a, b, c, ldb}, sc, ldb, ntiles, cs, active, op, tol2, maxit,
+                                   out, s);
+}
+template void reduce_dot2<double, double, double>(const Level &, const double *, const double *, const double *,
+                                                  Scratch &, int, int, ColState *, int *, int, double, int, double *,
+                                                  hipStream_t);
+template void reduce_dot2<double, float, double>(const Level &, const double *, const float *, const double *,
+                                                 Scratch &, int, int, ColState *, int *, int, double, int, double *,
+                                                 hipStream_t);
+
+void update_xr(const Level &L, double *x, double *r, const double *p, const double *q, Scratch &sc, int ldb,
+               int ntiles, ColState *cs, int *active, double tol2, int maxit, hipStream_t s) {
+  run_reduce<FUpdateXR, 1>(L, FUpdateXR{x, r, p, q, cs, ldb}, sc, ldb, ntiles, cs, active, OP_CHECK, tol2, maxit,
+                           nullptr, s);
+}
+
+// ------------------------------------------------------------------ elementwise row kernels
+template <class F>
+__global__ __launch_bounds__(256) void k_rows(F f, RowCtx rc, const int *__restrict__ active) {
+  const int ct = blockIdx.y;
+  if (active && !active[ct]) return;
+  const int col = ct * CT + threadIdx.x;
+  const int wave = wave_uniform(threadIdx.y);
+  for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < rc.R; r += (int64_t)gridDim.x * 4) {
+    if (!row_interior(r, rc.W, rc.P, rc.n1)) continue;
+    f(r, col);
+  }
+}
+
+template <class F>
+static void run_rows(const Level &L, F f, int ldb, int ntiles, const int *active, hipStream_t s) {
+  const int nrb = row_blocks(L, ntiles);
+  hipLaunchKernelGGL(k_rows<F>, dim3(nrb, ntiles), dim3(CT, 4), 0, s, f, rowctx(L, ldb), active);
+  HIPCHK(hipGetLastError());
+}
+
+template <typename TZ>
+struct FUpdateP {  // p = z + beta p
+  double *p;
+  const TZ *z;
+  const ColState *cs;
+  int ldb;
+  __device__ void operator()(int64_t r, int col) const {
+    const int64_t i = r * ldb + col;
+    p[i] = (double)z[i] + cs[col].beta * p[i];
+  }
+};
+template <typename TZ>
+void update_p(const Level &L, double *p, const TZ *z, const ColState *cs, int ldb, int ntiles, const int *active,
+              hipStream_t s) {
+  run_rows(L, FUpdateP<TZ>{p, z, cs, ldb}, ldb, ntiles, active, s);
+}
+template void update_p<double>(const Level &, double *, const double *, const ColState *, int, int, const int *,
+                               hipStream_t);
+template void update_p<float>(const Level &, double *, const float *, const ColState *, int, int, const int *,
+                              hipStream_t);
+
+template <typename TS, typename TD>
+struct FConvert {
+  const TS *a;
+  TD *b;
+  int ldb;
+  __device__ void operator()(int64_t r, int col) const { b[r * ldb + col] = (TD)a[r * ldb + col]; }
+};
+template <typename TS, typename TD>
+void convert_rows(const Level &L, const TS *a, TD *b, int ldb, int ntiles, const int *active, hipStream_t s) {
+  run_rows(L, FConvert<TS, TD>{a, b, ldb}, ldb, ntiles, active, s);
+}
+template void convert_rows<double, float>(const Level &, const double *, float *, int, int, const int *,
+                                          hipStream_t);
+template void convert_rows<float, double>(const Level &, const float *, double *, int, int, const int *,
+                                          hipStream_t);
+template void convert_rows<double, double>(const Level &, const double *, double *, int, int, const int *,
+                                           hipStream_t);
+
+// Chebyshev-Jacobi step on D^-1 A, D = sigma diag(M) + diag(S) (assembled diagonals):
+//   res = (r - Az)/D  (Az == null: initial guess zero),  d = c1 d + c2 invb res,  z = z + d
+// (z = d when `first`).  invb is the per-system reciprocal of the upper spectral bound.
+template <typename T>
+struct FCheb {
+  T *z, *d;
+  const T *r, *Az;
+  const T *dM, *dS, *sig, *invb;
+  T c1, c2;
+  int first, ldb;
+  __device__ void operator()(int64_t row, int col) const {
+    const int64_t i = row * ldb + col;
+    const T D = sig[col] * dM[row] + dS[row];
+    const T res = (Az ? (r[i] - Az[i]) : r[i]) / D;
+    const T dn = (c1 != T(0) ? c1 * d[i] : T(0)) + c2 * invb[col] * res;
+    d[i] = dn;
+    z[i] = first ? dn : z[i] + dn;
+  }
+};
+template <typename T>
+void cheb_step(const Level &L, T *z, T *d, const T *r, const T *Az, const T *dM, const T *dS, const T *sig,
+               const T *invb, T c1, T c2, int first, int ldb, int ntiles, const int *active, hipStream_t s) {
+  run_rows(L, FCheb<T>{z, d, r, Az, dM, dS, sig, invb, c1, c2, first, ldb}, ldb, ntiles, active, s);
+}
+template void cheb_step<double>(const Level &, double *, double *, const double *, const double *, const double *,
+                                const double *, const double *, const double *, double, double, int, int, int,
+                                const int *, hipStream_t);
+template void cheb_step<float>(const Level &, float *, float *, const float *, const float *, const float *,
+                               const float *, const float *, const float *, float, float, int, int, int, const int *,
+                               hipStream_t);
+
+// power-iteration step for the spectral bound of D^-1 A: v = w / D
+struct FDivDiag {
+  double *v;
+  const double *w, *dM, *dS, *sig;
+  int ldb;
+  __device__ void operator()(int64_t row, int col) const {
+    const int64_t i = row * ldb + col;
+    v[i] = w[i] / (sig[col] * dM[row] + dS[row]);
+  }
+};
+void div_diag(const Level &L, double *v, const double *w, const double *sig, int ldb, int ntiles, hipStream_t s) {
+  run_rows(L, FDivDiag{v, w, L.dM.p, L.dS.p, sig, ldb}, ldb, ntiles, nullptr, s);
+}
+
+// deterministic start vector in [0.5, 1.5) from a hash of (row, column)
+struct FHashFill {
+  double *v;
+  int ldb;
+  __device__ void operator()(int64_t row, int col) const {
+    uint64_t h = (uint64_t)row * 0x9E3779B97F4A7C15ull ^ ((uint64_t)col + 0x632BE59BD9B4E019ull);
+    h ^= h >> 31;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 27;
+    h *= 0x94D049BB133111EBull;
+    h ^= h >> 31;
+    v[row * ldb + col] = 0.5 + (double)(h >> 11) * (1.0 / 9007199254740992.0);
+  }
+};
+void hash_fill(const Level &L, double *v, int ldb, int ntiles, hipStream_t s) {
+  run_rows(L, FHashFill{v, ldb}, ldb, ntiles, nullptr, s);
+}
+
+// ------------------------------------------------------------------ transfers
+// Restriction of a residual: rc = P^T (owner mask (r - Az)) per patch, 1D knot-insertion
+// matrices in both directions (tensor product).  The owner mask turns the assembled fine
+// residual into one contribution per unknown; the coarse interface sum follows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(T *rc, const T *r, const T *Az, const uint8_t *__restrict__ ownf,
+                                                  int Wf, int Wc, int n1c, int P, int ldb,
+                                                  const int *__restrict__ rs, const T *__restrict__ rcoef, int rw,
+                                                  const int *__restrict__ active) {
+  const int ct = blockIdx.y;
+  if (active && !active[ct]) return;
+  const int col = ct * CT + threadIdx.x;
+  const int id = wave_uniform(blockIdx.x * 4 + threadIdx.y);
+  if (id >= 6 * n1c * n1c) return;
+  const int ixc = id % n1c, iyc = (id / n1c) % n1c, m = id / (n1c * n1c);
+  const int64_t fbase = (int64_t)m * Wf * Wf;
+  const int fy0 = rs[iyc], fx0 = rs[ixc];
+  T acc = 0;
+  for (int k = 0; k < rw; ++k) {
+    const T wy = rcoef[iyc * rw + k];
+    if (wy == T(0)) continue;
+    for (int l = 0; l < rw; ++l) {
+      const T wx = rcoef[ixc * rw + l];
+      if (wx == T(0)) continue;
+      const int64_t rf = fbase + (int64_t)(fy0 + k + P) * Wf + (fx0 + l + P);
+      if (!ownf[rf]) continue;
+      const int64_t i = rf * ldb + col;
+      acc += wy * wx * (Az ? r[i] - Az[i] : r[i]);
+    }
+  }
+  rc[((int64_t)m * Wc * Wc + (int64_t)(iyc + P) * Wc + (ixc + P)) * ldb + col] = acc;
+}
+
+// Prolongation: zf += P zc (knot insertion, tensor product per patch).
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(T *zf, const T *zc, int Wf, int Wc, int n1f, int P, int ldb,
+                                                 const int *__restrict__ ps, const T *__restrict__ pcoef, int pw,
+                                                 const int *__restrict__ active) {
+  const int ct = blockIdx.y;
+  if (active && !active[ct]) return;
+  const int col = ct * CT + threadIdx.x;
+  const int id = wave_uniform(blockIdx.x * 4 + threadIdx.y);
+  if (id >= 6 * n1f * n1f) return;
+  const int ixf = id % n1f, iyf = (id / n1f) % n1f, m = id / (n1f * n1f);
+  const int64_t cbase = (int64_t)m * Wc * Wc;
+  const int cy0 = ps[iyf], cx0 = ps[ixf];
+  T acc = 0;
+  for (int k = 0; k < pw; ++k) {
+    const T wy = pcoef[iyf * pw + k];
+    if (wy == T(0)) continue;
+    for (int l = 0; l < pw; ++l) {
+      const T wx = pcoef[ixf * pw + l];
+      if (wx == T(0)) continue;
+      acc += wy * wx * zc[(cbase + (int64_t)(cy0 + k + P) * Wc + (cx0 + l + P)) * ldb + col];
+    }
+  }
+  const int64_t i = ((int64_t)m * Wf * Wf + (int64_t)(iyf + P) * Wf + (ixf + P)) * ldb + col;
+  zf[i] += acc;
+}
+
+template <typename T>
+static const T *res_coef(const Level &F);
+template <>
+const double *res_coef<double>(const Level &F) { return F.res_c.p; }
+template <>
+const float *res_coef<float>(const Level &F) { return F.res_c32.p; }
+template <typename T>
+static const T *pro_coef(const Level &F);
+template <>
+const double *pro_coef<double>(const Level &F) { return F.pro_c.p; }
+template <>
+const float *pro_coef<float>(const Level &F) { return F.pro_c32.p; }
+
+template <typename T>
+void restrict_residual(const Level &F, const Level &C, T *rc, const T *r, const T *Az, int ldb, int ntiles,
+                       const int *active, hipStream_t s) {
+  const int n = 6 * C.n1 * C.n1;
+  hipLaunchKernelGGL(k_restrict<T>, dim3((n + 3) / 4, ntiles), dim3(CT, 4), 0, s, rc, r, Az, F.owner.p, F.W, C.W,
+                     C.n1, F.p, ldb, F.res_start.p, res_coef<T>(F), F.rw, active);
+  HIPCHK(hipGetLastError());
+}
+template void restrict_residual<double>(const Level &, const Level &, double *, const double *, const double *, int,
+                                        int, const int *, hipStream_t);
+template void restrict_residual<float>(const Level &, const Level &, float *, const float *, const float *, int, int,
+                                       const int *, hipStream_t);
+
+template <typename T>
+void prolong_add(const Level &F, const Level &C, T *zf, const T *zc, int ldb, int ntiles, const int *active,
+                 hipStream_t s) {
+  const int n = 6 * F.n1 * F.n1;
+  hipLaunchKernelGGL(k_prolong<T>, dim3((n + 3) / 4, ntiles), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1, F.p, ldb,
+                     F.pro_start.p, pro_coef<T>(F), F.pw, active);
+  HIPCHK(hipGetLastError());
+}
+template void prolong_add<double>(const Level &, const Level &, double *, const double *, int, int, const int *,
+                                  hipStream_t);
+template void prolong_add<float>(const Level &, const Level &, float *, const float *, int, int, const int *,
+                                 hipStream_t);
+
+// ------------------------------------------------------------------ coarse solve
+// z = (sigma M0 + S0)^-1 r on the coarsest level, in FP64 with the per-node Cholesky factor:
+// gather the owner copies into the global coarse vector, forward and backward substitution,
+// scatter to every copy.  One lane per system; the work vector lives in LDS.
+template <typename T>
+__global__ __launch_bounds__(64) void k_coarse(T *z, const T *r, const double *__restrict__ Lf,
+                                               const int *__restrict__ node, int N0, const int *__restrict__ orow,
+                                               const int *__restrict__ rgid, int64_t R0, int ldb,
+                                               const int *__restrict__ active) {
+  extern __shared__ double sh[];
+  const int ct = blockIdx.x;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x;
+  const int col = ct * CT + lane;
+  double *v = sh;  // v[i*64 + lane]
+  const double *L = Lf + (size_t)node[col] * N0 * N0;
+  for (int i = 0; i < N0; ++i) {
+    double s = (double)r[(int64_t)orow[i] * ldb + col];
+    for (int k = 0; k < i; ++k) s -= L[i * N0 + k] * v[k * CT + lane];
+    v[i * CT + lane] = s / L[i * N0 + i];
+  }
+  for (int i = N0 - 1; i >= 0; --i) {
+    double s = v[i * CT + lane];
+    for (int k = i + 1; k < N0; ++k) s -= L[k * N0 + i] * v[k * CT + lane];
+    v[i * CT + lane] = s / L[i * N0 + i];
+  }
+  for (int64_t rr = 0; rr < R0; ++rr) {
+    const int g = rgid[rr];
+    if (g >= 0) z[rr * ldb + col] = (T)v[g * CT + lane];
+  }
+}
+
+template <typename T>
+void coarse_solve(const Level &C, int N0, T *z, const T *r, const double *Lf, const int *node, int ldb, int ntiles,
+                  const int *active, hipStream_t s) {
+  const size_t shm = (size_t)N0 * CT * sizeof(double);
+  if (shm > 65536) fail(GF_EUNSUPPORTED, "coarsest level too large for the LDS Cholesky solve; use a coarser level");
+  hipLaunchKernelGGL(k_coarse<T>, dim3(ntiles), dim3(CT), shm, s, z, r, Lf, node, N0, C.owner_row.p, C.row_gid.p,
+                     C.R, ldb, active);
+  HIPCHK(hipGetLastError());
+}
+template void coarse_solve<double>(const Level &, int, double *, const double *, const double *, const int *, int,
+                                   int, const int *, hipStream_t);
+template void coarse_solve<float>(const Level &, int, float *, const float *, const double *, const int *, int, int,
+                                  const int *, hipStream_t);
+
+// ------------------------------------------------------------------ layout conversions
+// X[row][c] = src[c][gid(row)] for c < nvec (every copy of an unknown gets its value), 0 else.
+__global__ void k_g2l(double *X, const double *src, int64_t N, int nvec, const int *__restrict__ rgid, int64_t R,
+                      int ldb) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (id >= R) return;
+  const int g = rgid[id];
+  for (int c = threadIdx.x; c < ldb; c += blockDim.x)
+    X[id * ldb + c] = (g >= 0 && c < nvec) ? src[(int64_t)c * N + g] : 0.0;
+}
+void global_to_local(const Level &L, double *X, const double *src, int nvec, int ldb, hipStream_t s) {
+  hipLaunchKernelGGL(k_g2l, dim3((unsigned)((L.R + 3) / 4)), dim3(64, 4), 0, s, X, src, (int64_t)L.N, nvec,
+                     L.row_gid.p, L.R, ldb);
+  HIPCHK(hipGetLastError());
+}
+
+// dst[c][g] = X[owner_row(g)][c0 + c] for c < nvec
+__global__ void k_l2g(double *dst, const double *X, int64_t N, int nvec, int c0, const int *__restrict__ orow,
+                      int ldb) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (g >= N) return;
+  const int64_t r = orow[g];
+  for (int c = threadIdx.x; c < nvec; c += blockDim.x) dst[(int64_t)c * N + g] = X[r * ldb + c0 + c];
+}
+void local_to_global(const Level &L, double *dst, const double *X, int nvec, int c0, int ldb, hipStream_t s) {
+  hipLaunchKernelGGL(k_l2g, dim3((unsigned)((L.N + 3) / 4)), dim3(64, 4), 0, s, dst, X, (int64_t)L.N, nvec, c0,
+                     L.owner_row.p, ldb);
+  HIPCHK(hipGetLastError());
+}
+
+// Y[row][k*S + s] = X[row][s]: the same right-hand side for every node
+__global__ void k_replicate(double *Y, int ldy, const double *X, int ldx, int S, int K, int64_t R) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (r >= R) return;
+  for (int c = threadIdx.x; c < ldy; c += blockDim.x) Y[r * ldy + c] = (c < K * S) ? X[r * ldx + (c % S)] : 0.0;
+}
+void replicate_cols(const Level &L, double *Y, int ldy, const double *X, int ldx, int S, int K, hipStream_t s) {
+  hipLaunchKernelGGL(k_replicate, dim3((unsigned)((L.R + 3) / 4)), dim3(64, 4), 0, s, Y, ldy, X, ldx, S, K, L.R);
+  HIPCHK(hipGetLastError());
+}
+
+// Quadrature sum (eq. beta-approx): u[s][g] = sum_k omega_k X[owner(g)][k*S + s], k ascending, FP64.
+__global__ void k_qsum(double *u, const double *X, const double *__restrict__ omega, int K, int S, int64_t N,
+                       const int *__restrict__ orow, int ldb) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
+  if (g >= N) return;
+  const int64_t r = orow[g];
+  for (int s = threadIdx.x; s < S; s += blockDim.x) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc += omega[k] * X[r * ldb + (int64_t)k * S + s];
+    u[(int64_t)s * N + g] = acc;
+  }
+}
+void quadrature_sum(const Level &L, double *u, const double *X, const double *omega, int K, int S, int ldb,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_qsum, dim3((unsigned)((L.N + 3) / 4)), dim3(64, 4), 0, s, u, X, omega, K, S, (int64_t)L.N,
+                     L.owner_row.p, ldb);
+  HIPCHK(hipGetLastError());
+}
+
+}  // namespace gf

@@ -1,0 +1,245 @@
+"""ctypes binding of libgfield.so (the C ABI declared in include/gfield.h).
+
+Argument marshalling only: every step of the computation runs in the HIP library.
+Arrays are either NumPy arrays (host memory, GF_HOST) or torch tensors on the
+context's GPU (device memory, GF_DEVICE); outputs are returned in the same kind
+of container as the main input.  PyTorch supplies device memory and the stream.
+
+If the library has not been built, importing this module raises ImportError --
+there is no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+# torch first: the library then binds to the HIP runtime torch already loaded, so that one
+# runtime serves both (two HIP/HSA runtimes in one process do not see the device)
+try:
+    import torch  # noqa: F401
+except ImportError:  # host-only use (argument checks, gf_locate)
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfield.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_24882_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+GF_OK, GF_EINVAL, GF_ENOMEM, GF_EDEVICE, GF_ENOCONV, GF_EBREAKDOWN, GF_EUNSUPPORTED = range(7)
+GF_HOST, GF_DEVICE = 0, 1
+GF_APPLY_STENCIL, GF_APPLY_SUMFACT = 0, 1
+GF_PREC_FP64, GF_PREC_MIXED = 0, 1
+GF_FLAG_TIME_APPLY = 1
+STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ENOMEM", 3: "GF_EDEVICE", 4: "GF_ENOCONV",
+                5: "GF_EBREAKDOWN", 6: "GF_EUNSUPPORTED"}
+
+
+class QuadRule(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("k_minus", ctypes.c_int32), ("k_plus", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("cheb_degree", ctypes.c_int32), ("apply_kind", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("n_systems", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_rel_resid", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("apply_ms", ctypes.c_double),
+                ("apply_launches", ctypes.c_int32), ("apply_cols", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+_SIGS = {
+    "gf_last_error": (ctypes.c_char_p, []),
+    "gf_abi_version": (ctypes.c_int, []),
+    "gf_context_create": (_i32, [_i32, _vp, ctypes.POINTER(_vp)]),
+    "gf_context_destroy": (None, [_vp]),
+    "gf_geometry_sphere": (_i32, [_vp, _i32, ctypes.POINTER(_vp)]),
+    "gf_geometry_destroy": (None, [_vp]),
+    "gf_locate": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "gf_space_create": (_i32, [_vp, _vp, _i32, _i32, _i32, ctypes.POINTER(_vp)]),
+    "gf_space_destroy": (None, [_vp]),
+    "gf_space_ndofs": (_i64, [_vp]),
+    "gf_space_noise_length": (_i64, [_vp]),
+    "gf_space_dofmap": (_i32, [_vp, _vp]),
+    "gf_space_apply": (_i32, [_vp, _dbl, _dbl, _i32, _vp, _vp, _i32, _i32]),
+    "gf_white_noise": (_i32, [_vp, _i32, _vp, _vp, _i32]),
+    "gf_sample": (_i32, [_vp, _dbl, _dbl, ctypes.POINTER(QuadRule), ctypes.POINTER(SolveOpts), _i32, _vp, _vp,
+                         _i32, ctypes.POINTER(SolveStats)]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class GfieldError(RuntimeError):
+    def __init__(self, status, msg, stats=None):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.stats = stats
+
+
+def _check(status, stats=None):
+    if status != GF_OK:
+        raise GfieldError(status, _lib.gf_last_error().decode(), stats)
+
+
+def abi_version():
+    return _lib.gf_abi_version()
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _marshal_in(a, n):
+    """(pointer, mem, keepalive) of a float64 input with n entries."""
+    if _is_torch(a):
+        import torch
+        if a.dtype != torch.float64 or not a.is_cuda:
+            raise TypeError("device arrays must be float64 CUDA tensors")
+        a = a.contiguous()
+        if a.numel() != n:
+            raise ValueError(f"expected {n} entries, got {a.numel()}")
+        return a.data_ptr(), GF_DEVICE, a
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != n:
+        raise ValueError(f"expected {n} entries, got {a.size}")
+    return a.ctypes.data, GF_HOST, a
+
+
+def _alloc_like(a, shape):
+    if _is_torch(a):
+        import torch
+        return torch.empty(shape, dtype=torch.float64, device=a.device)
+    return np.empty(shape, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.data_ptr() if _is_torch(a) else a.ctypes.data
+
+
+class Context:
+    """One GPU and one HIP stream (torch's current stream on `device` when torch is given)."""
+
+    def __init__(self, device=0, stream=None, use_torch_stream=True):
+        h = _vp()
+        s = stream
+        if s is None and use_torch_stream:
+            import torch
+            s = torch.cuda.current_stream(device).cuda_stream
+        _check(_lib.gf_context_create(device, s, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            _lib.gf_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Geometry:
+    def __init__(self, ctx, perturbed=False):
+        h = _vp()
+        _check(_lib.gf_geometry_sphere(ctx.h if ctx is not None else None, 1 if perturbed else 0, ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+
+    def locate(self, xyz):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+        n = len(xyz)
+        patch = np.empty(n, dtype=np.int32)
+        st = np.empty((n, 2), dtype=np.float64)
+        _check(_lib.gf_locate(self.h, n, xyz.ctypes.data, patch.ctypes.data, st.ctypes.data))
+        return patch, st
+
+    def close(self):
+        if self.h:
+            _lib.gf_geometry_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Space:
+    """S^0_{level,degree} on a geometry, with its multigrid hierarchy."""
+
+    def __init__(self, ctx, geom, degree, level, coarse_level=-1):
+        h = _vp()
+        _check(_lib.gf_space_create(ctx.h, geom.h, degree, level, coarse_level, ctypes.byref(h)))
+        self.h = h
+        self.ctx, self.geom = ctx, geom
+        self.degree, self.level = degree, level
+        self.ndofs = int(_lib.gf_space_ndofs(h))
+        self.noise_length = int(_lib.gf_space_noise_length(h))
+
+    def dofmap(self):
+        n = 2 ** self.level + self.degree
+        out = np.empty((6, n, n), dtype=np.int32)
+        _check(_lib.gf_space_dofmap(self.h, out.ctypes.data))
+        return out
+
+    def apply(self, sigma, s_scale, x, kind=GF_APPLY_STENCIL):
+        """y = (sigma M + s_scale S) x for x of shape (nvec, N) or (N,)."""
+        single = len(x.shape) == 1
+        nvec = 1 if single else x.shape[0]
+        px, mem, keep = _marshal_in(x, nvec * self.ndofs)
+        y = _alloc_like(x, x.shape)
+        _check(_lib.gf_space_apply(self.h, sigma, s_scale, nvec, px, _ptr(y), mem, kind))
+        return y
+
+    def white_noise(self, z):
+        """b = sum_e R_e^T L_e z_e for z of shape (nsamp, noise_length)."""
+        nsamp = 1 if len(z.shape) == 1 else z.shape[0]
+        pz, mem, keep = _marshal_in(z, nsamp * self.noise_length)
+        b = _alloc_like(z, (nsamp, self.ndofs))
+        _check(_lib.gf_white_noise(self.h, nsamp, pz, _ptr(b), mem))
+        return b
+
+    def sample(self, kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=GF_PREC_FP64, rtol=1e-10,
+               max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0):
+        """Field samples u for loads b (nsamp, N); returns (u, stats dict)."""
+        nsamp = 1 if len(b.shape) == 1 else b.shape[0]
+        pb, mem, keep = _marshal_in(b, nsamp * self.ndofs)
+        u = _alloc_like(b, (nsamp, self.ndofs))
+        rule = QuadRule(h, k_minus, k_plus)
+        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
+        st = SolveStats()
+        status = _lib.gf_sample(self.h, kappa, beta, ctypes.byref(rule), ctypes.byref(opts), nsamp, pb, _ptr(u),
+                                mem, ctypes.byref(st))
+        _check(status, st.as_dict())
+        return u, st.as_dict()
+
+    def close(self):
+        if self.h:
+            _lib.gf_space_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared entry point,
+validates arguments before touching a device, and its host-only calls match the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2605_24882_amd import gfield as g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "gfield.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gf_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(g._lib, n), n
+        assert n in g.EXPORTED, n
+
+
+def test_abi_version():
+    assert g.abi_version() == 1
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_context_without_device_is_edevice():
+    with pytest.raises(g.GfieldError) as e:
+        g.Context(0, use_torch_stream=False)
+    assert e.value.status == g.GF_EDEVICE
+
+
+def test_null_handles_are_einval():
+    import ctypes
+    x = np.zeros(4)
+    assert g._lib.gf_space_apply(None, 1.0, 1.0, 1, x.ctypes.data, x.ctypes.data, g.GF_HOST, 0) == g.GF_EINVAL
+    assert b"null" in g._lib.gf_last_error()
+    out = ctypes.c_void_p()
+    assert g._lib.gf_space_create(None, None, 2, 2, -1, ctypes.byref(out)) == g.GF_EINVAL
+    assert g._lib.gf_geometry_sphere(None, 3, ctypes.byref(out)) == g.GF_EINVAL
+    rule = g.QuadRule(0.4, 15, 15)
+    opts = g.SolveOpts(0, 1e-10, 100, 0, 0, 0)
+    st = g.SolveStats()
+    assert g._lib.gf_sample(None, 4.0, 0.75, ctypes.byref(rule), ctypes.byref(opts), 1, x.ctypes.data,
+                            x.ctypes.data, g.GF_HOST, ctypes.byref(st)) == g.GF_EINVAL
+
+
+def test_locate_matches_oracle_inversion():
+    from oracle import geometry
+    from paper_2605_24882_amd import inputs
+    pts, _ = inputs.sphere_points_and_targets(1000, seed=7)
+    geo = g.Geometry(None, perturbed=False)
+    patch, st = geo.locate(pts)
+    op, os_, ot = geometry.invert(pts)
+    assert np.array_equal(patch, op)
+    assert np.allclose(st[:, 0], os_, atol=1e-15) and np.allclose(st[:, 1], ot, atol=1e-15)
+    with pytest.raises(g.GfieldError):
+        geo.locate(np.zeros((1, 3)))

@@ -1,0 +1,150 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on the same inputs.
+
+Tolerances: operator and load 1e-13 relative (same arithmetic up to summation order);
+fields of the FP64 solver 1e-10 relative in the M-norm with CG rtol 1e-13 (the conditioning
+of the shifted systems turns rtol into a field error of at most cond * rtol);
+mixed precision (FP32 V-cycle inside the FP64 CG) with the same outer rtol also 1e-10,
+because the outer residual is FP64.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import assembly, fractional, noise, sinc
+from paper_2605_24882_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+g = pytest.importorskip("paper_2605_24882_amd.gfield")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    return g.Context(0)
+
+
+_spaces = {}
+_discs = {}
+
+
+def space(ctx, p, j, perturbed=False, lc=-1):
+    key = (p, j, perturbed, lc)
+    if key not in _spaces:
+        geo = g.Geometry(ctx, perturbed)
+        _spaces[key] = g.Space(ctx, geo, p, j, lc)
+    return _spaces[key]
+
+
+def disc(p, j, perturbed=False):
+    key = (p, j, perturbed)
+    if key not in _discs:
+        _discs[key] = assembly.Discretisation(p, j, perturbed)
+    return _discs[key]
+
+
+def mrel(d, u, ref):
+    """max over samples of |u - ref|_M / |ref|_M"""
+    u, ref = np.atleast_2d(u), np.atleast_2d(ref)
+    out = 0.0
+    for a, b in zip(u, ref):
+        e = a - b
+        out = max(out, math.sqrt(e @ (d.M @ e)) / math.sqrt(b @ (d.M @ b)))
+    return out
+
+
+CASES = [(2, 2, False), (3, 2, False), (2, 3, True), (1, 3, False), (3, 3, True), (4, 2, False), (5, 1, False)]
+
+
+@pytest.mark.parametrize("p,j,pert", CASES)
+def test_dofmap_matches_oracle(ctx, p, j, pert):
+    sp, d = space(ctx, p, j, pert), disc(p, j, pert)
+    assert sp.ndofs == d.N == assembly.n_dofs_formula(p, j)
+    assert np.array_equal(sp.dofmap(), d.l2g)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("p,j,pert", CASES)
+def test_apply_matches_oracle(ctx, p, j, pert, kind):
+    sp, d = space(ctx, p, j, pert), disc(p, j, pert)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal((3, d.N))
+    for sigma, ss in [(1.0, 0.0), (0.0, 1.0), (16.0 + 0.3, 1.0)]:
+        y = sp.apply(sigma, ss, x, kind)
+        ref = np.stack([(sigma * d.M + ss * d.S) @ v for v in x])
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max(), (sigma, ss)
+
+
+def test_apply_device_arrays_and_many_columns(ctx):
+    import torch
+    sp, d = space(ctx, 2, 3), disc(2, 3)
+    x = np.random.default_rng(2).standard_normal((130, d.N))  # three column tiles, ragged
+    y = sp.apply(2.5, 1.0, torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = (2.5 * d.M + d.S) @ x.T
+    assert np.abs(y - ref.T).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("p,j,pert", [(2, 2, False), (3, 3, True), (1, 2, False)])
+def test_white_noise_matches_oracle(ctx, p, j, pert):
+    sp, d = space(ctx, p, j, pert), disc(p, j, pert)
+    z = inputs.noise_vectors([0, 1, 2], inputs.noise_length(p, j))
+    b = sp.white_noise(z)
+    ref = noise.load(d, z)
+    assert np.abs(b - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def _oracle_u(d, kappa, beta, h, K, b):
+    return fractional.sample(d.M, d.S, kappa, beta, h, K, K, b)
+
+
+def test_sample_c1_fp64(ctx):
+    """Unit sphere, p = 2, 4 x 4 elements per patch, kappa = 4, beta = 0.75, h = 0.4, 31 nodes, 1 sample."""
+    sp, d = space(ctx, 2, 2), disc(2, 2)
+    z = inputs.noise_vectors([0], inputs.noise_length(2, 2))
+    b = noise.load(d, z)
+    u, st = sp.sample(4.0, 0.75, b, h=0.4, k_minus=15, k_plus=15, rtol=1e-13)
+    ref = _oracle_u(d, 4.0, 0.75, 0.4, 15, b)
+    assert st["n_systems"] == 31
+    assert mrel(d, u, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("beta", [0.75, 1.6, 2.3, 2.0])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sample_split_and_precision(ctx, beta, prec):
+    sp, d = space(ctx, 2, 3), disc(2, 3)
+    b = noise.load(d, inputs.noise_vectors([4, 5, 6], inputs.noise_length(2, 3)))
+    u, st = sp.sample(3.0, beta, b, h=0.4, k_minus=12, k_plus=12, precision=prec, rtol=1e-13)
+    ref = _oracle_u(d, 3.0, beta, 0.4, 12, b)
+    assert mrel(d, u, ref) <= 1e-10
+
+
+def test_sample_sumfact_operator(ctx):
+    sp, d = space(ctx, 3, 2), disc(3, 2)
+    b = noise.load(d, inputs.noise_vectors([1], inputs.noise_length(3, 2)))
+    u, st = sp.sample(2.0, 0.6, b, h=0.4, k_minus=10, k_plus=10, rtol=1e-13, apply_kind=1)
+    ref = _oracle_u(d, 2.0, 0.6, 0.4, 10, b)
+    assert mrel(d, u, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("beta", [0.75, 1.6, 2.3])
+def test_constant_load_closed_form(ctx, beta):
+    """b = M 1 gives u = kappa^{-2n} Q(kappa^2) 1 on any surface (perturbed sphere here)."""
+    sp, d = space(ctx, 3, 3, True), disc(3, 3, True)
+    b = (d.M @ np.ones(d.N))[None, :]
+    kappa, h, K = 2.5, 0.4, 12
+    u, _ = sp.sample(kappa, beta, b, h=h, k_minus=K, k_plus=K, rtol=1e-13)
+    n, bf = fractional.split_plain(beta)
+    expect = kappa ** (-2 * n) * sinc.sinc_sum(kappa ** 2, bf, h, K, K)
+    assert np.abs(u - expect).max() <= 1e-10 * abs(expect)
+
+
+def test_c2_mesh_subset(ctx):
+    """Unit sphere, p = 2, 64 x 64 elements per patch (25,352 unknowns), kappa = 10, beta = 1.6,
+    h = 0.4 with 41 nodes; samples 0..3 of the 64 (seeds 0..3)."""
+    sp, d = space(ctx, 2, 6), disc(2, 6)
+    b = noise.load(d, inputs.noise_vectors(range(4), inputs.noise_length(2, 6)))
+    u, st = sp.sample(10.0, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-12)
+    ref = _oracle_u(d, 10.0, 1.6, 0.4, 20, b)
+    assert mrel(d, u, ref) <= 1e-10
