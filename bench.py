@@ -1,0 +1,179 @@
+"""Throughput benchmark: Whittle-Matern field samples per second on one MI355X.
+
+Workload (default): unit sphere as six cube-face patches, degree-2 B-splines, 64 x 64 elements per
+patch (25,352 unknowns); kappa = 10, beta = 1.6 split into one integer solve plus the sinc rule for
+0.6 with h = 0.4 and 41 nodes; 64 independent white-noise loads (seeds 0..63); every shifted
+system solved by multigrid-preconditioned CG to relative residual 1e-10 in FP64.
+
+One step = one call of the sampler over the 64 loads, loads already resident in device memory:
+integer solves, the batch of 41 x 64 shifted systems, and the quadrature sum.
+
+Prints one JSON line.  The roofline entry is for the dominant kernel, the FP64 stencil operator
+application of the outer CG, timed with HIP events around every launch during the timed steps.
+The CPU baseline is the FP64 oracle on one of the 64 loads (single thread).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+CONFIGS = {
+    # name: (perturbed, p, level, kappa, beta, h, k, nsamp, precision, rtol)
+    "c2": (False, 2, 6, 10.0, 1.6, 0.4, 20, 64, 0, 1e-10),
+    "c2-mixed": (False, 2, 6, 10.0, 1.6, 0.4, 20, 64, 1, 1e-10),
+    "c1": (False, 2, 2, 4.0, 0.75, 0.4, 15, 1, 0, 1e-13),
+    "c5": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-9),
+}
+
+
+def workload_name(cfg):
+    pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
+    n1 = 2 ** lev + p
+    N = 6 * (n1 - 2) ** 2 + 12 * (n1 - 2) + 8
+    nint = math.floor(beta)
+    surf = "perturbed sphere" if pert else "unit sphere"
+    return (f"{surf}, 6 patches, degree {p}, {2**lev}x{2**lev} elements/patch ({N} DOF); kappa={kappa:g}, "
+            f"beta={beta:g} ({nint} integer solve(s) + {2*k+1} sinc nodes, h={h:g}); {nsamp} samples; "
+            f"{'FP64' if prec == 0 else 'FP32 V-cycle / FP64 CG'} MG-PCG to rel. residual {rtol:g}")
+
+
+def cpu_baseline(cfg, nodes_timed=6):
+    """The oracle (sparse LU, FP64, one thread) on the first load of the workload.
+
+    Bounded sample: the integer solves and `nodes_timed` of the sinc-node solves (evenly spaced in k)
+    are timed; the per-sample time adds the remaining nodes at the measured average per node (every
+    node solve is one SuperLU factorisation of the same sparsity plus one triangular solve)."""
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    from oracle import assembly, fractional, noise
+    from paper_2605_24882_amd import inputs
+    pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
+    n, bf = fractional.split_plain(beta)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        d = assembly.Discretisation(p, lev, pert)
+        t1 = time.perf_counter()
+        b = noise.load(d, inputs.noise_vectors([0], inputs.noise_length(p, lev)))
+        t2 = time.perf_counter()
+        ws = fractional.integer_chain(d.M, d.S, kappa, n, b)
+        r = b if n == 0 else np.stack([d.M @ w for w in ws[-1]])
+        t3 = time.perf_counter()
+        sigma, omega, _ = fractional.nodes(kappa, bf, h, k, k)
+        pick = np.linspace(0, len(sigma) - 1, nodes_timed).round().astype(int)
+        fractional.node_solutions(d.M, d.S, sigma[pick], r)
+        t4 = time.perf_counter()
+    per_node = (t4 - t3) / nodes_timed
+    per_sample = (t3 - t2) + per_node * len(sigma)
+    return {
+        "value": 1.0 / per_sample,
+        "unit": "samples/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"1 of the {nsamp} loads (seed 0): its {n} integer solve(s) ({t3 - t2:.2f} s) and {nodes_timed} of "
+                   f"the {len(sigma)} node solves ({per_node:.2f} s each) by SuperLU on one thread, extrapolated to all "
+                   f"{len(sigma)} nodes; assembly of M and S ({t1 - t0:.2f} s) excluded"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--apply-kind", type=int, default=0)
+    ap.add_argument("--cheb", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the timed steps, copy this many MiB device-to-device with a plain copy kernel "
+                         "(a known-size reference for the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sampler shards by "
+              f"sample with no communication, but this build measures one GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2605_24882_amd import gfield as g
+    from paper_2605_24882_amd import inputs
+
+    cfg = CONFIGS[args.config]
+    pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
+    ctx = g.Context(0)
+    geo = g.Geometry(ctx, pert)
+    t0 = time.perf_counter()
+    sp = g.Space(ctx, geo, p, lev)
+    space_s = time.perf_counter() - t0
+    z = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.noise_length)).cuda()
+    b = sp.white_noise(z)
+    del z
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
+              apply_kind=args.apply_kind)
+    for _ in range(args.warmup):
+        u, st = sp.sample(kappa, beta, b, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    agg = {"apply_ms": 0.0, "apply_launches": 0, "apply_col_sum": 0.0, "max_iters": 0, "max_rel_resid": 0.0}
+    for _ in range(args.steps):
+        u, st = sp.sample(kappa, beta, b, flags=g.GF_FLAG_TIME_APPLY, **kw)
+        for key in ("apply_ms", "apply_launches", "apply_col_sum"):
+            agg[key] += st[key]
+        agg["max_iters"] = max(agg["max_iters"], st["max_iters"])
+        agg["max_rel_resid"] = max(agg["max_rel_resid"], st["max_rel_resid"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = nsamp * args.steps / elapsed
+
+    # roofline of the dominant kernel: FP64 stencil apply of the outer CG.
+    # algorithmic bytes per launch = 2 x 8 B x columns x rows (read x, write y) + 2 x (2p+1)^2 x 8 B x rows
+    rows = st["apply_rows"]
+    launches = max(1, agg["apply_launches"])
+    cols_avg = agg["apply_col_sum"] / launches
+    bytes_per_launch = 2 * 8 * cols_avg * rows + 2 * (2 * p + 1) ** 2 * 8 * rows
+    avg_ms = agg["apply_ms"] / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "traffic": None,
+            "kernel": f"k_apply_fused<double,{p},*,EPI_STORE,dot> (outer CG operator, stencil form)", "avg_launch_us": round(avg_ms * 1e3, 2),
+            "bytes_per_launch": int(bytes_per_launch), "launches": agg["apply_launches"]}
+
+    out = {
+        "metric": "field samples/sec at rel-L2 err <=1e-6 vs FP64 oracle; operator-apply HBM GB/s",
+        "value": round(value, 3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": workload_name(cfg), "samples_per_step": nsamp, "systems_per_step": st["n_systems"],
+                   "max_cg_iters": agg["max_iters"], "max_rel_resid": agg["max_rel_resid"],
+                   "space_setup_s": round(space_s, 3)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

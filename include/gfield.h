@@ -145,13 +145,15 @@ typedef struct {
   double max_rel_resid;    /* largest final |r|/|b| */
   double setup_ms;         /* plan setup (Chebyshev bounds, coarse factors) of this call */
   double solve_ms;         /* device time of the solves, conversions and the quadrature sum */
-  double apply_ms;         /* with GF_FLAG_TIME_APPLY: summed duration of the outer operator applications */
+  double apply_ms;         /* with GF_FLAG_TIME_APPLY: summed duration of the outer-CG operator launches */
   int32_t apply_launches;  /* with GF_FLAG_TIME_APPLY: number of those launches */
-  int32_t apply_cols;      /* with GF_FLAG_TIME_APPLY: columns (systems incl. padding) of each such launch */
+  int32_t apply_rows;      /* rows (patch coefficients, copies included) one launch processes per column */
+  double apply_col_sum;    /* with GF_FLAG_TIME_APPLY: columns processed, summed over those launches */
 } gf_solve_stats;
 
 /* flags */
-#define GF_FLAG_TIME_APPLY 1 /* bracket each outer-CG operator application with HIP events */
+#define GF_FLAG_TIME_APPLY 1 /* bracket each outer-CG operator launch of the dominant batch (the sinc
+                                 nodes; the integer solves when beta is an integer) with HIP events */
 
 /* Field samples u for loads b (Sec. 3.4): n = floor(beta) integer solves A w_1 = b, A w_i = M w_{i-1},
  * then the sinc rule applied to r = M w_n (r = b if n = 0), u = sum_k omega_k x_k summed in ascending k.

@@ -73,6 +73,13 @@ void element_basis(int p, int nel, int e, double u, double *val, double *der);
 std::vector<double> refinement_matrix(int p, int lc);
 void glue_patches(int p, int lev, std::vector<int> &l2g, int &N);
 
+// launch shape of the fused stencil apply, chosen by the autotuner: TY coefficient rows per
+// wavefront strip (1, 2 or 4) and at most TX coefficients along the strip
+struct ApplyTune {
+  int TY = 1, TX = 32, NC = 1;  // NC: 64-column tiles per wavefront
+  float us = 0.f;               // measured duration of one launch
+};
+
 // ------------------------------------------------------------------ per-level data
 // Vectors of a level live in the padded patch-local layout: patch m, coefficient (iy, ix)
 // (0 <= iy, ix < n1) sits at row m*W*W + (iy+p)*W + (ix+p), W = n1 + 2p; the p ghost rows
@@ -101,6 +108,8 @@ struct Level {
   DBuf<int> pro_start, res_start;   // per fine index: first coarse index; per coarse index: first fine index
   DBuf<double> pro_c, res_c;        // [n1f][pw], [n1c][rw]
   DBuf<float> pro_c32, res_c32;
+  // autotuned launch shapes, keyed by (element size, column stride)
+  mutable std::map<std::pair<int, int>, ApplyTune> tune;
 };
 
 }  // namespace gf
@@ -154,9 +163,6 @@ void launch_coarse_factor(const double *M0, const double *S0, int N0, const doub
                           int *info, hipStream_t s);
 
 // solver kernels (k_solve.hip)
-template <typename T>
-void launch_stencil_apply(const Level &L, const T *stM, const T *stS, const T *x, T *y, const T *ca, const T *cb,
-                          int ldb, int ntiles, const int *active, hipStream_t s);
 template <typename T>
 void launch_interface_sum(const Level &L, T *y, int ldb, int ntiles, const int *active, hipStream_t s);
 

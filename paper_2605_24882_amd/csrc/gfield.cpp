@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <sstream>
 
@@ -244,15 +245,15 @@ struct Plan {
 };
 
 struct LevelWork {
-  DBuf<double> r64, z64, d64, a64;  // V-cycle vectors (FP64 mode)
-  DBuf<float> r32, z32, d32, a32;   // V-cycle vectors (mixed mode)
+  DBuf<double> r64, z64a, z64b, d64, a64;  // V-cycle vectors (FP64 mode)
+  DBuf<float> r32, z32a, z32b, d32, a32;   // V-cycle vectors (mixed mode)
   DBuf<double> invb64;
   DBuf<float> invb32;
 };
 
 struct Workspace {
   int ldb = 0, ntiles = 0, prec = 0;
-  DBuf<double> x, r, z, p, q;  // outer CG (FP64); z unused in mixed mode (z32 of the finest level)
+  DBuf<double> x, r, p, q;  // outer CG (FP64)
   std::vector<LevelWork> lw;
   DBuf<double> sig64, one64, zero64;
   DBuf<float> sig32, one32;
@@ -277,6 +278,12 @@ static std::map<const gf_space *, std::unique_ptr<gf_workspaces>> &ws_registry()
   return r;
 }
 
+static size_t scratch_slots(gf_space *sp, int ldb, int ntiles) {
+  size_t slots = 2 * (size_t)kMaxRowBlocks;
+  for (auto &L : sp->lev) slots = std::max(slots, (size_t)partial_slots(*L, ldb, ntiles));
+  return slots;
+}
+
 static Workspace &get_workspace(gf_space *sp, int ldb, int prec) {
   auto &reg = ws_registry()[sp];
   if (!reg) reg.reset(new gf_workspaces());
@@ -293,7 +300,6 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec) {
   w->r.alloc(nf);
   w->p.alloc(nf);
   w->q.alloc(nf);
-  if (prec == GF_PREC_FP64) w->z.alloc(nf);
   w->lw.resize(sp->nlev());
   for (int li = 0; li < sp->nlev(); ++li) {
     const Level &L = *sp->lev[li];
@@ -301,15 +307,15 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec) {
     LevelWork &v = w->lw[li];
     const bool finest = (li == sp->nlev() - 1);
     if (prec == GF_PREC_FP64) {
-      if (!finest) {
-        v.r64.alloc(n);
-        v.z64.alloc(n);
-      }
+      if (!finest) v.r64.alloc(n);
+      v.z64a.alloc(n);
+      v.z64b.alloc(n);
       v.d64.alloc(n);
       v.a64.alloc(n);
     } else {
       v.r32.alloc(n);
-      v.z32.alloc(n);
+      v.z32a.alloc(n);
+      v.z32b.alloc(n);
       v.d32.alloc(n);
       v.a32.alloc(n);
     }
@@ -324,40 +330,136 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec) {
   w->node.alloc(ldb);
   w->active.alloc(w->ntiles);
   w->cs.alloc(ldb);
-  w->partial.alloc((size_t)2 * kMaxRowBlocks * ldb);
+  w->partial.alloc(scratch_slots(sp, ldb, w->ntiles) * ldb);
   w->counter.alloc(w->ntiles);
   std::vector<double> ones(ldb, 1.0);
   std::vector<float> onesf(ldb, 1.0f);
   w->one64.upload(ones, sp->ctx->stream);
   w->one32.upload(onesf, sp->ctx->stream);
   w->active_h.assign(w->ntiles, 0);
-  HIPCHK(hipStreamSynchronize(sp->ctx->stream));
   Workspace &ref = *w;
   reg->m[key] = std::move(w);
   return ref;
 }
 
-// y = (ca M + cb S) x with interface sum, for one level and the chosen operator kind
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+  static const double *stM(const Level &L) { return L.stM.p; }
+  static const double *stS(const Level &L) { return L.stS.p; }
+  static const double *dM(const Level &L) { return L.dM.p; }
+  static const double *dS(const Level &L) { return L.dS.p; }
+  static double *r(LevelWork &l) { return l.r64.p; }
+  static double *za(LevelWork &l) { return l.z64a.p; }
+  static double *zb(LevelWork &l) { return l.z64b.p; }
+  static double *d(LevelWork &l) { return l.d64.p; }
+  static double *a(LevelWork &l) { return l.a64.p; }
+  static double *inv(LevelWork &l) { return l.invb64.p; }
+  static double *sig(Workspace &w) { return w.sig64.p; }
+  static double *one(Workspace &w) { return w.one64.p; }
+};
+template <>
+struct Prec<float> {
+  static const float *stM(const Level &L) { return L.stM32.p; }
+  static const float *stS(const Level &L) { return L.stS32.p; }
+  static const float *dM(const Level &L) { return L.dM32.p; }
+  static const float *dS(const Level &L) { return L.dS32.p; }
+  static float *r(LevelWork &l) { return l.r32.p; }
+  static float *za(LevelWork &l) { return l.z32a.p; }
+  static float *zb(LevelWork &l) { return l.z32b.p; }
+  static float *d(LevelWork &l) { return l.d32.p; }
+  static float *a(LevelWork &l) { return l.a32.p; }
+  static float *inv(LevelWork &l) { return l.invb32.p; }
+  static float *sig(Workspace &w) { return w.sig32.p; }
+  static float *one(Workspace &w) { return w.one32.p; }
+};
+
+// Autotuner of the fused stencil apply: on first use for a (level, precision, column stride) every
+// candidate launch shape is timed with HIP events on the caller's buffers (one warm-up and three
+// timed launches, all column tiles active) and the fastest is kept for the lifetime of the space.
+static bool g_autotune = true;
+
+template <typename T>
+static const ApplyTune &get_tune(const Level &L, int ldb, int ntiles, const T *x, T *y, const T *ca, const T *cb,
+                                 hipStream_t s) {
+  const auto key = std::make_pair((int)sizeof(T), ldb);
+  auto it = L.tune.find(key);
+  if (it != L.tune.end()) return it->second;
+  ApplyTune best;
+  if (g_autotune && L.n1 >= 8) {
+    const int tys[2] = {1, 2}, txs[3] = {16, 32, 64}, ncs[1] = {1};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    EpiArgs<T> e;
+    e.kind = EPI_STORE;
+    e.y = y;
+    Scratch none;
+    float best_us = 1e30f;
+    for (int ty : tys)
+      for (int nc : ncs)
+      for (int tx : txs) {
+        if (tx > 2 * L.n1 && tx != 16) continue;
+        if (nc > 1 && (L.p >= 4 || nc > ntiles)) continue;
+        ApplyTune t;
+        t.TY = ty;
+        t.TX = tx;
+        t.NC = nc;
+        apply_fused<T>(L, Prec<T>::stM(L), Prec<T>::stS(L), x, ca, cb, e, none, nullptr, nullptr, ldb, ntiles, 0.0,
+                       0, s, t);
+        HIPCHK(hipEventRecord(e0, s));
+        for (int k = 0; k < 3; ++k)
+          apply_fused<T>(L, Prec<T>::stM(L), Prec<T>::stS(L), x, ca, cb, e, none, nullptr, nullptr, ldb, ntiles, 0.0,
+                         0, s, t);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const float us = ms * 1e3f / 3.f;
+        if (std::getenv("GF_TUNE_LOG"))
+          std::fprintf(stderr, "tune p=%d lev=%d T=%d ldb=%d TY=%d NC=%d TX=%d: %.1f us\n", L.p, L.lev,
+                       (int)sizeof(T), ldb, ty, nc, tx, us);
+        if (us < best_us) {
+          best_us = us;
+          best = t;
+          best.us = us;
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  return L.tune.emplace(key, best).first->second;
+}
+
+// One operator application with epilogue e: the fused stencil kernel, or the sum-factorised
+// kernel followed by the interface sum and the epilogue over all rows.
+template <typename T>
+static void apply_epi(const Level &L, int kind, const T *x, const T *ca, const T *cb, const EpiArgs<T> &e,
+                      Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2, int maxit,
+                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+  if (kind == GF_APPLY_SUMFACT) {
+    if (ev0) HIPCHK(hipEventRecord(ev0, s));
+    launch_sumfact_apply<T>(L, x, e.y, ca, cb, ldb, ntiles, active, s);
+    if (ev1) HIPCHK(hipEventRecord(ev1, s));
+    launch_interface_sum<T>(L, e.y, ldb, ntiles, active, s);
+    if (e.kind != EPI_STORE || e.dot) epi_rows<T>(L, x, e, sc, cs, active, ldb, ntiles, tol2, maxit, s);
+  } else {
+    const ApplyTune &t = get_tune<T>(L, ldb, ntiles, x, e.y, ca, cb, s);
+    apply_fused<T>(L, Prec<T>::stM(L), Prec<T>::stS(L), x, ca, cb, e, sc, cs, active, ldb, ntiles, tol2, maxit, s,
+                   t, ev0, ev1);
+  }
+}
+
+// y = (ca M + cb S) x, assembled (interface sums included)
 template <typename T>
 static void apply_level(const Level &L, int kind, const T *x, T *y, const T *ca, const T *cb, int ldb, int ntiles,
-                        const int *active, hipStream_t s);
-template <>
-void apply_level<double>(const Level &L, int kind, const double *x, double *y, const double *ca, const double *cb,
-                         int ldb, int ntiles, const int *active, hipStream_t s) {
-  if (kind == GF_APPLY_SUMFACT)
-    launch_sumfact_apply<double>(L, x, y, ca, cb, ldb, ntiles, active, s);
-  else
-    launch_stencil_apply<double>(L, L.stM.p, L.stS.p, x, y, ca, cb, ldb, ntiles, active, s);
-  launch_interface_sum<double>(L, y, ldb, ntiles, active, s);
-}
-template <>
-void apply_level<float>(const Level &L, int kind, const float *x, float *y, const float *ca, const float *cb,
-                        int ldb, int ntiles, const int *active, hipStream_t s) {
-  if (kind == GF_APPLY_SUMFACT)
-    launch_sumfact_apply<float>(L, x, y, ca, cb, ldb, ntiles, active, s);
-  else
-    launch_stencil_apply<float>(L, L.stM32.p, L.stS32.p, x, y, ca, cb, ldb, ntiles, active, s);
-  launch_interface_sum<float>(L, y, ldb, ntiles, active, s);
+                        const int *active, hipStream_t s) {
+  EpiArgs<T> e;
+  e.kind = EPI_STORE;
+  e.y = y;
+  Scratch none;
+  apply_epi<T>(L, kind, x, ca, cb, e, none, nullptr, const_cast<int *>(active), ldb, ntiles, 0.0, 0, s);
 }
 
 // Chebyshev interval [b/alpha, b] with b = 1.1 x the estimated largest eigenvalue of D^-1 A
@@ -459,33 +561,7 @@ struct SolveResult {
   int flags = 0;
   double apply_ms = 0.0;
   int apply_launches = 0;
-};
-
-template <typename T>
-struct VT;
-template <>
-struct VT<double> {
-  static double *r(LevelWork &l) { return l.r64.p; }
-  static double *z(LevelWork &l) { return l.z64.p; }
-  static double *d(LevelWork &l) { return l.d64.p; }
-  static double *a(LevelWork &l) { return l.a64.p; }
-  static double *inv(LevelWork &l) { return l.invb64.p; }
-  static const double *dM(const Level &L) { return L.dM.p; }
-  static const double *dS(const Level &L) { return L.dS.p; }
-  static double *sig(Workspace &w) { return w.sig64.p; }
-  static double *one(Workspace &w) { return w.one64.p; }
-};
-template <>
-struct VT<float> {
-  static float *r(LevelWork &l) { return l.r32.p; }
-  static float *z(LevelWork &l) { return l.z32.p; }
-  static float *d(LevelWork &l) { return l.d32.p; }
-  static float *a(LevelWork &l) { return l.a32.p; }
-  static float *inv(LevelWork &l) { return l.invb32.p; }
-  static const float *dM(const Level &L) { return L.dM32.p; }
-  static const float *dS(const Level &L) { return L.dS32.p; }
-  static float *sig(Workspace &w) { return w.sig32.p; }
-  static float *one(Workspace &w) { return w.one32.p; }
+  double apply_col_sum = 0.0;
 };
 
 // Chebyshev recurrence coefficients for interval [b/alpha, b], in units of 1/b
@@ -504,53 +580,76 @@ static void cheb_coeffs(int deg, std::vector<double> &c1, std::vector<double> &c
   }
 }
 
-template <typename T>
-static void vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, T *r, T *z, hipStream_t s) {
+// Multigrid V-cycle on level li for the assembled right-hand side rsrc (type TR; converted to T into
+// rconv when the types differ).  Pre-smoothing: Chebyshev-Jacobi from zero; coarse correction with
+// the knot-insertion restriction of the residual, recursion, prolongation; post-smoothing with the
+// same polynomial (a symmetric preconditioner).  Returns the buffer holding the result.  With
+// fin_op >= 0 the last smoothing step also reduces r . z and applies fin_op (then *fused = true).
+template <typename T, typename TR>
+static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, const TR *rsrc, T *rconv, int fin_op,
+                 bool *fused, hipStream_t s) {
   const Level &L = *sp->lev[li];
   const int ldb = w.ldb, nt = w.ntiles;
-  const int *act = w.active.p;
-  if (li == 0) {
-    coarse_solve<T>(L, sp->N0, z, r, spec.plan->Lf.p, w.node.p, ldb, nt, act, s);
-    return;
-  }
+  int *act = w.active.p;
   LevelWork &lw = w.lw[li];
-  T *d = VT<T>::d(lw), *Az = VT<T>::a(lw), *inv = VT<T>::inv(lw);
-  const T *dM = VT<T>::dM(L), *dS = VT<T>::dS(L), *sig = VT<T>::sig(w), *one = VT<T>::one(w);
+  T *za = Prec<T>::za(lw), *zb = Prec<T>::zb(lw);
+  if (fused) *fused = false;
+  if (li == 0) {
+    const T *r = (const T *)rsrc;
+    if (rconv) {
+      convert_rows<TR, T>(L, rsrc, rconv, ldb, nt, act, s);
+      r = rconv;
+    }
+    coarse_solve<T>(L, sp->N0, za, r, spec.plan->Lf.p, w.node.p, ldb, nt, act, s);
+    return za;
+  }
+  const T *r = rconv ? (const T *)rconv : (const T *)rsrc;
+  T *d = Prec<T>::d(lw), *a = Prec<T>::a(lw), *inv = Prec<T>::inv(lw);
+  const T *dM = Prec<T>::dM(L), *dS = Prec<T>::dS(L), *sig = Prec<T>::sig(w), *one = Prec<T>::one(w);
+  Scratch sc = w.scratch();
   std::vector<double> c1, c2;
   cheb_coeffs(spec.cheb, c1, c2);
-  // pre-smoothing from z = 0
-  cheb_step<T>(L, z, d, r, nullptr, dM, dS, sig, inv, (T)0, (T)c2[0], 1, ldb, nt, act, s);
-  for (int k = 1; k < spec.cheb; ++k) {
-    apply_level<T>(L, spec.kind, z, Az, sig, one, ldb, nt, act, s);
-    cheb_step<T>(L, z, d, r, Az, dM, dS, sig, inv, (T)c1[k], (T)c2[k], 0, ldb, nt, act, s);
+  auto smooth = [&](int k, bool last) {
+    EpiArgs<T> e;
+    e.kind = EPI_CHEB;
+    e.y = a;
+    e.zout = zb;
+    e.d = d;
+    e.r = r;
+    e.dM = dM;
+    e.dS = dS;
+    e.sig = sig;
+    e.invb = inv;
+    e.c1 = (T)c1[k];
+    e.c2 = (T)c2[k];
+    if (last && fin_op >= 0) {
+      e.dot = 1;
+      e.op = fin_op;
+      if (fused) *fused = true;
+    }
+    apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, spec.rtol * spec.rtol, spec.max_iter, s);
+    std::swap(za, zb);
+  };
+  // pre-smoothing from zero
+  cheb_first<T, TR>(L, rsrc, rconv, za, d, dM, dS, sig, inv, (T)c2[0], ldb, nt, act, s);
+  for (int k = 1; k < spec.cheb; ++k) smooth(k, false);
+  // residual, restriction, coarse correction, prolongation
+  {
+    EpiArgs<T> e;
+    e.kind = EPI_RESID;
+    e.y = a;
+    e.r = r;
+    apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, 0.0, 0, s);
   }
-  // coarse correction
-  apply_level<T>(L, spec.kind, z, Az, sig, one, ldb, nt, act, s);
   const Level &C = *sp->lev[li - 1];
-  LevelWork &cw = w.lw[li - 1];
-  T *rc = VT<T>::r(cw), *zc = VT<T>::z(cw);
-  restrict_residual<T>(L, C, rc, r, Az, ldb, nt, act, s);
+  T *rc = Prec<T>::r(w.lw[li - 1]);
+  restrict_residual<T>(L, C, rc, a, nullptr, ldb, nt, act, s);
   launch_interface_sum<T>(C, rc, ldb, nt, act, s);
-  vcycle<T>(sp, w, spec, li - 1, rc, zc, s);
-  prolong_add<T>(L, C, z, zc, ldb, nt, act, s);
+  T *zc = vcycle<T, T>(sp, w, spec, li - 1, rc, nullptr, -1, nullptr, s);
+  prolong_add<T>(L, C, za, zc, ldb, nt, act, s);
   // post-smoothing
-  for (int k = 0; k < spec.cheb; ++k) {
-    apply_level<T>(L, spec.kind, z, Az, sig, one, ldb, nt, act, s);
-    cheb_step<T>(L, z, d, r, Az, dM, dS, sig, inv, (T)c1[k], (T)c2[k], 0, ldb, nt, act, s);
-  }
-}
-
-// z = B r (multigrid preconditioner) for the outer FP64 residual r
-static void precondition(gf_space *sp, Workspace &w, const SolveSpec &spec, hipStream_t s) {
-  const int fi = sp->nlev() - 1;
-  const Level &F = sp->fine();
-  if (spec.prec == GF_PREC_FP64) {
-    vcycle<double>(sp, w, spec, fi, w.r.p, w.z.p, s);
-  } else {
-    LevelWork &fw = w.lw[fi];
-    convert_rows<double, float>(F, w.r.p, fw.r32.p, w.ldb, w.ntiles, w.active.p, s);
-    vcycle<float>(sp, w, spec, fi, fw.r32.p, fw.z32.p, s);
-  }
+  for (int k = 0; k < spec.cheb; ++k) smooth(k, k == spec.cheb - 1);
+  return za;
 }
 
 // Solves (sigma_c M + S) x_c = r_c for all columns c; on entry w.r holds the right-hand sides
@@ -591,47 +690,58 @@ static SolveResult solve_batch(gf_space *sp, Workspace &w, const SolveSpec &spec
   Scratch sc = w.scratch();
   const double tol2 = spec.rtol * spec.rtol;
   const bool mixed = spec.prec == GF_PREC_MIXED;
-  const double *zd = mixed ? nullptr : w.z.p;
-  const float *zf = mixed ? w.lw[fi].z32.p : nullptr;
   SolveResult res;
   std::vector<hipEvent_t> evs;
-  auto timed_apply = [&]() {
+  // preconditioner: returns z (FP64 or FP32 buffer); fin_op fused into the last smoothing step when possible
+  double *zd = nullptr;
+  float *zf = nullptr;
+  auto precondition = [&](int fin_op_fp64) -> bool {
+    bool fused = false;
+    if (!mixed) {
+      zd = vcycle<double, double>(sp, w, spec, fi, w.r.p, nullptr, fin_op_fp64, &fused, s);
+    } else {
+      zf = vcycle<float, double>(sp, w, spec, fi, w.r.p, w.lw[fi].r32.p, -1, nullptr, s);
+    }
+    return fused;
+  };
+  auto outer_apply = [&]() {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (spec.flags & GF_FLAG_TIME_APPLY) {
+      int act = 0;
+      for (int t = 0; t < nt; ++t) act += w.active_h[t] ? 1 : 0;
+      res.apply_col_sum += (double)act * CT;
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
-      HIPCHK(hipEventRecord(e0, s));
-    }
-    if (spec.kind == GF_APPLY_SUMFACT)
-      launch_sumfact_apply<double>(F, w.p.p, w.q.p, w.sig64.p, w.one64.p, ldb, nt, w.active.p, s);
-    else
-      launch_stencil_apply<double>(F, F.stM.p, F.stS.p, w.p.p, w.q.p, w.sig64.p, w.one64.p, ldb, nt, w.active.p, s);
-    if (spec.flags & GF_FLAG_TIME_APPLY) {
-      HIPCHK(hipEventRecord(e1, s));
       evs.push_back(e0);
       evs.push_back(e1);
     }
-    launch_interface_sum<double>(F, w.q.p, ldb, nt, w.active.p, s);
+    EpiArgs<double> e;
+    e.kind = EPI_STORE;
+    e.y = w.q.p;
+    e.dot = 1;
+    e.op = OP_ALPHA;
+    apply_epi<double>(F, spec.kind, w.p.p, w.sig64.p, w.one64.p, e, sc, w.cs.p, w.active.p, ldb, nt, tol2,
+                      spec.max_iter, s, e0, e1);
   };
   // r = b - A 0 = b;  bb = |b|^2
   reduce_dot<double, double>(F, w.r.p, w.r.p, sc, ldb, nt, w.cs.p, w.active.p, OP_BB, tol2, spec.max_iter, nullptr,
                              s);
-  precondition(sp, w, spec, s);
-  if (mixed) {
-    reduce_dot<double, float>(F, w.r.p, zf, sc, ldb, nt, w.cs.p, w.active.p, OP_RZ0, tol2, spec.max_iter, nullptr,
-                              s);
-    convert_rows<float, double>(F, zf, w.p.p, ldb, nt, w.active.p, s);
-  } else {
-    reduce_dot<double, double>(F, w.r.p, zd, sc, ldb, nt, w.cs.p, w.active.p, OP_RZ0, tol2, spec.max_iter, nullptr,
-                               s);
-    convert_rows<double, double>(F, zd, w.p.p, ldb, nt, w.active.p, s);
+  if (!precondition(OP_RZ0)) {
+    if (mixed)
+      reduce_dot<double, float>(F, w.r.p, zf, sc, ldb, nt, w.cs.p, w.active.p, OP_RZ0, tol2, spec.max_iter,
+                                nullptr, s);
+    else
+      reduce_dot<double, double>(F, w.r.p, zd, sc, ldb, nt, w.cs.p, w.active.p, OP_RZ0, tol2, spec.max_iter,
+                                 nullptr, s);
   }
+  if (mixed)
+    convert_rows<float, double>(F, zf, w.p.p, ldb, nt, w.active.p, s);
+  else
+    convert_rows<double, double>(F, zd, w.p.p, ldb, nt, w.active.p, s);
   const int check_every = 1;
   for (int it = 0; it < spec.max_iter; ++it) {
-    timed_apply();
-    reduce_dot<double, double>(F, w.p.p, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, OP_ALPHA, tol2, spec.max_iter,
-                               nullptr, s);
-    update_xr(F, w.x.p, w.r.p, w.p.p, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, tol2, spec.max_iter, s);
+    outer_apply();
+    update_xr2(F, w.x.p, w.r.p, w.p.p, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, tol2, spec.max_iter, s);
     if ((it + 1) % check_every == 0) {
       HIPCHK(hipMemcpyAsync(w.active_h.data(), w.active.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -639,15 +749,16 @@ static SolveResult solve_batch(gf_space *sp, Workspace &w, const SolveSpec &spec
       for (int t = 0; t < nt; ++t) any = any || w.active_h[t];
       if (!any) break;
     }
-    precondition(sp, w, spec, s);
     if (mixed) {
+      precondition(-1);
       reduce_dot2<double, float, double>(F, w.r.p, zf, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, OP_BETA_FLEX, tol2,
                                          spec.max_iter, nullptr, s);
-      update_p<float>(F, w.p.p, zf, w.cs.p, ldb, nt, w.active.p, s);
+      update_p2<float>(F, w.p.p, zf, w.cs.p, ldb, nt, w.active.p, s);
     } else {
-      reduce_dot<double, double>(F, w.r.p, zd, sc, ldb, nt, w.cs.p, w.active.p, OP_BETA, tol2, spec.max_iter,
-                                 nullptr, s);
-      update_p<double>(F, w.p.p, zd, w.cs.p, ldb, nt, w.active.p, s);
+      if (!precondition(OP_BETA))
+        reduce_dot<double, double>(F, w.r.p, zd, sc, ldb, nt, w.cs.p, w.active.p, OP_BETA, tol2, spec.max_iter,
+                                   nullptr, s);
+      update_p2<double>(F, w.p.p, zd, w.cs.p, ldb, nt, w.active.p, s);
     }
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -934,16 +1045,16 @@ gf_status gf_sample(gf_space *sp, double kappa, double beta, const gf_quad_rule 
     base.flags = opts->flags;
     double setup_ms = 0.0;
     int max_it = 0, flags = 0, nsys = 0;
-    double max_rel = 0.0, apply_ms = 0.0;
-    int apply_launches = 0, apply_cols = 0;
-    auto account = [&](const SolveResult &r, int ncols, int ldb) {
+    double max_rel = 0.0, apply_ms = 0.0, apply_col_sum = 0.0;
+    int apply_launches = 0;
+    auto account = [&](const SolveResult &r, int ncols) {
       max_it = std::max(max_it, r.max_it);
       max_rel = std::max(max_rel, r.max_rel);
       flags |= r.flags;
       nsys += ncols;
       apply_ms += r.apply_ms;
       apply_launches += r.apply_launches;
-      if (r.apply_launches) apply_cols = ldb;
+      apply_col_sum += r.apply_col_sum;
     };
     // plans first (their set-up is reported separately from the solve time)
     const Plan *chain_plan = nullptr, *frac_plan = nullptr;
@@ -972,13 +1083,14 @@ gf_status gf_sample(gf_space *sp, double kappa, double beta, const gf_quad_rule 
       Workspace &w = get_workspace(sp, ldc, base.prec);
       global_to_local(F, w.r.p, bin.p, nsamp, ldc, s);
       SolveSpec spec = base;
+      if (bf > 0.0) spec.flags &= ~GF_FLAG_TIME_APPLY;  // the node batch is timed instead
       spec.ncols = nsamp;
       spec.col_sig.assign(nsamp, kappa * kappa);
       spec.col_node.assign(nsamp, 0);
       spec.plan = chain_plan;
       for (int i = 1; i <= n; ++i) {
         SolveResult r = solve_batch(sp, w, spec);
-        account(r, nsamp, ldc);
+        account(r, nsamp);
         if (i < n || bf > 0.0) {
           // next right-hand side M w_i (assembled)
           apply_level<double>(F, GF_APPLY_STENCIL, w.x.p, w.r.p, w.one64.p, w.zero64.p, ldc, ldc / CT, nullptr, s);
@@ -1011,7 +1123,7 @@ gf_status gf_sample(gf_space *sp, double kappa, double beta, const gf_quad_rule 
         }
       spec.plan = frac_plan;
       SolveResult r = solve_batch(sp, w, spec);
-      account(r, ncols, ldf);
+      account(r, ncols);
       DBuf<double> om;
       om.upload(omega, s);
       quadrature_sum(F, uout.p, w.x.p, om.p, K, nsamp, ldf, s);
@@ -1031,7 +1143,8 @@ gf_status gf_sample(gf_space *sp, double kappa, double beta, const gf_quad_rule 
       stats->solve_ms = ms;
       stats->apply_ms = apply_ms;
       stats->apply_launches = apply_launches;
-      stats->apply_cols = apply_cols;
+      stats->apply_rows = 6 * F.n1 * F.n1;
+      stats->apply_col_sum = apply_col_sum;
     }
     if (flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
     if (flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");

@@ -1,0 +1,591 @@
+// Fused operator application and the streaming CG kernels.
+//
+// The patch operator (sigma M + S) of eq. mass / eq. stiffness is applied from its per-patch
+// (2p+1)^2 stencils, and the consumer of the result runs in the same kernel (epilogue), so the
+// product A z is never written to memory for unknowns inside a patch:
+//   EPI_STORE  y = A x                       (optionally the inner product x . y)
+//   EPI_RESID  y = r - A x                   (residual for the restriction)
+//   EPI_CHEB   Chebyshev-Jacobi step on D^-1 A: res = (r - A z)/D, d = c1 d + c2 res / b_max,
+//              z_out = z + d                (optionally the inner product r . z_out)
+// Unknowns on patch boundaries are shared with neighbouring patches: there the kernel stores its
+// patch contribution, and the interface kernel sums the copies and runs the same epilogue.
+//
+// Mapping: one wavefront per strip of TY coefficient rows x TX coefficients of one patch and one
+// 64-wide column tile (lane = system).  The wavefront keeps a (TY + 2p) x (2p + 1) window of the
+// input in registers and moves it along the strip, loading one new column of TY + 2p values per
+// step.  Linear block ids are remapped so that every XCD walks a contiguous run of strips: the
+// halo rows shared by neighbouring strips then hit the same L2.
+#include "gf_internal.h"
+#include "k_solve.h"
+
+namespace gf {
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ bool interior_row(int64_t r, int W, int P, int n1) {
+  const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P;
+  return lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
+}
+
+// Epilogue operands as direct kernel arguments (global, non-aliasing): stores through them then cannot
+// clobber the stencil coefficients, which therefore stay scalar (wavefront-uniform) loads.
+template <typename T>
+struct EpiPtrs {
+  T *__restrict__ y;
+  T *__restrict__ zout;
+  T *__restrict__ d;
+  const T *__restrict__ r;
+  const T *__restrict__ dM;
+  const T *__restrict__ dS;
+  const T *__restrict__ sig;
+  const T *__restrict__ invb;
+};
+
+template <typename T>
+__device__ __forceinline__ void epi_interior(int kind, int dot, T c1, T c2, T *__restrict__ y, T *__restrict__ zout,
+                                             T *__restrict__ d, const T *__restrict__ r, const T *__restrict__ dM,
+                                             const T *__restrict__ dS, const T *__restrict__ sig,
+                                             const T *__restrict__ invb, int64_t row, int64_t i, int col, T Az, T xc,
+                                             double &acc) {
+  switch (kind) {
+    case EPI_STORE:
+      y[i] = Az;
+      if (dot) acc += (double)xc * (double)Az;
+      break;
+    case EPI_RESID:
+      y[i] = r[i] - Az;
+      break;
+    default: {  // EPI_CHEB
+      const T rv = r[i];
+      const T D = sig[col] * dM[row] + dS[row];
+      const T res = (rv - Az) / D;
+      const T dn = (c1 != T(0) ? c1 * d[i] : T(0)) + c2 * invb[col] * res;
+      d[i] = dn;
+      const T zo = xc + dn;
+      zout[i] = zo;
+      if (dot) acc += (double)rv * (double)zo;
+    }
+  }
+}
+
+// reduce one double per lane over the 4 wavefronts of the block into partial[slot][col]
+__device__ __forceinline__ void block_partial(double acc, double *partial, int64_t slot, int ldb, int col) {
+  __shared__ double red[4][CT];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0) partial[slot * ldb + col] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+// The stencil coefficients of the current row (wavefront-uniform) are scalar loads; the window of x
+// shifts by one column per step.  The epilogue kind and the inner-product flag are compile-time
+// parameters, so a kernel keeps only the operands its epilogue uses live in scalar registers.
+template <typename T, int P, int TY, int KIND, int DOT>
+__global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__restrict__ stM,
+                                                     const T *__restrict__ stS, const T *__restrict__ x,
+                                                     const T *__restrict__ ca, const T *__restrict__ cb, T c1, T c2,
+                                                     T *__restrict__ y, T *__restrict__ zout, T *__restrict__ d,
+                                                     const T *__restrict__ r, const T *__restrict__ dM,
+                                                     const T *__restrict__ dS, const T *__restrict__ invb,
+                                                     double *__restrict__ partial, const int *__restrict__ active) {
+  constexpr int S = 2 * P + 1, WR = TY + 2 * P, SS = S * S;
+  const int Lb = blockIdx.x;
+  const int bl = (Lb & 7) * g.q + (Lb >> 3);
+  if (bl >= g.nsb * g.ntiles) return;
+  const int ct = bl % g.ntiles, sb = bl / g.ntiles;  // column tile fastest: contiguous rows in memory
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int W = g.W, n1 = g.n1;
+  const int64_t ldb = g.ldb;
+  const int strip = sb * 4 + wave;
+  double acc = 0.0;
+  if (strip < g.nstrip) {
+    const int iyb = strip % g.nyb;
+    const int seg = (strip / g.nyb) % g.nseg;
+    const int m = strip / (g.nyb * g.nseg);
+    const int iy0 = iyb * TY;
+    const int x0 = seg * g.TX, x1 = min(x0 + g.TX, n1);
+    const T a = ca[col], b = cb[col];
+    T sg = 0, ib = 0;
+    if (KIND == EPI_CHEB) {
+      sg = a;  // the shift of this system
+      ib = invb[col];
+    }
+    const int64_t pbase = (int64_t)m * W * W;
+    const T *xc = x + col;
+    T win[WR][S];
+#pragma unroll
+    for (int k = 0; k < WR; ++k) {
+      const int py = iy0 + k;
+#pragma unroll
+      for (int c = 1; c < S; ++c)
+        win[k][c] = (py < W) ? xc[(pbase + (int64_t)py * W + (x0 + c - 1)) * ldb] : T(0);
+    }
+    for (int ix = x0; ix < x1; ++ix) {
+#pragma unroll
+      for (int k = 0; k < WR; ++k) {
+        const int py = iy0 + k;
+#pragma unroll
+        for (int c = 0; c < S - 1; ++c) win[k][c] = win[k][c + 1];
+        win[k][S - 1] = (py < W) ? xc[(pbase + (int64_t)py * W + (ix + 2 * P)) * ldb] : T(0);
+      }
+#pragma unroll
+      for (int t = 0; t < TY; ++t) {
+        const int iy = iy0 + t;
+        if (iy >= n1) break;
+        const int64_t row = pbase + (int64_t)(iy + P) * W + (ix + P);
+        const T *cm = stM + row * SS;
+        const T *cs = stS + row * SS;
+        T am = 0, as = 0;
+#pragma unroll
+        for (int dy = 0; dy < S; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < S; ++dx) {
+            am = fma(cm[dy * S + dx], win[t + dy][dx], am);
+            as = fma(cs[dy * S + dx], win[t + dy][dx], as);
+          }
+        const T Az = a * am + b * as;
+        const int64_t i = row * ldb + col;
+        const bool shared = (ix == 0) | (ix == n1 - 1) | (iy == 0) | (iy == n1 - 1);
+        if (shared) {
+          y[i] = Az;  // patch contribution; the interface kernel completes it
+        } else if (KIND == EPI_STORE) {
+          y[i] = Az;
+          if (DOT) acc += (double)win[t + P][P] * (double)Az;
+        } else if (KIND == EPI_RESID) {
+          y[i] = r[i] - Az;
+        } else {
+          const T rv = r[i];
+          const T D = sg * dM[row] + dS[row];
+          const T dn = (c1 != T(0) ? c1 * d[i] : T(0)) + c2 * ib * ((rv - Az) / D);
+          d[i] = dn;
+          const T zo = win[t + P][P] + dn;
+          zout[i] = zo;
+          if (DOT) acc += (double)rv * (double)zo;
+        }
+      }
+    }
+  }
+  if (DOT) block_partial(acc, partial, sb, (int)ldb, col);
+}
+
+// Interface completion: sum the patch contributions of every shared unknown and run the epilogue on
+// each copy.  With e.dot the last block of a column tile adds the partials of both kernels (apply
+// blocks first, then interface blocks, in block order) and applies the per-system step e.op.
+template <typename T>
+__global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__restrict__ x, EpiArgs<T> e,
+                                                      double *partial, ColState *cs,
+                                                      const int *__restrict__ gp, const int *__restrict__ gr,
+                                                      int *active, double tol2, int maxit) {
+  const int ct = blockIdx.x % g.ntiles, gb = blockIdx.x / g.ntiles;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int ldb = g.ldb;
+  const int grp = gb * 4 + wave;
+  double acc = 0.0;
+  if (grp < g.ngroups) {
+    const int k0 = gp[grp], k1 = gp[grp + 1];
+    T s = 0;
+    for (int k = k0; k < k1; ++k) s += e.y[(int64_t)gr[k] * ldb + col];
+    for (int k = k0; k < k1; ++k) {
+      const int64_t row = gr[k];
+      const int64_t i = row * ldb + col;
+      const bool own = (k == k0);
+      double a2 = 0.0;
+      if (e.kind == EPI_STORE) {
+        e.y[i] = s;
+        if (e.dot) a2 = (double)x[i] * (double)s;
+      } else if (e.kind == EPI_RESID) {
+        e.y[i] = e.r[i] - s;
+      } else {
+        const T rv = e.r[i];
+        const T D = e.sig[col] * e.dM[row] + e.dS[row];
+        const T res = (rv - s) / D;
+        const T dn = (e.c1 != T(0) ? e.c1 * e.d[i] : T(0)) + e.c2 * e.invb[col] * res;
+        e.d[i] = dn;
+        const T zo = x[i] + dn;
+        e.zout[i] = zo;
+        if (e.dot) a2 = (double)rv * (double)zo;
+      }
+      if (own) acc += a2;
+    }
+  }
+  if (e.dot) block_partial(acc, partial, g.nsb_apply + gb, ldb, col);
+}
+
+// Per-system scalar step after a reduction: one block per column tile sums the partials of all blocks
+// (fixed order, see sum_partials) and applies `op`; for OP_CHECK it also refreshes the tile's
+// active flag.  A separate launch rather than a last-block-done counter: the kernel boundary makes
+// the partials of every block visible without device-scope fences in the producers.
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int nslot, int nd, int ldb,
+                                                  int op, ColState *cs, int *active, double tol2, int maxit,
+                                                  double *out) {
+  const int ct = blockIdx.x;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x & 63;
+  const int col = ct * CT + lane;
+  double tot[2] = {0.0, 0.0};
+  tot[0] = sum_partials(partial, nslot, ldb, col);
+  if (nd > 1) {
+    __syncthreads();
+    tot[1] = sum_partials(partial + (int64_t)nslot * ldb, nslot, ldb, col);
+  }
+  if (threadIdx.x >= 64) return;
+  if (op == OP_STORE) {
+    out[col] = tot[0];
+    out[ldb + col] = tot[1];
+    return;
+  }
+  finalize_col(op, col, tot, cs, tol2, maxit);
+  if (op == OP_CHECK && active) {
+    const unsigned long long any = __ballot(!cs[col].done);
+    if (lane == 0) active[ct] = any ? 1 : 0;
+  }
+}
+
+void finalize(int nslot, int nd, int op, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
+              int maxit, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(ntiles), dim3(256), 0, s, sc.partial, nslot, nd, ldb, op, cs, active, tol2, maxit,
+                     out);
+  HIPCHK(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ launchers
+static int xcd_q(int total) { return (total + 7) / 8; }
+
+template <typename T, int P, int TY, int KIND, int DOT>
+static void launch_apply_k(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
+                           const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s) {
+  hipLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca, cb,
+                     e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active);
+}
+
+template <typename T, int P, int TY>
+static void launch_apply_pt(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
+                            const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s) {
+  if (e.kind == EPI_STORE) {
+    if (e.dot) launch_apply_k<T, P, TY, EPI_STORE, 1>(g, stM, stS, x, ca, cb, e, partial, active, s);
+    else launch_apply_k<T, P, TY, EPI_STORE, 0>(g, stM, stS, x, ca, cb, e, partial, active, s);
+  } else if (e.kind == EPI_CHEB) {
+    if (e.dot) launch_apply_k<T, P, TY, EPI_CHEB, 1>(g, stM, stS, x, ca, cb, e, partial, active, s);
+    else launch_apply_k<T, P, TY, EPI_CHEB, 0>(g, stM, stS, x, ca, cb, e, partial, active, s);
+  } else {
+    launch_apply_k<T, P, TY, EPI_RESID, 0>(g, stM, stS, x, ca, cb, e, partial, active, s);
+  }
+}
+
+template <typename T, int P>
+static void launch_apply_p(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
+                           const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s) {
+  if (g.TY == 1 || P >= 4) launch_apply_pt<T, P, 1>(g, stM, stS, x, ca, cb, e, partial, active, s);
+  else launch_apply_pt<T, P, 2>(g, stM, stS, x, ca, cb, e, partial, active, s);
+}
+
+ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int NC) {
+  ApplyGeom g;
+  g.W = L.W;
+  g.n1 = L.n1;
+  g.ldb = ldb;
+  g.ntiles = ntiles;
+  g.TY = (L.p >= 4 || TY < 2) ? 1 : 2;
+  g.NC = 1;
+  g.nseg = (L.n1 + TXmax - 1) / TXmax;
+  g.TX = (L.n1 + g.nseg - 1) / g.nseg;
+  g.nyb = (L.n1 + g.TY - 1) / g.TY;
+  g.nstrip = 6 * g.nseg * g.nyb;
+  g.nsb = (g.nstrip + 3) / 4;
+  g.q = xcd_q(g.nsb * ntiles);
+  return g;
+}
+
+int partial_slots(const Level &L, int ldb, int ntiles) {
+  const ApplyGeom g = apply_geom(L, ldb, ntiles, 1, 16, 1);  // the most strips of any tuning candidate
+  const int ngb = (L.ngroups + 3) / 4;
+  return std::max(g.nsb + ngb, kRowBlocks);
+}
+
+template <typename T>
+void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
+                 const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
+                 int maxit, hipStream_t s, const ApplyTune &tune, hipEvent_t ev0, hipEvent_t ev1) {
+  const ApplyGeom g = apply_geom(L, ldb, ntiles, tune.TY, tune.TX, tune.NC);
+  if (ev0) HIPCHK(hipEventRecord(ev0, s));
+  switch (L.p) {
+    case 1: launch_apply_p<T, 1>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
+    case 2: launch_apply_p<T, 2>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
+    case 3: launch_apply_p<T, 3>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
+    case 4: launch_apply_p<T, 4>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
+    case 5: launch_apply_p<T, 5>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
+    default: fail(GF_EUNSUPPORTED, "degree out of range");
+  }
+  HIPCHK(hipGetLastError());
+  if (ev1) HIPCHK(hipEventRecord(ev1, s));
+  iface_finish<T>(L, x, e, sc, cs, active, ldb, ntiles, g.nsb, tol2, maxit, s);
+}
+template void apply_fused<double>(const Level &, const double *, const double *, const double *, const double *,
+                                  const double *, const EpiArgs<double> &, Scratch &, ColState *, int *, int, int,
+                                  double, int, hipStream_t, const ApplyTune &, hipEvent_t, hipEvent_t);
+template void apply_fused<float>(const Level &, const float *, const float *, const float *, const float *,
+                                 const float *, const EpiArgs<float> &, Scratch &, ColState *, int *, int, int, double,
+                                 int, hipStream_t, const ApplyTune &, hipEvent_t, hipEvent_t);
+
+template <typename T>
+void iface_finish(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb,
+                  int ntiles, int nsb_apply, double tol2, int maxit, hipStream_t s) {
+  if (L.ngroups == 0) {
+    if (e.dot) fail(GF_EUNSUPPORTED, "inner product epilogue needs interface groups");
+    return;
+  }
+  IfaceGeom g;
+  g.ldb = ldb;
+  g.ntiles = ntiles;
+  g.ngroups = L.ngroups;
+  g.ngb = (L.ngroups + 3) / 4;
+  g.nsb_apply = nsb_apply;
+  hipLaunchKernelGGL(k_iface_finish<T>, dim3(g.ngb * ntiles), dim3(256), 0, s, g, x, e, sc.partial, cs,
+                     L.grp_ptr.p, L.grp_rows.p, active, tol2, maxit);
+  HIPCHK(hipGetLastError());
+  if (e.dot) finalize(nsb_apply + g.ngb, 1, e.op, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
+}
+template void iface_finish<double>(const Level &, const double *, const EpiArgs<double> &, Scratch &, ColState *,
+                                   int *, int, int, int, double, int, hipStream_t);
+template void iface_finish<float>(const Level &, const float *, const EpiArgs<float> &, Scratch &, ColState *, int *,
+                                  int, int, int, double, int, hipStream_t);
+
+// ------------------------------------------------------------------ streaming row kernels
+// One wavefront per row and column tile, four rows per loop step so that every wavefront keeps
+// four independent loads of each operand in flight.
+// Blocks are numbered with the column tile fastest, so that blocks running together touch whole
+// rows of the [row][column] layout (contiguous memory).
+struct RowGeom {
+  int64_t R;
+  int W, P, n1, ldb, nrb, ntiles;
+  const uint8_t *owner;
+};
+
+static RowGeom row_geom(const Level &L, int ldb) {
+  RowGeom g;
+  g.ntiles = ldb / CT;
+  g.R = L.R;
+  g.W = L.W;
+  g.P = L.p;
+  g.n1 = L.n1;
+  g.ldb = ldb;
+  g.owner = L.owner.p;
+  g.nrb = kRowBlocks;
+  const int64_t need = (L.R + 15) / 16;
+  if (need < g.nrb) g.nrb = (int)std::max<int64_t>(1, need);
+  return g;
+}
+
+// x += alpha p, r -= alpha q; |r|^2 over owned unknowns -> convergence test
+__global__ __launch_bounds__(256) void k_update_xr(RowGeom g, double *__restrict__ x, double *__restrict__ r,
+                                                   const double *__restrict__ p, const double *__restrict__ q,
+                                                   ColState *cs, double *partial, int *active,
+                                                   double tol2, int maxit) {
+  const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int ldb = g.ldb;
+  const double al = cs[col].alpha;
+  const int64_t stride = (int64_t)g.nrb * 4;
+  double acc = 0.0;
+  for (int64_t r0 = (int64_t)rb * 4 + wave; r0 < g.R; r0 += 4 * stride) {
+    double pv[4], qv[4], xv[4], rv[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + u * stride;
+      ok[u] = row < g.R;
+      if (ok[u]) {
+        const int64_t i = row * ldb + col;
+        pv[u] = p[i];
+        qv[u] = q[i];
+        xv[u] = x[i];
+        rv[u] = r[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!ok[u]) continue;
+      const int64_t row = r0 + u * stride;
+      const int64_t i = row * ldb + col;
+      const double rn = rv[u] - al * qv[u];
+      x[i] = xv[u] + al * pv[u];
+      r[i] = rn;
+      if (g.owner[row]) acc += rn * rn;
+    }
+  }
+  block_partial(acc, partial, rb, ldb, col);
+}
+
+// p = z + beta p
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_update_p(RowGeom g, double *__restrict__ p, const TZ *__restrict__ z,
+                                                  const ColState *cs, const int *active) {
+  const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int ldb = g.ldb;
+  const double be = cs[col].beta;
+  const int64_t stride = (int64_t)g.nrb * 4;
+  for (int64_t r0 = (int64_t)rb * 4 + wave; r0 < g.R; r0 += 4 * stride) {
+    double pv[4], zv[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + u * stride;
+      ok[u] = row < g.R;
+      if (ok[u]) {
+        const int64_t i = row * ldb + col;
+        pv[u] = p[i];
+        zv[u] = (double)z[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ok[u]) p[(r0 + u * stride) * ldb + col] = zv[u] + be * pv[u];
+  }
+}
+
+// First Chebyshev step from z = 0: d = z = c2 r / (D b_max).  TR is the type of the incoming
+// right-hand side; with r32 != null it is also stored in the V-cycle precision.
+template <typename T, typename TR>
+__global__ __launch_bounds__(256) void k_cheb_first(RowGeom g, const TR *__restrict__ r, T *__restrict__ r32,
+                                                    T *__restrict__ z, T *__restrict__ d, const T *__restrict__ dM,
+                                                    const T *__restrict__ dS, const T *__restrict__ sig,
+                                                    const T *__restrict__ invb, T c2, const int *active) {
+  const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int ldb = g.ldb;
+  const T sg = sig[col], sc = c2 * invb[col];
+  const int64_t stride = (int64_t)g.nrb * 4;
+  for (int64_t r0 = (int64_t)rb * 4 + wave; r0 < g.R; r0 += 4 * stride) {
+    T rv[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + u * stride;
+      ok[u] = row < g.R;
+      if (ok[u]) rv[u] = (T)r[row * ldb + col];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!ok[u]) continue;
+      const int64_t row = r0 + u * stride;
+      const int64_t i = row * ldb + col;
+      const T v = sc * rv[u] / (sg * dM[row] + dS[row]);
+      if (r32) r32[i] = rv[u];
+      d[i] = v;
+      z[i] = v;
+    }
+  }
+}
+
+void update_xr2(const Level &L, double *x, double *r, const double *p, const double *q, Scratch &sc, int ldb,
+                int ntiles, ColState *cs, int *active, double tol2, int maxit, hipStream_t s) {
+  const RowGeom g = row_geom(L, ldb);
+  hipLaunchKernelGGL(k_update_xr, dim3(g.nrb * ntiles), dim3(256), 0, s, g, x, r, p, q, cs, sc.partial,
+                     active, tol2, maxit);
+  HIPCHK(hipGetLastError());
+  finalize(g.nrb, 1, OP_CHECK, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
+}
+
+template <typename TZ>
+void update_p2(const Level &L, double *p, const TZ *z, const ColState *cs, int ldb, int ntiles, const int *active,
+               hipStream_t s) {
+  const RowGeom g = row_geom(L, ldb);
+  hipLaunchKernelGGL(k_update_p<TZ>, dim3(g.nrb * ntiles), dim3(256), 0, s, g, p, z, cs, active);
+  HIPCHK(hipGetLastError());
+}
+template void update_p2<double>(const Level &, double *, const double *, const ColState *, int, int, const int *,
+                                hipStream_t);
+template void update_p2<float>(const Level &, double *, const float *, const ColState *, int, int, const int *,
+                               hipStream_t);
+
+template <typename T, typename TR>
+void cheb_first(const Level &L, const TR *r, T *r32, T *z, T *d, const T *dM, const T *dS, const T *sig,
+                const T *invb, T c2, int ldb, int ntiles, const int *active, hipStream_t s) {
+  const RowGeom g = row_geom(L, ldb);
+  hipLaunchKernelGGL((k_cheb_first<T, TR>), dim3(g.nrb * ntiles), dim3(256), 0, s, g, r, r32, z, d, dM, dS, sig,
+                     invb, c2, active);
+  HIPCHK(hipGetLastError());
+}
+template void cheb_first<double, double>(const Level &, const double *, double *, double *, double *,
+                                         const double *, const double *, const double *, const double *, double, int,
+                                         int, const int *, hipStream_t);
+template void cheb_first<float, float>(const Level &, const float *, float *, float *, float *, const float *,
+                                       const float *, const float *, const float *, float, int, int, const int *,
+                                       hipStream_t);
+template void cheb_first<float, double>(const Level &, const double *, float *, float *, float *, const float *,
+                                        const float *, const float *, const float *, float, int, int, const int *,
+                                        hipStream_t);
+
+}  // namespace gf
+
+namespace gf {
+
+// Epilogue over every row after an operator application that wrote A x into e.y (sum-factorised
+// path): the same epilogues as the fused stencil kernel, for all unknowns.
+template <typename T>
+__global__ __launch_bounds__(256) void k_epi_rows(RowGeom g, const T *__restrict__ x, EpiArgs<T> e,
+                                                  double *partial, ColState *cs, int *active,
+                                                  double tol2, int maxit) {
+  const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int ldb = g.ldb;
+  const int64_t stride = (int64_t)g.nrb * 4;
+  double acc = 0.0;
+  for (int64_t row = (int64_t)rb * 4 + wave; row < g.R; row += stride) {
+    const int64_t i = row * ldb + col;
+    const T Az = e.y[i];
+    double a2 = 0.0;
+    if (e.kind == EPI_STORE) {
+      if (e.dot) a2 = (double)x[i] * (double)Az;
+    } else if (e.kind == EPI_RESID) {
+      e.y[i] = e.r[i] - Az;
+    } else {
+      const T rv = e.r[i];
+      const T D = e.sig[col] * e.dM[row] + e.dS[row];
+      const T res = (rv - Az) / D;
+      const T dn = (e.c1 != T(0) ? e.c1 * e.d[i] : T(0)) + e.c2 * e.invb[col] * res;
+      e.d[i] = dn;
+      const T zo = x[i] + dn;
+      e.zout[i] = zo;
+      if (e.dot) a2 = (double)rv * (double)zo;
+    }
+    if (g.owner[row]) acc += a2;
+  }
+  if (!e.dot) return;
+  block_partial(acc, partial, rb, ldb, col);
+}
+
+template <typename T>
+void epi_rows(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb,
+              int ntiles, double tol2, int maxit, hipStream_t s) {
+  const RowGeom g = row_geom(L, ldb);
+  hipLaunchKernelGGL(k_epi_rows<T>, dim3(g.nrb * ntiles), dim3(256), 0, s, g, x, e, sc.partial, cs,
+                     active, tol2, maxit);
+  HIPCHK(hipGetLastError());
+  if (e.dot) finalize(g.nrb, 1, e.op, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
+}
+template void epi_rows<double>(const Level &, const double *, const EpiArgs<double> &, Scratch &, ColState *, int *,
+                               int, int, double, int, hipStream_t);
+template void epi_rows<float>(const Level &, const float *, const EpiArgs<float> &, Scratch &, ColState *, int *,
+                              int, int, double, int, hipStream_t);
+
+}  // namespace gf

@@ -280,9 +280,18 @@ void launch_extract_stencil(const Level &L, const double *y, int ldb, double *st
 }
 
 // diagonals: the stencil centre of every copy, then summed over the copies of shared unknowns
-__global__ void k_diag_centre(const double *stM, const double *stS, double *dM, double *dS, int64_t R, int c) {
+// Ghost rows (outside every patch grid) get dM = 1, dS = 0: their D = sigma is positive, so the
+// streaming kernels may run over ghost rows, whose vector entries stay zero.
+__global__ void k_diag_centre(const double *stM, const double *stS, double *dM, double *dS, int64_t R, int c, int W,
+                              int n1) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
+  const int lx = (int)(r % W) - c, ly = (int)((r / W) % W) - c;
+  if (lx < 0 || lx >= n1 || ly < 0 || ly >= n1) {
+    dM[r] = 1.0;
+    dS[r] = 0.0;
+    return;
+  }
   dM[r] = stM[r * (2 * c + 1) * (2 * c + 1) + c * (2 * c + 1) + c];
   dS[r] = stS[r * (2 * c + 1) * (2 * c + 1) + c * (2 * c + 1) + c];
 }
@@ -300,7 +309,7 @@ __global__ void k_to_f32(const double *a, float *b, int64_t n) {
 
 void launch_stencil_diag(const Level &L, hipStream_t s) {
   hipLaunchKernelGGL(k_diag_centre, dim3((unsigned)((L.R + 255) / 256)), dim3(256), 0, s, L.stM.p, L.stS.p, L.dM.p,
-                     L.dS.p, L.R, L.p);
+                     L.dS.p, L.R, L.p, L.W, L.n1);
   if (L.ngroups > 0)
     hipLaunchKernelGGL(k_diag_sum, dim3((L.ngroups + 255) / 256), dim3(256), 0, s, L.dM.p, L.dS.p, L.grp_ptr.p,
                        L.grp_rows.p, L.ngroups);

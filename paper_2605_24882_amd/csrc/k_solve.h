@@ -19,13 +19,140 @@ struct ColState {
 
 enum ReduceOp { OP_STORE = 0, OP_BB, OP_RZ0, OP_ALPHA, OP_CHECK, OP_BETA, OP_BETA_FLEX };
 
-constexpr int kMaxRowBlocks = 1024;
+constexpr int kMaxRowBlocks = 1024;  // row blocks of the generic reduction kernels
+constexpr int kRowBlocks = 256;      // row blocks per column tile of the streaming kernels
 
-// partial sums [2][kMaxRowBlocks][ldb] and one counter per column tile
+// partial sums [slots][ldb] and one counter per column tile
 struct Scratch {
   double *partial = nullptr;
   int *counter = nullptr;
 };
+
+// Per-system scalar step applied by the last block of a column tile to the reduced sums.
+__device__ inline void finalize_col(int op, int col, const double *tot, ColState *cs, double tol2, int maxit) {
+  ColState &c = cs[col];
+  switch (op) {
+    case OP_BB:
+      c.bb = tot[0];
+      c.rr = tot[0];
+      c.it = 0;
+      c.flag = 0;
+      c.alpha = 0;
+      c.beta = 0;
+      c.done = (c.done || !(tot[0] > 0.0)) ? 1 : 0;
+      break;
+    case OP_RZ0:
+      c.rz = tot[0];
+      break;
+    case OP_ALPHA:
+      if (c.done) {
+        c.alpha = 0.0;
+      } else if (!(tot[0] > 0.0) || !isfinite(tot[0]) || !isfinite(c.rz)) {
+        c.flag |= 2;
+        c.done = 1;
+        c.alpha = 0.0;
+      } else {
+        c.alpha = c.rz / tot[0];
+      }
+      break;
+    case OP_CHECK:
+      c.rr = tot[0];
+      if (!c.done) {
+        c.it += 1;
+        if (!isfinite(tot[0])) {
+          c.flag |= 2;
+          c.done = 1;
+        } else if (tot[0] <= tol2 * c.bb) {
+          c.done = 1;
+        } else if (c.it >= maxit) {
+          c.flag |= 1;
+          c.done = 1;
+        }
+      }
+      break;
+    case OP_BETA:
+      c.beta = c.done ? 0.0 : tot[0] / c.rz;
+      c.rz = tot[0];
+      break;
+    case OP_BETA_FLEX:
+      // Polak-Ribiere: beta = z_new^T (r_new - r_old) / rz_old with r_new - r_old = -alpha q
+      c.beta = c.done ? 0.0 : -c.alpha * tot[1] / c.rz;
+      c.rz = tot[0];
+      break;
+    default:
+      break;
+  }
+}
+
+// Sum of the per-block partials of one column tile, by all 256 threads of the last block: wavefront w
+// adds slots w, w+4, w+8, ... (four independent chains), then the four wavefront sums are added in
+// order.  The partition depends only on nslot, so the result is bitwise reproducible.
+__device__ inline double sum_partials(const double *partial, int nslot, int ldb, int col) {
+  __shared__ double red_sp[4][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int b = w;
+  for (; b + 12 < nslot; b += 16) {
+    s0 += partial[(int64_t)b * ldb + col];
+    s1 += partial[(int64_t)(b + 4) * ldb + col];
+    s2 += partial[(int64_t)(b + 8) * ldb + col];
+    s3 += partial[(int64_t)(b + 12) * ldb + col];
+  }
+  for (; b < nslot; b += 4) s0 += partial[(int64_t)b * ldb + col];
+  red_sp[w][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  return ((red_sp[0][lane] + red_sp[1][lane]) + red_sp[2][lane]) + red_sp[3][lane];
+}
+
+// per-system scalar step over the partials of a reduction (k_fused.hip)
+void finalize(int nslot, int nd, int op, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
+              int maxit, double *out, hipStream_t s);
+
+// ---- fused operator application (k_fused.hip)
+enum EpiKind { EPI_STORE = 0, EPI_CHEB = 1, EPI_RESID = 2 };
+
+template <typename T>
+struct EpiArgs {
+  int kind = EPI_STORE;
+  int dot = 0;            // accumulate x.y (STORE) or r.z_out (CHEB); the interface kernel applies `op`
+  int op = OP_STORE;
+  T *y = nullptr;         // STORE: output; CHEB/RESID: patch contributions of shared rows; RESID: output
+  T *zout = nullptr;      // CHEB: new iterate (a different buffer than the input)
+  T *d = nullptr;         // CHEB: Chebyshev direction
+  const T *r = nullptr;   // CHEB/RESID: right-hand side
+  const T *dM = nullptr, *dS = nullptr, *sig = nullptr, *invb = nullptr;
+  T c1 = 0, c2 = 0;
+};
+
+struct ApplyGeom {
+  int W, n1, ldb, ntiles, TY, NC, nseg, TX, nyb, nstrip, nsb, q;
+};
+
+struct IfaceGeom {
+  int ldb, ntiles, ngroups, ngb, nsb_apply;
+};
+
+ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int NC);
+int partial_slots(const Level &L, int ldb, int ntiles);
+template <typename T>
+void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
+                 const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
+                 int maxit, hipStream_t s, const ApplyTune &tune, hipEvent_t ev0 = nullptr,
+                 hipEvent_t ev1 = nullptr);
+template <typename T>
+void iface_finish(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb,
+                  int ntiles, int nsb_apply, double tol2, int maxit, hipStream_t s);
+void update_xr2(const Level &L, double *x, double *r, const double *p, const double *q, Scratch &sc, int ldb,
+                int ntiles, ColState *cs, int *active, double tol2, int maxit, hipStream_t s);
+template <typename TZ>
+void update_p2(const Level &L, double *p, const TZ *z, const ColState *cs, int ldb, int ntiles, const int *active,
+               hipStream_t s);
+template <typename T>
+void epi_rows(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb,
+              int ntiles, double tol2, int maxit, hipStream_t s);
+template <typename T, typename TR>
+void cheb_first(const Level &L, const TR *r, T *r32, T *z, T *d, const T *dM, const T *dS, const T *sig,
+                const T *invb, T c2, int ldb, int ntiles, const int *active, hipStream_t s);
 
 template <typename TA, typename TB>
 void reduce_dot(const Level &L, const TA *a, const TB *b, Scratch &sc, int ldb, int ntiles, ColState *cs,

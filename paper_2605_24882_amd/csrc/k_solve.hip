@@ -19,84 +19,6 @@ __device__ __forceinline__ bool row_interior(int64_t r, int W, int P, int n1) {
   return lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
 }
 
-// ------------------------------------------------------------------ stencil apply
-// y = ca (M x) + cb (S x) with the per-patch (2p+1)^2 stencils (rows of the patch matrices
-// of eq. mass / eq. stiffness).  A wavefront walks a strip of TX coefficients along ix at
-// fixed (patch, iy), keeping a (2p+1) x (2p+1) window of x in registers: one new x value per
-// stencil row and step.  Ghost padding makes every window load valid.
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_stencil(const T *__restrict__ stM, const T *__restrict__ stS,
-                                                 const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ ca,
-                                                 const T *__restrict__ cb, int W, int n1, int ldb, int nseg, int TX,
-                                                 const int *__restrict__ active) {
-  constexpr int S = 2 * P + 1;
-  const int ct = blockIdx.y;
-  if (active && !active[ct]) return;
-  const int lane = threadIdx.x;
-  const int col = ct * CT + lane;
-  const int strip = wave_uniform(blockIdx.x * 4 + threadIdx.y);
-  if (strip >= 6 * nseg * n1) return;
-  const int iy = strip % n1;
-  const int seg = (strip / n1) % nseg;
-  const int m = strip / (n1 * nseg);
-  const int x0 = seg * TX;
-  const int x1 = min(x0 + TX, n1);
-  const T a = ca[col], b = cb[col];
-  const int64_t rowbase = (int64_t)m * W * W + (int64_t)(iy + P) * W + P;
-  const T *xc = x + col;
-  T win[S][S];
-#pragma unroll
-  for (int dy = 0; dy < S; ++dy)
-#pragma unroll
-    for (int dx = 0; dx < S - 1; ++dx)
-      win[dy][dx + 1] = xc[(rowbase + (int64_t)(dy - P) * W + (x0 - P + dx)) * ldb];
-  for (int ix = x0; ix < x1; ++ix) {
-#pragma unroll
-    for (int dy = 0; dy < S; ++dy) {
-#pragma unroll
-      for (int dx = 0; dx < S - 1; ++dx) win[dy][dx] = win[dy][dx + 1];
-      win[dy][S - 1] = xc[(rowbase + (int64_t)(dy - P) * W + (ix + P)) * ldb];
-    }
-    const int64_t row = rowbase + ix;
-    const T *cm = stM + row * (S * S);
-    const T *cs = stS + row * (S * S);
-    T am = 0, as = 0;
-#pragma unroll
-    for (int dy = 0; dy < S; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < S; ++dx) {
-        am = fma(cm[dy * S + dx], win[dy][dx], am);
-        as = fma(cs[dy * S + dx], win[dy][dx], as);
-      }
-    y[row * ldb + col] = a * am + b * as;
-  }
-}
-
-template <typename T>
-void launch_stencil_apply(const Level &L, const T *stM, const T *stS, const T *x, T *y, const T *ca, const T *cb,
-                          int ldb, int ntiles, const int *active, hipStream_t s) {
-  const int txmax = 32;
-  const int nseg = (L.n1 + txmax - 1) / txmax;
-  const int TX = (L.n1 + nseg - 1) / nseg;
-  const int nstrip = 6 * nseg * L.n1;
-  dim3 grid((nstrip + 3) / 4, ntiles), block(CT, 4);
-  switch (L.p) {
-#define GF_ST(PP)                                                                                                  \
-  case PP:                                                                                                         \
-    hipLaunchKernelGGL((k_stencil<T, PP>), grid, block, 0, s, stM, stS, x, y, ca, cb, L.W, L.n1, ldb, nseg, TX, \
-                       active);                                                                                    \
-    break;
-    GF_ST(1) GF_ST(2) GF_ST(3) GF_ST(4) GF_ST(5)
-#undef GF_ST
-    default: fail(GF_EUNSUPPORTED, "degree out of range");
-  }
-  HIPCHK(hipGetLastError());
-}
-template void launch_stencil_apply<double>(const Level &, const double *, const double *, const double *, double *,
-                                           const double *, const double *, int, int, const int *, hipStream_t);
-template void launch_stencil_apply<float>(const Level &, const float *, const float *, const float *, float *,
-                                          const float *, const float *, int, int, const int *, hipStream_t);
-
 // ------------------------------------------------------------------ interface sum
 // Copies of one unknown on neighbouring patches (2 on edges, 3 at cube corners) receive the
 // sum of their patch contributions: this turns patch-local results into the assembled
@@ -104,9 +26,10 @@ template void launch_stencil_apply<float>(const Level &, const float *, const fl
 template <typename T>
 __global__ __launch_bounds__(256) void k_iface(T *y, int ldb, const int *__restrict__ gp, const int *__restrict__ gr,
                                                int ng, const int *__restrict__ active) {
-  const int ct = blockIdx.y;
+  const int ntiles = ldb / CT;
+  const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
-  const int g = wave_uniform(blockIdx.x * 4 + threadIdx.y);
+  const int g = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
   if (g >= ng) return;
   const int col = ct * CT + threadIdx.x;
   const int k0 = gp[g], k1 = gp[g + 1];
@@ -118,7 +41,7 @@ __global__ __launch_bounds__(256) void k_iface(T *y, int ldb, const int *__restr
 template <typename T>
 void launch_interface_sum(const Level &L, T *y, int ldb, int ntiles, const int *active, hipStream_t s) {
   if (L.ngroups == 0) return;
-  hipLaunchKernelGGL(k_iface<T>, dim3((L.ngroups + 3) / 4, ntiles), dim3(CT, 4), 0, s, y, ldb, L.grp_ptr.p,
+  hipLaunchKernelGGL(k_iface<T>, dim3(ntiles * ((L.ngroups + 3) / 4)), dim3(CT, 4), 0, s, y, ldb, L.grp_ptr.p,
                      L.grp_rows.p, L.ngroups, active);
   HIPCHK(hipGetLastError());
 }
@@ -136,123 +59,27 @@ struct RowCtx {
   const uint8_t *owner;
 };
 
-__device__ void finalize_op(int op, int col, const double *tot, ColState *cs, double tol2, int maxit, double *out,
-                            int ldb) {
-  if (op == OP_STORE) {
-    out[col] = tot[0];
-    out[ldb + col] = tot[1];
-    return;
-  }
-  ColState &c = cs[col];
-  switch (op) {
-    case OP_BB:
-      c.bb = tot[0];
-      c.rr = tot[0];
-      c.it = 0;
-      c.flag = 0;
-      c.alpha = 0;
-      c.beta = 0;
-      c.done = (c.done || !(tot[0] > 0.0)) ? 1 : 0;
-      break;
-    case OP_RZ0:
-      c.rz = tot[0];
-      break;
-    case OP_ALPHA:
-      if (c.done) {
-        c.alpha = 0.0;
-      } else if (!(tot[0] > 0.0) || !isfinite(tot[0]) || !isfinite(c.rz)) {
-        c.flag |= 2;
-        c.done = 1;
-        c.alpha = 0.0;
-      } else {
-        c.alpha = c.rz / tot[0];
-      }
-      break;
-    case OP_CHECK:
-      c.rr = tot[0];
-      if (!c.done) {
-        c.it += 1;
-        if (!isfinite(tot[0])) {
-          c.flag |= 2;
-          c.done = 1;
-        } else if (tot[0] <= tol2 * c.bb) {
-          c.done = 1;
-        } else if (c.it >= maxit) {
-          c.flag |= 1;
-          c.done = 1;
-        }
-      }
-      break;
-    case OP_BETA:
-      c.beta = c.done ? 0.0 : tot[0] / c.rz;
-      c.rz = tot[0];
-      break;
-    case OP_BETA_FLEX:
-      // Polak-Ribiere: beta = z_new^T (r_new - r_old) / rz_old with r_new - r_old = -alpha q
-      c.beta = c.done ? 0.0 : -c.alpha * tot[1] / c.rz;
-      c.rz = tot[0];
-      break;
-    default:
-      break;
-  }
-}
-
 template <class F, int ND>
-__global__ __launch_bounds__(256) void k_rowreduce(F f, RowCtx rc, double *partial, int *counter, ColState *cs,
-                                                   int *active, int op, double tol2, int maxit, double *out) {
-  const int ct = blockIdx.y;
-  const bool was_active = !active || active[ct];
+__global__ __launch_bounds__(256) void k_rowreduce(F f, RowCtx rc, double *partial, const int *active) {
+  const int ct = blockIdx.x;
+  if (active && !active[ct]) return;
   const int lane = threadIdx.x;
   const int col = ct * CT + lane;
   const int wave = wave_uniform(threadIdx.y);
-  double acc[ND > 0 ? ND : 1];
+  double acc[ND];
 #pragma unroll
   for (int k = 0; k < ND; ++k) acc[k] = 0.0;
-  if (was_active) {
-    for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < rc.R; r += (int64_t)gridDim.x * 4) {
-      if (!row_interior(r, rc.W, rc.P, rc.n1)) continue;
-      f(r, col, rc.owner[r] != 0, acc);
-    }
-  }
-  if (ND == 0) return;
-  __shared__ double red[4][ND > 0 ? ND : 1][CT];
+  for (int64_t r = (int64_t)blockIdx.y * 4 + wave; r < rc.R; r += (int64_t)gridDim.y * 4) f(r, col, rc.owner[r] != 0, acc);
+  __shared__ double red[4][ND][CT];
 #pragma unroll
   for (int k = 0; k < ND; ++k) red[threadIdx.y][k][lane] = acc[k];
   __syncthreads();
-  __shared__ int last;
-  if (threadIdx.y == 0) {
-    const int nrb = gridDim.x;
-    const int ldb = rc.ldb;
+  if (threadIdx.y != 0) return;
+  const int nrb = gridDim.y;
 #pragma unroll
-    for (int k = 0; k < ND; ++k) {
-      const double v = red[0][k][lane] + red[1][k][lane] + red[2][k][lane] + red[3][k][lane];
-      partial[((int64_t)k * nrb + blockIdx.x) * ldb + col] = v;
-    }
-    __threadfence();
-    if (lane == 0) {
-      const int prev = atomicAdd(&counter[ct], 1);
-      last = (prev == nrb - 1);
-    }
-  }
-  __syncthreads();
-  if (!last || threadIdx.y != 0) return;
-  __threadfence();
-  const int nrb = gridDim.x;
-  double tot[2] = {0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < ND; ++k) {
-    double s = 0.0;
-    for (int b = 0; b < nrb; ++b) s += partial[((int64_t)k * nrb + b) * rc.ldb + col];
-    tot[k] = s;
-  }
-  if (lane == 0) counter[ct] = 0;
-  if (!was_active && op != OP_STORE) return;
-  finalize_op(op, col, tot, cs, tol2, maxit, out, rc.ldb);
-  if (op == OP_CHECK && active) {
-    const bool alive = !cs[col].done;
-    const unsigned long long any = __ballot(alive);
-    if (lane == 0) active[ct] = any ? 1 : 0;
-  }
+  for (int k = 0; k < ND; ++k)
+    partial[((int64_t)k * nrb + blockIdx.y) * rc.ldb + col] =
+        red[0][k][lane] + red[1][k][lane] + red[2][k][lane] + red[3][k][lane];
 }
 
 // row functors ------------------------------------------------------
@@ -306,9 +133,10 @@ template <class F, int ND>
 static void run_reduce(const Level &L, F f, Scratch &sc, int ldb, int ntiles, ColState *cs, int *active, int op,
                        double tol2, int maxit, double *out, hipStream_t s) {
   const int nrb = row_blocks(L, ntiles);
-  hipLaunchKernelGGL((k_rowreduce<F, ND>), dim3(nrb, ntiles), dim3(CT, 4), 0, s, f, rowctx(L, ldb), sc.partial,
-                     sc.counter, cs, active, op, tol2, maxit, out);
+  hipLaunchKernelGGL((k_rowreduce<F, ND>), dim3(ntiles, nrb), dim3(CT, 4), 0, s, f, rowctx(L, ldb), sc.partial,
+                     active);
   HIPCHK(hipGetLastError());
+  finalize(nrb, ND, op, sc, cs, active, ldb, ntiles, tol2, maxit, out, s);
 }
 
 template <typename TA, typename TB>
@@ -343,11 +171,11 @@ void update_xr(const Level &L, double *x, double *r, const double *p, const doub
 // ------------------------------------------------------------------ elementwise row kernels
 template <class F>
 __global__ __launch_bounds__(256) void k_rows(F f, RowCtx rc, const int *__restrict__ active) {
-  const int ct = blockIdx.y;
+  const int ct = blockIdx.x;
   if (active && !active[ct]) return;
   const int col = ct * CT + threadIdx.x;
   const int wave = wave_uniform(threadIdx.y);
-  for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < rc.R; r += (int64_t)gridDim.x * 4) {
+  for (int64_t r = (int64_t)blockIdx.y * 4 + wave; r < rc.R; r += (int64_t)gridDim.y * 4) {
     if (!row_interior(r, rc.W, rc.P, rc.n1)) continue;
     f(r, col);
   }
@@ -356,7 +184,7 @@ __global__ __launch_bounds__(256) void k_rows(F f, RowCtx rc, const int *__restr
 template <class F>
 static void run_rows(const Level &L, F f, int ldb, int ntiles, const int *active, hipStream_t s) {
   const int nrb = row_blocks(L, ntiles);
-  hipLaunchKernelGGL(k_rows<F>, dim3(nrb, ntiles), dim3(CT, 4), 0, s, f, rowctx(L, ldb), active);
+  hipLaunchKernelGGL(k_rows<F>, dim3(ntiles, nrb), dim3(CT, 4), 0, s, f, rowctx(L, ldb), active);
   HIPCHK(hipGetLastError());
 }
 
@@ -470,11 +298,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(T *rc, const T *r, const T *Az, const uint8_t *__restrict__ ownf,
                                                   int Wf, int Wc, int n1c, int P, int ldb,
                                                   const int *__restrict__ rs, const T *__restrict__ rcoef, int rw,
-                                                  const int *__restrict__ active) {
-  const int ct = blockIdx.y;
+                                                  const int *__restrict__ active, int ntiles) {
+  const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
   const int col = ct * CT + threadIdx.x;
-  const int id = wave_uniform(blockIdx.x * 4 + threadIdx.y);
+  const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
   if (id >= 6 * n1c * n1c) return;
   const int ixc = id % n1c, iyc = (id / n1c) % n1c, m = id / (n1c * n1c);
   const int64_t fbase = (int64_t)m * Wf * Wf;
@@ -499,11 +327,11 @@ __global__ __launch_bounds__(256) void k_restrict(T *rc, const T *r, const T *Az
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(T *zf, const T *zc, int Wf, int Wc, int n1f, int P, int ldb,
                                                  const int *__restrict__ ps, const T *__restrict__ pcoef, int pw,
-                                                 const int *__restrict__ active) {
-  const int ct = blockIdx.y;
+                                                 const int *__restrict__ active, int ntiles) {
+  const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
   const int col = ct * CT + threadIdx.x;
-  const int id = wave_uniform(blockIdx.x * 4 + threadIdx.y);
+  const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
   if (id >= 6 * n1f * n1f) return;
   const int ixf = id % n1f, iyf = (id / n1f) % n1f, m = id / (n1f * n1f);
   const int64_t cbase = (int64_t)m * Wc * Wc;
@@ -539,8 +367,8 @@ template <typename T>
 void restrict_residual(const Level &F, const Level &C, T *rc, const T *r, const T *Az, int ldb, int ntiles,
                        const int *active, hipStream_t s) {
   const int n = 6 * C.n1 * C.n1;
-  hipLaunchKernelGGL(k_restrict<T>, dim3((n + 3) / 4, ntiles), dim3(CT, 4), 0, s, rc, r, Az, F.owner.p, F.W, C.W,
-                     C.n1, F.p, ldb, F.res_start.p, res_coef<T>(F), F.rw, active);
+  hipLaunchKernelGGL(k_restrict<T>, dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, rc, r, Az, F.owner.p, F.W, C.W,
+                     C.n1, F.p, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles);
   HIPCHK(hipGetLastError());
 }
 template void restrict_residual<double>(const Level &, const Level &, double *, const double *, const double *, int,
@@ -552,8 +380,8 @@ template <typename T>
 void prolong_add(const Level &F, const Level &C, T *zf, const T *zc, int ldb, int ntiles, const int *active,
                  hipStream_t s) {
   const int n = 6 * F.n1 * F.n1;
-  hipLaunchKernelGGL(k_prolong<T>, dim3((n + 3) / 4, ntiles), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1, F.p, ldb,
-                     F.pro_start.p, pro_coef<T>(F), F.pw, active);
+  hipLaunchKernelGGL(k_prolong<T>, dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1, F.p, ldb,
+                     F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles);
   HIPCHK(hipGetLastError());
 }
 template void prolong_add<double>(const Level &, const Level &, double *, const double *, int, int, const int *,
