@@ -152,8 +152,10 @@ typedef struct {
 } gf_solve_stats;
 
 /* flags */
+#define GF_FLAG_NO_GRAPH 2   /* enqueue every CG iteration eagerly instead of replaying a captured HIP graph */
 #define GF_FLAG_TIME_APPLY 1 /* bracket each outer-CG operator launch of the dominant batch (the sinc
-                                 nodes; the integer solves when beta is an integer) with HIP events */
+                                 nodes; the integer solves when beta is an integer) with HIP events;
+                                 iterations are then enqueued eagerly (no graph replay) */
 
 /* Field samples u for loads b (Sec. 3.4): n = floor(beta) integer solves A w_1 = b, A w_i = M w_{i-1},
  * then the sinc rule applied to r = M w_n (r = b if n = 0), u = sum_k omega_k x_k summed in ascending k.

@@ -652,134 +652,282 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   return za;
 }
 
-// Solves (sigma_c M + S) x_c = r_c for all columns c; on entry w.r holds the right-hand sides
-// (assembled, patch-local layout), on exit w.x holds the solutions.
-static SolveResult solve_batch(gf_space *sp, Workspace &w, const SolveSpec &spec) {
-  hipStream_t s = sp->ctx->stream;
-  const Level &F = sp->fine();
-  const int ldb = w.ldb, nt = w.ntiles, fi = sp->nlev() - 1;
-  // per-column data
-  std::vector<double> sig(ldb, 1.0);
-  std::vector<float> sigf(ldb, 1.0f);
-  std::vector<int> node(ldb, 0);
-  std::vector<ColState> cs(ldb);
-  for (int c = 0; c < ldb; ++c) {
-    cs[c] = ColState{};
-    cs[c].done = (c < spec.ncols) ? 0 : 1;
-    if (c < spec.ncols) {
-      sig[c] = spec.col_sig[c];
-      node[c] = spec.col_node[c];
-    }
-    sigf[c] = (float)sig[c];
-  }
-  std::fill(w.active_h.begin(), w.active_h.end(), 0);
-  for (int c = 0; c < spec.ncols; ++c) w.active_h[c / CT] = 1;
-  w.sig64.upload(sig, s);
-  w.sig32.upload(sigf, s);
-  w.node.upload(node, s);
-  w.cs.upload(cs, s);
-  w.active.upload(w.active_h, s);
-  for (int li = 1; li < sp->nlev(); ++li) {
-    std::vector<double> ib(ldb, 1.0);
-    for (int c = 0; c < spec.ncols; ++c) ib[c] = spec.plan->invb[li][node[c]];
-    std::vector<float> ibf(ib.begin(), ib.end());
-    w.lw[li].invb64.upload(ib, s);
-    w.lw[li].invb32.upload(ibf, s);
-  }
-  HIPCHK(hipMemsetAsync(w.x.p, 0, (size_t)F.R * ldb * sizeof(double), s));
-  Scratch sc = w.scratch();
-  const double tol2 = spec.rtol * spec.rtol;
-  const bool mixed = spec.prec == GF_PREC_MIXED;
+// One batch of shifted systems (sigma_c M + S) x_c = r_c, one per column, on one space: on entry
+// w.r holds the right-hand sides (assembled, patch-local layout), on exit w.x the solutions.
+// prepare() and start() run eagerly; iterate() enqueues one CG iteration and is what the graph
+// captures.
+struct BatchSolve {
+  gf_space *sp = nullptr;
+  Workspace *w = nullptr;
+  SolveSpec spec;
   SolveResult res;
-  std::vector<hipEvent_t> evs;
-  // preconditioner: returns z (FP64 or FP32 buffer); fin_op fused into the last smoothing step when possible
   double *zd = nullptr;
   float *zf = nullptr;
-  auto precondition = [&](int fin_op_fp64) -> bool {
+  std::vector<hipEvent_t> evs;  // timed outer applies (pairs)
+  bool done = false;
+
+  bool mixed() const { return spec.prec == GF_PREC_MIXED; }
+  double tol2() const { return spec.rtol * spec.rtol; }
+
+  void prepare(hipStream_t s) {
+    const Level &F = sp->fine();
+    const int ldb = w->ldb;
+    std::vector<double> sig(ldb, 1.0);
+    std::vector<float> sigf(ldb, 1.0f);
+    std::vector<int> node(ldb, 0);
+    std::vector<ColState> cs(ldb);
+    for (int c = 0; c < ldb; ++c) {
+      cs[c] = ColState{};
+      cs[c].done = (c < spec.ncols) ? 0 : 1;
+      if (c < spec.ncols) {
+        sig[c] = spec.col_sig[c];
+        node[c] = spec.col_node[c];
+      }
+      sigf[c] = (float)sig[c];
+    }
+    std::fill(w->active_h.begin(), w->active_h.end(), 0);
+    for (int c = 0; c < spec.ncols; ++c) w->active_h[c / CT] = 1;
+    w->sig64.upload(sig, s);
+    w->sig32.upload(sigf, s);
+    w->node.upload(node, s);
+    w->cs.upload(cs, s);
+    w->active.upload(w->active_h, s);
+    for (int li = 1; li < sp->nlev(); ++li) {
+      std::vector<double> ib(ldb, 1.0);
+      for (int c = 0; c < spec.ncols; ++c) ib[c] = spec.plan->invb[li][node[c]];
+      std::vector<float> ibf(ib.begin(), ib.end());
+      w->lw[li].invb64.upload(ib, s);
+      w->lw[li].invb32.upload(ibf, s);
+    }
+    HIPCHK(hipMemsetAsync(w->x.p, 0, (size_t)F.R * ldb * sizeof(double), s));
+  }
+
+  // z = B r; the FP64 V-cycle fuses r.z with fin_op into its last smoothing step
+  bool precondition(int fin_op_fp64, hipStream_t s) {
+    const int fi = sp->nlev() - 1;
     bool fused = false;
-    if (!mixed) {
-      zd = vcycle<double, double>(sp, w, spec, fi, w.r.p, nullptr, fin_op_fp64, &fused, s);
-    } else {
-      zf = vcycle<float, double>(sp, w, spec, fi, w.r.p, w.lw[fi].r32.p, -1, nullptr, s);
-    }
+    if (!mixed())
+      zd = vcycle<double, double>(sp, *w, spec, fi, w->r.p, nullptr, fin_op_fp64, &fused, s);
+    else
+      zf = vcycle<float, double>(sp, *w, spec, fi, w->r.p, w->lw[fi].r32.p, -1, nullptr, s);
     return fused;
-  };
-  auto outer_apply = [&]() {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (spec.flags & GF_FLAG_TIME_APPLY) {
-      int act = 0;
-      for (int t = 0; t < nt; ++t) act += w.active_h[t] ? 1 : 0;
-      res.apply_col_sum += (double)act * CT;
-      HIPCHK(hipEventCreate(&e0));
-      HIPCHK(hipEventCreate(&e1));
-      evs.push_back(e0);
-      evs.push_back(e1);
+  }
+
+  void start(hipStream_t s) {
+    const Level &F = sp->fine();
+    const int ldb = w->ldb, nt = w->ntiles;
+    Scratch sc = w->scratch();
+    reduce_dot<double, double>(F, w->r.p, w->r.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BB, tol2(), spec.max_iter,
+                               nullptr, s);
+    if (!precondition(OP_RZ0, s)) {
+      if (mixed())
+        reduce_dot<double, float>(F, w->r.p, zf, sc, ldb, nt, w->cs.p, w->active.p, OP_RZ0, tol2(), spec.max_iter,
+                                  nullptr, s);
+      else
+        reduce_dot<double, double>(F, w->r.p, zd, sc, ldb, nt, w->cs.p, w->active.p, OP_RZ0, tol2(),
+                                   spec.max_iter, nullptr, s);
     }
+    if (mixed())
+      convert_rows<float, double>(F, zf, w->p.p, ldb, nt, w->active.p, s);
+    else
+      convert_rows<double, double>(F, zd, w->p.p, ldb, nt, w->active.p, s);
+  }
+
+  // one CG iteration: q = A p (+ p.q -> alpha), x += alpha p, r -= alpha q (+ |r|^2 -> test),
+  // z = B r (+ r.z -> beta), p = z + beta p
+  void iterate(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    const Level &F = sp->fine();
+    const int ldb = w->ldb, nt = w->ntiles;
+    Scratch sc = w->scratch();
     EpiArgs<double> e;
     e.kind = EPI_STORE;
-    e.y = w.q.p;
+    e.y = w->q.p;
     e.dot = 1;
     e.op = OP_ALPHA;
-    apply_epi<double>(F, spec.kind, w.p.p, w.sig64.p, w.one64.p, e, sc, w.cs.p, w.active.p, ldb, nt, tol2,
+    apply_epi<double>(F, spec.kind, w->p.p, w->sig64.p, w->one64.p, e, sc, w->cs.p, w->active.p, ldb, nt, tol2(),
                       spec.max_iter, s, e0, e1);
-  };
-  // r = b - A 0 = b;  bb = |b|^2
-  reduce_dot<double, double>(F, w.r.p, w.r.p, sc, ldb, nt, w.cs.p, w.active.p, OP_BB, tol2, spec.max_iter, nullptr,
-                             s);
-  if (!precondition(OP_RZ0)) {
-    if (mixed)
-      reduce_dot<double, float>(F, w.r.p, zf, sc, ldb, nt, w.cs.p, w.active.p, OP_RZ0, tol2, spec.max_iter,
-                                nullptr, s);
-    else
-      reduce_dot<double, double>(F, w.r.p, zd, sc, ldb, nt, w.cs.p, w.active.p, OP_RZ0, tol2, spec.max_iter,
-                                 nullptr, s);
-  }
-  if (mixed)
-    convert_rows<float, double>(F, zf, w.p.p, ldb, nt, w.active.p, s);
-  else
-    convert_rows<double, double>(F, zd, w.p.p, ldb, nt, w.active.p, s);
-  const int check_every = 1;
-  for (int it = 0; it < spec.max_iter; ++it) {
-    outer_apply();
-    update_xr2(F, w.x.p, w.r.p, w.p.p, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, tol2, spec.max_iter, s);
-    if ((it + 1) % check_every == 0) {
-      HIPCHK(hipMemcpyAsync(w.active_h.data(), w.active.p, nt * sizeof(int), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      bool any = false;
-      for (int t = 0; t < nt; ++t) any = any || w.active_h[t];
-      if (!any) break;
-    }
-    if (mixed) {
-      precondition(-1);
-      reduce_dot2<double, float, double>(F, w.r.p, zf, w.q.p, sc, ldb, nt, w.cs.p, w.active.p, OP_BETA_FLEX, tol2,
-                                         spec.max_iter, nullptr, s);
-      update_p2<float>(F, w.p.p, zf, w.cs.p, ldb, nt, w.active.p, s);
+    update_xr2(F, w->x.p, w->r.p, w->p.p, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, tol2(), spec.max_iter, s);
+    if (mixed()) {
+      precondition(-1, s);
+      reduce_dot2<double, float, double>(F, w->r.p, zf, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BETA_FLEX,
+                                         tol2(), spec.max_iter, nullptr, s);
+      update_p2<float>(F, w->p.p, zf, w->cs.p, ldb, nt, w->active.p, s);
     } else {
-      if (!precondition(OP_BETA))
-        reduce_dot<double, double>(F, w.r.p, zd, sc, ldb, nt, w.cs.p, w.active.p, OP_BETA, tol2, spec.max_iter,
-                                   nullptr, s);
-      update_p2<double>(F, w.p.p, zd, w.cs.p, ldb, nt, w.active.p, s);
+      if (!precondition(OP_BETA, s))
+        reduce_dot<double, double>(F, w->r.p, zd, sc, ldb, nt, w->cs.p, w->active.p, OP_BETA, tol2(),
+                                   spec.max_iter, nullptr, s);
+      update_p2<double>(F, w->p.p, zd, w->cs.p, ldb, nt, w->active.p, s);
     }
   }
-  HIPCHK(hipStreamSynchronize(s));
-  for (size_t i = 0; i + 1 < evs.size(); i += 2) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
-    res.apply_ms += ms;
-    res.apply_launches += 1;
-    (void)hipEventDestroy(evs[i]);
-    (void)hipEventDestroy(evs[i + 1]);
+
+  void new_event_pair(hipEvent_t *e0, hipEvent_t *e1) {
+    *e0 = *e1 = nullptr;
+    if (!(spec.flags & GF_FLAG_TIME_APPLY)) return;
+    HIPCHK(hipEventCreate(e0));
+    HIPCHK(hipEventCreate(e1));
+    evs.push_back(*e0);
+    evs.push_back(*e1);
   }
-  std::vector<ColState> out(ldb);
-  HIPCHK(hipMemcpy(out.data(), w.cs.p, ldb * sizeof(ColState), hipMemcpyDeviceToHost));
-  for (int c = 0; c < spec.ncols; ++c) {
-    res.max_it = std::max(res.max_it, out[c].it);
-    const double rel = out[c].bb > 0 ? std::sqrt(out[c].rr / out[c].bb) : 0.0;
-    res.max_rel = std::max(res.max_rel, rel);
-    res.flags |= out[c].flag;
-    if (!out[c].done) res.flags |= 1;
+
+  // read the timed pairs recorded since the last call (the stream is synchronised)
+  void harvest_events(int active_tiles) {
+    for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+      res.apply_ms += ms;
+      res.apply_launches += 1;
+      res.apply_col_sum += (double)active_tiles * CT;
+    }
   }
-  return res;
+
+  int active_tiles() const {
+    int a = 0;
+    for (int t = 0; t < w->ntiles; ++t) a += w->active_h[t] ? 1 : 0;
+    return a;
+  }
+
+  void read_active(hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(w->active_h.data(), w->active.p, w->ntiles * sizeof(int), hipMemcpyDeviceToHost, s));
+  }
+
+  void collect() {
+    for (auto e : evs) (void)hipEventDestroy(e);
+    evs.clear();
+    const int ldb = w->ldb;
+    std::vector<ColState> out(ldb);
+    HIPCHK(hipMemcpy(out.data(), w->cs.p, ldb * sizeof(ColState), hipMemcpyDeviceToHost));
+    for (int c = 0; c < spec.ncols; ++c) {
+      res.max_it = std::max(res.max_it, out[c].it);
+      const double rel = out[c].bb > 0 ? std::sqrt(out[c].rr / out[c].bb) : 0.0;
+      res.max_rel = std::max(res.max_rel, rel);
+      res.flags |= out[c].flag;
+      if (!out[c].done) res.flags |= 1;
+    }
+  }
+};
+
+// side streams of a context for the parallel branches of a multi-problem graph (default priority)
+static std::vector<hipStream_t> &side_streams(gf_context *ctx, size_t n) {
+  static std::map<gf_context *, std::vector<hipStream_t>> m;
+  auto &v = m[ctx];
+  while (v.size() < n) {
+    hipStream_t st;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    v.push_back(st);
+  }
+  return v;
+}
+
+// Runs the CG iterations of all batches together.  The first iteration is enqueued eagerly (it
+// also runs the launch-shape autotuner); then one iteration of every batch is captured into a single
+// HIP graph -- one branch per batch, forked from and joined back into the context stream -- and the
+// graph is launched until every system of every batch has converged (active tiles are read back after
+// each launch; converged column tiles exit at the top of every kernel).
+static void solve_all(gf_context *ctx, std::vector<BatchSolve *> &items, bool use_graph) {
+  hipStream_t s = ctx->stream;
+  for (auto *it : items) it->prepare(s);
+  for (auto *it : items) it->start(s);
+  int max_iter = 0;
+  for (auto *it : items) max_iter = std::max(max_iter, it->spec.max_iter);
+  auto all_done = [&]() {
+    bool any = false;
+    std::vector<int> prev(items.size());
+    for (size_t i = 0; i < items.size(); ++i) {
+      prev[i] = items[i]->active_tiles();  // tiles the operator launches just processed
+      items[i]->read_active(s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    for (size_t i = 0; i < items.size(); ++i) items[i]->harvest_events(prev[i]);
+    for (auto *it : items)
+      for (int t = 0; t < it->w->ntiles; ++t) any = any || it->w->active_h[t];
+    return !any;
+  };
+  // eager first iteration
+  for (auto *it : items) {
+    hipEvent_t e0, e1;
+    it->new_event_pair(&e0, &e1);
+    it->iterate(s, e0, e1);
+  }
+  if (all_done() || max_iter <= 1) {
+    for (auto *it : items) it->collect();
+    return;
+  }
+  for (auto *it : items) {
+    for (auto e : it->evs) (void)hipEventDestroy(e);
+    it->evs.clear();
+  }
+  if (!use_graph) {
+    for (int k = 1; k < max_iter; ++k) {
+      for (auto *it : items) {
+        hipEvent_t e0, e1;
+        it->new_event_pair(&e0, &e1);
+        it->iterate(s, e0, e1);
+      }
+      const bool fin = all_done();
+      for (auto *it : items) {
+        for (auto e : it->evs) (void)hipEventDestroy(e);
+        it->evs.clear();
+      }
+      if (fin) break;
+    }
+    for (auto *it : items) it->collect();
+    return;
+  }
+  // capture one iteration of every batch
+  std::vector<hipEvent_t> evpairs(2 * items.size(), nullptr);
+  for (size_t i = 0; i < items.size(); ++i) items[i]->new_event_pair(&evpairs[2 * i], &evpairs[2 * i + 1]);
+  std::vector<hipEvent_t> joins(items.size());
+  hipEvent_t fork;
+  HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  for (auto &j : joins) HIPCHK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+  // capture on a side stream (the context stream may be the null stream, which cannot capture);
+  // the graph is launched on the context stream, after all of its earlier work
+  std::vector<hipStream_t> &side = side_streams(ctx, items.size() + 1);
+  hipStream_t cap = side[0];
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+  try {
+    if (items.size() == 1) {
+      items[0]->iterate(cap, evpairs[0], evpairs[1]);
+    } else {
+      HIPCHK(hipEventRecord(fork, cap));
+      for (size_t i = 0; i < items.size(); ++i) {
+        HIPCHK(hipStreamWaitEvent(side[i + 1], fork, 0));
+        items[i]->iterate(side[i + 1], evpairs[2 * i], evpairs[2 * i + 1]);
+        HIPCHK(hipEventRecord(joins[i], side[i + 1]));
+        HIPCHK(hipStreamWaitEvent(cap, joins[i], 0));
+      }
+    }
+  } catch (...) {
+    hipGraph_t g2 = nullptr;
+    (void)hipStreamEndCapture(cap, &g2);
+    if (g2) (void)hipGraphDestroy(g2);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(cap, &graph));
+  HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  for (int k = 1; k < max_iter; ++k) {
+    HIPCHK(hipGraphLaunch(exec, s));
+    if (all_done()) break;
+  }
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  (void)hipEventDestroy(fork);
+  for (auto j : joins) (void)hipEventDestroy(j);
+  for (auto *it : items) it->collect();
+}
+
+static SolveResult solve_batch(gf_space *sp, Workspace &w, const SolveSpec &spec) {
+  // per-launch HIP events need the eager path (events recorded inside a graph are not timed)
+  const bool use_graph = !(spec.flags & (GF_FLAG_NO_GRAPH | GF_FLAG_TIME_APPLY));
+  BatchSolve b;
+  b.sp = sp;
+  b.w = &w;
+  b.spec = spec;
+  std::vector<BatchSolve *> items{&b};
+  solve_all(sp->ctx, items, use_graph);
+  return b.res;
 }
 
 }  // namespace gf

@@ -33,6 +33,7 @@ GF_HOST, GF_DEVICE = 0, 1
 GF_APPLY_STENCIL, GF_APPLY_SUMFACT = 0, 1
 GF_PREC_FP64, GF_PREC_MIXED = 0, 1
 GF_FLAG_TIME_APPLY = 1
+GF_FLAG_NO_GRAPH = 2
 STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ENOMEM", 3: "GF_EDEVICE", 4: "GF_ENOCONV",
                 5: "GF_EBREAKDOWN", 6: "GF_EUNSUPPORTED"}
 

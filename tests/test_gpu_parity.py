@@ -120,6 +120,16 @@ def test_sample_split_and_precision(ctx, beta, prec):
     assert mrel(d, u, ref) <= 1e-10
 
 
+def test_sample_eager_matches_graph(ctx):
+    """The graph-replayed iteration loop and the eagerly enqueued one give identical fields."""
+    sp, d = space(ctx, 2, 3), disc(2, 3)
+    b = noise.load(d, inputs.noise_vectors([7, 8], inputs.noise_length(2, 3)))
+    u1, s1 = sp.sample(3.0, 1.6, b, h=0.4, k_minus=12, k_plus=12, rtol=1e-12)
+    u2, s2 = sp.sample(3.0, 1.6, b, h=0.4, k_minus=12, k_plus=12, rtol=1e-12, flags=g.GF_FLAG_NO_GRAPH)
+    assert s1["max_iters"] == s2["max_iters"]
+    assert np.array_equal(u1, u2)
+
+
 def test_sample_sumfact_operator(ctx):
     sp, d = space(ctx, 3, 2), disc(3, 2)
     b = noise.load(d, inputs.noise_vectors([1], inputs.noise_length(3, 2)))
