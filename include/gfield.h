@@ -165,6 +165,28 @@ gf_status gf_sample(gf_space *space, double kappa, double beta, const gf_quad_ru
                     const gf_solve_opts *opts, int32_t nsamp, const double *b, double *u, int32_t mem,
                     gf_solve_stats *stats);
 
+/* One request of gf_sample_batch: the arguments of one gf_sample call.  Spaces may differ in degree
+ * and level but must belong to the context of the batch; b and u as in gf_sample, all of the same
+ * memory kind. */
+typedef struct {
+  gf_space *space;
+  double kappa, beta;
+  gf_quad_rule rule;
+  int32_t nsamp;
+  const double *b;
+  double *u;
+} gf_batch_item;
+
+/* Several gf_sample requests solved together (Sec. 3.4 for each request).  The integer solves of
+ * all requests advance step by step (step i batches every request with floor(beta) >= i); then the
+ * sinc-node systems of all requests (nodes x samples each) iterate together, one CG iteration of
+ * every request captured as one HIP graph with one branch per request.  Each request's u equals
+ * what gf_sample returns for it alone: the same kernels run on the same columns in the same order.
+ * 1 <= nitems <= 4096.  Errors as gf_sample; validation of every request precedes any work.  stats
+ * aggregates over all requests (n_systems summed, max_iters and max_rel_resid maxima). */
+gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *items,
+                          const gf_solve_opts *opts, int32_t mem, gf_solve_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

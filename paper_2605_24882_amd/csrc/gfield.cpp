@@ -268,7 +268,7 @@ struct Workspace {
 }  // namespace gf
 
 struct gf_workspaces {
-  std::map<std::pair<int, int>, std::unique_ptr<gf::Workspace>> m;
+  std::map<std::tuple<int, int, int>, std::unique_ptr<gf::Workspace>> m;
 };
 
 namespace gf {
@@ -284,10 +284,11 @@ static size_t scratch_slots(gf_space *sp, int ldb, int ntiles) {
   return slots;
 }
 
-static Workspace &get_workspace(gf_space *sp, int ldb, int prec) {
+// slot separates the workspaces of batches that run together on the same space
+static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
   auto &reg = ws_registry()[sp];
   if (!reg) reg.reset(new gf_workspaces());
-  auto key = std::make_pair(ldb, prec);
+  auto key = std::make_tuple(ldb, prec, slot);
   auto it = reg->m.find(key);
   if (it != reg->m.end()) return *it->second;
   std::unique_ptr<Workspace> w(new Workspace());
@@ -1164,138 +1165,255 @@ static void check_common(gf_space *sp, double kappa, double beta, const gf_quad_
   if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
 }
 
+}  // extern "C"
+
+namespace gf {
+
+// One sampling request: a space, kappa, beta, a node rule and nsamp loads.
+struct SampleItem {
+  gf_space *sp = nullptr;
+  double kappa = 0, beta = 0;
+  gf_quad_rule rule{};
+  int nsamp = 0;
+  const double *b = nullptr;
+  double *u = nullptr;
+  // derived
+  int n = 0;
+  double bf = 0;
+  std::vector<double> node_sig, omega;
+  const Plan *chain_plan = nullptr, *frac_plan = nullptr;
+  InArray bin;
+  OutArray uout;
+  DBuf<double> rloc;
+  Workspace *wc = nullptr, *wf = nullptr;
+};
+
+// All requests advance together: the integer chains step by step (step i batches every request with
+// n >= i), then the sinc-node batches of all requests in one graph.  Fields are summed per request.
+static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_solve_opts *opts, int32_t mem,
+                      gf_solve_stats *stats) {
+  hipStream_t s = ctx->stream;
+  SolveSpec base;
+  base.prec = opts->precision;
+  base.kind = opts->apply_kind;
+  base.cheb = opts->cheb_degree > 0 ? opts->cheb_degree : 2;
+  base.rtol = opts->rtol;
+  base.max_iter = opts->max_iter;
+  base.flags = opts->flags;
+  const bool any_frac = std::any_of(items.begin(), items.end(), [](const SampleItem &it) {
+    return it.beta - std::floor(it.beta) > 0.0;
+  });
+  // plans (their set-up is reported separately)
+  double setup_ms = 0.0;
+  {
+    auto c0 = std::chrono::steady_clock::now();
+    bool built = false;
+    for (auto &it : items) {
+      const size_t np = it.sp->plans.size();
+      it.n = (int)std::floor(it.beta);
+      it.bf = it.beta - it.n;
+      if (it.n > 0) it.chain_plan = &get_plan(it.sp, std::vector<double>{it.kappa * it.kappa});
+      if (it.bf > 0.0) {
+        for (int k = -it.rule.k_minus; k <= it.rule.k_plus; ++k) {
+          const double t = std::exp(-2.0 * k * it.rule.h);
+          it.node_sig.push_back(it.kappa * it.kappa + t);
+          it.omega.push_back(2.0 * it.rule.h * std::sin(M_PI * it.bf) / M_PI * std::pow(t, 1.0 - it.bf));
+        }
+        it.frac_plan = &get_plan(it.sp, it.node_sig);
+      }
+      built = built || it.sp->plans.size() != np;
+    }
+    if (built) setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+  }
+  for (auto &it : items) {
+    const size_t nv = (size_t)it.nsamp * it.sp->fine().N;
+    stage_in(it.bin, it.b, nv, mem, s);
+    stage_out(it.uout, it.u, nv, mem);
+  }
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  HIPCHK(hipEventRecord(t0, s));
+  int max_it = 0, flags = 0, nsys = 0;
+  double max_rel = 0.0, apply_ms = 0.0, apply_col_sum = 0.0;
+  int apply_launches = 0, apply_rows = 0;
+  auto account = [&](const BatchSolve &b) {
+    max_it = std::max(max_it, b.res.max_it);
+    max_rel = std::max(max_rel, b.res.max_rel);
+    flags |= b.res.flags;
+    nsys += b.spec.ncols;
+    apply_ms += b.res.apply_ms;
+    apply_launches += b.res.apply_launches;
+    apply_col_sum += b.res.apply_col_sum;
+    if (b.res.apply_launches) apply_rows = 6 * b.sp->fine().n1 * b.sp->fine().n1;
+  };
+  const bool use_graph = !(base.flags & (GF_FLAG_NO_GRAPH | GF_FLAG_TIME_APPLY));
+  // ---- integer chains: A w_1 = b, A w_i = M w_{i-1}
+  int max_n = 0;
+  for (auto &it : items) max_n = std::max(max_n, it.n);
+  for (size_t idx = 0; idx < items.size(); ++idx) {
+    auto &it = items[idx];
+    if (it.n == 0) continue;
+    const Level &F = it.sp->fine();
+    const int ldc = round_up(it.nsamp, CT);
+    it.wc = &get_workspace(it.sp, ldc, base.prec, (int)idx);
+    global_to_local(F, it.wc->r.p, it.bin.p, it.nsamp, ldc, s);
+  }
+  for (int i = 1; i <= max_n; ++i) {
+    std::vector<BatchSolve> bs;
+    bs.reserve(items.size());
+    for (auto &it : items) {
+      if (it.n < i) continue;
+      BatchSolve b;
+      b.sp = it.sp;
+      b.w = it.wc;
+      b.spec = base;
+      if (any_frac) b.spec.flags &= ~GF_FLAG_TIME_APPLY;  // the node batches are timed instead
+      b.spec.ncols = it.nsamp;
+      b.spec.col_sig.assign(it.nsamp, it.kappa * it.kappa);
+      b.spec.col_node.assign(it.nsamp, 0);
+      b.spec.plan = it.chain_plan;
+      bs.push_back(std::move(b));
+    }
+    std::vector<BatchSolve *> ptrs;
+    for (auto &b : bs) ptrs.push_back(&b);
+    solve_all(ctx, ptrs, use_graph);
+    for (auto &b : bs) account(b);
+    for (auto &it : items) {
+      if (it.n < i) continue;
+      const Level &F = it.sp->fine();
+      const int ldc = it.wc->ldb;
+      if (i < it.n || it.bf > 0.0)  // next right-hand side M w_i (assembled)
+        apply_level<double>(F, GF_APPLY_STENCIL, it.wc->x.p, it.wc->r.p, it.wc->one64.p, it.wc->zero64.p, ldc,
+                            ldc / CT, nullptr, s);
+      if (i == it.n && it.bf == 0.0) local_to_global(F, it.uout.p, it.wc->x.p, it.nsamp, 0, ldc, s);
+    }
+  }
+  // ---- sinc nodes: all nodes x samples of every request, one batch per request, one graph
+  {
+    std::vector<BatchSolve> bs;
+    std::vector<SampleItem *> owners;
+    bs.reserve(items.size());
+    for (size_t idx = 0; idx < items.size(); ++idx) {
+      auto &it = items[idx];
+      if (it.bf <= 0.0) continue;
+      const Level &F = it.sp->fine();
+      const int K = (int)it.node_sig.size();
+      const int ncols = K * it.nsamp;
+      const int ldc = round_up(it.nsamp, CT);
+      const int ldf = round_up(ncols, CT);
+      const double *rsrc;
+      int ldr;
+      if (it.n > 0) {
+        rsrc = it.wc->r.p;
+        ldr = it.wc->ldb;
+      } else {
+        it.rloc.alloc((size_t)F.R * ldc);
+        global_to_local(F, it.rloc.p, it.bin.p, it.nsamp, ldc, s);
+        rsrc = it.rloc.p;
+        ldr = ldc;
+      }
+      it.wf = &get_workspace(it.sp, ldf, base.prec, 1000 + (int)idx);
+      replicate_cols(F, it.wf->r.p, ldf, rsrc, ldr, it.nsamp, K, s);
+      BatchSolve b;
+      b.sp = it.sp;
+      b.w = it.wf;
+      b.spec = base;
+      b.spec.ncols = ncols;
+      b.spec.col_sig.resize(ncols);
+      b.spec.col_node.resize(ncols);
+      for (int k = 0; k < K; ++k)
+        for (int sm = 0; sm < it.nsamp; ++sm) {
+          b.spec.col_sig[k * it.nsamp + sm] = it.node_sig[k];
+          b.spec.col_node[k * it.nsamp + sm] = k;
+        }
+      b.spec.plan = it.frac_plan;
+      bs.push_back(std::move(b));
+      owners.push_back(&it);
+    }
+    if (!bs.empty()) {
+      std::vector<BatchSolve *> ptrs;
+      for (auto &b : bs) ptrs.push_back(&b);
+      solve_all(ctx, ptrs, use_graph);
+      for (size_t q = 0; q < bs.size(); ++q) {
+        account(bs[q]);
+        SampleItem &it = *owners[q];
+        DBuf<double> om;
+        om.upload(it.omega, s);
+        quadrature_sum(it.sp->fine(), it.uout.p, it.wf->x.p, om.p, (int)it.omega.size(), it.nsamp, it.wf->ldb, s);
+        HIPCHK(hipStreamSynchronize(s));
+      }
+    }
+  }
+  HIPCHK(hipEventRecord(t1, s));
+  for (auto &it : items) finish_out(it.uout, s);
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (stats) {
+    stats->n_systems = nsys;
+    stats->max_iters = max_it;
+    stats->max_rel_resid = max_rel;
+    stats->setup_ms = setup_ms;
+    stats->solve_ms = ms;
+    stats->apply_ms = apply_ms;
+    stats->apply_launches = apply_launches;
+    stats->apply_rows = apply_rows;
+    stats->apply_col_sum = apply_col_sum;
+  }
+  if (flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
+  if (flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
+}
+
+}  // namespace gf
+
+extern "C" {
+
 gf_status gf_sample(gf_space *sp, double kappa, double beta, const gf_quad_rule *rule, const gf_solve_opts *opts,
                     int32_t nsamp, const double *b, double *u, int32_t mem, gf_solve_stats *stats) {
   return guarded([&] {
     check_common(sp, kappa, beta, rule, opts, nsamp, mem);
     if (!b || !u) fail(GF_EINVAL, "null argument");
-    HIPCHK(hipSetDevice(sp->ctx->device));
-    hipStream_t s = sp->ctx->stream;
-    const Level &F = sp->fine();
-    const int n = (int)std::floor(beta);
-    const double bf = beta - n;
     const int K = rule->k_minus + rule->k_plus + 1;
-    if (bf > 0.0 && (int64_t)K * nsamp > (int64_t)1 << 20) fail(GF_EINVAL, "too many systems in one batch");
-    const size_t nv = (size_t)nsamp * F.N;
-    InArray bin;
-    stage_in(bin, b, nv, mem, s);
-    OutArray uout;
-    stage_out(uout, u, nv, mem);
-    hipEvent_t t0, t1;
-    HIPCHK(hipEventCreate(&t0));
-    HIPCHK(hipEventCreate(&t1));
-    SolveSpec base;
-    base.prec = opts->precision;
-    base.kind = opts->apply_kind;
-    base.cheb = opts->cheb_degree > 0 ? opts->cheb_degree : 2;
-    base.rtol = opts->rtol;
-    base.max_iter = opts->max_iter;
-    base.flags = opts->flags;
-    double setup_ms = 0.0;
-    int max_it = 0, flags = 0, nsys = 0;
-    double max_rel = 0.0, apply_ms = 0.0, apply_col_sum = 0.0;
-    int apply_launches = 0;
-    auto account = [&](const SolveResult &r, int ncols) {
-      max_it = std::max(max_it, r.max_it);
-      max_rel = std::max(max_rel, r.max_rel);
-      flags |= r.flags;
-      nsys += ncols;
-      apply_ms += r.apply_ms;
-      apply_launches += r.apply_launches;
-      apply_col_sum += r.apply_col_sum;
-    };
-    // plans first (their set-up is reported separately from the solve time)
-    const Plan *chain_plan = nullptr, *frac_plan = nullptr;
-    std::vector<double> node_sig;
-    std::vector<double> omega;
-    {
-      const size_t np = sp->plans.size();
-      auto c0 = std::chrono::steady_clock::now();
-      if (n > 0) chain_plan = &get_plan(sp, std::vector<double>{kappa * kappa});
-      if (bf > 0.0) {
-        for (int k = -rule->k_minus; k <= rule->k_plus; ++k) {
-          const double t = std::exp(-2.0 * k * rule->h);
-          node_sig.push_back(kappa * kappa + t);
-          omega.push_back(2.0 * rule->h * std::sin(M_PI * bf) / M_PI * std::pow(t, 1.0 - bf));
-        }
-        frac_plan = &get_plan(sp, node_sig);
-      }
-      if (sp->plans.size() != np)
-        setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+    if (beta - std::floor(beta) > 0.0 && (int64_t)K * nsamp > (int64_t)1 << 20)
+      fail(GF_EINVAL, "too many systems in one batch");
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    std::vector<SampleItem> items(1);
+    items[0].sp = sp;
+    items[0].kappa = kappa;
+    items[0].beta = beta;
+    items[0].rule = *rule;
+    items[0].nsamp = nsamp;
+    items[0].b = b;
+    items[0].u = u;
+    run_items(sp->ctx, items, opts, mem, stats);
+  });
+}
+
+gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *items_in, const gf_solve_opts *opts,
+                          int32_t mem, gf_solve_stats *stats) {
+  return guarded([&] {
+    if (!ctx || !items_in || !opts) fail(GF_EINVAL, "null argument");
+    if (nitems < 1 || nitems > 4096) fail(GF_EINVAL, "nitems must be in 1..4096");
+    HIPCHK(hipSetDevice(ctx->device));
+    std::vector<SampleItem> items(nitems);
+    for (int i = 0; i < nitems; ++i) {
+      const gf_batch_item &in = items_in[i];
+      check_common(in.space, in.kappa, in.beta, &in.rule, opts, in.nsamp, mem);
+      if (!in.b || !in.u) fail(GF_EINVAL, "null load or field pointer in a batch item");
+      if (in.space->ctx != ctx) fail(GF_EINVAL, "batch item space belongs to another context");
+      const int K = in.rule.k_minus + in.rule.k_plus + 1;
+      if ((int64_t)K * in.nsamp > (int64_t)1 << 20) fail(GF_EINVAL, "too many systems in one batch item");
+      items[i].sp = in.space;
+      items[i].kappa = in.kappa;
+      items[i].beta = in.beta;
+      items[i].rule = in.rule;
+      items[i].nsamp = in.nsamp;
+      items[i].b = in.b;
+      items[i].u = in.u;
     }
-    HIPCHK(hipEventRecord(t0, s));
-    const int ldc = round_up(nsamp, CT);
-    // ---- integer chain: A w_1 = b, A w_i = M w_{i-1}
-    DBuf<double> rloc;  // right-hand side of the fractional part, [R][ldc]
-    if (n > 0) {
-      Workspace &w = get_workspace(sp, ldc, base.prec);
-      global_to_local(F, w.r.p, bin.p, nsamp, ldc, s);
-      SolveSpec spec = base;
-      if (bf > 0.0) spec.flags &= ~GF_FLAG_TIME_APPLY;  // the node batch is timed instead
-      spec.ncols = nsamp;
-      spec.col_sig.assign(nsamp, kappa * kappa);
-      spec.col_node.assign(nsamp, 0);
-      spec.plan = chain_plan;
-      for (int i = 1; i <= n; ++i) {
-        SolveResult r = solve_batch(sp, w, spec);
-        account(r, nsamp);
-        if (i < n || bf > 0.0) {
-          // next right-hand side M w_i (assembled)
-          apply_level<double>(F, GF_APPLY_STENCIL, w.x.p, w.r.p, w.one64.p, w.zero64.p, ldc, ldc / CT, nullptr, s);
-        }
-      }
-      if (bf == 0.0) {
-        local_to_global(F, uout.p, w.x.p, nsamp, 0, ldc, s);
-      } else {
-        rloc.alloc((size_t)F.R * ldc);
-        HIPCHK(hipMemcpyAsync(rloc.p, w.r.p, (size_t)F.R * ldc * sizeof(double), hipMemcpyDeviceToDevice, s));
-      }
-    } else {
-      rloc.alloc((size_t)F.R * ldc);
-      global_to_local(F, rloc.p, bin.p, nsamp, ldc, s);
-    }
-    // ---- fractional part: all nodes x samples in one batch
-    if (bf > 0.0) {
-      const int ncols = K * nsamp;
-      const int ldf = round_up(ncols, CT);
-      Workspace &w = get_workspace(sp, ldf, base.prec);
-      replicate_cols(F, w.r.p, ldf, rloc.p, ldc, nsamp, K, s);
-      SolveSpec spec = base;
-      spec.ncols = ncols;
-      spec.col_sig.resize(ncols);
-      spec.col_node.resize(ncols);
-      for (int k = 0; k < K; ++k)
-        for (int sm = 0; sm < nsamp; ++sm) {
-          spec.col_sig[k * nsamp + sm] = node_sig[k];
-          spec.col_node[k * nsamp + sm] = k;
-        }
-      spec.plan = frac_plan;
-      SolveResult r = solve_batch(sp, w, spec);
-      account(r, ncols);
-      DBuf<double> om;
-      om.upload(omega, s);
-      quadrature_sum(F, uout.p, w.x.p, om.p, K, nsamp, ldf, s);
-      HIPCHK(hipStreamSynchronize(s));
-    }
-    HIPCHK(hipEventRecord(t1, s));
-    finish_out(uout, s);
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    if (stats) {
-      stats->n_systems = nsys;
-      stats->max_iters = max_it;
-      stats->max_rel_resid = max_rel;
-      stats->setup_ms = setup_ms;
-      stats->solve_ms = ms;
-      stats->apply_ms = apply_ms;
-      stats->apply_launches = apply_launches;
-      stats->apply_rows = 6 * F.n1 * F.n1;
-      stats->apply_col_sum = apply_col_sum;
-    }
-    if (flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
-    if (flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
+    run_items(ctx, items, opts, mem, stats);
   });
 }
 

@@ -57,6 +57,11 @@ class SolveStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("space", ctypes.c_void_p), ("kappa", ctypes.c_double), ("beta", ctypes.c_double),
+                ("rule", QuadRule), ("nsamp", ctypes.c_int32), ("b", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -78,6 +83,8 @@ _SIGS = {
     "gf_white_noise": (_i32, [_vp, _i32, _vp, _vp, _i32]),
     "gf_sample": (_i32, [_vp, _dbl, _dbl, ctypes.POINTER(QuadRule), ctypes.POINTER(SolveOpts), _i32, _vp, _vp,
                          _i32, ctypes.POINTER(SolveStats)]),
+    "gf_sample_batch": (_i32, [_vp, _i32, ctypes.POINTER(BatchItem), ctypes.POINTER(SolveOpts), _i32,
+                               ctypes.POINTER(SolveStats)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -245,3 +252,35 @@ class Space:
             self.close()
         except Exception:
             pass
+
+
+def sample_batch(ctx, requests, precision=GF_PREC_FP64, rtol=1e-10, max_iter=500, cheb_degree=0,
+                 apply_kind=GF_APPLY_STENCIL, flags=0):
+    """Several sampling requests solved together.
+
+    requests: sequence of dicts with keys space, kappa, beta, b and optionally h, k_minus, k_plus
+    (defaults 0.4, 20, 20).  All loads must be of one kind (NumPy or CUDA tensors).
+    Returns (list of u, stats dict)."""
+    if not requests:
+        raise ValueError("no requests")
+    items = (BatchItem * len(requests))()
+    keep, outs, mem0 = [], [], None
+    for i, r in enumerate(requests):
+        sp, b = r["space"], r["b"]
+        nsamp = 1 if len(b.shape) == 1 else b.shape[0]
+        pb, mem, kb = _marshal_in(b, nsamp * sp.ndofs)
+        if mem0 is None:
+            mem0 = mem
+        elif mem != mem0:
+            raise TypeError("all loads of a batch must be of one memory kind")
+        u = _alloc_like(b, (nsamp, sp.ndofs))
+        keep.append(kb)
+        outs.append(u)
+        items[i] = BatchItem(sp.h, r["kappa"], r["beta"],
+                             QuadRule(r.get("h", 0.4), r.get("k_minus", 20), r.get("k_plus", 20)), nsamp, pb,
+                             _ptr(u))
+    opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
+    st = SolveStats()
+    status = _lib.gf_sample_batch(ctx.h, len(requests), items, ctypes.byref(opts), mem0, ctypes.byref(st))
+    _check(status, st.as_dict())
+    return outs, st.as_dict()

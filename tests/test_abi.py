@@ -57,6 +57,8 @@ def test_null_handles_are_einval():
     st = g.SolveStats()
     assert g._lib.gf_sample(None, 4.0, 0.75, ctypes.byref(rule), ctypes.byref(opts), 1, x.ctypes.data,
                             x.ctypes.data, g.GF_HOST, ctypes.byref(st)) == g.GF_EINVAL
+    items = (g.BatchItem * 1)()
+    assert g._lib.gf_sample_batch(None, 1, items, ctypes.byref(opts), g.GF_HOST, ctypes.byref(st)) == g.GF_EINVAL
 
 
 def test_locate_matches_oracle_inversion():

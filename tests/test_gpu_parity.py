@@ -158,3 +158,42 @@ def test_c2_mesh_subset(ctx):
     u, st = sp.sample(10.0, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-12)
     ref = _oracle_u(d, 10.0, 1.6, 0.4, 20, b)
     assert mrel(d, u, ref) <= 1e-10
+
+
+BATCH = [
+    # (p, level, kappa, beta, seeds): perturbed sphere, uneven degrees and levels, chains of
+    # different lengths (beta 0.9, 1.6, 2.3) and two requests on one space
+    (2, 2, 5.0, 0.9, [0, 18]),
+    (3, 3, 10.0, 0.9, [1]),
+    (2, 3, 20.0, 0.9, [2, 20]),
+    (3, 2, 5.0, 1.6, [3]),
+    (2, 2, 10.0, 2.3, [4]),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sample_batch_matches_oracle_and_single(ctx, prec):
+    reqs, refs = [], []
+    for p, j, kappa, beta, seeds in BATCH:
+        sp, d = space(ctx, p, j, True), disc(p, j, True)
+        b = noise.load(d, inputs.noise_vectors(seeds, inputs.noise_length(p, j)))
+        reqs.append(dict(space=sp, kappa=kappa, beta=beta, b=b, h=0.4, k_minus=12, k_plus=12))
+        refs.append(_oracle_u(d, kappa, beta, 0.4, 12, b))
+    us, st = g.sample_batch(ctx, reqs, precision=prec, rtol=1e-13)
+    assert st["n_systems"] == sum(len(s) * (25 + math.floor(be)) for _, _, _, be, s in BATCH)
+    for (p, j, kappa, beta, seeds), r, u, ref in zip(BATCH, reqs, us, refs):
+        assert mrel(disc(p, j, True), u, ref) <= 1e-10, (p, j, kappa, beta)
+        u1, _ = r["space"].sample(kappa, beta, r["b"], h=0.4, k_minus=12, k_plus=12, precision=prec, rtol=1e-13)
+        assert np.array_equal(u, u1), (p, j, kappa, beta)
+
+
+def test_sample_batch_device_arrays(ctx):
+    import torch
+    sps = [space(ctx, 2, 2, True), space(ctx, 3, 2, True)]
+    bs = [torch.from_numpy(noise.load(disc(2, 2, True), inputs.noise_vectors([5], inputs.noise_length(2, 2)))).cuda(),
+          torch.from_numpy(noise.load(disc(3, 2, True), inputs.noise_vectors([6, 7], inputs.noise_length(3, 2)))).cuda()]
+    reqs = [dict(space=s, kappa=6.0, beta=0.9, b=b, k_minus=10, k_plus=10) for s, b in zip(sps, bs)]
+    us, _ = g.sample_batch(ctx, reqs, rtol=1e-12)
+    for s, b, u in zip(sps, bs, us):
+        u1, _ = s.sample(6.0, 0.9, b, k_minus=10, k_plus=10, rtol=1e-12)
+        assert torch.equal(u, u1)
