@@ -13,6 +13,9 @@ application of the outer CG, timed with HIP events around every launch during th
 The CPU baseline is the FP64 oracle on one of the 64 loads (single thread).
 """
 import argparse
+import collections
+import csv
+import hashlib
 import json
 import math
 import os
@@ -41,6 +44,80 @@ def workload_name(cfg):
     return (f"{surf}, 6 patches, degree {p}, {2**lev}x{2**lev} elements/patch ({N} DOF); kappa={kappa:g}, "
             f"beta={beta:g} ({nint} integer solve(s) + {2*k+1} sinc nodes, h={h:g}); {nsamp} samples; "
             f"{'FP64' if prec == 0 else 'FP32 V-cycle / FP64 CG'} MG-PCG to rel. residual {rtol:g}")
+
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_24882_amd", "csrc", "k_fused.hip")
+
+
+def traffic_file(config):
+    return os.path.join(ROOT, "profiles", f"traffic_apply_outer_{config}.json")
+
+
+def source_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _outer_apply_rows(path, p, value_key):
+    """(grid, value) of every outer-CG operator launch of the node batch in a rocprofv3 csv:
+    k_apply_fused<double, p, *, EPI_STORE, dot> at the largest grid of that instance."""
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0]
+        if name.startswith(f"void gf::k_apply_fused<double, {p}, ") and name.endswith(", 0, 1>"):
+            grid = int(r.get("Grid_Size") or r.get("Grid_Size_X"))
+            out.append((grid, value_key(r)))
+    big = max(g for g, _ in out)
+    return [v for g, v in out if g == big], big
+
+
+def pmc_summary(fetch_csv, write_csv, config, probe_mib):
+    """Per-launch HBM traffic of the outer operator from two counter runs (FETCH_SIZE, WRITE_SIZE, KiB
+    per dispatch), each scaled by what the counter reads for the plain elementwise probe kernel
+    (dst = -src over probe_mib MiB, which reads and writes exactly that many bytes)."""
+    p = CONFIGS[config][1]
+    known_kib = probe_mib * 1024.0
+    out = {"config": config, "kernel_source_sha256": source_sha(), "probe_mib": probe_mib}
+    for key, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = list(csv.DictReader(open(path)))
+        probe = [float(r["Counter_Value"]) for r in rows if "neg_kernel" in r["Kernel_Name"]]
+        if not probe:
+            raise SystemExit(f"{path}: no probe kernel dispatch")
+        factor = known_kib / (sum(probe) / len(probe))
+        vals, grid = _outer_apply_rows(path, p, lambda r: float(r["Counter_Value"]))
+        out[f"{key}_probe_kib"] = sum(probe) / len(probe)
+        out[f"{key}_factor"] = round(factor, 4)
+        out[f"{key}_kib_per_launch"] = sum(vals) / len(vals)
+        out[f"{key}_launches"] = len(vals)
+        out[f"{key}_grid"] = grid
+        out[f"{key}_bytes_per_launch"] = sum(vals) / len(vals) * 1024.0 * factor
+    out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    return out
+
+
+def trace_summary(trace_csv, p, top=25):
+    """Text summary of a rocprofv3 kernel trace: time per kernel and grid, and the outer operator."""
+    rows = list(csv.DictReader(open(trace_csv)))
+    agg = collections.defaultdict(list)
+    for r in rows:
+        g = (int(r["Grid_Size_X"]), int(r["Grid_Size_Y"]), int(r["Grid_Size_Z"]))
+        agg[(r["Kernel_Name"].split("(")[0], g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    tot = sum(sum(v) for v in agg.values())
+    lines = [f"total kernel time {tot / 1e3:.2f} ms over {len(rows)} dispatches", "",
+             "| ms | % | calls | avg us | kernel | grid |", "|---:|---:|---:|---:|---|---|"]
+    for (k, g), v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        lines.append(f"| {sum(v) / 1e3:.2f} | {100 * sum(v) / tot:.1f} | {len(v)} | {sum(v) / len(v):.2f} | `{k}` | {g[0]} |")
+    ts = []
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0]
+        if name.startswith(f"void gf::k_apply_fused<double, {p}, ") and name.endswith(", 0, 1>"):
+            ts.append((int(r["Start_Timestamp"]), int(r["Grid_Size_X"]),
+                       (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    big = max(g for _, g, _ in ts)
+    d = [x for _, g, x in sorted(ts) if g == big]
+    lines += ["", f"outer operator (node batch, grid {big}): {len(d)} launches, avg {sum(d) / len(d):.2f} us"]
+    return "\n".join(lines), d
 
 
 def cpu_baseline(cfg, nodes_timed=6):
@@ -90,10 +167,27 @@ def main():
     ap.add_argument("--apply-kind", type=int, default=0)
     ap.add_argument("--cheb", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-shape", default="",
+                    help="fix the operator launch shape 'TY,TX' instead of autotuning it (profiling runs)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-launch traffic of the outer operator from two rocprofv3 counter runs "
+                         "(made with --copy-probe-mib) as JSON to stdout, then exit")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="print a summary of a rocprofv3 kernel trace of this benchmark, then exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="before the timed steps, copy this many MiB device-to-device with a plain copy kernel "
-                         "(a known-size reference for the FETCH_SIZE / WRITE_SIZE counters)")
+                    help="before the timed steps, stream this many MiB through a plain elementwise kernel "
+                         "(dst = -src: reads and writes exactly that many bytes; the known-size reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.config,
+                                     args.copy_probe_mib or 512), indent=1))
+        return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, CONFIGS[args.config][1])[0])
+        return
+    if args.apply_shape:
+        os.environ["GF_APPLY_SHAPE"] = args.apply_shape
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sampler shards by "
               f"sample with no communication, but this build measures one GPU)", file=sys.stderr)
@@ -118,7 +212,8 @@ def main():
         n = args.copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
     kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
@@ -151,8 +246,16 @@ def main():
     bytes_per_launch = 2 * 8 * cols_avg * rows + 2 * (2 * p + 1) ** 2 * 8 * rows
     avg_ms = agg["apply_ms"] / launches
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    # measured HBM traffic per launch (counter runs of the same kernel source), else null
+    traffic = None
+    tf = traffic_file(args.config)
+    if os.path.exists(tf):
+        with open(tf) as f:
+            t = json.load(f)
+        if t.get("kernel_source_sha256") == source_sha():
+            traffic = round(t["traffic_bytes_per_launch"])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(achieved / 8000.0, 4), "traffic": None,
+            "frac": round(achieved / 8000.0, 4), "traffic": traffic,
             "kernel": f"k_apply_fused<double,{p},*,EPI_STORE,dot> (outer CG operator, stencil form)", "avg_launch_us": round(avg_ms * 1e3, 2),
             "bytes_per_launch": int(bytes_per_launch), "launches": agg["apply_launches"]}
 

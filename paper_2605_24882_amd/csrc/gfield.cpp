@@ -388,6 +388,15 @@ static const ApplyTune &get_tune(const Level &L, int ldb, int ntiles, const T *x
   auto it = L.tune.find(key);
   if (it != L.tune.end()) return it->second;
   ApplyTune best;
+  // GF_APPLY_SHAPE="TY,TX" fixes the launch shape (reproducible profiling runs)
+  if (const char *fixed = std::getenv("GF_APPLY_SHAPE")) {
+    int ty = 0, tx = 0;
+    if (std::sscanf(fixed, "%d,%d", &ty, &tx) != 2 || ty < 1 || ty > 2 || tx < 1)
+      fail(GF_EINVAL, "GF_APPLY_SHAPE must be \"TY,TX\" with TY in {1,2} and TX >= 1");
+    best.TY = ty;
+    best.TX = tx;
+    return L.tune.emplace(key, best).first->second;
+  }
   if (g_autotune && L.n1 >= 8) {
     const int tys[2] = {1, 2}, txs[3] = {16, 32, 64}, ncs[1] = {1};
     hipEvent_t e0, e1;

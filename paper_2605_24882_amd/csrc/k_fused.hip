@@ -18,6 +18,8 @@
 #include "gf_internal.h"
 #include "k_solve.h"
 
+#include <hip/hip_ext.h>
+
 namespace gf {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -259,30 +261,39 @@ static int xcd_q(int total) { return (total + 7) / 8; }
 
 template <typename T, int P, int TY, int KIND, int DOT>
 static void launch_apply_k(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
-                           const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s) {
+                           const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  if (ev0) {
+    // the runtime stamps the events at the start and end of this dispatch itself
+    hipExtLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM,
+                          stS, x, ca, cb, e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active);
+    return;
+  }
   hipLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca, cb,
                      e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active);
 }
 
 template <typename T, int P, int TY>
 static void launch_apply_pt(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
-                            const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s) {
+                            const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1) {
   if (e.kind == EPI_STORE) {
-    if (e.dot) launch_apply_k<T, P, TY, EPI_STORE, 1>(g, stM, stS, x, ca, cb, e, partial, active, s);
-    else launch_apply_k<T, P, TY, EPI_STORE, 0>(g, stM, stS, x, ca, cb, e, partial, active, s);
+    if (e.dot) launch_apply_k<T, P, TY, EPI_STORE, 1>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    else launch_apply_k<T, P, TY, EPI_STORE, 0>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
   } else if (e.kind == EPI_CHEB) {
-    if (e.dot) launch_apply_k<T, P, TY, EPI_CHEB, 1>(g, stM, stS, x, ca, cb, e, partial, active, s);
-    else launch_apply_k<T, P, TY, EPI_CHEB, 0>(g, stM, stS, x, ca, cb, e, partial, active, s);
+    if (e.dot) launch_apply_k<T, P, TY, EPI_CHEB, 1>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    else launch_apply_k<T, P, TY, EPI_CHEB, 0>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
   } else {
-    launch_apply_k<T, P, TY, EPI_RESID, 0>(g, stM, stS, x, ca, cb, e, partial, active, s);
+    launch_apply_k<T, P, TY, EPI_RESID, 0>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
   }
 }
 
 template <typename T, int P>
 static void launch_apply_p(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
-                           const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s) {
-  if (g.TY == 1 || P >= 4) launch_apply_pt<T, P, 1>(g, stM, stS, x, ca, cb, e, partial, active, s);
-  else launch_apply_pt<T, P, 2>(g, stM, stS, x, ca, cb, e, partial, active, s);
+                           const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1) {
+  if (g.TY == 1 || P >= 4) launch_apply_pt<T, P, 1>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+  else launch_apply_pt<T, P, 2>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
 }
 
 ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int NC) {
@@ -313,17 +324,15 @@ void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T
                  const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
                  int maxit, hipStream_t s, const ApplyTune &tune, hipEvent_t ev0, hipEvent_t ev1) {
   const ApplyGeom g = apply_geom(L, ldb, ntiles, tune.TY, tune.TX, tune.NC);
-  if (ev0) HIPCHK(hipEventRecord(ev0, s));
   switch (L.p) {
-    case 1: launch_apply_p<T, 1>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
-    case 2: launch_apply_p<T, 2>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
-    case 3: launch_apply_p<T, 3>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
-    case 4: launch_apply_p<T, 4>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
-    case 5: launch_apply_p<T, 5>(g, stM, stS, x, ca, cb, e, sc.partial, active, s); break;
+    case 1: launch_apply_p<T, 1>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 2: launch_apply_p<T, 2>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 3: launch_apply_p<T, 3>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 4: launch_apply_p<T, 4>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 5: launch_apply_p<T, 5>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
     default: fail(GF_EUNSUPPORTED, "degree out of range");
   }
   HIPCHK(hipGetLastError());
-  if (ev1) HIPCHK(hipEventRecord(ev1, s));
   iface_finish<T>(L, x, e, sc, cs, active, ldb, ntiles, g.nsb, tol2, maxit, s);
 }
 template void apply_fused<double>(const Level &, const double *, const double *, const double *, const double *,
