@@ -187,6 +187,41 @@ typedef struct {
 gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *items,
                           const gf_solve_opts *opts, int32_t mem, gf_solve_stats *stats);
 
+/* ---- differentiation in kappa (Sec. 3.4 differentiated; the sinc nodes t_k and weights omega_k do
+ * not depend on kappa, sigma_k = kappa^2 + t_k).
+ *
+ * gf_sample_tape: gf_sample that also returns a tape holding the solutions the adjoint needs (the
+ * node solutions x_{k,s} and the integer-chain solutions w_{i,s}: about (K + floor(beta)) x nsamp x N
+ * doubles of device memory).  *tape is set only on GF_OK (NULL otherwise).  The tape refers to its
+ * space: destroy the tape before the space. */
+gf_status gf_sample_tape(gf_space *space, double kappa, double beta, const gf_quad_rule *rule,
+                         const gf_solve_opts *opts, int32_t nsamp, const double *b, double *u, int32_t mem,
+                         gf_tape **tape, gf_solve_stats *stats);
+
+/* Per-sample derivative dL_s/dkappa of a loss L = sum_s L_s(u_s), given g_s = dL/du_s (global
+ * coefficients, [nsamp][N], the row-major layout of u).  Adjoint route, with A = kappa^2 M + S:
+ *   lambda_{k,s} = (sigma_k M + S)^-1 g_s,  mu_s = sum_k omega_k lambda_{k,s},
+ *   nu_n = A^-1 M mu (A^-1 g when beta is an integer), nu_{i-1} = A^-1 M nu_i,
+ *   dL_s/dkappa = -2 kappa [ sum_k omega_k lambda_{k,s}^T M x_{k,s} + sum_i nu_{i,s}^T M w_{i,s} ].
+ * The adjoint systems are solved by the same batched solver with the tape's options.  A tape can be
+ * used any number of times.  dl_dkappa: [nsamp].  Errors as gf_sample (GF_ENOCONV / GF_EBREAKDOWN:
+ * dl_dkappa holds the value from the last iterates). */
+gf_status gf_grad_kappa(gf_tape *tape, const double *dl_du, double *dl_dkappa, int32_t mem,
+                        gf_solve_stats *stats);
+void gf_tape_destroy(gf_tape *tape);
+
+/* Point evaluation (Sec. 2.3): the field with global coefficients u at the surface point F_m(s, t)
+ * is sum over the (p+1)^2 B-splines that do not vanish there of B_iy(t) B_ix(s) u[gid(m, iy, ix)].
+ * patch: [npts] in 0..5; st: [npts][2] = (s, t) in [0, 1]^2 (gf_locate gives both for points on the
+ * surface); u: [nvec][N]; vals: [nvec][npts].  All arrays of the memory kind mem.  Invalid patch or
+ * parameter values give GF_EINVAL before any work. */
+gf_status gf_eval(const gf_space *space, int32_t npts, const int32_t *patch, const double *st, int32_t nvec,
+                  const double *u, double *vals, int32_t mem);
+/* Transpose of gf_eval: out = Phi^T r, r: [nvec][npts], out: [nvec][N].  Points that share a
+ * coefficient add into it atomically, so the last bits of out may differ between runs. */
+gf_status gf_eval_adjoint(const gf_space *space, int32_t npts, const int32_t *patch, const double *st,
+                          int32_t nvec, const double *r, double *out, int32_t mem);
+
 #ifdef __cplusplus
 }
 #endif

@@ -271,6 +271,20 @@ struct gf_workspaces {
   std::map<std::tuple<int, int, int>, std::unique_ptr<gf::Workspace>> m;
 };
 
+// Saved forward state of one gf_sample_tape call: the request and every solution the adjoint needs
+// (the node solutions x_{k,s} and the chain solutions w_{i,s}, patch-local layout).
+struct gf_tape {
+  gf_space *sp = nullptr;
+  double kappa = 0, beta = 0;
+  gf_quad_rule rule{};
+  gf_solve_opts opts{};
+  int nsamp = 0, n = 0, ldc = 0, ldf = 0;
+  double bf = 0;
+  std::vector<double> node_sig, omega;
+  gf::DBuf<double> xk;                  // [R][ldf] node solutions, column k*nsamp + s
+  std::vector<gf::DBuf<double>> w;      // w[i-1]: [R][ldc] chain solution w_i
+};
+
 namespace gf {
 
 static std::map<const gf_space *, std::unique_ptr<gf_workspaces>> &ws_registry() {
@@ -1186,6 +1200,7 @@ struct SampleItem {
   int nsamp = 0;
   const double *b = nullptr;
   double *u = nullptr;
+  gf_tape *tape = nullptr;  // when set, the solutions are saved for the adjoint
   // derived
   int n = 0;
   double bf = 0;
@@ -1292,6 +1307,11 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
       if (it.n < i) continue;
       const Level &F = it.sp->fine();
       const int ldc = it.wc->ldb;
+      if (it.tape) {
+        DBuf<double> &dst = it.tape->w[i - 1];
+        dst.alloc((size_t)F.R * ldc);
+        HIPCHK(hipMemcpyAsync(dst.p, it.wc->x.p, (size_t)F.R * ldc * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
       if (i < it.n || it.bf > 0.0)  // next right-hand side M w_i (assembled)
         apply_level<double>(F, GF_APPLY_STENCIL, it.wc->x.p, it.wc->r.p, it.wc->one64.p, it.wc->zero64.p, ldc,
                             ldc / CT, nullptr, s);
@@ -1347,6 +1367,11 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
       for (size_t q = 0; q < bs.size(); ++q) {
         account(bs[q]);
         SampleItem &it = *owners[q];
+        if (it.tape) {
+          const size_t nx = (size_t)it.sp->fine().R * it.wf->ldb;
+          it.tape->xk.alloc(nx);
+          HIPCHK(hipMemcpyAsync(it.tape->xk.p, it.wf->x.p, nx * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
         DBuf<double> om;
         om.upload(it.omega, s);
         quadrature_sum(it.sp->fine(), it.uout.p, it.wf->x.p, om.p, (int)it.omega.size(), it.nsamp, it.wf->ldb, s);
@@ -1373,6 +1398,203 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
   }
   if (flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
   if (flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
+}
+
+// d L_s / d kappa for every sample s from dL/du_s = g_s and a tape of the forward solve (Sec. 3.4
+// differentiated in kappa; omega_k and t_k do not depend on kappa, sigma_k = kappa^2 + t_k, and every
+// matrix is symmetric):
+//   lambda_{k,s} = (sigma_k M + S)^-1 g_s                          (one batch: all nodes x samples)
+//   term_s  = sum_k omega_k lambda_{k,s}^T M x_{k,s}
+//   mu_s    = sum_k omega_k lambda_{k,s};   nu_n = A^-1 M mu  (nu_n = A^-1 g if beta is an integer)
+//   nu_{i-1} = A^-1 M nu_i,   term_s += sum_i nu_{i,s}^T M w_{i,s},     A = kappa^2 M + S
+//   dL_s/dkappa = -2 kappa term_s
+// The adjoint systems are solved by the same batched MG-PCG as the forward ones.
+static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_solve_stats *stats) {
+  gf_space *sp = t.sp;
+  gf_context *ctx = sp->ctx;
+  hipStream_t s = ctx->stream;
+  const Level &F = sp->fine();
+  const int nsamp = t.nsamp;
+  const int K = (int)t.node_sig.size();
+  SolveSpec base;
+  base.prec = t.opts.precision;
+  base.kind = t.opts.apply_kind;
+  base.cheb = t.opts.cheb_degree > 0 ? t.opts.cheb_degree : 2;
+  base.rtol = t.opts.rtol;
+  base.max_iter = t.opts.max_iter;
+  base.flags = t.opts.flags;
+  const bool use_graph = !(base.flags & (GF_FLAG_NO_GRAPH | GF_FLAG_TIME_APPLY));
+  double setup_ms = 0.0;
+  const Plan *chain_plan = nullptr, *frac_plan = nullptr;
+  {
+    const size_t np = sp->plans.size();
+    auto c0 = std::chrono::steady_clock::now();
+    if (t.n > 0) chain_plan = &get_plan(sp, std::vector<double>{t.kappa * t.kappa});
+    if (t.bf > 0.0) frac_plan = &get_plan(sp, t.node_sig);
+    if (sp->plans.size() != np)
+      setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+  }
+  InArray gin;
+  stage_in(gin, g_in, (size_t)nsamp * F.N, mem, s);
+  OutArray gout;
+  stage_out(gout, grad, (size_t)nsamp, mem);
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  HIPCHK(hipEventRecord(t0, s));
+  DBuf<double> acc, dots, one;
+  acc.alloc(nsamp);
+  dots.alloc((size_t)2 * std::max(t.ldf, t.ldc));
+  one.upload(std::vector<double>{1.0}, s);
+  SolveResult tot;
+  int nsys = 0;
+  auto account = [&](const BatchSolve &b) {
+    tot.max_it = std::max(tot.max_it, b.res.max_it);
+    tot.max_rel = std::max(tot.max_rel, b.res.max_rel);
+    tot.flags |= b.res.flags;
+    tot.apply_ms += b.res.apply_ms;
+    tot.apply_launches += b.res.apply_launches;
+    tot.apply_col_sum += b.res.apply_col_sum;
+    nsys += b.spec.ncols;
+  };
+  Workspace *wc = t.n > 0 ? &get_workspace(sp, t.ldc, base.prec, 0) : nullptr;
+  if (t.bf > 0.0) {
+    Workspace &wf = get_workspace(sp, t.ldf, base.prec, 1000);
+    DBuf<double> gloc;
+    gloc.alloc((size_t)F.R * t.ldc);
+    global_to_local(F, gloc.p, gin.p, nsamp, t.ldc, s);
+    replicate_cols(F, wf.r.p, t.ldf, gloc.p, t.ldc, nsamp, K, s);
+    BatchSolve b;
+    b.sp = sp;
+    b.w = &wf;
+    b.spec = base;
+    b.spec.ncols = K * nsamp;
+    b.spec.col_sig.resize(b.spec.ncols);
+    b.spec.col_node.resize(b.spec.ncols);
+    for (int k = 0; k < K; ++k)
+      for (int sm = 0; sm < nsamp; ++sm) {
+        b.spec.col_sig[k * nsamp + sm] = t.node_sig[k];
+        b.spec.col_node[k * nsamp + sm] = k;
+      }
+    b.spec.plan = frac_plan;
+    std::vector<BatchSolve *> ptrs{&b};
+    solve_all(ctx, ptrs, use_graph);
+    account(b);
+    // lambda^T M x per column, then the omega-weighted sum over nodes
+    Scratch sc = wf.scratch();
+    apply_level<double>(F, GF_APPLY_STENCIL, t.xk.p, wf.q.p, wf.one64.p, wf.zero64.p, t.ldf, t.ldf / CT, nullptr, s);
+    reduce_dot<double, double>(F, wf.x.p, wf.q.p, sc, t.ldf, t.ldf / CT, nullptr, nullptr, OP_STORE, 0.0, 0, dots.p,
+                               s);
+    DBuf<double> om;
+    om.upload(t.omega, s);
+    grad_accum(dots.p, om.p, K, nsamp, acc.p, s);
+    if (t.n > 0) {
+      // mu = sum_k omega_k lambda_k (global numbering), then the chain right-hand side M mu
+      DBuf<double> mu;
+      mu.alloc((size_t)nsamp * F.N);
+      quadrature_sum(F, mu.p, wf.x.p, om.p, K, nsamp, t.ldf, s);
+      global_to_local(F, gloc.p, mu.p, nsamp, t.ldc, s);
+      apply_level<double>(F, GF_APPLY_STENCIL, gloc.p, wc->r.p, wc->one64.p, wc->zero64.p, t.ldc, t.ldc / CT,
+                          nullptr, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));  // before gloc, mu and om are released
+  } else {
+    global_to_local(F, wc->r.p, gin.p, nsamp, t.ldc, s);
+  }
+  for (int i = t.n; i >= 1; --i) {
+    BatchSolve b;
+    b.sp = sp;
+    b.w = wc;
+    b.spec = base;
+    if (t.bf > 0.0) b.spec.flags &= ~GF_FLAG_TIME_APPLY;
+    b.spec.ncols = nsamp;
+    b.spec.col_sig.assign(nsamp, t.kappa * t.kappa);
+    b.spec.col_node.assign(nsamp, 0);
+    b.spec.plan = chain_plan;
+    std::vector<BatchSolve *> ptrs{&b};
+    solve_all(ctx, ptrs, use_graph);
+    account(b);
+    // nu_i^T M w_i
+    Scratch sc = wc->scratch();
+    apply_level<double>(F, GF_APPLY_STENCIL, t.w[i - 1].p, wc->q.p, wc->one64.p, wc->zero64.p, t.ldc, t.ldc / CT,
+                        nullptr, s);
+    reduce_dot<double, double>(F, wc->x.p, wc->q.p, sc, t.ldc, t.ldc / CT, nullptr, nullptr, OP_STORE, 0.0, 0,
+                               dots.p, s);
+    grad_accum(dots.p, one.p, 1, nsamp, acc.p, s);
+    if (i > 1)  // next right-hand side M nu_i
+      apply_level<double>(F, GF_APPLY_STENCIL, wc->x.p, wc->r.p, wc->one64.p, wc->zero64.p, t.ldc, t.ldc / CT,
+                          nullptr, s);
+  }
+  grad_scale(acc.p, nsamp, -2.0 * t.kappa, gout.p, s);
+  HIPCHK(hipEventRecord(t1, s));
+  finish_out(gout, s);
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (stats) {
+    stats->n_systems = nsys;
+    stats->max_iters = tot.max_it;
+    stats->max_rel_resid = tot.max_rel;
+    stats->setup_ms = setup_ms;
+    stats->solve_ms = ms;
+    stats->apply_ms = tot.apply_ms;
+    stats->apply_launches = tot.apply_launches;
+    stats->apply_rows = 6 * F.n1 * F.n1;
+    stats->apply_col_sum = tot.apply_col_sum;
+  }
+  if (tot.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some adjoint system");
+  if (tot.flags & 1) fail(GF_ENOCONV, "some adjoint system did not reach rtol within max_iter");
+}
+
+// host copies of evaluation points, validated
+static void check_points(const gf_space *sp, int npts, const int32_t *patch, const double *st, int mem,
+                         std::vector<int32_t> &ph, std::vector<double> &sh) {
+  ph.resize(npts);
+  sh.resize((size_t)2 * npts);
+  if (npts == 0) return;
+  if (mem == GF_DEVICE) {
+    HIPCHK(hipMemcpy(ph.data(), patch, npts * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(sh.data(), st, 2 * (size_t)npts * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(ph.data(), patch, npts * sizeof(int32_t));
+    std::memcpy(sh.data(), st, 2 * (size_t)npts * sizeof(double));
+  }
+  for (int i = 0; i < npts; ++i) {
+    if (ph[i] < 0 || ph[i] > 5) fail(GF_EINVAL, "patch index out of 0..5");
+    for (int c = 0; c < 2; ++c)
+      if (!(sh[2 * i + c] >= 0.0 && sh[2 * i + c] <= 1.0)) fail(GF_EINVAL, "parameter (s, t) outside [0, 1]");
+  }
+}
+
+static void run_eval(const gf_space *csp, int npts, const int32_t *patch, const double *st, int nvec,
+                     const double *in, double *out, int mem, bool adjoint) {
+  gf_space *sp = const_cast<gf_space *>(csp);
+  if (!sp || (npts > 0 && (!patch || !st)) || !in || !out) fail(GF_EINVAL, "null argument");
+  if (npts < 0 || nvec < 1) fail(GF_EINVAL, "npts must be >= 0 and nvec >= 1");
+  if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
+  HIPCHK(hipSetDevice(sp->ctx->device));
+  hipStream_t s = sp->ctx->stream;
+  const Level &F = sp->fine();
+  std::vector<int32_t> ph;
+  std::vector<double> sh;
+  check_points(sp, npts, patch, st, mem, ph, sh);
+  DBuf<int> pd;
+  DBuf<double> sd;
+  if (npts > 0) {
+    pd.upload(ph, s);
+    sd.upload(sh, s);
+  }
+  const size_t nin = (size_t)nvec * (adjoint ? npts : F.N), nout = (size_t)nvec * (adjoint ? F.N : npts);
+  InArray a;
+  stage_in(a, in, nin, mem, s);
+  OutArray o;
+  stage_out(o, out, nout, mem);
+  if (adjoint)
+    launch_eval_adjoint(F, npts, pd.p, sd.p, nvec, a.p, o.p, s);
+  else
+    launch_eval(F, npts, pd.p, sd.p, nvec, a.p, o.p, s);
+  finish_out(o, s);
 }
 
 }  // namespace gf
@@ -1424,6 +1646,66 @@ gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *
     }
     run_items(ctx, items, opts, mem, stats);
   });
+}
+
+gf_status gf_sample_tape(gf_space *sp, double kappa, double beta, const gf_quad_rule *rule,
+                         const gf_solve_opts *opts, int32_t nsamp, const double *b, double *u, int32_t mem,
+                         gf_tape **tape, gf_solve_stats *stats) {
+  return guarded([&] {
+    check_common(sp, kappa, beta, rule, opts, nsamp, mem);
+    if (!b || !u || !tape) fail(GF_EINVAL, "null argument");
+    *tape = nullptr;
+    const int K = rule->k_minus + rule->k_plus + 1;
+    if (beta - std::floor(beta) > 0.0 && (int64_t)K * nsamp > (int64_t)1 << 20)
+      fail(GF_EINVAL, "too many systems in one batch");
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    std::unique_ptr<gf_tape> t(new gf_tape());
+    t->sp = sp;
+    t->kappa = kappa;
+    t->beta = beta;
+    t->rule = *rule;
+    t->opts = *opts;
+    t->nsamp = nsamp;
+    t->n = (int)std::floor(beta);
+    t->bf = beta - t->n;
+    t->ldc = round_up(nsamp, CT);
+    t->ldf = round_up(K * nsamp, CT);
+    t->w.resize(t->n);
+    std::vector<SampleItem> items(1);
+    items[0].sp = sp;
+    items[0].kappa = kappa;
+    items[0].beta = beta;
+    items[0].rule = *rule;
+    items[0].nsamp = nsamp;
+    items[0].b = b;
+    items[0].u = u;
+    items[0].tape = t.get();
+    run_items(sp->ctx, items, opts, mem, stats);
+    t->node_sig = items[0].node_sig;
+    t->omega = items[0].omega;
+    *tape = t.release();
+  });
+}
+
+gf_status gf_grad_kappa(gf_tape *tape, const double *dl_du, double *dl_dkappa, int32_t mem, gf_solve_stats *stats) {
+  return guarded([&] {
+    if (!tape || !dl_du || !dl_dkappa) fail(GF_EINVAL, "null argument");
+    if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
+    HIPCHK(hipSetDevice(tape->sp->ctx->device));
+    run_grad(*tape, dl_du, dl_dkappa, mem, stats);
+  });
+}
+
+void gf_tape_destroy(gf_tape *tape) { delete tape; }
+
+gf_status gf_eval(const gf_space *space, int32_t npts, const int32_t *patch, const double *st, int32_t nvec,
+                  const double *u, double *vals, int32_t mem) {
+  return guarded([&] { run_eval(space, npts, patch, st, nvec, u, vals, mem, false); });
+}
+
+gf_status gf_eval_adjoint(const gf_space *space, int32_t npts, const int32_t *patch, const double *st, int32_t nvec,
+                          const double *r, double *out, int32_t mem) {
+  return guarded([&] { run_eval(space, npts, patch, st, nvec, r, out, mem, true); });
 }
 
 }  // extern "C"

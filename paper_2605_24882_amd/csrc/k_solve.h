@@ -188,5 +188,13 @@ void quadrature_sum(const Level &L, double *u, const double *X, const double *om
                     hipStream_t s);
 void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s);
 void launch_white_noise(const Level &L, const double *z, int nsamp, double *ye, double *bl, int ldb, hipStream_t s);
+// point evaluation Phi u (vals [nvec][npts]) and its transpose Phi^T r (out [nvec][N], zeroed first)
+void launch_eval(const Level &L, int npts, const int *patch, const double *st, int nvec, const double *u,
+                 double *vals, hipStream_t s);
+void launch_eval_adjoint(const Level &L, int npts, const int *patch, const double *st, int nvec, const double *r,
+                         double *out, hipStream_t s);
+// acc[s] += sum_k w[k] dots[k*nsamp + s];  out[s] = c acc[s]
+void grad_accum(const double *dots, const double *w, int K, int nsamp, double *acc, hipStream_t s);
+void grad_scale(const double *acc, int nsamp, double c, double *out, hipStream_t s);
 
 }  // namespace gf

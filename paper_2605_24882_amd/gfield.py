@@ -85,6 +85,12 @@ _SIGS = {
                          _i32, ctypes.POINTER(SolveStats)]),
     "gf_sample_batch": (_i32, [_vp, _i32, ctypes.POINTER(BatchItem), ctypes.POINTER(SolveOpts), _i32,
                                ctypes.POINTER(SolveStats)]),
+    "gf_sample_tape": (_i32, [_vp, _dbl, _dbl, ctypes.POINTER(QuadRule), ctypes.POINTER(SolveOpts), _i32, _vp,
+                              _vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(SolveStats)]),
+    "gf_grad_kappa": (_i32, [_vp, _vp, _vp, _i32, ctypes.POINTER(SolveStats)]),
+    "gf_tape_destroy": (None, [_vp]),
+    "gf_eval": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _i32]),
+    "gf_eval_adjoint": (_i32, [_vp, _i32, _vp, _vp, _i32, _vp, _vp, _i32]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -242,9 +248,84 @@ class Space:
         _check(status, st.as_dict())
         return u, st.as_dict()
 
+    def sample_tape(self, kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=GF_PREC_FP64, rtol=1e-10,
+                    max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0):
+        """sample() that also keeps the forward solutions; returns (u, Tape, stats dict)."""
+        nsamp = 1 if len(b.shape) == 1 else b.shape[0]
+        pb, mem, keep = _marshal_in(b, nsamp * self.ndofs)
+        u = _alloc_like(b, (nsamp, self.ndofs))
+        rule = QuadRule(h, k_minus, k_plus)
+        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
+        st = SolveStats()
+        th = _vp()
+        status = _lib.gf_sample_tape(self.h, kappa, beta, ctypes.byref(rule), ctypes.byref(opts), nsamp, pb,
+                                     _ptr(u), mem, ctypes.byref(th), ctypes.byref(st))
+        _check(status, st.as_dict())
+        return u, Tape(th, self, nsamp), st.as_dict()
+
+    def _points(self, patch, st, like):
+        """patch (npts,) int32 and st (npts, 2) float64 in the memory kind of `like`."""
+        if _is_torch(like):
+            import torch
+            patch = torch.as_tensor(patch, dtype=torch.int32, device=like.device).contiguous()
+            st = torch.as_tensor(st, dtype=torch.float64, device=like.device).reshape(-1, 2).contiguous()
+        else:
+            patch = np.ascontiguousarray(patch, dtype=np.int32)
+            st = np.ascontiguousarray(st, dtype=np.float64).reshape(-1, 2)
+        if patch.shape[0] != st.shape[0]:
+            raise ValueError("patch and st must describe the same points")
+        return patch, st
+
+    def eval(self, patch, st, u):
+        """Point values Phi u: u (nvec, N) -> (nvec, npts)."""
+        nvec = 1 if len(u.shape) == 1 else u.shape[0]
+        pu, mem, keep = _marshal_in(u, nvec * self.ndofs)
+        patch, st = self._points(patch, st, u)
+        npts = patch.shape[0]
+        vals = _alloc_like(u, (nvec, npts))
+        _check(_lib.gf_eval(self.h, npts, _ptr(patch), _ptr(st), nvec, pu, _ptr(vals), mem))
+        return vals
+
+    def eval_adjoint(self, patch, st, r):
+        """Phi^T r: r (nvec, npts) -> (nvec, N)."""
+        patch, st = self._points(patch, st, r)
+        npts = patch.shape[0]
+        nvec = 1 if len(r.shape) == 1 else r.shape[0]
+        pr, mem, keep = _marshal_in(r, nvec * npts)
+        out = _alloc_like(r, (nvec, self.ndofs))
+        _check(_lib.gf_eval_adjoint(self.h, npts, _ptr(patch), _ptr(st), nvec, pr, _ptr(out), mem))
+        return out
+
     def close(self):
         if self.h:
             _lib.gf_space_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tape:
+    """Forward state of one sample_tape call (keeps its space alive)."""
+
+    def __init__(self, h, space, nsamp):
+        self.h, self.space, self.nsamp = h, space, nsamp
+
+    def grad_kappa(self, dl_du):
+        """Per-sample dL_s/dkappa from dL/du (nsamp, N); returns (grad (nsamp,), stats dict)."""
+        pg, mem, keep = _marshal_in(dl_du, self.nsamp * self.space.ndofs)
+        out = _alloc_like(dl_du, (self.nsamp,))
+        st = SolveStats()
+        status = _lib.gf_grad_kappa(self.h, pg, _ptr(out), mem, ctypes.byref(st))
+        _check(status, st.as_dict())
+        return out, st.as_dict()
+
+    def close(self):
+        if self.h:
+            _lib.gf_tape_destroy(self.h)
             self.h = None
 
     def __del__(self):

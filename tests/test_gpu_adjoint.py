@@ -1,0 +1,183 @@
+"""GPU parity of the differentiation form: point evaluation, its transpose, and d loss / d kappa by
+adjoint solves, against the FP64 oracle (adjoint formula with direct solves, dense eigen-expansion,
+central differences).
+
+Tolerances: evaluation 1e-13 relative (same sums up to order).  Gradients with CG rtol 1e-13:
+1e-9 relative to the largest per-sample gradient (solver error times the conditioning of the
+shifted systems, amplified by the cancellation between the node terms).  Central differences with
+step 1e-5: 1e-6 relative (truncation O(delta^2) plus solver error / delta).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import assembly, evaluate, geometry, gradient, noise
+from paper_2605_24882_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+g = pytest.importorskip("paper_2605_24882_amd.gfield")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    return g.Context(0)
+
+
+_cache = {}
+
+
+def setup(ctx, p, j, pert=False):
+    key = (p, j, pert)
+    if key not in _cache:
+        geo = g.Geometry(ctx, pert)
+        _cache[key] = (geo, g.Space(ctx, geo, p, j), assembly.Discretisation(p, j, pert))
+    return _cache[key]
+
+
+def points(geo, npts, seed=7):
+    """library-side (patch, st) and oracle-side Phi inputs of the same seeded surface points"""
+    pts, y = inputs.sphere_points_and_targets(npts, seed=seed)
+    patch, st = geo.locate(pts)
+    return pts, y, patch, st
+
+
+@pytest.mark.parametrize("p,j,pert", [(2, 2, False), (3, 3, True), (1, 2, False), (5, 1, False)])
+def test_eval_and_adjoint_match_oracle(ctx, p, j, pert):
+    geo, sp, d = setup(ctx, p, j, pert)
+    pts, y, patch, st = points(geo, 300)
+    # patch corners and edges as well (s, t in {0, 1})
+    extra_p = np.array([0, 1, 2, 3, 4, 5, 0, 5], dtype=np.int32)
+    extra_st = np.array([[0, 0], [1, 1], [0, 1], [1, 0], [0.5, 1], [1, 0.5], [0.25, 0], [1, 1]], dtype=np.float64)
+    patch = np.concatenate([patch, extra_p])
+    st = np.concatenate([st, extra_st])
+    op, os_, ot = geometry.invert(pts)
+    Phi = evaluate.phi_matrix(d, np.concatenate([op, extra_p]), np.concatenate([os_, extra_st[:, 0]]),
+                              np.concatenate([ot, extra_st[:, 1]]))
+    u = np.random.default_rng(3).standard_normal((3, d.N))
+    vals = sp.eval(patch, st, u)
+    ref = np.stack([Phi @ v for v in u])
+    assert np.abs(vals - ref).max() <= 1e-13 * np.abs(ref).max()
+    r = np.random.default_rng(4).standard_normal((2, len(patch)))
+    out = sp.eval_adjoint(patch, st, r)
+    ref_t = np.stack([Phi.T @ v for v in r])
+    assert np.abs(out - ref_t).max() <= 1e-13 * np.abs(ref_t).max()
+
+
+def test_eval_rejects_bad_points(ctx):
+    geo, sp, d = setup(ctx, 2, 2)
+    u = np.zeros((1, d.N))
+    with pytest.raises(g.GfieldError) as e:
+        sp.eval(np.array([6], dtype=np.int32), np.array([[0.5, 0.5]]), u)
+    assert e.value.status == g.GF_EINVAL
+    with pytest.raises(g.GfieldError):
+        sp.eval(np.array([0], dtype=np.int32), np.array([[0.5, 1.5]]), u)
+
+
+def _grad_case(ctx, p, j, kappa, beta, seeds, npts, prec, K=12):
+    geo, sp, d = setup(ctx, p, j)
+    pts, y, patch, st = points(geo, npts)
+    b = noise.load(d, inputs.noise_vectors(seeds, inputs.noise_length(p, j)))
+    u, tape, _ = sp.sample_tape(kappa, beta, b, h=0.4, k_minus=K, k_plus=K, precision=prec, rtol=1e-13)
+    vals = sp.eval(patch, st, u)
+    dl_du = sp.eval_adjoint(patch, st, vals - y[None, :])
+    grad, stats = tape.grad_kappa(dl_du)
+    op, os_, ot = geometry.invert(pts)
+    Phi = evaluate.phi_matrix(d, op, os_, ot)
+    return sp, d, b, Phi, y, u, grad, stats
+
+
+@pytest.mark.parametrize("beta", [0.8, 1.6, 2.0, 2.3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grad_kappa_matches_oracle_adjoint(ctx, beta, prec):
+    kappa, K = 8.0, 12
+    sp, d, b, Phi, y, u, grad, stats = _grad_case(ctx, 3, 2, kappa, beta, [0, 1, 2], 120, prec, K)
+    ref, u_ref = gradient.adjoint(d.M, d.S, kappa, beta, 0.4, K, K, b, Phi, y)
+    assert np.abs(u - u_ref).max() <= 1e-10 * np.abs(u_ref).max()
+    assert np.abs(grad - ref).max() <= 1e-9 * np.abs(ref).max(), (grad, ref)
+    n = math.floor(beta)
+    nodes = 0 if beta == n else 2 * K + 1
+    assert stats["n_systems"] == 3 * (nodes + n)
+
+
+def test_grad_kappa_matches_eigen_expansion(ctx):
+    """Dense generalised eigen-decomposition route on a tiny mesh (p = 2, 4 x 4 elements per patch)."""
+    kappa, beta, K = 4.0, 0.75, 15
+    sp, d, b, Phi, y, u, grad, _ = _grad_case(ctx, 2, 2, kappa, beta, [0, 5], 60, 0, K)
+    ref, _ = gradient.eigen_expansion(d.M, d.S, kappa, beta, 0.4, K, K, b, Phi, y)
+    assert np.abs(grad - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_tape_reuse_and_device_arrays(ctx):
+    import torch
+    geo, sp, d = setup(ctx, 2, 3)
+    b = torch.from_numpy(noise.load(d, inputs.noise_vectors([3, 4], inputs.noise_length(2, 3)))).cuda()
+    u, tape, _ = sp.sample_tape(5.0, 1.3, b, k_minus=10, k_plus=10, rtol=1e-12)
+    u1, _ = sp.sample(5.0, 1.3, b, k_minus=10, k_plus=10, rtol=1e-12)
+    assert torch.equal(u, u1)
+    gvec = torch.from_numpy(np.random.default_rng(9).standard_normal((2, d.N))).cuda()
+    g1, _ = tape.grad_kappa(gvec)
+    g2, _ = tape.grad_kappa(gvec)
+    assert torch.equal(g1, g2)
+    g3, _ = tape.grad_kappa(gvec.cpu().numpy())
+    assert np.array_equal(g1.cpu().numpy(), g3)
+
+
+def test_autograd_function_matches_oracle(ctx):
+    import torch
+    from paper_2605_24882_amd import autograd as ag
+    kappa0, beta, K = 5.0, 0.8, 12
+    geo, sp, d = setup(ctx, 2, 3)
+    pts, y, patch, st = points(geo, 200)
+    b = noise.load(d, inputs.noise_vectors([0, 1], inputs.noise_length(2, 3)))
+    kappa = torch.tensor(kappa0, dtype=torch.float64, requires_grad=True)
+    u = ag.sample_field(kappa, torch.from_numpy(b).cuda(), sp, beta, k_minus=K, k_plus=K, rtol=1e-13)
+    vals = ag.evaluate(u, sp, patch, st)
+    yt = torch.from_numpy(y).cuda()
+    loss = 0.5 * ((vals - yt[None, :]) ** 2).sum()
+    loss.backward()
+    op, os_, ot = geometry.invert(pts)
+    Phi = evaluate.phi_matrix(d, op, os_, ot)
+    ref, u_ref = gradient.adjoint(d.M, d.S, kappa0, beta, 0.4, K, K, b, Phi, y)
+    fd = gradient.finite_difference(d.M, d.S, kappa0, beta, 0.4, K, K, b, Phi, y, delta=1e-5)
+    assert abs(kappa.grad.item() - ref.sum()) <= 1e-9 * np.abs(ref).sum()
+    assert abs(kappa.grad.item() - fd.sum()) <= 1e-6 * np.abs(fd).sum()
+    assert abs(loss.item() - gradient.loss(u_ref, Phi, y).sum()) <= 1e-10 * loss.item()
+
+
+def test_c4_adjoint_matches_central_difference(ctx):
+    """Unit sphere, p = 3, 64 x 64 elements per patch (26,138 unknowns), kappa = 8, beta = 0.8,
+    16 samples, loss over 1000 seeded surface points: the adjoint gradient against central
+    differences (step 1e-5) of the same sampler, per sample."""
+    import torch
+    kappa, beta, K, dk = 8.0, 0.8, 20, 1e-5
+    geo, sp, _ = setup_space_only(ctx, 3, 6)
+    pts, y, patch, st = points(geo, 1000)
+    z = torch.from_numpy(inputs.noise_vectors(range(16), sp.noise_length)).cuda()
+    b = sp.white_noise(z)
+    yt = torch.from_numpy(y).cuda()
+    kw = dict(h=0.4, k_minus=K, k_plus=K, rtol=1e-13, max_iter=1000)
+    u, tape, _ = sp.sample_tape(kappa, beta, b, **kw)
+    vals = sp.eval(patch, st, u)
+    grad, _ = tape.grad_kappa(sp.eval_adjoint(patch, st, vals - yt[None, :]))
+
+    def losses(k):
+        uk, _ = sp.sample(k, beta, b, **kw)
+        r = sp.eval(patch, st, uk) - yt[None, :]
+        return 0.5 * (r * r).sum(dim=1)
+
+    fd = (losses(kappa + dk) - losses(kappa - dk)) / (2 * dk)
+    err = (grad - fd).abs().max().item()
+    print(f"C4 adjoint vs central difference: max abs diff {err:.3e}, max |grad| {grad.abs().max().item():.3e}")
+    assert err <= 1e-5 * grad.abs().max().item(), (err, grad.abs().max().item())
+
+
+def setup_space_only(ctx, p, j, pert=False):
+    key = ("space", p, j, pert)
+    if key not in _cache:
+        geo = g.Geometry(ctx, pert)
+        _cache[key] = (geo, g.Space(ctx, geo, p, j), None)
+    return _cache[key]
