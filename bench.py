@@ -35,6 +35,26 @@ CONFIGS = {
 }
 
 
+# several sampling requests solved together (one call of the batched sampler per step): every
+# combination of degree, level and kappa is one request; sample s goes to request s mod (number of
+# requests), with white-noise seed s
+BATCH_CONFIGS = {
+    "c3": dict(perturbed=True, degrees=(2, 3), levels=(5, 6, 7), kappas=(5.0, 10.0, 20.0), beta=0.9, h=0.4, k=20,
+               nsamp=256, precision=1, rtol=1e-6),
+    "c3-fp64": dict(perturbed=True, degrees=(2, 3), levels=(5, 6, 7), kappas=(5.0, 10.0, 20.0), beta=0.9, h=0.4,
+                    k=20, nsamp=256, precision=0, rtol=1e-6),
+}
+
+
+def batch_workload_name(bc, nreq):
+    surf = "perturbed sphere" if bc["perturbed"] else "unit sphere"
+    lv = "/".join(f"{2**l}x{2**l}" for l in bc["levels"])
+    return (f"{surf}, 6 patches, degrees {bc['degrees']}, {lv} elements/patch, kappa in {bc['kappas']}, "
+            f"beta={bc['beta']:g} ({2*bc['k']+1} sinc nodes, h={bc['h']:g}); {bc['nsamp']} samples over {nreq} "
+            f"requests in one batched call; {'FP64' if bc['precision'] == 0 else 'FP32 V-cycle / FP64 CG'} MG-PCG "
+            f"to rel. residual {bc['rtol']:g}")
+
+
 def workload_name(cfg):
     pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
     n1 = 2 ** lev + p
@@ -163,7 +183,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + sorted(BATCH_CONFIGS))
     ap.add_argument("--apply-kind", type=int, default=0)
     ap.add_argument("--cheb", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -198,16 +218,43 @@ def main():
     from paper_2605_24882_amd import gfield as g
     from paper_2605_24882_amd import inputs
 
-    cfg = CONFIGS[args.config]
-    pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
     ctx = g.Context(0)
-    geo = g.Geometry(ctx, pert)
     t0 = time.perf_counter()
-    sp = g.Space(ctx, geo, p, lev)
-    space_s = time.perf_counter() - t0
-    z = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.noise_length)).cuda()
-    b = sp.white_noise(z)
-    del z
+    if args.config in BATCH_CONFIGS:
+        bc = BATCH_CONFIGS[args.config]
+        pert, prec, rtol, nsamp, p = bc["perturbed"], bc["precision"], bc["rtol"], bc["nsamp"], max(bc["degrees"])
+        geo = g.Geometry(ctx, pert)
+        spaces = {(dg, lv): g.Space(ctx, geo, dg, lv) for dg in bc["degrees"] for lv in bc["levels"]}
+        space_s = time.perf_counter() - t0
+        combos = [(dg, lv, kp) for dg in bc["degrees"] for lv in bc["levels"] for kp in bc["kappas"]]
+        reqs = []
+        for i, (dg, lv, kp) in enumerate(combos):
+            sp = spaces[(dg, lv)]
+            seeds = [s_ for s_ in range(nsamp) if s_ % len(combos) == i]
+            z = torch.from_numpy(inputs.noise_vectors(seeds, sp.noise_length)).cuda()
+            reqs.append(dict(space=sp, kappa=kp, beta=bc["beta"], b=sp.white_noise(z), h=bc["h"],
+                             k_minus=bc["k"], k_plus=bc["k"]))
+            del z
+        kw = dict(precision=prec, rtol=rtol, max_iter=2000, cheb_degree=args.cheb, apply_kind=args.apply_kind)
+
+        def step(flags=0):
+            return g.sample_batch(ctx, reqs, flags=flags, **kw)
+        workload = batch_workload_name(bc, len(combos))
+    else:
+        cfg = CONFIGS[args.config]
+        pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
+        geo = g.Geometry(ctx, pert)
+        sp = g.Space(ctx, geo, p, lev)
+        space_s = time.perf_counter() - t0
+        z = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.noise_length)).cuda()
+        b = sp.white_noise(z)
+        del z
+        kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
+                  apply_kind=args.apply_kind)
+
+        def step(flags=0):
+            return sp.sample(kappa, beta, b, flags=flags, **kw)
+        workload = workload_name(cfg)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -216,34 +263,32 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
-              apply_kind=args.apply_kind)
     for _ in range(args.warmup):
-        u, st = sp.sample(kappa, beta, b, **kw)
+        u, st = step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    agg = {"apply_ms": 0.0, "apply_launches": 0, "apply_col_sum": 0.0, "max_iters": 0, "max_rel_resid": 0.0}
+    agg = {"apply_ms": 0.0, "apply_launches": 0, "apply_bytes": 0.0, "max_iters": 0, "max_rel_resid": 0.0}
     for _ in range(args.steps):
-        u, st = sp.sample(kappa, beta, b, **kw)
+        u, st = step()
         agg["max_iters"] = max(agg["max_iters"], st["max_iters"])
         agg["max_rel_resid"] = max(agg["max_rel_resid"], st["max_rel_resid"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = nsamp * args.steps / elapsed
-    # dominant-kernel timing: the same steps once more with HIP events around every outer operator
-    # launch (events need the eagerly enqueued loop; the kernels and launch shapes are the same)
+    # dominant-kernel timing: the same steps once more with HIP events stamped around every outer
+    # operator launch of the node batch (events need the eagerly enqueued loop; kernels and launch
+    # shapes are the same)
     for _ in range(max(1, args.steps // 2)):
-        u, st = sp.sample(kappa, beta, b, flags=g.GF_FLAG_TIME_APPLY, **kw)
-        for key in ("apply_ms", "apply_launches", "apply_col_sum"):
+        u, st = step(flags=g.GF_FLAG_TIME_APPLY)
+        for key in ("apply_ms", "apply_launches", "apply_bytes"):
             agg[key] += st[key]
 
-    # roofline of the dominant kernel: FP64 stencil apply of the outer CG.
-    # algorithmic bytes per launch = 2 x 8 B x columns x rows (read x, write y) + 2 x (2p+1)^2 x 8 B x rows
-    rows = st["apply_rows"]
+    # roofline of the dominant kernel: the FP64 stencil operator of the outer CG.  Algorithmic bytes
+    # per launch (library count): read x and write y, 8 B each, per active column and patch row, plus
+    # the two (2p+1)^2 FP64 stencils per row
     launches = max(1, agg["apply_launches"])
-    cols_avg = agg["apply_col_sum"] / launches
-    bytes_per_launch = 2 * 8 * cols_avg * rows + 2 * (2 * p + 1) ** 2 * 8 * rows
+    bytes_per_launch = agg["apply_bytes"] / launches
     avg_ms = agg["apply_ms"] / launches
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     # measured HBM traffic per launch (counter runs of the same kernel source), else null
@@ -256,8 +301,9 @@ def main():
             traffic = round(t["traffic_bytes_per_launch"])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
             "frac": round(achieved / 8000.0, 4), "traffic": traffic,
-            "kernel": f"k_apply_fused<double,{p},*,EPI_STORE,dot> (outer CG operator, stencil form)", "avg_launch_us": round(avg_ms * 1e3, 2),
-            "bytes_per_launch": int(bytes_per_launch), "launches": agg["apply_launches"]}
+            "kernel": f"k_apply_fused<double,p,*,EPI_STORE,dot> (outer CG operator, stencil form)",
+            "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch),
+            "launches": agg["apply_launches"]}
 
     out = {
         "metric": "field samples/sec at rel-L2 err <=1e-6 vs FP64 oracle; operator-apply HBM GB/s",
@@ -272,13 +318,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": workload_name(cfg), "samples_per_step": nsamp, "systems_per_step": st["n_systems"],
+        "config": {"workload": workload, "samples_per_step": nsamp, "systems_per_step": st["n_systems"],
                    "max_cg_iters": agg["max_iters"], "max_rel_resid": agg["max_rel_resid"],
                    "space_setup_s": round(space_s, 3)},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg)
+    if not args.no_cpu_baseline and args.config in CONFIGS:
+        out["cpu_baseline"] = cpu_baseline(CONFIGS[args.config])
     print(json.dumps(out))
 
 

@@ -149,6 +149,9 @@ typedef struct {
   int32_t apply_launches;  /* with GF_FLAG_TIME_APPLY: number of those launches */
   int32_t apply_rows;      /* rows (patch coefficients, copies included) one launch processes per column */
   double apply_col_sum;    /* with GF_FLAG_TIME_APPLY: columns processed, summed over those launches */
+  double apply_bytes;      /* with GF_FLAG_TIME_APPLY: algorithmic bytes of those launches (8-byte x read
+                              and y written per active column and patch row, plus the two (2p+1)^2
+                              FP64 stencils per row), summed */
 } gf_solve_stats;
 
 /* flags */

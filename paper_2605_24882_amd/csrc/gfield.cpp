@@ -586,6 +586,7 @@ struct SolveResult {
   double apply_ms = 0.0;
   int apply_launches = 0;
   double apply_col_sum = 0.0;
+  double apply_bytes = 0.0;
 };
 
 // Chebyshev recurrence coefficients for interval [b/alpha, b], in units of 1/b
@@ -801,6 +802,11 @@ struct BatchSolve {
       res.apply_ms += ms;
       res.apply_launches += 1;
       res.apply_col_sum += (double)active_tiles * CT;
+      // algorithmic bytes: read x and write y for every active column of every patch row, plus the
+      // two FP64 stencils of every row
+      const Level &F = sp->fine();
+      const double rows = 6.0 * F.n1 * F.n1;
+      res.apply_bytes += 2.0 * 8.0 * active_tiles * CT * rows + 2.0 * F.S * F.S * 8.0 * rows;
     }
   }
 
@@ -1259,7 +1265,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
   HIPCHK(hipEventCreate(&t1));
   HIPCHK(hipEventRecord(t0, s));
   int max_it = 0, flags = 0, nsys = 0;
-  double max_rel = 0.0, apply_ms = 0.0, apply_col_sum = 0.0;
+  double max_rel = 0.0, apply_ms = 0.0, apply_col_sum = 0.0, apply_bytes = 0.0;
   int apply_launches = 0, apply_rows = 0;
   auto account = [&](const BatchSolve &b) {
     max_it = std::max(max_it, b.res.max_it);
@@ -1269,6 +1275,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     apply_ms += b.res.apply_ms;
     apply_launches += b.res.apply_launches;
     apply_col_sum += b.res.apply_col_sum;
+    apply_bytes += b.res.apply_bytes;
     if (b.res.apply_launches) apply_rows = 6 * b.sp->fine().n1 * b.sp->fine().n1;
   };
   const bool use_graph = !(base.flags & (GF_FLAG_NO_GRAPH | GF_FLAG_TIME_APPLY));
@@ -1395,6 +1402,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     stats->apply_launches = apply_launches;
     stats->apply_rows = apply_rows;
     stats->apply_col_sum = apply_col_sum;
+    stats->apply_bytes = apply_bytes;
   }
   if (flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
   if (flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
@@ -1455,6 +1463,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
     tot.apply_ms += b.res.apply_ms;
     tot.apply_launches += b.res.apply_launches;
     tot.apply_col_sum += b.res.apply_col_sum;
+    tot.apply_bytes += b.res.apply_bytes;
     nsys += b.spec.ncols;
   };
   Workspace *wc = t.n > 0 ? &get_workspace(sp, t.ldc, base.prec, 0) : nullptr;
@@ -1542,6 +1551,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
     stats->apply_launches = tot.apply_launches;
     stats->apply_rows = 6 * F.n1 * F.n1;
     stats->apply_col_sum = tot.apply_col_sum;
+    stats->apply_bytes = tot.apply_bytes;
   }
   if (tot.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some adjoint system");
   if (tot.flags & 1) fail(GF_ENOCONV, "some adjoint system did not reach rtol within max_iter");

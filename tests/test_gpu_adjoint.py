@@ -172,7 +172,7 @@ def test_c4_adjoint_matches_central_difference(ctx):
     fd = (losses(kappa + dk) - losses(kappa - dk)) / (2 * dk)
     err = (grad - fd).abs().max().item()
     print(f"C4 adjoint vs central difference: max abs diff {err:.3e}, max |grad| {grad.abs().max().item():.3e}")
-    assert err <= 1e-5 * grad.abs().max().item(), (err, grad.abs().max().item())
+    assert err <= 1e-6 * grad.abs().max().item(), (err, grad.abs().max().item())
 
 
 def setup_space_only(ctx, p, j, pert=False):

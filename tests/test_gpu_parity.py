@@ -197,3 +197,35 @@ def test_sample_batch_device_arrays(ctx):
     for s, b, u in zip(sps, bs, us):
         u1, _ = s.sample(6.0, 0.9, b, k_minus=10, k_plus=10, rtol=1e-12)
         assert torch.equal(u, u1)
+
+
+def test_c3_mixed_precision_batch_error(ctx):
+    """Perturbed sphere, uneven degrees and levels in one batched call, beta = 0.9, 41 nodes, FP32
+    V-cycle / FP64 CG to relative residual 1e-6 (the throughput setting of this workload): field error
+    at most 1e-6 in the relative M-norm, against the oracle on the 32 x 32 meshes and against the FP64
+    path (itself pinned to the oracle above) on a 64 x 64 mesh."""
+    import torch
+    c = ctx
+    K = 20
+    cases = [(2, 5, 5.0, [0, 18]), (3, 5, 20.0, [1]), (3, 5, 10.0, [7]), (2, 6, 20.0, [2])]
+    reqs, bs = [], []
+    for p, j, kappa, seeds in cases:
+        sp = space(c, p, j, True)
+        z = torch.from_numpy(inputs.noise_vectors(seeds, sp.noise_length)).cuda()
+        b = sp.white_noise(z)
+        bs.append(b)
+        reqs.append(dict(space=sp, kappa=kappa, beta=0.9, b=b, h=0.4, k_minus=K, k_plus=K))
+    us, st = g.sample_batch(c, reqs, precision=1, rtol=1e-6, max_iter=1000)
+    for (p, j, kappa, seeds), u, b in zip(cases, us, bs):
+        if j == 5:
+            d = disc(p, j, True)
+            ref = _oracle_u(d, kappa, 0.9, 0.4, K, b.cpu().numpy())
+            err = mrel(d, u.cpu().numpy(), ref)
+        else:
+            sp = space(c, p, j, True)
+            ref, _ = sp.sample(kappa, 0.9, b, h=0.4, k_minus=K, k_plus=K, rtol=1e-12, max_iter=1000)
+            dlt = u - ref
+            err = ((dlt * sp.apply(1.0, 0.0, dlt)).sum(dim=1).sqrt()
+                   / (ref * sp.apply(1.0, 0.0, ref)).sum(dim=1).sqrt()).max().item()
+        print(f"C3 subset p={p} level={j} kappa={kappa}: rel. M-norm error {err:.3e}")
+        assert err <= 1e-6, (p, j, kappa, err)
