@@ -31,7 +31,7 @@ CONFIGS = {
     "c2": (False, 2, 6, 10.0, 1.6, 0.4, 20, 64, 0, 1e-10),
     "c2-mixed": (False, 2, 6, 10.0, 1.6, 0.4, 20, 64, 1, 1e-10),
     "c1": (False, 2, 2, 4.0, 0.75, 0.4, 15, 1, 0, 1e-13),
-    "c5": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-9),
+    "c5": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-6),
 }
 
 
