@@ -32,7 +32,10 @@ CONFIGS = {
     "c2-mixed": (False, 2, 6, 10.0, 1.6, 0.4, 20, 64, 1, 1e-10),
     "c1": (False, 2, 2, 4.0, 0.75, 0.4, 15, 1, 0, 1e-13),
     "c5": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-6),
+    "c4": (False, 3, 6, 8.0, 0.8, 0.4, 20, 16, 1, 1e-6),
 }
+# configs whose step also computes d loss / d kappa by the adjoint (loss over 1000 seeded points)
+GRADIENT_CONFIGS = {"c4"}
 
 
 # several sampling requests solved together (one call of the batched sampler per step): every
@@ -140,6 +143,40 @@ def trace_summary(trace_csv, p, top=25):
     return "\n".join(lines), d
 
 
+def one_at_a_time(g, sp, b, cfg, kw, nodes_timed=6):
+    """The same shifted systems solved one per call (gf_solve_shifted with one system, FP64, same
+    solver and tolerance) on the GPU: the unbatched reference the batched sampler is measured against.
+
+    Bounded sample: for load 0, its integer-chain system (shift kappa^2) and `nodes_timed` of the node
+    systems (evenly spaced in k), each with load 0 as right-hand side; per sample, the chain systems
+    and all nodes at the measured average (multigrid plans are built before timing, as the batched
+    path's are cached)."""
+    import torch
+    pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
+    n = math.floor(beta)
+    bf = beta - n
+    t = [math.exp(-2.0 * kk * h) for kk in range(-k, k + 1)]
+    pick = [round(i * (len(t) - 1) / (nodes_timed - 1)) for i in range(nodes_timed)] if bf > 0 else []
+    shifts = ([kappa * kappa] if n > 0 else []) + [kappa * kappa + t[i] for i in pick]
+    b0 = b[0:1].contiguous()
+    for sg in shifts:  # plans
+        sp.solve_shifted(sg, b0, precision=0, rtol=rtol, max_iter=kw["max_iter"])
+    torch.cuda.synchronize()
+    times = []
+    for sg in shifts:
+        t0 = time.perf_counter()
+        sp.solve_shifted(sg, b0, precision=0, rtol=rtol, max_iter=kw["max_iter"])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    chain = times[0] if n > 0 else 0.0
+    node = sum(times[1:] if n > 0 else times) / max(1, len(pick))
+    per_sample = n * chain + (len(t) * node if bf > 0 else 0.0)
+    return {"value": round(1.0 / per_sample, 3), "unit": "samples/s", "dtype": "f64",
+            "sample": (f"load 0: {'its chain system and ' if n > 0 else ''}{len(pick)} of the {len(t)} node systems, "
+                       f"one system per call; per sample {n} chain system(s) at {chain * 1e3:.1f} ms and {len(t)} "
+                       f"node systems at {node * 1e3:.1f} ms on average")}
+
+
 def cpu_baseline(cfg, nodes_timed=6):
     """The oracle (sparse LU, FP64, one thread) on the first load of the workload.
 
@@ -187,6 +224,8 @@ def main():
     ap.add_argument("--apply-kind", type=int, default=0)
     ap.add_argument("--cheb", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-one-at-a-time", action="store_true",
+                    help="skip the one-system-per-call FP64 GPU reference timing")
     ap.add_argument("--apply-shape", default="",
                     help="fix the operator launch shape 'TY,TX' instead of autotuning it (profiling runs)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -252,9 +291,27 @@ def main():
         kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
                   apply_kind=args.apply_kind)
 
-        def step(flags=0):
-            return sp.sample(kappa, beta, b, flags=flags, **kw)
-        workload = workload_name(cfg)
+        if args.config in GRADIENT_CONFIGS:
+            pts, yv = inputs.sphere_points_and_targets(1000, seed=7)
+            patch, stp = geo.locate(pts)
+            yt = torch.from_numpy(yv).cuda()
+
+            def step(flags=0):
+                u, tape, st1 = sp.sample_tape(kappa, beta, b, flags=flags, **kw)
+                vals = sp.eval(patch, stp, u)
+                gk, st2 = tape.grad_kappa(sp.eval_adjoint(patch, stp, vals - yt[None, :]))
+                tape.close()
+                st = dict(st1)
+                for key in ("apply_ms", "apply_launches", "apply_bytes", "n_systems"):
+                    st[key] = st1[key] + st2[key]
+                st["max_iters"] = max(st1["max_iters"], st2["max_iters"])
+                st["max_rel_resid"] = max(st1["max_rel_resid"], st2["max_rel_resid"])
+                return gk, st
+            workload = workload_name(cfg) + "; plus d loss/d kappa by adjoint solves (loss over 1000 points)"
+        else:
+            def step(flags=0):
+                return sp.sample(kappa, beta, b, flags=flags, **kw)
+            workload = workload_name(cfg)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -323,6 +380,8 @@ def main():
                    "space_setup_s": round(space_s, 3)},
         "roofline": roof,
     }
+    if args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_one_at_a_time:
+        out["gpu_one_solve_at_a_time"] = one_at_a_time(g, sp, b, CONFIGS[args.config], kw)
     if not args.no_cpu_baseline and args.config in CONFIGS:
         out["cpu_baseline"] = cpu_baseline(CONFIGS[args.config])
     print(json.dumps(out))

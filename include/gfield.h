@@ -168,6 +168,14 @@ gf_status gf_sample(gf_space *space, double kappa, double beta, const gf_quad_ru
                     const gf_solve_opts *opts, int32_t nsamp, const double *b, double *u, int32_t mem,
                     gf_solve_stats *stats);
 
+/* The batch of shifted systems itself: (sigma_i M + S) x_i = b_i for i < nsys (the systems of
+ * eq. beta-approx and of the integer chain, Sec. 3.4), solved together by the batched
+ * multigrid-preconditioned CG that gf_sample uses.  sigma: host array [nsys], every entry > 0 and
+ * finite (S is singular on a closed surface); at most 4096 distinct values per call.  b, x: [nsys][N]
+ * (b assembled, like a load).  Errors as gf_sample. */
+gf_status gf_solve_shifted(gf_space *space, int32_t nsys, const double *sigma, const double *b, double *x,
+                           const gf_solve_opts *opts, int32_t mem, gf_solve_stats *stats);
+
 /* One request of gf_sample_batch: the arguments of one gf_sample call.  Spaces may differ in degree
  * and level but must belong to the context of the batch; b and u as in gf_sample, all of the same
  * memory kind. */

@@ -1658,6 +1658,88 @@ gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *
   });
 }
 
+gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, const double *b, double *x,
+                           const gf_solve_opts *opts, int32_t mem, gf_solve_stats *stats) {
+  return guarded([&] {
+    if (!sp || !sigma || !b || !x || !opts) fail(GF_EINVAL, "null argument");
+    if (nsys < 1 || nsys > (1 << 20)) fail(GF_EINVAL, "nsys must be in 1..2^20");
+    if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
+    if (opts->precision != GF_PREC_FP64 && opts->precision != GF_PREC_MIXED) fail(GF_EINVAL, "unknown precision");
+    if (!(opts->rtol > 0.0) || !(opts->rtol < 1.0)) fail(GF_EINVAL, "rtol must be in (0, 1)");
+    if (opts->max_iter < 1) fail(GF_EINVAL, "max_iter must be >= 1");
+    if (opts->cheb_degree < 0 || opts->cheb_degree > 16) fail(GF_EINVAL, "cheb_degree must be in 0..16");
+    if (opts->apply_kind != GF_APPLY_STENCIL && opts->apply_kind != GF_APPLY_SUMFACT)
+      fail(GF_EINVAL, "unknown apply_kind");
+    // distinct shifts in order of first appearance: one multigrid plan node each
+    std::vector<double> distinct;
+    std::vector<int> node(nsys);
+    for (int i = 0; i < nsys; ++i) {
+      if (!(sigma[i] > 0.0) || !std::isfinite(sigma[i])) fail(GF_EINVAL, "every shift must be positive and finite");
+      auto f = std::find(distinct.begin(), distinct.end(), sigma[i]);
+      node[i] = (int)(f - distinct.begin());
+      if (f == distinct.end()) distinct.push_back(sigma[i]);
+    }
+    if (distinct.size() > 4096) fail(GF_EINVAL, "at most 4096 distinct shifts per call");
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    hipStream_t s = sp->ctx->stream;
+    const Level &F = sp->fine();
+    double setup_ms = 0.0;
+    const Plan *plan;
+    {
+      const size_t np = sp->plans.size();
+      auto c0 = std::chrono::steady_clock::now();
+      plan = &get_plan(sp, distinct);
+      if (sp->plans.size() != np)
+        setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+    }
+    const size_t nv = (size_t)nsys * F.N;
+    InArray bin;
+    stage_in(bin, b, nv, mem, s);
+    OutArray xout;
+    stage_out(xout, x, nv, mem);
+    const int ldb = round_up(nsys, CT);
+    Workspace &w = get_workspace(sp, ldb, opts->precision, 3000);
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, s));
+    global_to_local(F, w.r.p, bin.p, nsys, ldb, s);
+    SolveSpec spec;
+    spec.prec = opts->precision;
+    spec.kind = opts->apply_kind;
+    spec.cheb = opts->cheb_degree > 0 ? opts->cheb_degree : 2;
+    spec.rtol = opts->rtol;
+    spec.max_iter = opts->max_iter;
+    spec.flags = opts->flags;
+    spec.ncols = nsys;
+    spec.col_sig.assign(sigma, sigma + nsys);
+    spec.col_node = node;
+    spec.plan = plan;
+    SolveResult r = solve_batch(sp, w, spec);
+    local_to_global(F, xout.p, w.x.p, nsys, 0, ldb, s);
+    HIPCHK(hipEventRecord(t1, s));
+    finish_out(xout, s);
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (stats) {
+      stats->n_systems = nsys;
+      stats->max_iters = r.max_it;
+      stats->max_rel_resid = r.max_rel;
+      stats->setup_ms = setup_ms;
+      stats->solve_ms = ms;
+      stats->apply_ms = r.apply_ms;
+      stats->apply_launches = r.apply_launches;
+      stats->apply_rows = 6 * F.n1 * F.n1;
+      stats->apply_col_sum = r.apply_col_sum;
+      stats->apply_bytes = r.apply_bytes;
+    }
+    if (r.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
+    if (r.flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
+  });
+}
+
 gf_status gf_sample_tape(gf_space *sp, double kappa, double beta, const gf_quad_rule *rule,
                          const gf_solve_opts *opts, int32_t nsamp, const double *b, double *u, int32_t mem,
                          gf_tape **tape, gf_solve_stats *stats) {

@@ -85,6 +85,8 @@ _SIGS = {
                          _i32, ctypes.POINTER(SolveStats)]),
     "gf_sample_batch": (_i32, [_vp, _i32, ctypes.POINTER(BatchItem), ctypes.POINTER(SolveOpts), _i32,
                                ctypes.POINTER(SolveStats)]),
+    "gf_solve_shifted": (_i32, [_vp, _i32, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), _i32,
+                                ctypes.POINTER(SolveStats)]),
     "gf_sample_tape": (_i32, [_vp, _dbl, _dbl, ctypes.POINTER(QuadRule), ctypes.POINTER(SolveOpts), _i32, _vp,
                               _vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(SolveStats)]),
     "gf_grad_kappa": (_i32, [_vp, _vp, _vp, _i32, ctypes.POINTER(SolveStats)]),
@@ -247,6 +249,20 @@ class Space:
                                 mem, ctypes.byref(st))
         _check(status, st.as_dict())
         return u, st.as_dict()
+
+    def solve_shifted(self, sigma, b, precision=GF_PREC_FP64, rtol=1e-10, max_iter=500, cheb_degree=0,
+                      apply_kind=GF_APPLY_STENCIL, flags=0):
+        """x_i = (sigma_i M + S)^-1 b_i for b of shape (nsys, N); returns (x, stats dict)."""
+        nsys = 1 if len(b.shape) == 1 else b.shape[0]
+        sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (nsys,)))
+        pb, mem, keep = _marshal_in(b, nsys * self.ndofs)
+        x = _alloc_like(b, (nsys, self.ndofs))
+        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
+        st = SolveStats()
+        status = _lib.gf_solve_shifted(self.h, nsys, sig.ctypes.data, pb, _ptr(x), ctypes.byref(opts), mem,
+                                       ctypes.byref(st))
+        _check(status, st.as_dict())
+        return x, st.as_dict()
 
     def sample_tape(self, kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=GF_PREC_FP64, rtol=1e-10,
                     max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0):
