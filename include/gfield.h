@@ -127,7 +127,7 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * V-cycle and its operator applications in float32; the outer CG (its operator application,
  * residuals, inner products), the coarsest-level Cholesky solve, the metric terms and the
  * quadrature sum in float64.  rtol: stop a system when |r| <= rtol |b| (Euclidean, global unknowns).
- * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction (0: default).
+ * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction (0: three).
  * apply_kind: GF_APPLY_STENCIL or GF_APPLY_SUMFACT for every operator application in the solver. */
 typedef struct {
   int32_t precision;

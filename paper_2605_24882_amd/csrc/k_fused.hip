@@ -29,47 +29,6 @@ __device__ __forceinline__ bool interior_row(int64_t r, int W, int P, int n1) {
   return lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
 }
 
-// Epilogue operands as direct kernel arguments (global, non-aliasing): stores through them then cannot
-// clobber the stencil coefficients, which therefore stay scalar (wavefront-uniform) loads.
-template <typename T>
-struct EpiPtrs {
-  T *__restrict__ y;
-  T *__restrict__ zout;
-  T *__restrict__ d;
-  const T *__restrict__ r;
-  const T *__restrict__ dM;
-  const T *__restrict__ dS;
-  const T *__restrict__ sig;
-  const T *__restrict__ invb;
-};
-
-template <typename T>
-__device__ __forceinline__ void epi_interior(int kind, int dot, T c1, T c2, T *__restrict__ y, T *__restrict__ zout,
-                                             T *__restrict__ d, const T *__restrict__ r, const T *__restrict__ dM,
-                                             const T *__restrict__ dS, const T *__restrict__ sig,
-                                             const T *__restrict__ invb, int64_t row, int64_t i, int col, T Az, T xc,
-                                             double &acc) {
-  switch (kind) {
-    case EPI_STORE:
-      y[i] = Az;
-      if (dot) acc += (double)xc * (double)Az;
-      break;
-    case EPI_RESID:
-      y[i] = r[i] - Az;
-      break;
-    default: {  // EPI_CHEB
-      const T rv = r[i];
-      const T D = sig[col] * dM[row] + dS[row];
-      const T res = (rv - Az) / D;
-      const T dn = (c1 != T(0) ? c1 * d[i] : T(0)) + c2 * invb[col] * res;
-      d[i] = dn;
-      const T zo = xc + dn;
-      zout[i] = zo;
-      if (dot) acc += (double)rv * (double)zo;
-    }
-  }
-}
-
 // reduce one double per lane over the 4 wavefronts of the block into partial[slot][col]
 __device__ __forceinline__ void block_partial(double acc, double *partial, int64_t slot, int ldb, int col) {
   __shared__ double red[4][CT];
@@ -89,7 +48,8 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
                                                      T *__restrict__ y, T *__restrict__ zout, T *__restrict__ d,
                                                      const T *__restrict__ r, const T *__restrict__ dM,
                                                      const T *__restrict__ dS, const T *__restrict__ invb,
-                                                     double *__restrict__ partial, const int *__restrict__ active) {
+                                                     double *__restrict__ partial, const int *__restrict__ active,
+                                                     int dflags) {
   constexpr int S = 2 * P + 1, WR = TY + 2 * P, SS = S * S;
   const int Lb = blockIdx.x;
   const int bl = (Lb & 7) * g.q + (Lb >> 3);
@@ -161,8 +121,9 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
         } else {
           const T rv = r[i];
           const T D = sg * dM[row] + dS[row];
-          const T dn = (c1 != T(0) ? c1 * d[i] : T(0)) + c2 * ib * ((rv - Az) / D);
-          d[i] = dn;
+          const T dp = (c1 != T(0)) ? ((dflags & 1) ? win[t + P][P] : d[i]) : T(0);
+          const T dn = c1 * dp + c2 * ib * ((rv - Az) / D);
+          if (!(dflags & 2)) d[i] = dn;
           const T zo = win[t + P][P] + dn;
           zout[i] = zo;
           if (DOT) acc += (double)rv * (double)zo;
@@ -207,8 +168,9 @@ __global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__re
         const T rv = e.r[i];
         const T D = e.sig[col] * e.dM[row] + e.dS[row];
         const T res = (rv - s) / D;
-        const T dn = (e.c1 != T(0) ? e.c1 * e.d[i] : T(0)) + e.c2 * e.invb[col] * res;
-        e.d[i] = dn;
+        const T dp = (e.c1 != T(0)) ? ((e.dflags & 1) ? x[i] : e.d[i]) : T(0);
+        const T dn = e.c1 * dp + e.c2 * e.invb[col] * res;
+        if (!(e.dflags & 2)) e.d[i] = dn;
         const T zo = x[i] + dn;
         e.zout[i] = zo;
         if (e.dot) a2 = (double)rv * (double)zo;
@@ -266,11 +228,12 @@ static void launch_apply_k(const ApplyGeom &g, const T *stM, const T *stS, const
   if (ev0) {
     // the runtime stamps the events at the start and end of this dispatch itself
     hipExtLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM,
-                          stS, x, ca, cb, e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active);
+                          stS, x, ca, cb, e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active,
+                          e.dflags);
     return;
   }
   hipLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca, cb,
-                     e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active);
+                     e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active, e.dflags);
 }
 
 template <typename T, int P, int TY>
@@ -496,7 +459,7 @@ __global__ __launch_bounds__(256) void k_cheb_first(RowGeom g, const TR *__restr
       const int64_t i = row * ldb + col;
       const T v = sc * rv[u] / (sg * dM[row] + dS[row]);
       if (r32) r32[i] = rv[u];
-      d[i] = v;
+      if (d) d[i] = v;
       z[i] = v;
     }
   }
@@ -571,8 +534,9 @@ __global__ __launch_bounds__(256) void k_epi_rows(RowGeom g, const T *__restrict
       const T rv = e.r[i];
       const T D = e.sig[col] * e.dM[row] + e.dS[row];
       const T res = (rv - Az) / D;
-      const T dn = (e.c1 != T(0) ? e.c1 * e.d[i] : T(0)) + e.c2 * e.invb[col] * res;
-      e.d[i] = dn;
+      const T dp = (e.c1 != T(0)) ? ((e.dflags & 1) ? x[i] : e.d[i]) : T(0);
+      const T dn = e.c1 * dp + e.c2 * e.invb[col] * res;
+      if (!(e.dflags & 2)) e.d[i] = dn;
       const T zo = x[i] + dn;
       e.zout[i] = zo;
       if (e.dot) a2 = (double)rv * (double)zo;

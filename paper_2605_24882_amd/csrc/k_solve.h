@@ -122,6 +122,10 @@ struct EpiArgs {
   const T *r = nullptr;   // CHEB/RESID: right-hand side
   const T *dM = nullptr, *dS = nullptr, *sig = nullptr, *invb = nullptr;
   T c1 = 0, c2 = 0;
+  // CHEB: bit 0 -- the previous direction equals the input iterate (first step after a start from
+  // zero), so it is taken from the input instead of d; bit 1 -- the new direction is not needed
+  // afterwards and is not stored
+  int dflags = 0;
 };
 
 struct ApplyGeom {

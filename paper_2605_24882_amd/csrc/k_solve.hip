@@ -350,6 +350,117 @@ __global__ __launch_bounds__(256) void k_prolong(T *zf, const T *zc, int Wf, int
   zf[i] += acc;
 }
 
+// Line-marching forms of the two transfers.  One wavefront per (patch, output row, column tile)
+// walks the input columns of its band of input rows in order: the contraction across rows is done
+// once per input column and pushed into a register window, and every output whose band ends at that
+// column is formed from the window.  Each input value is thus loaded once per output row that needs
+// it (instead of once per output value) and the loop body has no data-dependent branches.  The
+// knot-insertion bands have fixed widths rw <= p+2 (restriction) and pw <= (p+3)/2 (prolongation)
+// and start at non-decreasing input indices (rs, ps).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restrict__ r, const uint8_t *__restrict__ ownf,
+                                                       int Wf, int Wc, int n1f, int n1c, int ldb,
+                                                       const int *__restrict__ rs, const T *__restrict__ rcoef, int rw,
+                                                       const int *__restrict__ active, int ntiles) {
+  constexpr int RW = P + 2;
+  const int ct = blockIdx.x % ntiles;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x;
+  const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
+  if (id >= 6 * n1c) return;
+  const int iyc = id % n1c, m = id / n1c;
+  const int64_t ct0 = (int64_t)ct * CT;
+  const int64_t fbase = (int64_t)m * Wf * Wf;
+  const int fy0 = rs[iyc];
+  T wy[RW];
+  int64_t frow[RW];
+#pragma unroll
+  for (int k = 0; k < RW; ++k) {
+    wy[k] = k < rw ? rcoef[iyc * rw + k] : T(0);
+    // rows past the band carry weight 0; clamped so that their loads stay inside the patch
+    frow[k] = fbase + (int64_t)(min(fy0 + k, n1f - 1) + P) * Wf + P;
+  }
+  const int64_t cbase = (int64_t)m * Wc * Wc + (int64_t)(iyc + P) * Wc + P;
+  T tw[RW];
+#pragma unroll
+  for (int l = 0; l < RW; ++l) tw[l] = 0;
+  int ixc = 0;
+  int last = rs[0] + rw - 1;  // last fine column of output ixc's band
+  for (int fx = 0; fx < n1f; ++fx) {
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+      const int64_t rf = frow[k] + fx;
+      const T w = ownf[rf] ? wy[k] : T(0);  // one contribution per unknown: owner copies only
+      t += w * (r + rf * ldb + ct0)[lane];
+    }
+#pragma unroll
+    for (int l = 0; l < RW - 1; ++l) tw[l] = tw[l + 1];
+    tw[RW - 1] = t;  // the window now holds fine columns fx-RW+1 .. fx
+    while (ixc < n1c && last == fx) {
+      T acc = 0;
+#pragma unroll
+      for (int l = 0; l < RW; ++l) {
+        const int j = l - (RW - rw);
+        if (j >= 0) acc += rcoef[ixc * rw + j] * tw[l];
+      }
+      (rc + (cbase + ixc) * ldb + ct0)[lane] = acc;
+      ++ixc;
+      if (ixc < n1c) last = rs[ixc] + rw - 1;
+    }
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_prolong_rows(T *zf, const T *__restrict__ zc, int Wf, int Wc, int n1f, int n1c,
+                                                      int ldb, const int *__restrict__ ps,
+                                                      const T *__restrict__ pcoef, int pw,
+                                                      const int *__restrict__ active, int ntiles) {
+  constexpr int PW = (P + 3) / 2;
+  const int ct = blockIdx.x % ntiles;
+  if (active && !active[ct]) return;
+  const int lane = threadIdx.x;
+  const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
+  if (id >= 6 * n1f) return;
+  const int iyf = id % n1f, m = id / n1f;
+  const int64_t ct0 = (int64_t)ct * CT;
+  const int64_t cbase = (int64_t)m * Wc * Wc;
+  const int cy0 = ps[iyf];
+  T wy[PW];
+  int64_t crow[PW];
+#pragma unroll
+  for (int k = 0; k < PW; ++k) {
+    wy[k] = k < pw ? pcoef[iyf * pw + k] : T(0);
+    crow[k] = cbase + (int64_t)(min(cy0 + k, n1c - 1) + P) * Wc + P;
+  }
+  const int64_t fbase = (int64_t)m * Wf * Wf + (int64_t)(iyf + P) * Wf + P;
+  T sw[PW];
+#pragma unroll
+  for (int l = 0; l < PW; ++l) sw[l] = 0;
+  int ixf = 0;
+  int last = ps[0] + pw - 1;  // last coarse column of fine output ixf's band
+  for (int cx = 0; cx < n1c; ++cx) {
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < PW; ++k) t += wy[k] * (zc + (crow[k] + cx) * ldb + ct0)[lane];
+#pragma unroll
+    for (int l = 0; l < PW - 1; ++l) sw[l] = sw[l + 1];
+    sw[PW - 1] = t;
+    while (ixf < n1f && last == cx) {
+      T acc = 0;
+#pragma unroll
+      for (int l = 0; l < PW; ++l) {
+        const int j = l - (PW - pw);
+        if (j >= 0) acc += pcoef[ixf * pw + j] * sw[l];
+      }
+      T *zp = zf + (fbase + ixf) * ldb + ct0;
+      zp[lane] += acc;
+      ++ixf;
+      if (ixf < n1f) last = ps[ixf] + pw - 1;
+    }
+  }
+}
+
 template <typename T>
 static const T *res_coef(const Level &F);
 template <>
@@ -363,12 +474,30 @@ const double *pro_coef<double>(const Level &F) { return F.pro_c.p; }
 template <>
 const float *pro_coef<float>(const Level &F) { return F.pro_c32.p; }
 
+template <typename T, int P>
+static void launch_restrict_rows(const Level &F, const Level &C, T *rc, const T *r, int ldb, int ntiles,
+                                 const int *active, hipStream_t s) {
+  const int n = 6 * C.n1;
+  hipLaunchKernelGGL((k_restrict_rows<T, P>), dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, rc, r, F.owner.p, F.W,
+                     C.W, F.n1, C.n1, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles);
+}
+
 template <typename T>
 void restrict_residual(const Level &F, const Level &C, T *rc, const T *r, const T *Az, int ldb, int ntiles,
                        const int *active, hipStream_t s) {
-  const int n = 6 * C.n1 * C.n1;
-  hipLaunchKernelGGL(k_restrict<T>, dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, rc, r, Az, F.owner.p, F.W, C.W,
-                     C.n1, F.p, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles);
+  if (Az == nullptr && F.rw <= F.p + 2) {
+    switch (F.p) {
+      case 1: launch_restrict_rows<T, 1>(F, C, rc, r, ldb, ntiles, active, s); break;
+      case 2: launch_restrict_rows<T, 2>(F, C, rc, r, ldb, ntiles, active, s); break;
+      case 3: launch_restrict_rows<T, 3>(F, C, rc, r, ldb, ntiles, active, s); break;
+      case 4: launch_restrict_rows<T, 4>(F, C, rc, r, ldb, ntiles, active, s); break;
+      default: launch_restrict_rows<T, 5>(F, C, rc, r, ldb, ntiles, active, s); break;
+    }
+  } else {
+    const int n = 6 * C.n1 * C.n1;
+    hipLaunchKernelGGL(k_restrict<T>, dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, rc, r, Az, F.owner.p, F.W,
+                       C.W, C.n1, F.p, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles);
+  }
   HIPCHK(hipGetLastError());
 }
 template void restrict_residual<double>(const Level &, const Level &, double *, const double *, const double *, int,
@@ -376,12 +505,30 @@ template void restrict_residual<double>(const Level &, const Level &, double *, 
 template void restrict_residual<float>(const Level &, const Level &, float *, const float *, const float *, int, int,
                                        const int *, hipStream_t);
 
+template <typename T, int P>
+static void launch_prolong_rows(const Level &F, const Level &C, T *zf, const T *zc, int ldb, int ntiles,
+                                const int *active, hipStream_t s) {
+  const int n = 6 * F.n1;
+  hipLaunchKernelGGL((k_prolong_rows<T, P>), dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1,
+                     C.n1, ldb, F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles);
+}
+
 template <typename T>
 void prolong_add(const Level &F, const Level &C, T *zf, const T *zc, int ldb, int ntiles, const int *active,
                  hipStream_t s) {
-  const int n = 6 * F.n1 * F.n1;
-  hipLaunchKernelGGL(k_prolong<T>, dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1, F.p, ldb,
-                     F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles);
+  if (F.pw <= (F.p + 3) / 2) {
+    switch (F.p) {
+      case 1: launch_prolong_rows<T, 1>(F, C, zf, zc, ldb, ntiles, active, s); break;
+      case 2: launch_prolong_rows<T, 2>(F, C, zf, zc, ldb, ntiles, active, s); break;
+      case 3: launch_prolong_rows<T, 3>(F, C, zf, zc, ldb, ntiles, active, s); break;
+      case 4: launch_prolong_rows<T, 4>(F, C, zf, zc, ldb, ntiles, active, s); break;
+      default: launch_prolong_rows<T, 5>(F, C, zf, zc, ldb, ntiles, active, s); break;
+    }
+  } else {
+    const int n = 6 * F.n1 * F.n1;
+    hipLaunchKernelGGL(k_prolong<T>, dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1, F.p,
+                       ldb, F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles);
+  }
   HIPCHK(hipGetLastError());
 }
 template void prolong_add<double>(const Level &, const Level &, double *, const double *, int, int, const int *,
