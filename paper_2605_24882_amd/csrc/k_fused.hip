@@ -13,7 +13,8 @@
 // Mapping: one wavefront per strip of TY coefficient rows x TX coefficients of one patch and one
 // 64-wide column tile (lane = system).  The wavefront keeps a (TY + 2p) x (2p + 1) window of the
 // input in registers and moves it along the strip, loading one new column of TY + 2p values per
-// step.  Linear block ids are remapped so that every XCD walks a contiguous run of strips: the
+// step (one step ahead).  The stencil coefficients are shared by every system of the row: they
+// arrive as vector loads and are broadcast from their lanes.  Linear block ids are remapped so that every XCD walks a contiguous run of strips: the
 // halo rows shared by neighbouring strips then hit the same L2.
 #include "gf_internal.h"
 #include "k_solve.h"
@@ -23,6 +24,17 @@
 namespace gf {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// the value of v held by lane l (l wavefront-uniform), for every lane
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 
 __device__ __forceinline__ bool interior_row(int64_t r, int W, int P, int n1) {
   const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P;
@@ -76,37 +88,63 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
       ib = invb[col];
     }
     const int64_t pbase = (int64_t)m * W * W;
-    const T *xc = x + col;
-    T win[WR][S];
+    const int64_t ct0 = (int64_t)ct * CT;
+    // window rows iy0 .. iy0 + TY + 2P - 1, clamped into the padded patch: a clamped row only feeds
+    // outputs past the patch edge, which are not computed; the column of the next step is loaded
+    // before the arithmetic of the current one
+    int64_t roff[WR];
+#pragma unroll
+    for (int k = 0; k < WR; ++k) roff[k] = (pbase + (int64_t)min(iy0 + k, W - 1) * W) * ldb + ct0;
+    T win[WR][S], nxt[WR];
 #pragma unroll
     for (int k = 0; k < WR; ++k) {
-      const int py = iy0 + k;
 #pragma unroll
-      for (int c = 1; c < S; ++c)
-        win[k][c] = (py < W) ? xc[(pbase + (int64_t)py * W + (x0 + c - 1)) * ldb] : T(0);
+      for (int c = 1; c < S; ++c) win[k][c] = (x + roff[k] + (int64_t)(x0 + c - 1) * ldb)[lane];
+      nxt[k] = (x + roff[k] + (int64_t)(x0 + 2 * P) * ldb)[lane];
     }
+    // The (M, S) stencil pair of an output row is fetched with vector loads (lane l holds
+    // coefficient l of the concatenated pair), one output row ahead, and each coefficient is
+    // broadcast to the wavefront from its lane.  Scalar loads of the same data leave a full cache
+    // round trip per cache line exposed in every step.
+    constexpr int NCO = 2 * SS, NV = (NCO + 63) / 64;
+    auto coef_load = [&](int64_t crow, T *cv) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int lc = min(v * 64 + lane, NCO - 1);
+        cv[v] = lc < SS ? stM[crow * SS + lc] : stS[crow * SS + (lc - SS)];
+      }
+    };
+    T cvn[NV];
+    coef_load(pbase + (int64_t)(iy0 + P) * W + (x0 + P), cvn);
     for (int ix = x0; ix < x1; ++ix) {
 #pragma unroll
       for (int k = 0; k < WR; ++k) {
-        const int py = iy0 + k;
 #pragma unroll
         for (int c = 0; c < S - 1; ++c) win[k][c] = win[k][c + 1];
-        win[k][S - 1] = (py < W) ? xc[(pbase + (int64_t)py * W + (ix + 2 * P)) * ldb] : T(0);
+        win[k][S - 1] = nxt[k];
       }
+      const int64_t cn = (int64_t)min(ix + 1 + 2 * P, W - 1) * ldb;
+#pragma unroll
+      for (int k = 0; k < WR; ++k) nxt[k] = (x + roff[k] + cn)[lane];
 #pragma unroll
       for (int t = 0; t < TY; ++t) {
         const int iy = iy0 + t;
         if (iy >= n1) break;
         const int64_t row = pbase + (int64_t)(iy + P) * W + (ix + P);
-        const T *cm = stM + row * SS;
-        const T *cs = stS + row * SS;
+        T cv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cv[v] = cvn[v];
+        // next output row of this wavefront: row t+1 of this step, else row 0 of the next step
+        coef_load((t + 1 < TY && iy + 1 < n1) ? row + W : pbase + (int64_t)(iy0 + P) * W + (min(ix + 1, x1 - 1) + P),
+                  cvn);
         T am = 0, as = 0;
 #pragma unroll
         for (int dy = 0; dy < S; ++dy)
 #pragma unroll
           for (int dx = 0; dx < S; ++dx) {
-            am = fma(cm[dy * S + dx], win[t + dy][dx], am);
-            as = fma(cs[dy * S + dx], win[t + dy][dx], as);
+            const int im = dy * S + dx, is = SS + dy * S + dx;
+            am = fma(lane_bcast(cv[im / 64], im % 64), win[t + dy][dx], am);
+            as = fma(lane_bcast(cv[is / 64], is % 64), win[t + dy][dx], as);
           }
         const T Az = a * am + b * as;
         const int64_t i = row * ldb + col;
