@@ -105,3 +105,44 @@ def test_white_noise_factor_reproduces_mass(c1):
     assert np.allclose(F @ F.T, c1.M.toarray(), atol=1e-15)
     z = inputs.noise_vectors([3], F.shape[1])
     assert np.allclose(noise.load(c1, z)[0], F @ z[0], atol=1e-15)
+
+
+@pytest.mark.parametrize("beta,expect", [(0.8, (0, 0.4, 2)), (2.3, (1, 0.65, 2)), (1.5, (1, 0.5, 1)),
+                                         (0.2, (0, 0.2, 1)), (2.9, (2, 0.45, 2)), (3.0, (3, 0.0, 1))])
+def test_improved_split_rule(beta, expect):
+    """Sec. 3.4: beta' < 1/3 -> (n-1) + 2 (beta'+1)/2, beta' > 2/3 -> n + 2 beta'/2, else plain;
+    with n = 0 and beta' < 1/3 there is no integer part to borrow from, so the split stays plain."""
+    n, bf, passes = fractional.split(beta, "improved")
+    assert (n, passes) == expect[::2] and abs(bf - expect[1]) < 1e-14
+    assert abs(n + passes * bf - beta) < 1e-14
+
+
+@pytest.mark.parametrize("beta", [0.8, 2.3, 2.9])
+def test_improved_split_constant_load_and_dense_identity(c1, beta):
+    """Two passes of the rule: b = M 1 gives kappa^{-2n} Q(kappa^2)^2 1, and a white-noise load gives
+    V diag(lam^-n Q(lam)^2) V^T b."""
+    kappa, h, K = 4.0, 0.4, 15
+    n, bf, passes = fractional.split(beta, "improved")
+    assert passes == 2
+    u = fractional.sample(c1.M, c1.S, kappa, beta, h, K, K, c1.M @ np.ones(c1.N), mode="improved")[0]
+    assert np.allclose(u, kappa ** (-2 * n) * sinc.sinc_sum(kappa ** 2, bf, h, K, K) ** 2, rtol=1e-12)
+    b = noise.load(c1, inputs.noise_vectors([3], inputs.noise_length(2, 2)))
+    u = fractional.sample(c1.M, c1.S, kappa, beta, h, K, K, b, mode="improved")
+    ud = fractional.dense_quadrature(c1.M, c1.S, kappa, beta, h, K, K, b, mode="improved")
+    assert np.linalg.norm(u - ud) <= 1e-12 * np.linalg.norm(ud)
+
+
+@pytest.mark.parametrize("beta", [2.2, 0.9])
+def test_improved_split_is_more_accurate_at_equal_solves(c1, beta):
+    """The paper's claim behind the modification (Fig. 6): for beta' near 0 or 1 the improved split
+    with K/2 nodes per pass is closer to the exact power than the plain split with K nodes, once K is
+    in the exponential regime (K = 200 here; at K of a few dozen the plain rule can still win)."""
+    z = inputs.noise_vectors([0], inputs.noise_length(2, 2))
+    b = noise.load(c1, z)
+    kappa, K = 4.0, 200
+    ue = fractional.dense_exact(c1.M, c1.S, kappa, beta, b)
+    up = fractional.sample(c1.M, c1.S, kappa, beta, 1 / math.sqrt(K), K, K, b)
+    ui = fractional.sample(c1.M, c1.S, kappa, beta, 1 / math.sqrt(K // 2), K // 2, K // 2, b, mode="improved")
+    ep = np.linalg.norm(up - ue) / np.linalg.norm(ue)
+    ei = np.linalg.norm(ui - ue) / np.linalg.norm(ue)
+    assert ei < ep, (ei, ep)
