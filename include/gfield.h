@@ -116,10 +116,17 @@ gf_status gf_white_noise(const gf_space *space, int32_t nsamp, const double *z, 
 /* Sinc rule of eq. (beta-approx) with step h and nodes y_k = k h, k = -k_minus..k_plus:
  * t_k = exp(-2 y_k), shifted systems (t_k M + kappa^2 M + S) x_k = r, weights
  * omega_k = (2 h sin(pi beta')/pi) t_k^(1-beta').  The paper's rule is h = 1/sqrt(K),
- * k_minus = k_plus = K. */
+ * k_minus = k_plus = K.
+ * split: GF_SPLIT_PLAIN, beta = n + beta' with n = floor(beta), one application of the rule for
+ * beta'; or GF_SPLIT_IMPROVED, the modification of Sec. 3.4 for beta' near an integer: beta' < 1/3
+ * (with n >= 1) gives n-1 integer solves and the rule for beta'' = (beta'+1)/2 applied twice,
+ * beta' > 2/3 gives n integer solves and the rule for beta'' = beta'/2 applied twice (the second
+ * application on M times the first result); otherwise the plain split. */
+enum { GF_SPLIT_PLAIN = 0, GF_SPLIT_IMPROVED = 1 };
 typedef struct {
   double h;
   int32_t k_minus, k_plus;
+  int32_t split;
 } gf_quad_rule;
 
 enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
@@ -204,7 +211,8 @@ gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *
  * gf_sample_tape: gf_sample that also returns a tape holding the solutions the adjoint needs (the
  * node solutions x_{k,s} and the integer-chain solutions w_{i,s}: about (K + floor(beta)) x nsamp x N
  * doubles of device memory).  *tape is set only on GF_OK (NULL otherwise).  The tape refers to its
- * space: destroy the tape before the space. */
+ * space: destroy the tape before the space.  GF_EUNSUPPORTED for a rule applied twice (improved
+ * split). */
 gf_status gf_sample_tape(gf_space *space, double kappa, double beta, const gf_quad_rule *rule,
                          const gf_solve_opts *opts, int32_t nsamp, const double *b, double *u, int32_t mem,
                          gf_tape **tape, gf_solve_stats *stats);

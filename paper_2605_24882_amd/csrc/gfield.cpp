@@ -1188,6 +1188,7 @@ gf_status gf_white_noise(const gf_space *csp, int32_t nsamp, const double *z, do
 static void check_common(gf_space *sp, double kappa, double beta, const gf_quad_rule *rule,
                          const gf_solve_opts *opts, int32_t nsamp, int32_t mem) {
   if (!sp || !rule || !opts) fail(GF_EINVAL, "null argument");
+  if (rule->split != GF_SPLIT_PLAIN && rule->split != GF_SPLIT_IMPROVED) fail(GF_EINVAL, "unknown split");
   if (!(kappa > 0.0) || !std::isfinite(kappa)) fail(GF_EINVAL, "kappa must be positive and finite");
   if (!(beta > 0.0) || !std::isfinite(beta) || beta > 64.0) fail(GF_EINVAL, "beta must be in (0, 64]");
   if (!(rule->h > 0.0) || !std::isfinite(rule->h) || rule->k_minus < 0 || rule->k_plus < 0)
@@ -1206,6 +1207,24 @@ static void check_common(gf_space *sp, double kappa, double beta, const gf_quad_
 
 namespace gf {
 
+// beta = n + passes * bf: the plain split n = floor(beta), bf = beta - n, one pass; or the improved
+// split of Sec. 3.4: bf < 1/3 (and n >= 1) -> n-1 integer solves and the rule for (bf+1)/2 twice;
+// bf > 2/3 -> n integer solves and the rule for bf/2 twice
+static void split_beta(double beta, int mode, int *n, double *bf, int *passes) {
+  *n = (int)std::floor(beta);
+  *bf = beta - *n;
+  *passes = 1;
+  if (mode != GF_SPLIT_IMPROVED) return;
+  if (*bf > 0.0 && *bf < 1.0 / 3.0 && *n >= 1) {
+    *n -= 1;
+    *bf = (*bf + 1.0) / 2.0;
+    *passes = 2;
+  } else if (*bf > 2.0 / 3.0) {
+    *bf /= 2.0;
+    *passes = 2;
+  }
+}
+
 // One sampling request: a space, kappa, beta, a node rule and nsamp loads.
 struct SampleItem {
   gf_space *sp = nullptr;
@@ -1216,8 +1235,9 @@ struct SampleItem {
   double *u = nullptr;
   gf_tape *tape = nullptr;  // when set, the solutions are saved for the adjoint
   // derived
-  int n = 0;
-  double bf = 0;
+  int n = 0;       // integer solves
+  double bf = 0;   // order of the sinc rule
+  int passes = 1;  // applications of the rule (2 for the improved split)
   std::vector<double> node_sig, omega;
   const Plan *chain_plan = nullptr, *frac_plan = nullptr;
   InArray bin;
@@ -1248,8 +1268,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     bool built = false;
     for (auto &it : items) {
       const size_t np = it.sp->plans.size();
-      it.n = (int)std::floor(it.beta);
-      it.bf = it.beta - it.n;
+      split_beta(it.beta, it.rule.split, &it.n, &it.bf, &it.passes);
       if (it.n > 0) it.chain_plan = &get_plan(it.sp, std::vector<double>{it.kappa * it.kappa});
       if (it.bf > 0.0) {
         for (int k = -it.rule.k_minus; k <= it.rule.k_plus; ++k) {
@@ -1333,14 +1352,18 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
       if (i == it.n && it.bf == 0.0) local_to_global(F, it.uout.p, it.wc->x.p, it.nsamp, 0, ldc, s);
     }
   }
-  // ---- sinc nodes: all nodes x samples of every request, one batch per request, one graph
-  {
+  // ---- sinc nodes: all nodes x samples of every request, one batch per request, one graph.  The
+  // improved split applies the rule a second time, to M times the first result.
+  int max_pass = 0;
+  for (auto &it : items)
+    if (it.bf > 0.0) max_pass = std::max(max_pass, it.passes);
+  for (int pass = 0; pass < max_pass; ++pass) {
     std::vector<BatchSolve> bs;
     std::vector<SampleItem *> owners;
     bs.reserve(items.size());
     for (size_t idx = 0; idx < items.size(); ++idx) {
       auto &it = items[idx];
-      if (it.bf <= 0.0) continue;
+      if (it.bf <= 0.0 || pass >= it.passes) continue;
       const Level &F = it.sp->fine();
       const int K = (int)it.node_sig.size();
       const int ncols = K * it.nsamp;
@@ -1348,7 +1371,10 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
       const int ldf = round_up(ncols, CT);
       const double *rsrc;
       int ldr;
-      if (it.n > 0) {
+      if (pass > 0) {
+        rsrc = it.rloc.p;  // M v of the previous pass
+        ldr = ldc;
+      } else if (it.n > 0) {
         rsrc = it.wc->r.p;
         ldr = it.wc->ldb;
       } else {
@@ -1375,23 +1401,35 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
       bs.push_back(std::move(b));
       owners.push_back(&it);
     }
-    if (!bs.empty()) {
-      std::vector<BatchSolve *> ptrs;
-      for (auto &b : bs) ptrs.push_back(&b);
-      solve_all(ctx, ptrs, use_graph);
-      for (size_t q = 0; q < bs.size(); ++q) {
-        account(bs[q]);
-        SampleItem &it = *owners[q];
-        if (it.tape) {
-          const size_t nx = (size_t)it.sp->fine().R * it.wf->ldb;
-          it.tape->xk.alloc(nx);
-          HIPCHK(hipMemcpyAsync(it.tape->xk.p, it.wf->x.p, nx * sizeof(double), hipMemcpyDeviceToDevice, s));
-        }
-        DBuf<double> om;
-        om.upload(it.omega, s);
-        quadrature_sum(it.sp->fine(), it.uout.p, it.wf->x.p, om.p, (int)it.omega.size(), it.nsamp, it.wf->ldb, s);
-        HIPCHK(hipStreamSynchronize(s));
+    if (bs.empty()) continue;
+    std::vector<BatchSolve *> ptrs;
+    for (auto &b : bs) ptrs.push_back(&b);
+    solve_all(ctx, ptrs, use_graph);
+    for (size_t q = 0; q < bs.size(); ++q) {
+      account(bs[q]);
+      SampleItem &it = *owners[q];
+      const Level &F = it.sp->fine();
+      if (it.tape) {
+        const size_t nx = (size_t)F.R * it.wf->ldb;
+        it.tape->xk.alloc(nx);
+        HIPCHK(hipMemcpyAsync(it.tape->xk.p, it.wf->x.p, nx * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
+      DBuf<double> om;
+      om.upload(it.omega, s);
+      // the sum lands in u; before a further pass it becomes that pass's right-hand side M u
+      quadrature_sum(F, it.uout.p, it.wf->x.p, om.p, (int)it.omega.size(), it.nsamp, it.wf->ldb, s);
+      if (pass + 1 < it.passes) {
+        const int ldc = round_up(it.nsamp, CT);
+        DBuf<double> vloc;
+        vloc.alloc((size_t)F.R * ldc);
+        global_to_local(F, vloc.p, it.uout.p, it.nsamp, ldc, s);
+        it.rloc.alloc((size_t)F.R * ldc);
+        Workspace &wv = *it.wf;
+        apply_level<double>(F, GF_APPLY_STENCIL, vloc.p, it.rloc.p, wv.one64.p, wv.zero64.p, ldc, ldc / CT, nullptr,
+                            s);
+        HIPCHK(hipStreamSynchronize(s));  // before vloc is released
+      }
+      HIPCHK(hipStreamSynchronize(s));
     }
   }
   HIPCHK(hipEventRecord(t1, s));
@@ -1766,8 +1804,11 @@ gf_status gf_sample_tape(gf_space *sp, double kappa, double beta, const gf_quad_
     t->rule = *rule;
     t->opts = *opts;
     t->nsamp = nsamp;
-    t->n = (int)std::floor(beta);
-    t->bf = beta - t->n;
+    int passes = 1;
+    split_beta(beta, rule->split, &t->n, &t->bf, &passes);
+    if (passes != 1)
+      fail(GF_EUNSUPPORTED, "the adjoint is implemented for one pass of the rule (plain split, or an improved "
+                            "split that reduces to it)");
     t->ldc = round_up(nsamp, CT);
     t->ldf = round_up(K * nsamp, CT);
     t->w.resize(t->n);

@@ -34,12 +34,14 @@ GF_APPLY_STENCIL, GF_APPLY_SUMFACT = 0, 1
 GF_PREC_FP64, GF_PREC_MIXED = 0, 1
 GF_FLAG_TIME_APPLY = 1
 GF_FLAG_NO_GRAPH = 2
+GF_SPLIT_PLAIN, GF_SPLIT_IMPROVED = 0, 1
 STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ENOMEM", 3: "GF_EDEVICE", 4: "GF_ENOCONV",
                 5: "GF_EBREAKDOWN", 6: "GF_EUNSUPPORTED"}
 
 
 class QuadRule(ctypes.Structure):
-    _fields_ = [("h", ctypes.c_double), ("k_minus", ctypes.c_int32), ("k_plus", ctypes.c_int32)]
+    _fields_ = [("h", ctypes.c_double), ("k_minus", ctypes.c_int32), ("k_plus", ctypes.c_int32),
+                ("split", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -237,12 +239,12 @@ class Space:
         return b
 
     def sample(self, kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=GF_PREC_FP64, rtol=1e-10,
-               max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0):
+               max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0, split=GF_SPLIT_PLAIN):
         """Field samples u for loads b (nsamp, N); returns (u, stats dict)."""
         nsamp = 1 if len(b.shape) == 1 else b.shape[0]
         pb, mem, keep = _marshal_in(b, nsamp * self.ndofs)
         u = _alloc_like(b, (nsamp, self.ndofs))
-        rule = QuadRule(h, k_minus, k_plus)
+        rule = QuadRule(h, k_minus, k_plus, split)
         opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
         st = SolveStats()
         status = _lib.gf_sample(self.h, kappa, beta, ctypes.byref(rule), ctypes.byref(opts), nsamp, pb, _ptr(u),
@@ -265,12 +267,12 @@ class Space:
         return x, st.as_dict()
 
     def sample_tape(self, kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=GF_PREC_FP64, rtol=1e-10,
-                    max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0):
+                    max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0, split=GF_SPLIT_PLAIN):
         """sample() that also keeps the forward solutions; returns (u, Tape, stats dict)."""
         nsamp = 1 if len(b.shape) == 1 else b.shape[0]
         pb, mem, keep = _marshal_in(b, nsamp * self.ndofs)
         u = _alloc_like(b, (nsamp, self.ndofs))
-        rule = QuadRule(h, k_minus, k_plus)
+        rule = QuadRule(h, k_minus, k_plus, split)
         opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
         st = SolveStats()
         th = _vp()
@@ -355,8 +357,8 @@ def sample_batch(ctx, requests, precision=GF_PREC_FP64, rtol=1e-10, max_iter=500
                  apply_kind=GF_APPLY_STENCIL, flags=0):
     """Several sampling requests solved together.
 
-    requests: sequence of dicts with keys space, kappa, beta, b and optionally h, k_minus, k_plus
-    (defaults 0.4, 20, 20).  All loads must be of one kind (NumPy or CUDA tensors).
+    requests: sequence of dicts with keys space, kappa, beta, b and optionally h, k_minus, k_plus,
+    split (defaults 0.4, 20, 20, plain).  All loads must be of one kind (NumPy or CUDA tensors).
     Returns (list of u, stats dict)."""
     if not requests:
         raise ValueError("no requests")
@@ -374,7 +376,8 @@ def sample_batch(ctx, requests, precision=GF_PREC_FP64, rtol=1e-10, max_iter=500
         keep.append(kb)
         outs.append(u)
         items[i] = BatchItem(sp.h, r["kappa"], r["beta"],
-                             QuadRule(r.get("h", 0.4), r.get("k_minus", 20), r.get("k_plus", 20)), nsamp, pb,
+                             QuadRule(r.get("h", 0.4), r.get("k_minus", 20), r.get("k_plus", 20),
+                                      r.get("split", GF_SPLIT_PLAIN)), nsamp, pb,
                              _ptr(u))
     opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
     st = SolveStats()

@@ -248,3 +248,39 @@ def test_solve_shifted_matches_direct_solves(ctx):
     with pytest.raises(g.GfieldError) as e:
         sp.solve_shifted([1.0, -1.0], b[:2])
     assert e.value.status == g.GF_EINVAL
+
+
+@pytest.mark.parametrize("beta", [0.8, 2.3, 2.9, 1.5])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_improved_split_matches_oracle(ctx, beta, prec):
+    """Sec. 3.4's improved split (the rule for beta'' applied twice where beta' < 1/3 or > 2/3;
+    beta = 1.5 keeps the plain split)."""
+    sp, d = space(ctx, 2, 3, True), disc(2, 3, True)
+    b = noise.load(d, inputs.noise_vectors([2, 9], inputs.noise_length(2, 3)))
+    K = 12
+    u, st = sp.sample(3.0, beta, b, h=0.4, k_minus=K, k_plus=K, precision=prec, rtol=1e-13,
+                      split=g.GF_SPLIT_IMPROVED)
+    ref = fractional.sample(d.M, d.S, 3.0, beta, 0.4, K, K, b, mode="improved")
+    n, bf, passes = fractional.split(beta, "improved")
+    assert st["n_systems"] == 2 * (n + passes * (2 * K + 1))
+    assert mrel(d, u, ref) <= 1e-10
+    if passes == 1:
+        u1, _ = sp.sample(3.0, beta, b, h=0.4, k_minus=K, k_plus=K, precision=prec, rtol=1e-13)
+        assert np.array_equal(u, u1)
+
+
+def test_improved_split_in_a_batch_and_tape_refusal(ctx):
+    sps = [space(ctx, 2, 2, True), space(ctx, 3, 2, True)]
+    ds = [disc(2, 2, True), disc(3, 2, True)]
+    reqs, refs = [], []
+    for sp_, d_, beta, split in zip(sps, ds, (2.2, 0.95), (g.GF_SPLIT_IMPROVED, g.GF_SPLIT_PLAIN)):
+        b = noise.load(d_, inputs.noise_vectors([1], inputs.noise_length(d_.p, 2)))
+        reqs.append(dict(space=sp_, kappa=4.0, beta=beta, b=b, k_minus=10, k_plus=10, split=split))
+        refs.append(fractional.sample(d_.M, d_.S, 4.0, beta, 0.4, 10, 10, b,
+                                      mode="improved" if split == g.GF_SPLIT_IMPROVED else "plain"))
+    us, _ = g.sample_batch(ctx, reqs, rtol=1e-13)
+    for d_, u, ref in zip(ds, us, refs):
+        assert mrel(d_, u, ref) <= 1e-10
+    with pytest.raises(g.GfieldError) as e:
+        sps[0].sample_tape(4.0, 2.2, reqs[0]["b"], k_minus=10, k_plus=10, split=g.GF_SPLIT_IMPROVED)
+    assert e.value.status == g.GF_EUNSUPPORTED
