@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + sorted(BATCH_CONFIGS))
     ap.add_argument("--apply-kind", type=int, default=0)
     ap.add_argument("--cheb", type=int, default=0)
+    ap.add_argument("--split", choices=("plain", "improved"), default="plain",
+                    help="split of beta: plain n + beta', or the improved split (the rule applied twice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the one-system-per-call FP64 GPU reference timing")
@@ -289,7 +291,8 @@ def main():
         b = sp.white_noise(z)
         del z
         kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
-                  apply_kind=args.apply_kind)
+                  apply_kind=args.apply_kind,
+                  split=g.GF_SPLIT_IMPROVED if args.split == "improved" else g.GF_SPLIT_PLAIN)
 
         if args.config in GRADIENT_CONFIGS:
             pts, yv = inputs.sphere_points_and_targets(1000, seed=7)
@@ -312,6 +315,8 @@ def main():
             def step(flags=0):
                 return sp.sample(kappa, beta, b, flags=flags, **kw)
             workload = workload_name(cfg)
+        if args.split == "improved":
+            workload += "; improved split (rule applied twice where beta' < 1/3 or > 2/3)"
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

@@ -284,3 +284,40 @@ def test_improved_split_in_a_batch_and_tape_refusal(ctx):
     with pytest.raises(g.GfieldError) as e:
         sps[0].sample_tape(4.0, 2.2, reqs[0]["b"], k_minus=10, k_plus=10, split=g.GF_SPLIT_IMPROVED)
     assert e.value.status == g.GF_EUNSUPPORTED
+
+
+def test_edge_cases(ctx):
+    """Degenerate and boundary requests: a single sinc node, integer beta (chain only), beta < 1 (no
+    chain), one sample, zero evaluation points, and invalid sizes rejected before any work."""
+    import scipy.sparse.linalg as spla
+    sp, d = space(ctx, 2, 2), disc(2, 2)
+    b = noise.load(d, inputs.noise_vectors([11], inputs.noise_length(2, 2)))
+    # one node: u = omega_0 (t_0 M + kappa^2 M + S)^-1 b with t_0 = 1
+    u, st = sp.sample(2.0, 0.5, b, h=0.4, k_minus=0, k_plus=0, rtol=1e-13)
+    _, omega, _ = fractional.nodes(2.0, 0.5, 0.4, 0, 0)
+    ref = omega[0] * spla.spsolve((5.0 * d.M + d.S).tocsc(), b[0])
+    assert st["n_systems"] == 1 and mrel(d, u, ref) <= 1e-10
+    # beta = 1: one chain solve, no nodes
+    u, st = sp.sample(2.0, 1.0, b, rtol=1e-13)
+    ref = spla.spsolve((4.0 * d.M + d.S).tocsc(), b[0])
+    assert st["n_systems"] == 1 and mrel(d, u, ref) <= 1e-10
+    # zero points
+    vals = sp.eval(np.zeros(0, dtype=np.int32), np.zeros((0, 2)), b)
+    assert vals.shape == (1, 0)
+    out = sp.eval_adjoint(np.zeros(0, dtype=np.int32), np.zeros((0, 2)), np.zeros((1, 0)))
+    assert out.shape == (1, d.N) and not out.any()
+    # invalid requests
+    import ctypes
+    rule = g.QuadRule(0.4, 5, 5, 0)
+    opts = g.SolveOpts(0, 1e-10, 100, 0, 0, 0)
+    x = np.zeros(d.N)
+    for kappa, beta, nsamp, r, o in [(0.0, 0.5, 1, rule, opts), (2.0, -1.0, 1, rule, opts), (2.0, 0.5, 0, rule, opts),
+                                     (2.0, 0.5, 1, g.QuadRule(0.0, 5, 5, 0), opts),
+                                     (2.0, 0.5, 1, g.QuadRule(0.4, -1, 5, 0), opts),
+                                     (2.0, 0.5, 1, g.QuadRule(0.4, 5, 5, 7), opts),
+                                     (2.0, 0.5, 1, rule, g.SolveOpts(0, 2.0, 100, 0, 0, 0)),
+                                     (2.0, 0.5, 1, rule, g.SolveOpts(3, 1e-10, 100, 0, 0, 0)),
+                                     (float("nan"), 0.5, 1, rule, opts)]:
+        st = g.SolveStats()
+        assert g._lib.gf_sample(sp.h, kappa, beta, ctypes.byref(r), ctypes.byref(o), nsamp, x.ctypes.data,
+                                x.ctypes.data, g.GF_HOST, ctypes.byref(st)) == g.GF_EINVAL, (kappa, beta, nsamp)
