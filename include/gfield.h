@@ -134,7 +134,9 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * V-cycle and its operator applications in float32; the outer CG (its operator application,
  * residuals, inner products), the coarsest-level Cholesky solve, the metric terms and the
  * quadrature sum in float64.  rtol: stop a system when |r| <= rtol |b| (Euclidean, global unknowns).
- * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction (0: three).
+ * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction on the finest
+ * level (0: three); the coarser levels take one (two on levels of more than 50,000 patch coefficients),
+ * at most cheb_degree.
  * apply_kind: GF_APPLY_STENCIL or GF_APPLY_SUMFACT for every operator application in the solver. */
 typedef struct {
   int32_t precision;

@@ -494,6 +494,7 @@ constexpr int kPowerIters = 16;
 // gave the fewest seconds per sample on degrees 2 and 3 at 64x64 and 128x128 elements per patch
 // (two and four were within 5% for degree 2)
 constexpr int kDefaultCheb = 3;
+constexpr double kChebTwoRows = 50000.0;
 
 static std::string plan_key(const std::vector<double> &sig) {
   std::ostringstream os;
@@ -637,7 +638,13 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   const T *dM = Prec<T>::dM(L), *dS = Prec<T>::dS(L), *sig = Prec<T>::sig(w), *one = Prec<T>::one(w);
   Scratch sc = w.scratch();
   std::vector<double> c1, c2;
-  cheb_coeffs(spec.cheb, c1, c2);
+  // smoothing degree of this level: spec.cheb on the finest level; below it, where each smoothing
+  // step is cheap in bytes but a full round of launches, one step (two on levels with more than
+  // kChebTwoRows patch rows).  Measured on the workloads of bench.py: the CG iteration count is set
+  // by the finest level's smoothing, and fewer coarse steps save time.
+  int deg = spec.cheb;
+  if (li + 1 < sp->nlev()) deg = std::min(spec.cheb, (6.0 * L.n1 * L.n1 > kChebTwoRows) ? 2 : 1);
+  cheb_coeffs(deg, c1, c2);
   // dflags: the first step after the start from zero takes its previous direction from the
   // iterate itself (d = z after the first step); the last step of each sweep keeps no direction
   // (the next sweep starts with c1 = 0)
@@ -665,7 +672,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   };
   // pre-smoothing from zero (the first step's direction is the iterate itself and is not stored)
   cheb_first<T, TR>(L, rsrc, rconv, za, nullptr, dM, dS, sig, inv, (T)c2[0], ldb, nt, act, s);
-  for (int k = 1; k < spec.cheb; ++k) smooth(k, false, (k == 1 ? 1 : 0) | (k == spec.cheb - 1 ? 2 : 0));
+  for (int k = 1; k < deg; ++k) smooth(k, false, (k == 1 ? 1 : 0) | (k == deg - 1 ? 2 : 0));
   // residual, restriction, coarse correction, prolongation
   {
     EpiArgs<T> e;
@@ -681,7 +688,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   T *zc = vcycle<T, T>(sp, w, spec, li - 1, rc, nullptr, -1, nullptr, s);
   prolong_add<T>(L, C, za, zc, ldb, nt, act, s);
   // post-smoothing
-  for (int k = 0; k < spec.cheb; ++k) smooth(k, k == spec.cheb - 1, k == spec.cheb - 1 ? 2 : 0);
+  for (int k = 0; k < deg; ++k) smooth(k, k == deg - 1, k == deg - 1 ? 2 : 0);
   return za;
 }
 
