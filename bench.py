@@ -81,14 +81,16 @@ def source_sha():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def _outer_apply_rows(path, p, value_key):
-    """(grid, value) of every outer-CG operator launch of the node batch in a rocprofv3 csv:
-    k_apply_fused<double, p, *, EPI_STORE, dot> at the largest grid of that instance."""
+def _kernel_rows(path, p, kind, value_key):
+    """values of every launch of the FP64 stencil kernel with epilogue `kind` ("outer": EPI_STORE with
+    the inner product, "smoother": EPI_CHEB) at the finest level (the largest grid of that kernel)."""
     rows = list(csv.DictReader(open(path)))
     out = []
     for r in rows:
         name = r["Kernel_Name"].split("(")[0]
-        if name.startswith(f"void gf::k_apply_fused<double, {p}, ") and name.endswith(", 0, 1>"):
+        if not name.startswith(f"void gf::k_apply_fused<double, {p}, "):
+            continue
+        if (kind == "outer" and name.endswith(", 0, 1>")) or (kind == "smoother" and (", 1, 0>" in name or ", 1, 1>" in name)):
             grid = int(r.get("Grid_Size") or r.get("Grid_Size_X"))
             out.append((grid, value_key(r)))
     big = max(g for g, _ in out)
@@ -96,26 +98,32 @@ def _outer_apply_rows(path, p, value_key):
 
 
 def pmc_summary(fetch_csv, write_csv, config, probe_mib):
-    """Per-launch HBM traffic of the outer operator from two counter runs (FETCH_SIZE, WRITE_SIZE, KiB
-    per dispatch), each scaled by what the counter reads for the plain elementwise probe kernel
-    (dst = -src over probe_mib MiB, which reads and writes exactly that many bytes)."""
+    """Per-launch HBM traffic of the finest-level smoothing launches and of the outer operator from
+    two counter runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads
+    for the plain elementwise probe kernel (dst = -src over probe_mib MiB, which reads and writes
+    exactly that many bytes)."""
     p = CONFIGS[config][1]
     known_kib = probe_mib * 1024.0
     out = {"config": config, "kernel_source_sha256": source_sha(), "probe_mib": probe_mib}
+    factors = {}
     for key, path in (("fetch", fetch_csv), ("write", write_csv)):
         rows = list(csv.DictReader(open(path)))
         probe = [float(r["Counter_Value"]) for r in rows if "neg_kernel" in r["Kernel_Name"]]
         if not probe:
             raise SystemExit(f"{path}: no probe kernel dispatch")
-        factor = known_kib / (sum(probe) / len(probe))
-        vals, grid = _outer_apply_rows(path, p, lambda r: float(r["Counter_Value"]))
+        factors[key] = known_kib / (sum(probe) / len(probe))
         out[f"{key}_probe_kib"] = sum(probe) / len(probe)
-        out[f"{key}_factor"] = round(factor, 4)
-        out[f"{key}_kib_per_launch"] = sum(vals) / len(vals)
-        out[f"{key}_launches"] = len(vals)
-        out[f"{key}_grid"] = grid
-        out[f"{key}_bytes_per_launch"] = sum(vals) / len(vals) * 1024.0 * factor
-    out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+        out[f"{key}_factor"] = round(factors[key], 4)
+    for kind in ("smoother", "outer"):
+        e = {}
+        for key, path in (("fetch", fetch_csv), ("write", write_csv)):
+            vals, grid = _kernel_rows(path, p, kind, lambda r: float(r["Counter_Value"]))
+            e[f"{key}_kib_per_launch"] = sum(vals) / len(vals)
+            e[f"{key}_launches"] = len(vals)
+            e[f"{key}_grid"] = grid
+            e[f"{key}_bytes_per_launch"] = sum(vals) / len(vals) * 1024.0 * factors[key]
+        e["traffic_bytes_per_launch"] = e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
+        out[kind] = e
     return out
 
 
@@ -131,15 +139,20 @@ def trace_summary(trace_csv, p, top=25):
              "| ms | % | calls | avg us | kernel | grid |", "|---:|---:|---:|---:|---|---|"]
     for (k, g), v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
         lines.append(f"| {sum(v) / 1e3:.2f} | {100 * sum(v) / tot:.1f} | {len(v)} | {sum(v) / len(v):.2f} | `{k}` | {g[0]} |")
-    ts = []
-    for r in rows:
-        name = r["Kernel_Name"].split("(")[0]
-        if name.startswith(f"void gf::k_apply_fused<double, {p}, ") and name.endswith(", 0, 1>"):
-            ts.append((int(r["Start_Timestamp"]), int(r["Grid_Size_X"]),
-                       (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
-    big = max(g for _, g, _ in ts)
-    d = [x for _, g, x in sorted(ts) if g == big]
-    lines += ["", f"outer operator (node batch, grid {big}): {len(d)} launches, avg {sum(d) / len(d):.2f} us"]
+    d = {}
+    for kind in ("smoother", "outer"):
+        ts = []
+        for r in rows:
+            name = r["Kernel_Name"].split("(")[0]
+            if not name.startswith(f"void gf::k_apply_fused<double, {p}, "):
+                continue
+            if (kind == "outer" and name.endswith(", 0, 1>")) or (kind == "smoother" and (", 1, 0>" in name or ", 1, 1>" in name)):
+                ts.append((int(r["Start_Timestamp"]), int(r["Grid_Size_X"]),
+                           (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+        big = max(g for _, g, _ in ts)
+        d[kind] = [x for _, g, x in sorted(ts) if g == big]
+        lines += ["", f"{kind} ({'finest-level Chebyshev smoothing step' if kind == 'smoother' else 'outer CG operator'}, "
+                      f"grid {big}): {len(d[kind])} launches, avg {sum(d[kind]) / len(d[kind]):.2f} us"]
     return "\n".join(lines), d
 
 
@@ -305,7 +318,8 @@ def main():
                 gk, st2 = tape.grad_kappa(sp.eval_adjoint(patch, stp, vals - yt[None, :]))
                 tape.close()
                 st = dict(st1)
-                for key in ("apply_ms", "apply_launches", "apply_bytes", "n_systems"):
+                for key in ("apply_ms", "apply_launches", "apply_bytes", "smooth_ms", "smooth_launches",
+                            "smooth_bytes", "n_systems"):
                     st[key] = st1[key] + st2[key]
                 st["max_iters"] = max(st1["max_iters"], st2["max_iters"])
                 st["max_rel_resid"] = max(st1["max_rel_resid"], st2["max_rel_resid"])
@@ -329,7 +343,8 @@ def main():
         u, st = step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    agg = {"apply_ms": 0.0, "apply_launches": 0, "apply_bytes": 0.0, "max_iters": 0, "max_rel_resid": 0.0}
+    agg = {"apply_ms": 0.0, "apply_launches": 0, "apply_bytes": 0.0, "smooth_ms": 0.0, "smooth_launches": 0,
+           "smooth_bytes": 0.0, "max_iters": 0, "max_rel_resid": 0.0}
     for _ in range(args.steps):
         u, st = step()
         agg["max_iters"] = max(agg["max_iters"], st["max_iters"])
@@ -343,29 +358,35 @@ def main():
     # shapes are the same)
     for _ in range(max(1, args.steps // 2)):
         u, st = step(flags=g.GF_FLAG_TIME_APPLY)
-        for key in ("apply_ms", "apply_launches", "apply_bytes"):
+        for key in ("apply_ms", "apply_launches", "apply_bytes", "smooth_ms", "smooth_launches", "smooth_bytes"):
             agg[key] += st[key]
 
-    # roofline of the dominant kernel: the FP64 stencil operator of the outer CG.  Algorithmic bytes
-    # per launch (library count): read x and write y, 8 B each, per active column and patch row, plus
-    # the two (2p+1)^2 FP64 stencils per row
-    launches = max(1, agg["apply_launches"])
-    bytes_per_launch = agg["apply_bytes"] / launches
-    avg_ms = agg["apply_ms"] / launches
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    # measured HBM traffic per launch (counter runs of the same kernel source), else null
-    traffic = None
-    tf = traffic_file(args.config)
-    if os.path.exists(tf):
-        with open(tf) as f:
-            t = json.load(f)
-        if t.get("kernel_source_sha256") == source_sha():
-            traffic = round(t["traffic_bytes_per_launch"])
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(achieved / 8000.0, 4), "traffic": traffic,
-            "kernel": f"k_apply_fused<double,p,*,EPI_STORE,dot> (outer CG operator, stencil form)",
-            "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch),
-            "launches": agg["apply_launches"]}
+    # roofline of the dominant kernel: the Chebyshev smoothing step on the finest level (the stencil
+    # operator with the smoother's epilogue; most of the step's time), and, as a second entry, the
+    # FP64 stencil operator of the outer CG.  Algorithmic bytes (library count): the batch vectors
+    # each launch reads and writes, per active column and patch row, plus the two stencils per row
+    def roof_entry(ms, launches, nbytes, kernel, kind):
+        launches = max(1, launches)
+        per_launch = nbytes / launches
+        avg_ms = ms / launches
+        achieved = per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+        traffic = None
+        tf = traffic_file(args.config)
+        if os.path.exists(tf):
+            with open(tf) as f:
+                t = json.load(f)
+            if t.get("kernel_source_sha256") == source_sha() and kind in t:
+                traffic = round(t[kind]["traffic_bytes_per_launch"])
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                "frac": round(achieved / 8000.0, 4), "traffic": traffic, "kernel": kernel,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(per_launch), "launches": launches}
+
+    vt = "double" if prec == 0 else "float"
+    roof = roof_entry(agg["smooth_ms"], agg["smooth_launches"], agg["smooth_bytes"],
+                      f"k_apply_fused<{vt},p,*,EPI_CHEB,*> (Chebyshev smoothing step on the finest level, stencil form)",
+                      "smoother")
+    roof_outer = roof_entry(agg["apply_ms"], agg["apply_launches"], agg["apply_bytes"],
+                            "k_apply_fused<double,p,*,EPI_STORE,dot> (outer CG operator, stencil form)", "outer")
 
     out = {
         "metric": "field samples/sec at rel-L2 err <=1e-6 vs FP64 oracle; operator-apply HBM GB/s",
@@ -384,6 +405,7 @@ def main():
                    "max_cg_iters": agg["max_iters"], "max_rel_resid": agg["max_rel_resid"],
                    "space_setup_s": round(space_s, 3)},
         "roofline": roof,
+        "roofline_outer_operator": roof_outer,
     }
     if args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_one_at_a_time:
         out["gpu_one_solve_at_a_time"] = one_at_a_time(g, sp, b, CONFIGS[args.config], kw)

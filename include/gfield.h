@@ -161,13 +161,20 @@ typedef struct {
   double apply_bytes;      /* with GF_FLAG_TIME_APPLY: algorithmic bytes of those launches (8-byte x read
                               and y written per active column and patch row, plus the two (2p+1)^2
                               FP64 stencils per row), summed */
+  double smooth_ms;        /* with GF_FLAG_TIME_APPLY: summed duration of the Chebyshev smoothing launches on
+                              the finest level (same batches as apply_ms) */
+  int32_t smooth_launches; /* with GF_FLAG_TIME_APPLY: number of those launches */
+  double smooth_bytes;     /* with GF_FLAG_TIME_APPLY: their algorithmic bytes (the batch vectors each launch
+                              reads and writes -- z, r, z_out and, where the recurrence needs it, d -- per
+                              active column and patch row, plus the two stencils per row), summed */
 } gf_solve_stats;
 
 /* flags */
 #define GF_FLAG_NO_GRAPH 2   /* enqueue every CG iteration eagerly instead of replaying a captured HIP graph */
-#define GF_FLAG_TIME_APPLY 1 /* bracket each outer-CG operator launch of the dominant batch (the sinc
-                                 nodes; the integer solves when beta is an integer) with HIP events;
-                                 iterations are then enqueued eagerly (no graph replay) */
+#define GF_FLAG_TIME_APPLY 1 /* bracket each outer-CG operator launch and each finest-level smoothing
+                                 launch of the dominant batch (the sinc nodes; the integer solves when
+                                 beta is an integer) with HIP events; iterations are then enqueued
+                                 eagerly (no graph replay) */
 
 /* Field samples u for loads b (Sec. 3.4): n = floor(beta) integer solves A w_1 = b, A w_i = M w_{i-1},
  * then the sinc rule applied to r = M w_n (r = b if n = 0), u = sum_k omega_k x_k summed in ascending k.

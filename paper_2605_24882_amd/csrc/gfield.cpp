@@ -251,7 +251,25 @@ struct LevelWork {
   DBuf<float> invb32;
 };
 
+// Event pairs around the finest-level smoothing launches of one batch (GF_FLAG_TIME_APPLY), each
+// with the number of batch vectors the launch reads and writes and the element size
+struct SmoothLog {
+  struct Entry {
+    hipEvent_t e0, e1;
+    int vecs, elem;
+  };
+  std::vector<Entry> entries;
+  void clear() {
+    for (auto &e : entries) {
+      (void)hipEventDestroy(e.e0);
+      (void)hipEventDestroy(e.e1);
+    }
+    entries.clear();
+  }
+};
+
 struct Workspace {
+  SmoothLog *slog = nullptr;  // set while a timed batch runs
   int ldb = 0, ntiles = 0, prec = 0;
   DBuf<double> x, r, p, q;  // outer CG (FP64)
   std::vector<LevelWork> lw;
@@ -592,6 +610,9 @@ struct SolveResult {
   int apply_launches = 0;
   double apply_col_sum = 0.0;
   double apply_bytes = 0.0;
+  double smooth_ms = 0.0;
+  int smooth_launches = 0;
+  double smooth_bytes = 0.0;
 };
 
 // Chebyshev recurrence coefficients for interval [b/alpha, b], in units of 1/b
@@ -667,7 +688,16 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
       e.op = fin_op;
       if (fused) *fused = true;
     }
-    apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, spec.rtol * spec.rtol, spec.max_iter, s);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (w.slog && li + 1 == sp->nlev()) {
+      HIPCHK(hipEventCreate(&ev0));
+      HIPCHK(hipEventCreate(&ev1));
+      // read z, r (and d), write z_out (and d)
+      const int vecs = 3 + ((c1[k] != 0.0 && !(dflags & 1)) ? 1 : 0) + ((dflags & 2) ? 0 : 1);
+      w.slog->entries.push_back({ev0, ev1, vecs, (int)sizeof(T)});
+    }
+    apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, spec.rtol * spec.rtol, spec.max_iter, s,
+                 ev0, ev1);
     std::swap(za, zb);
   };
   // pre-smoothing from zero (the first step's direction is the iterate itself and is not stored)
@@ -704,6 +734,7 @@ struct BatchSolve {
   double *zd = nullptr;
   float *zf = nullptr;
   std::vector<hipEvent_t> evs;  // timed outer applies (pairs)
+  SmoothLog slog;               // timed finest-level smoothing launches
   bool done = false;
 
   bool mixed() const { return spec.prec == GF_PREC_MIXED; }
@@ -802,6 +833,7 @@ struct BatchSolve {
 
   void new_event_pair(hipEvent_t *e0, hipEvent_t *e1) {
     *e0 = *e1 = nullptr;
+    w->slog = (spec.flags & GF_FLAG_TIME_APPLY) ? &slog : nullptr;
     if (!(spec.flags & GF_FLAG_TIME_APPLY)) return;
     HIPCHK(hipEventCreate(e0));
     HIPCHK(hipEventCreate(e1));
@@ -823,6 +855,18 @@ struct BatchSolve {
       const double rows = 6.0 * F.n1 * F.n1;
       res.apply_bytes += 2.0 * 8.0 * active_tiles * CT * rows + 2.0 * F.S * F.S * 8.0 * rows;
     }
+    const Level &F = sp->fine();
+    const double rows = 6.0 * F.n1 * F.n1;
+    for (auto &e : slog.entries) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e.e0, e.e1));
+      res.smooth_ms += ms;
+      res.smooth_launches += 1;
+      // algorithmic bytes: the batch vectors read and written per active column and patch row, plus
+      // the two stencils per row
+      res.smooth_bytes += (double)e.vecs * e.elem * active_tiles * CT * rows + 2.0 * F.S * F.S * e.elem * rows;
+    }
+    slog.clear();
   }
 
   int active_tiles() const {
@@ -838,6 +882,8 @@ struct BatchSolve {
   void collect() {
     for (auto e : evs) (void)hipEventDestroy(e);
     evs.clear();
+    slog.clear();
+    w->slog = nullptr;
     const int ldb = w->ldb;
     std::vector<ColState> out(ldb);
     HIPCHK(hipMemcpy(out.data(), w->cs.p, ldb * sizeof(ColState), hipMemcpyDeviceToHost));
@@ -1299,7 +1345,8 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
   HIPCHK(hipEventCreate(&t1));
   HIPCHK(hipEventRecord(t0, s));
   int max_it = 0, flags = 0, nsys = 0;
-  double max_rel = 0.0, apply_ms = 0.0, apply_col_sum = 0.0, apply_bytes = 0.0;
+  double max_rel = 0.0, apply_ms = 0.0, apply_col_sum = 0.0, apply_bytes = 0.0, smooth_ms = 0.0, smooth_bytes = 0.0;
+  int smooth_launches = 0;
   int apply_launches = 0, apply_rows = 0;
   auto account = [&](const BatchSolve &b) {
     max_it = std::max(max_it, b.res.max_it);
@@ -1310,6 +1357,9 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     apply_launches += b.res.apply_launches;
     apply_col_sum += b.res.apply_col_sum;
     apply_bytes += b.res.apply_bytes;
+    smooth_ms += b.res.smooth_ms;
+    smooth_launches += b.res.smooth_launches;
+    smooth_bytes += b.res.smooth_bytes;
     if (b.res.apply_launches) apply_rows = 6 * b.sp->fine().n1 * b.sp->fine().n1;
   };
   const bool use_graph = !(base.flags & (GF_FLAG_NO_GRAPH | GF_FLAG_TIME_APPLY));
@@ -1456,6 +1506,9 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     stats->apply_rows = apply_rows;
     stats->apply_col_sum = apply_col_sum;
     stats->apply_bytes = apply_bytes;
+    stats->smooth_ms = smooth_ms;
+    stats->smooth_launches = smooth_launches;
+    stats->smooth_bytes = smooth_bytes;
   }
   if (flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
   if (flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
@@ -1517,6 +1570,9 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
     tot.apply_launches += b.res.apply_launches;
     tot.apply_col_sum += b.res.apply_col_sum;
     tot.apply_bytes += b.res.apply_bytes;
+    tot.smooth_ms += b.res.smooth_ms;
+    tot.smooth_launches += b.res.smooth_launches;
+    tot.smooth_bytes += b.res.smooth_bytes;
     nsys += b.spec.ncols;
   };
   Workspace *wc = t.n > 0 ? &get_workspace(sp, t.ldc, base.prec, 0) : nullptr;
@@ -1605,6 +1661,9 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
     stats->apply_rows = 6 * F.n1 * F.n1;
     stats->apply_col_sum = tot.apply_col_sum;
     stats->apply_bytes = tot.apply_bytes;
+    stats->smooth_ms = tot.smooth_ms;
+    stats->smooth_launches = tot.smooth_launches;
+    stats->smooth_bytes = tot.smooth_bytes;
   }
   if (tot.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some adjoint system");
   if (tot.flags & 1) fail(GF_ENOCONV, "some adjoint system did not reach rtol within max_iter");
@@ -1787,6 +1846,9 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
       stats->apply_rows = 6 * F.n1 * F.n1;
       stats->apply_col_sum = r.apply_col_sum;
       stats->apply_bytes = r.apply_bytes;
+      stats->smooth_ms = r.smooth_ms;
+      stats->smooth_launches = r.smooth_launches;
+      stats->smooth_bytes = r.smooth_bytes;
     }
     if (r.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
     if (r.flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");

@@ -53,7 +53,9 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("n_systems", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("max_rel_resid", ctypes.c_double),
                 ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double), ("apply_ms", ctypes.c_double),
                 ("apply_launches", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
-                ("apply_col_sum", ctypes.c_double), ("apply_bytes", ctypes.c_double)]
+                ("apply_col_sum", ctypes.c_double), ("apply_bytes", ctypes.c_double),
+                ("smooth_ms", ctypes.c_double), ("smooth_launches", ctypes.c_int32),
+                ("smooth_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

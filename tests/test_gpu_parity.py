@@ -321,3 +321,19 @@ def test_edge_cases(ctx):
         st = g.SolveStats()
         assert g._lib.gf_sample(sp.h, kappa, beta, ctypes.byref(r), ctypes.byref(o), nsamp, x.ctypes.data,
                                 x.ctypes.data, g.GF_HOST, ctypes.byref(st)) == g.GF_EINVAL, (kappa, beta, nsamp)
+
+
+def test_timed_launches_do_not_change_results(ctx):
+    """GF_FLAG_TIME_APPLY brackets the outer operator and the finest-level smoothing launches with
+    runtime-stamped events; the fields are those of the untimed eager loop, bit for bit."""
+    sp, d = space(ctx, 2, 3), disc(2, 3)
+    b = noise.load(d, inputs.noise_vectors([3, 4], inputs.noise_length(2, 3)))
+    kw = dict(h=0.4, k_minus=8, k_plus=8, rtol=1e-12)
+    u1, s1 = sp.sample(3.0, 1.4, b, flags=g.GF_FLAG_NO_GRAPH, **kw)
+    u2, s2 = sp.sample(3.0, 1.4, b, flags=g.GF_FLAG_TIME_APPLY, **kw)
+    assert np.array_equal(u1, u2)
+    assert s1["apply_launches"] == 0 and s1["smooth_launches"] == 0
+    assert s2["apply_launches"] > 0 and s2["apply_ms"] > 0
+    # three smoothing steps before and after the coarse correction, minus the first (no operator)
+    assert s2["smooth_launches"] == 5 * s2["apply_launches"]
+    assert s2["smooth_bytes"] > s2["apply_bytes"]
