@@ -73,7 +73,7 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_24882_amd", "csrc", "k_fused.hip"
 
 
 def traffic_file(config):
-    return os.path.join(ROOT, "profiles", f"traffic_apply_outer_{config}.json")
+    return os.path.join(ROOT, "profiles", f"traffic_stencil_{config}.json")
 
 
 def source_sha():
