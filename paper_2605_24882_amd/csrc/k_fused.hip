@@ -36,11 +36,6 @@ __device__ __forceinline__ float lane_bcast(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-__device__ __forceinline__ bool interior_row(int64_t r, int W, int P, int n1) {
-  const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P;
-  return lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
-}
-
 // reduce one double per lane over the 4 wavefronts of the block into partial[slot][col]
 __device__ __forceinline__ void block_partial(double acc, double *partial, int64_t slot, int ldb, int col) {
   __shared__ double red[4][CT];

@@ -164,16 +164,8 @@ void reduce_dot(const Level &L, const TA *a, const TB *b, Scratch &sc, int ldb, 
 template <typename TA, typename TB, typename TC>
 void reduce_dot2(const Level &L, const TA *a, const TB *b, const TC *c, Scratch &sc, int ldb, int ntiles,
                  ColState *cs, int *active, int op, double tol2, int maxit, double *out, hipStream_t s);
-void update_xr(const Level &L, double *x, double *r, const double *p, const double *q, Scratch &sc, int ldb,
-               int ntiles, ColState *cs, int *active, double tol2, int maxit, hipStream_t s);
-template <typename TZ>
-void update_p(const Level &L, double *p, const TZ *z, const ColState *cs, int ldb, int ntiles, const int *active,
-              hipStream_t s);
 template <typename TS, typename TD>
 void convert_rows(const Level &L, const TS *a, TD *b, int ldb, int ntiles, const int *active, hipStream_t s);
-template <typename T>
-void cheb_step(const Level &L, T *z, T *d, const T *r, const T *Az, const T *dM, const T *dS, const T *sig,
-               const T *invb, T c1, T c2, int first, int ldb, int ntiles, const int *active, hipStream_t s);
 void div_diag(const Level &L, double *v, const double *w, const double *sig, int ldb, int ntiles, hipStream_t s);
 void hash_fill(const Level &L, double *v, int ldb, int ntiles, hipStream_t s);
 template <typename T>

@@ -106,20 +106,6 @@ struct FDot2 {  // acc0 = a.b, acc1 = b.c
     }
   }
 };
-struct FUpdateXR {  // x += alpha p, r -= alpha q, acc = r.r
-  double *x, *r;
-  const double *p, *q;
-  const ColState *cs;
-  int ldb;
-  __device__ void operator()(int64_t row, int col, bool own, double *acc) const {
-    const double al = cs[col].alpha;
-    const int64_t i = row * ldb + col;
-    const double rn = r[i] - al * q[i];
-    x[i] += al * p[i];
-    r[i] = rn;
-    if (own) acc[0] += rn * rn;
-  }
-};
 
 static RowCtx rowctx(const Level &L, int ldb) { return RowCtx{L.R, L.W, L.p, L.n1, ldb, L.owner.p}; }
 
@@ -162,11 +148,6 @@ template void reduce_dot2<double, float, double>(const Level &, const double *, 
                                                  Scratch &, int, int, ColState *, int *, int, double, int, double *,
                                                  hipStream_t);
 
-void update_xr(const Level &L, double *x, double *r, const double *p, const double *q, Scratch &sc, int ldb,
-               int ntiles, ColState *cs, int *active, double tol2, int maxit, hipStream_t s) {
-  run_reduce<FUpdateXR, 1>(L, FUpdateXR{x, r, p, q, cs, ldb}, sc, ldb, ntiles, cs, active, OP_CHECK, tol2, maxit,
-                           nullptr, s);
-}
 
 // ------------------------------------------------------------------ elementwise row kernels
 template <class F>
@@ -188,26 +169,6 @@ static void run_rows(const Level &L, F f, int ldb, int ntiles, const int *active
   HIPCHK(hipGetLastError());
 }
 
-template <typename TZ>
-struct FUpdateP {  // p = z + beta p
-  double *p;
-  const TZ *z;
-  const ColState *cs;
-  int ldb;
-  __device__ void operator()(int64_t r, int col) const {
-    const int64_t i = r * ldb + col;
-    p[i] = (double)z[i] + cs[col].beta * p[i];
-  }
-};
-template <typename TZ>
-void update_p(const Level &L, double *p, const TZ *z, const ColState *cs, int ldb, int ntiles, const int *active,
-              hipStream_t s) {
-  run_rows(L, FUpdateP<TZ>{p, z, cs, ldb}, ldb, ntiles, active, s);
-}
-template void update_p<double>(const Level &, double *, const double *, const ColState *, int, int, const int *,
-                               hipStream_t);
-template void update_p<float>(const Level &, double *, const float *, const ColState *, int, int, const int *,
-                              hipStream_t);
 
 template <typename TS, typename TD>
 struct FConvert {
@@ -230,33 +191,6 @@ template void convert_rows<double, double>(const Level &, const double *, double
 // Chebyshev-Jacobi step on D^-1 A, D = sigma diag(M) + diag(S) (assembled diagonals):
 //   res = (r - Az)/D  (Az == null: initial guess zero),  d = c1 d + c2 invb res,  z = z + d
 // (z = d when `first`).  invb is the per-system reciprocal of the upper spectral bound.
-template <typename T>
-struct FCheb {
-  T *z, *d;
-  const T *r, *Az;
-  const T *dM, *dS, *sig, *invb;
-  T c1, c2;
-  int first, ldb;
-  __device__ void operator()(int64_t row, int col) const {
-    const int64_t i = row * ldb + col;
-    const T D = sig[col] * dM[row] + dS[row];
-    const T res = (Az ? (r[i] - Az[i]) : r[i]) / D;
-    const T dn = (c1 != T(0) ? c1 * d[i] : T(0)) + c2 * invb[col] * res;
-    d[i] = dn;
-    z[i] = first ? dn : z[i] + dn;
-  }
-};
-template <typename T>
-void cheb_step(const Level &L, T *z, T *d, const T *r, const T *Az, const T *dM, const T *dS, const T *sig,
-               const T *invb, T c1, T c2, int first, int ldb, int ntiles, const int *active, hipStream_t s) {
-  run_rows(L, FCheb<T>{z, d, r, Az, dM, dS, sig, invb, c1, c2, first, ldb}, ldb, ntiles, active, s);
-}
-template void cheb_step<double>(const Level &, double *, double *, const double *, const double *, const double *,
-                                const double *, const double *, const double *, double, double, int, int, int,
-                                const int *, hipStream_t);
-template void cheb_step<float>(const Level &, float *, float *, const float *, const float *, const float *,
-                               const float *, const float *, const float *, float, float, int, int, int, const int *,
-                               hipStream_t);
 
 // power-iteration step for the spectral bound of D^-1 A: v = w / D
 struct FDivDiag {
