@@ -170,6 +170,9 @@ typedef struct {
 } gf_solve_stats;
 
 /* flags */
+#define GF_FLAG_MASS_SHIFT 4 /* gf_solve_shifted: the operator is M + sigma I (I the identity of the global
+                                 unknowns), sigma >= 0, solved by Jacobi-preconditioned CG in FP64 (the
+                                 shifted mass systems of gf_sqrt_mass) */
 #define GF_FLAG_NO_GRAPH 2   /* enqueue every CG iteration eagerly instead of replaying a captured HIP graph */
 #define GF_FLAG_TIME_APPLY 1 /* bracket each outer-CG operator launch and each finest-level smoothing
                                  launch of the dominant batch (the sinc nodes; the integer solves when
@@ -213,6 +216,27 @@ typedef struct {
  * aggregates over all requests (n_systems summed, max_iters and max_rel_resid maxima). */
 gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *items,
                           const gf_solve_opts *opts, int32_t mem, gf_solve_stats *stats);
+
+/* ---- the load f = sqrt(M) y of Sec. 3.3, eq. (sqrt), for y ~ N(0, I) (f ~ N(0, M)).
+ *
+ * With bounds 0 < lo < lambda_min(M), hi > lambda_max(M) and q = 1 - lo/hi the rule is
+ *   f = (2 K sqrt(lo) / (pi Khat)) M sum_{k=1..Khat} a_k (M + w_k^2 I)^-1 y,
+ *   t_k = (k - 1/2) K / Khat,  w_k = sqrt(lo) sn(t_k|q)/cn(t_k|q),  a_k = dn(t_k|q)/cn(t_k|q)^2,
+ * with sn, cn, dn the Jacobi elliptic functions of parameter q and K = K(q) the complete elliptic
+ * integral of the first kind at that parameter (the paper prints E; the first-kind integral is what
+ * the substitution behind the rule produces).  I is the identity of the global unknowns.
+ *
+ * gf_sqrt_mass_rule: the shifts w_k^2, weights a_k ([khat] each, host) and the prefactor c; host
+ * only.  1 <= khat <= 4096. */
+gf_status gf_sqrt_mass_rule(double lo, double hi, int32_t khat, double *w2, double *a, double *c);
+
+/* f = sqrt(M) y for nsamp vectors y ([nsamp][N], global numbering): the khat x nsamp shifted mass
+ * systems are solved as one batch by CG with a Jacobi preconditioner (opts: rtol, max_iter, flags;
+ * precision is FP64).  lo = hi = 0: the library estimates the bounds, hi as the largest row sum of M
+ * (a Gershgorin bound; M has no negative entries) and lo as half the Rayleigh quotient after eight
+ * steps of inverse iteration (an estimate, not a guaranteed bound).  Errors as gf_sample. */
+gf_status gf_sqrt_mass(gf_space *space, int32_t nsamp, const double *y, double *f, int32_t khat, double lo,
+                       double hi, const gf_solve_opts *opts, int32_t mem, gf_solve_stats *stats);
 
 /* ---- differentiation in kappa (Sec. 3.4 differentiated; the sinc nodes t_k and weights omega_k do
  * not depend on kappa, sigma_k = kappa^2 + t_k).

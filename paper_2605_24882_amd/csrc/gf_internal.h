@@ -72,6 +72,10 @@ void gauss_legendre(int q, std::vector<double> &x, std::vector<double> &w);
 void element_basis(int p, int nel, int e, double u, double *val, double *der);
 std::vector<double> refinement_matrix(int p, int lc);
 void glue_patches(int p, int lev, std::vector<int> &l2g, int &N);
+// Jacobi elliptic functions sn, cn, dn of parameter q in [0, 1) and the complete elliptic integral
+// of the first kind K(q)
+void jacobi_sncndn(double u, double q, double *sn, double *cn, double *dn);
+double complete_k(double q);
 
 // launch shape of the fused stencil apply, chosen by the autotuner: TY coefficient rows per
 // wavefront strip (1, 2 or 4) and at most TX coefficients along the strip
@@ -97,6 +101,8 @@ struct Level {
   DBuf<double> stM, stS;            // [R][S*S] patch stencils (FP64)
   DBuf<float> stM32, stS32;         // same, FP32
   DBuf<double> dM, dS;              // interface-summed diagonals [R]
+  DBuf<double> stI, dI;             // identity of the global unknowns as a stencil (centre 1/copies) and its
+                                    // interface-summed diagonal (1); built on first use
   DBuf<float> dM32, dS32;
   DBuf<uint8_t> owner;              // [R] 1 on the owner copy of each unknown
   DBuf<int> grp_ptr, grp_rows;      // shared unknowns: CSR list of their rows

@@ -479,7 +479,13 @@ static const ApplyTune &get_tune(const Level &L, int ldb, int ntiles, const T *x
 template <typename T>
 static void apply_epi(const Level &L, int kind, const T *x, const T *ca, const T *cb, const EpiArgs<T> &e,
                       Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2, int maxit,
-                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                      const T *stB = nullptr) {
+  if (stB) {  // second operator given as a stencil (stencil path only)
+    const ApplyTune &t = get_tune<T>(L, ldb, ntiles, x, e.y, ca, cb, s);
+    apply_fused<T>(L, Prec<T>::stM(L), stB, x, ca, cb, e, sc, cs, active, ldb, ntiles, tol2, maxit, s, t, ev0, ev1);
+    return;
+  }
   if (kind == GF_APPLY_SUMFACT) {
     if (ev0) HIPCHK(hipEventRecord(ev0, s));
     launch_sumfact_apply<T>(L, x, e.y, ca, cb, ldb, ntiles, active, s);
@@ -600,6 +606,9 @@ struct SolveSpec {
   double rtol = 1e-10;
   int max_iter = 500;
   int flags = 0;
+  // operator M + sigma I (I the identity of the global unknowns) with a Jacobi preconditioner,
+  // FP64, no multigrid plan (the shifted mass systems of the square root of M)
+  bool mass_shift = false;
 };
 
 struct SolveResult {
@@ -765,7 +774,8 @@ struct BatchSolve {
     w->active.upload(w->active_h, s);
     for (int li = 1; li < sp->nlev(); ++li) {
       std::vector<double> ib(ldb, 1.0);
-      for (int c = 0; c < spec.ncols; ++c) ib[c] = spec.plan->invb[li][node[c]];
+      if (!spec.mass_shift)
+        for (int c = 0; c < spec.ncols; ++c) ib[c] = spec.plan->invb[li][node[c]];
       std::vector<float> ibf(ib.begin(), ib.end());
       w->lw[li].invb64.upload(ib, s);
       w->lw[li].invb32.upload(ibf, s);
@@ -777,6 +787,12 @@ struct BatchSolve {
   bool precondition(int fin_op_fp64, hipStream_t s) {
     const int fi = sp->nlev() - 1;
     bool fused = false;
+    if (spec.mass_shift) {  // z = D^-1 r, D = diag(M) + sigma diag(I)
+      const Level &F = sp->fine();
+      zd = w->lw[fi].z64a.p;
+      div_diag2(F, zd, w->r.p, w->one64.p, F.dM.p, w->sig64.p, F.dI.p, w->ldb, w->ntiles, w->active.p, s);
+      return false;
+    }
     if (!mixed())
       zd = vcycle<double, double>(sp, *w, spec, fi, w->r.p, nullptr, fin_op_fp64, &fused, s);
     else
@@ -815,8 +831,12 @@ struct BatchSolve {
     e.y = w->q.p;
     e.dot = 1;
     e.op = OP_ALPHA;
-    apply_epi<double>(F, spec.kind, w->p.p, w->sig64.p, w->one64.p, e, sc, w->cs.p, w->active.p, ldb, nt, tol2(),
-                      spec.max_iter, s, e0, e1);
+    if (spec.mass_shift)
+      apply_epi<double>(F, GF_APPLY_STENCIL, w->p.p, w->one64.p, w->sig64.p, e, sc, w->cs.p, w->active.p, ldb, nt,
+                        tol2(), spec.max_iter, s, e0, e1, F.stI.p);
+    else
+      apply_epi<double>(F, spec.kind, w->p.p, w->sig64.p, w->one64.p, e, sc, w->cs.p, w->active.p, ldb, nt, tol2(),
+                        spec.max_iter, s, e0, e1);
     update_xr2(F, w->x.p, w->r.p, w->p.p, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, tol2(), spec.max_iter, s);
     if (mixed()) {
       precondition(-1, s);
@@ -1719,9 +1739,210 @@ static void run_eval(const gf_space *csp, int npts, const int32_t *patch, const 
   finish_out(o, s);
 }
 
+// The identity of the global unknowns as a patch stencil: centre coefficient 1/(number of copies)
+// on every patch row, so that the interface sum gives 1 per unknown; its diagonal is 1 on patch rows
+// and 0 on ghost rows (whose mass diagonal is 1).  Built for the finest level on first use.
+static void ensure_identity(gf_space *sp) {
+  Level &F = sp->fine();
+  if (F.stI.p) return;
+  hipStream_t s = sp->ctx->stream;
+  const int SS = F.S * F.S, W = F.W, n1 = F.n1, p = F.p;
+  std::vector<int> copies(F.N, 0);
+  for (int v : F.l2g) copies[v] += 1;
+  std::vector<double> st((size_t)F.R * SS, 0.0), di((size_t)F.R, 0.0);
+  for (int m = 0; m < 6; ++m)
+    for (int iy = 0; iy < n1; ++iy)
+      for (int ix = 0; ix < n1; ++ix) {
+        const int64_t row = (int64_t)m * W * W + (int64_t)(iy + p) * W + (ix + p);
+        const int gid = F.l2g[((size_t)m * n1 + iy) * n1 + ix];
+        st[(size_t)row * SS + p * F.S + p] = 1.0 / copies[gid];
+        di[row] = 1.0;
+      }
+  F.stI.upload(st, s);
+  F.dI.upload(di, s);
+}
+
+// Nodes, weights and prefactor of the square-root rule (Sec. 3.3, eq. sqrt) for bounds lo < hi:
+// q = 1 - lo/hi, t_k = (k - 1/2) K(q)/Khat, w_k^2 = lo (sn/cn)^2, a_k = dn/cn^2, c = 2 K sqrt(lo)/(pi Khat)
+static void sqrt_rule(double lo, double hi, int khat, std::vector<double> &w2, std::vector<double> &a, double *c) {
+  const double q = 1.0 - lo / hi;
+  const double K = complete_k(q);
+  w2.resize(khat);
+  a.resize(khat);
+  for (int k = 0; k < khat; ++k) {
+    double sn, cn, dn;
+    jacobi_sncndn((k + 0.5) * K / khat, q, &sn, &cn, &dn);
+    w2[k] = lo * (sn / cn) * (sn / cn);
+    a[k] = dn / (cn * cn);
+  }
+  *c = 2.0 * K * std::sqrt(lo) / (M_PI * khat);
+}
+
+// Batched CG with the Jacobi preconditioner on (M + w_c I) x_c = r_c for the columns of w.r
+static BatchSolve mass_solve(gf_space *sp, Workspace &w, const std::vector<double> &shift, const gf_solve_opts *o) {
+  BatchSolve b;
+  b.sp = sp;
+  b.w = &w;
+  b.spec.prec = GF_PREC_FP64;
+  b.spec.kind = GF_APPLY_STENCIL;
+  b.spec.rtol = o->rtol;
+  b.spec.max_iter = o->max_iter;
+  b.spec.flags = o->flags;
+  b.spec.mass_shift = true;
+  b.spec.ncols = (int)shift.size();
+  b.spec.col_sig = shift;
+  b.spec.col_node.assign(shift.size(), 0);
+  std::vector<BatchSolve *> ptrs{&b};
+  solve_all(sp->ctx, ptrs, !(o->flags & (GF_FLAG_NO_GRAPH | GF_FLAG_TIME_APPLY)));
+  return b;
+}
+
+// Bounds of the spectrum of M: hi = max row sum of M (Gershgorin; the entries of M are
+// non-negative), lo = half the Rayleigh quotient after eight steps of inverse iteration.
+static void mass_bounds(gf_space *sp, const gf_solve_opts *o, double *lo, double *hi) {
+  Level &F = sp->fine();
+  hipStream_t s = sp->ctx->stream;
+  Workspace &w = get_workspace(sp, CT, GF_PREC_FP64, 4001);
+  DBuf<double> ones, row, g;
+  {
+    std::vector<double> h((size_t)F.R * CT, 0.0);
+    for (int m = 0; m < 6; ++m)
+      for (int iy = 0; iy < F.n1; ++iy)
+        for (int ix = 0; ix < F.n1; ++ix)
+          h[((size_t)m * F.W * F.W + (size_t)(iy + F.p) * F.W + (ix + F.p)) * CT] = 1.0;
+    ones.upload(h, s);
+  }
+  row.alloc((size_t)F.R * CT);
+  g.alloc((size_t)F.N);
+  apply_level<double>(F, GF_APPLY_STENCIL, ones.p, row.p, w.one64.p, w.zero64.p, CT, 1, nullptr, s);
+  local_to_global(F, g.p, row.p, 1, 0, CT, s);
+  std::vector<double> hg(F.N);
+  HIPCHK(hipMemcpyAsync(hg.data(), g.p, F.N * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *hi = *std::max_element(hg.begin(), hg.end());
+  // inverse iteration v <- M^-1 v / |v| from a hashed start vector
+  gf_solve_opts io = *o;
+  io.rtol = 1e-8;
+  io.flags = 0;
+  // hashed start vector, made consistent on the copies of shared unknowns (owner copy's value)
+  hash_fill(F, w.r.p, CT, 1, s);
+  local_to_global(F, g.p, w.r.p, 1, 0, CT, s);
+  global_to_local(F, w.r.p, g.p, 1, CT, s);
+  DBuf<double> dots, Mx;
+  dots.alloc(2 * CT);
+  Mx.alloc((size_t)F.R * CT);
+  Scratch sc = w.scratch();
+  double lam = 0.0;
+  for (int it = 0; it < 8; ++it) {
+    mass_solve(sp, w, std::vector<double>{0.0}, &io);
+    // Rayleigh quotient x^T M x / x^T x of the new iterate, then r = x / |x|
+    apply_level<double>(F, GF_APPLY_STENCIL, w.x.p, Mx.p, w.one64.p, w.zero64.p, CT, 1, nullptr, s);
+    reduce_dot<double, double>(F, w.x.p, Mx.p, sc, CT, 1, nullptr, nullptr, OP_STORE, 0.0, 0, dots.p, s);
+    std::vector<double> h1(2);
+    HIPCHK(hipMemcpyAsync(h1.data(), dots.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    reduce_dot<double, double>(F, w.x.p, w.x.p, sc, CT, 1, nullptr, nullptr, OP_STORE, 0.0, 0, dots.p, s);
+    HIPCHK(hipMemcpyAsync(h1.data() + 1, dots.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(h1[0] > 0.0) || !(h1[1] > 0.0)) fail(GF_EDEVICE, "mass-matrix bound estimate failed");
+    lam = h1[0] / h1[1];
+    // r = x / |x| on every patch row: the diagonal kernel with D = |x| dI + 0 dM
+    DBuf<double> nrm;
+    nrm.upload(std::vector<double>(CT, std::sqrt(h1[1])), s);
+    div_diag2(F, w.r.p, w.x.p, nrm.p, F.dI.p, w.zero64.p, F.dM.p, CT, 1, nullptr, s);
+    HIPCHK(hipStreamSynchronize(s));  // before nrm is released
+  }
+  *lo = 0.5 * lam;
+}
+
 }  // namespace gf
 
 extern "C" {
+
+gf_status gf_sqrt_mass_rule(double lo, double hi, int32_t khat, double *w2, double *a, double *c) {
+  return guarded([&] {
+    if (!w2 || !a || !c) fail(GF_EINVAL, "null argument");
+    if (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi)) fail(GF_EINVAL, "need 0 < lo < hi, finite");
+    if (khat < 1 || khat > 4096) fail(GF_EINVAL, "khat must be in 1..4096");
+    std::vector<double> vw, va;
+    sqrt_rule(lo, hi, khat, vw, va, c);
+    std::copy(vw.begin(), vw.end(), w2);
+    std::copy(va.begin(), va.end(), a);
+  });
+}
+
+gf_status gf_sqrt_mass(gf_space *sp, int32_t nsamp, const double *y, double *f, int32_t khat, double lo, double hi,
+                       const gf_solve_opts *opts, int32_t mem, gf_solve_stats *stats) {
+  return guarded([&] {
+    if (!sp || !y || !f || !opts) fail(GF_EINVAL, "null argument");
+    if (nsamp < 1) fail(GF_EINVAL, "nsamp must be >= 1");
+    if (khat < 1 || khat > 4096) fail(GF_EINVAL, "khat must be in 1..4096");
+    if ((int64_t)khat * nsamp > (int64_t)1 << 20) fail(GF_EINVAL, "too many systems in one batch");
+    if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
+    if (!(opts->rtol > 0.0) || !(opts->rtol < 1.0)) fail(GF_EINVAL, "rtol must be in (0, 1)");
+    if (opts->max_iter < 1) fail(GF_EINVAL, "max_iter must be >= 1");
+    const bool estimate = (lo == 0.0 && hi == 0.0);
+    if (!estimate && (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi))) fail(GF_EINVAL, "need 0 < lo < hi, finite");
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    hipStream_t s = sp->ctx->stream;
+    const Level &F = sp->fine();
+    auto c0 = std::chrono::steady_clock::now();
+    ensure_identity(sp);
+    if (estimate) mass_bounds(sp, opts, &lo, &hi);
+    std::vector<double> w2, a;
+    double c = 0.0;
+    sqrt_rule(lo, hi, khat, w2, a, &c);
+    const double setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+    const size_t nv = (size_t)nsamp * F.N;
+    InArray yin;
+    stage_in(yin, y, nv, mem, s);
+    OutArray fout;
+    stage_out(fout, f, nv, mem);
+    hipEvent_t t0, t1;
+    HIPCHK(hipEventCreate(&t0));
+    HIPCHK(hipEventCreate(&t1));
+    HIPCHK(hipEventRecord(t0, s));
+    const int ldc = round_up(nsamp, CT), ncols = khat * nsamp, ldf = round_up(ncols, CT);
+    DBuf<double> yl;
+    yl.alloc((size_t)F.R * ldc);
+    global_to_local(F, yl.p, yin.p, nsamp, ldc, s);
+    Workspace &w = get_workspace(sp, ldf, GF_PREC_FP64, 4000);
+    replicate_cols(F, w.r.p, ldf, yl.p, ldc, nsamp, khat, s);
+    std::vector<double> shift(ncols);
+    for (int k = 0; k < khat; ++k)
+      for (int sm = 0; sm < nsamp; ++sm) shift[k * nsamp + sm] = w2[k];
+    BatchSolve b = mass_solve(sp, w, shift, opts);
+    // g = c sum_k a_k z_k (ascending k), f = M g
+    std::vector<double> om(khat);
+    for (int k = 0; k < khat; ++k) om[k] = c * a[k];
+    DBuf<double> omd, g;
+    omd.upload(om, s);
+    g.alloc(nv);
+    quadrature_sum(F, g.p, w.x.p, omd.p, khat, nsamp, ldf, s);
+    global_to_local(F, yl.p, g.p, nsamp, ldc, s);
+    apply_level<double>(F, GF_APPLY_STENCIL, yl.p, w.q.p, w.one64.p, w.zero64.p, ldc, ldc / CT, nullptr, s);
+    local_to_global(F, fout.p, w.q.p, nsamp, 0, ldc, s);
+    HIPCHK(hipEventRecord(t1, s));
+    finish_out(fout, s);
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (stats) {
+      *stats = gf_solve_stats{};
+      stats->n_systems = ncols;
+      stats->max_iters = b.res.max_it;
+      stats->max_rel_resid = b.res.max_rel;
+      stats->setup_ms = setup_ms;
+      stats->solve_ms = ms;
+      stats->apply_ms = b.res.apply_ms;
+      stats->apply_launches = b.res.apply_launches;
+      stats->apply_rows = 6 * F.n1 * F.n1;
+      stats->apply_bytes = b.res.apply_bytes;
+    }
+    if (b.res.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
+    if (b.res.flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
+  });
+}
 
 gf_status gf_sample(gf_space *sp, double kappa, double beta, const gf_quad_rule *rule, const gf_solve_opts *opts,
                     int32_t nsamp, const double *b, double *u, int32_t mem, gf_solve_stats *stats) {
@@ -1782,11 +2003,13 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     if (opts->cheb_degree < 0 || opts->cheb_degree > 16) fail(GF_EINVAL, "cheb_degree must be in 0..16");
     if (opts->apply_kind != GF_APPLY_STENCIL && opts->apply_kind != GF_APPLY_SUMFACT)
       fail(GF_EINVAL, "unknown apply_kind");
+    const bool mass = (opts->flags & GF_FLAG_MASS_SHIFT) != 0;
     // distinct shifts in order of first appearance: one multigrid plan node each
     std::vector<double> distinct;
     std::vector<int> node(nsys);
     for (int i = 0; i < nsys; ++i) {
-      if (!(sigma[i] > 0.0) || !std::isfinite(sigma[i])) fail(GF_EINVAL, "every shift must be positive and finite");
+      if (!(mass ? sigma[i] >= 0.0 : sigma[i] > 0.0) || !std::isfinite(sigma[i]))
+        fail(GF_EINVAL, mass ? "every shift must be non-negative and finite" : "every shift must be positive and finite");
       auto f = std::find(distinct.begin(), distinct.end(), sigma[i]);
       node[i] = (int)(f - distinct.begin());
       if (f == distinct.end()) distinct.push_back(sigma[i]);
@@ -1796,11 +2019,14 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     hipStream_t s = sp->ctx->stream;
     const Level &F = sp->fine();
     double setup_ms = 0.0;
-    const Plan *plan;
+    const Plan *plan = nullptr;
     {
       const size_t np = sp->plans.size();
       auto c0 = std::chrono::steady_clock::now();
-      plan = &get_plan(sp, distinct);
+      if (mass)
+        ensure_identity(sp);
+      else
+        plan = &get_plan(sp, distinct);
       if (sp->plans.size() != np)
         setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
     }
@@ -1810,19 +2036,21 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     OutArray xout;
     stage_out(xout, x, nv, mem);
     const int ldb = round_up(nsys, CT);
-    Workspace &w = get_workspace(sp, ldb, opts->precision, 3000);
+    const int prec = mass ? GF_PREC_FP64 : opts->precision;
+    Workspace &w = get_workspace(sp, ldb, prec, 3000);
     hipEvent_t t0, t1;
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
     HIPCHK(hipEventRecord(t0, s));
     global_to_local(F, w.r.p, bin.p, nsys, ldb, s);
     SolveSpec spec;
-    spec.prec = opts->precision;
-    spec.kind = opts->apply_kind;
+    spec.prec = prec;
+    spec.kind = mass ? GF_APPLY_STENCIL : opts->apply_kind;
     spec.cheb = opts->cheb_degree > 0 ? opts->cheb_degree : kDefaultCheb;
     spec.rtol = opts->rtol;
     spec.max_iter = opts->max_iter;
     spec.flags = opts->flags;
+    spec.mass_shift = mass;
     spec.ncols = nsys;
     spec.col_sig.assign(sigma, sigma + nsys);
     spec.col_node = node;

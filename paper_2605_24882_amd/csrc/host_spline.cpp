@@ -192,4 +192,45 @@ void glue_patches(int p, int lev, std::vector<int> &l2g, int &N) {
   }
 }
 
+// Jacobi elliptic functions by the arithmetic-geometric mean and the descending recurrence of the
+// amplitude (Abramowitz & Stegun, Sec. 16.4): with a_0 = 1, b_0 = sqrt(1-q), c_0 = sqrt(q),
+// a_n = (a_{n-1}+b_{n-1})/2, b_n = sqrt(a_{n-1} b_{n-1}), c_n = (a_{n-1}-b_{n-1})/2 until c_N is
+// negligible, phi_N = 2^N a_N u and phi_{n-1} = (phi_n + asin(c_n sin(phi_n)/a_n))/2; then
+// sn = sin(phi_0), cn = cos(phi_0), dn = cos(phi_0)/cos(phi_1 - phi_0).  K(q) = pi/(2 a_N).
+namespace {
+int agm(double q, double *a, double *c) {
+  a[0] = 1.0;
+  double b = std::sqrt(1.0 - q);
+  c[0] = std::sqrt(q);
+  int n = 0;
+  while (n < 30 && std::fabs(c[n]) > 1e-17 * a[n]) {
+    a[n + 1] = 0.5 * (a[n] + b);
+    c[n + 1] = 0.5 * (a[n] - b);
+    b = std::sqrt(a[n] * b);
+    ++n;
+  }
+  return n;
+}
+}  // namespace
+
+void jacobi_sncndn(double u, double q, double *sn, double *cn, double *dn) {
+  double a[32], c[32];
+  const int n = agm(q, a, c);
+  double phi = std::ldexp(a[n] * u, n);
+  double prev = phi;
+  for (int k = n; k >= 1; --k) {
+    prev = phi;
+    phi = 0.5 * (phi + std::asin(c[k] * std::sin(phi) / a[k]));
+  }
+  *sn = std::sin(phi);
+  *cn = std::cos(phi);
+  *dn = (n == 0) ? 1.0 : *cn / std::cos(prev - phi);
+}
+
+double complete_k(double q) {
+  double a[32], c[32];
+  const int n = agm(q, a, c);
+  return M_PI / (2.0 * a[n]);
+}
+
 }  // namespace gf

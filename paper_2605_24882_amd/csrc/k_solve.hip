@@ -206,6 +206,21 @@ void div_diag(const Level &L, double *v, const double *w, const double *sig, int
   run_rows(L, FDivDiag{v, w, L.dM.p, L.dS.p, sig, ldb}, ldb, ntiles, nullptr, s);
 }
 
+// v = w / (ca dA + cb dB) with per-column ca, cb and per-row diagonals dA, dB
+struct FDivDiag2 {
+  double *v;
+  const double *w, *ca, *dA, *cb, *dB;
+  int ldb;
+  __device__ void operator()(int64_t row, int col) const {
+    const int64_t i = row * ldb + col;
+    v[i] = w[i] / (ca[col] * dA[row] + cb[col] * dB[row]);
+  }
+};
+void div_diag2(const Level &L, double *v, const double *w, const double *ca, const double *dA, const double *cb,
+               const double *dB, int ldb, int ntiles, const int *active, hipStream_t s) {
+  run_rows(L, FDivDiag2{v, w, ca, dA, cb, dB, ldb}, ldb, ntiles, active, s);
+}
+
 // deterministic start vector in [0.5, 1.5) from a hash of (row, column)
 struct FHashFill {
   double *v;

@@ -34,6 +34,7 @@ GF_APPLY_STENCIL, GF_APPLY_SUMFACT = 0, 1
 GF_PREC_FP64, GF_PREC_MIXED = 0, 1
 GF_FLAG_TIME_APPLY = 1
 GF_FLAG_NO_GRAPH = 2
+GF_FLAG_MASS_SHIFT = 4
 GF_SPLIT_PLAIN, GF_SPLIT_IMPROVED = 0, 1
 STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ENOMEM", 3: "GF_EDEVICE", 4: "GF_ENOCONV",
                 5: "GF_EBREAKDOWN", 6: "GF_EUNSUPPORTED"}
@@ -91,6 +92,9 @@ _SIGS = {
                                ctypes.POINTER(SolveStats)]),
     "gf_solve_shifted": (_i32, [_vp, _i32, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), _i32,
                                 ctypes.POINTER(SolveStats)]),
+    "gf_sqrt_mass_rule": (_i32, [_dbl, _dbl, _i32, _vp, _vp, ctypes.POINTER(_dbl)]),
+    "gf_sqrt_mass": (_i32, [_vp, _i32, _vp, _vp, _i32, _dbl, _dbl, ctypes.POINTER(SolveOpts), _i32,
+                            ctypes.POINTER(SolveStats)]),
     "gf_sample_tape": (_i32, [_vp, _dbl, _dbl, ctypes.POINTER(QuadRule), ctypes.POINTER(SolveOpts), _i32, _vp,
                               _vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(SolveStats)]),
     "gf_grad_kappa": (_i32, [_vp, _vp, _vp, _i32, ctypes.POINTER(SolveStats)]),
@@ -268,6 +272,18 @@ class Space:
         _check(status, st.as_dict())
         return x, st.as_dict()
 
+    def sqrt_mass(self, y, khat=16, lo=0.0, hi=0.0, rtol=1e-12, max_iter=1000, flags=0):
+        """f = sqrt(M) y for y of shape (nsamp, N) by the elliptic-function rule; returns (f, stats)."""
+        nsamp = 1 if len(y.shape) == 1 else y.shape[0]
+        py, mem, keep = _marshal_in(y, nsamp * self.ndofs)
+        f = _alloc_like(y, (nsamp, self.ndofs))
+        opts = SolveOpts(GF_PREC_FP64, rtol, max_iter, 0, GF_APPLY_STENCIL, flags)
+        st = SolveStats()
+        status = _lib.gf_sqrt_mass(self.h, nsamp, py, _ptr(f), khat, lo, hi, ctypes.byref(opts), mem,
+                                   ctypes.byref(st))
+        _check(status, st.as_dict())
+        return f, st.as_dict()
+
     def sample_tape(self, kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=GF_PREC_FP64, rtol=1e-10,
                     max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0, split=GF_SPLIT_PLAIN):
         """sample() that also keeps the forward solutions; returns (u, Tape, stats dict)."""
@@ -386,3 +402,12 @@ def sample_batch(ctx, requests, precision=GF_PREC_FP64, rtol=1e-10, max_iter=500
     status = _lib.gf_sample_batch(ctx.h, len(requests), items, ctypes.byref(opts), mem0, ctypes.byref(st))
     _check(status, st.as_dict())
     return outs, st.as_dict()
+
+
+def sqrt_mass_rule(lo, hi, khat):
+    """(w2, a, c) of the square-root rule (host computation in the library)."""
+    w2 = np.empty(khat)
+    a = np.empty(khat)
+    c = ctypes.c_double()
+    _check(_lib.gf_sqrt_mass_rule(lo, hi, khat, w2.ctypes.data, a.ctypes.data, ctypes.byref(c)))
+    return w2, a, c.value

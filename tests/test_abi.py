@@ -72,3 +72,17 @@ def test_locate_matches_oracle_inversion():
     assert np.allclose(st[:, 0], os_, atol=1e-15) and np.allclose(st[:, 1], ot, atol=1e-15)
     with pytest.raises(g.GfieldError):
         geo.locate(np.zeros((1, 3)))
+
+
+def test_sqrt_mass_rule_matches_oracle():
+    """The library's Jacobi elliptic functions (arithmetic-geometric mean) against SciPy's, through the
+    nodes and weights of the square-root rule; host computation, no device needed."""
+    from oracle import sqrt_mass
+    for lo, hi, khat in [(0.1, 1.0, 8), (1e-4, 3e-3, 16), (0.02, 50.0, 24), (0.5, 0.5000001, 3)]:
+        w2, a, c = g.sqrt_mass_rule(lo, hi, khat)
+        rw2, ra, rc = sqrt_mass.rule(lo, hi, khat)
+        assert np.allclose(w2, rw2, rtol=1e-12, atol=0) and np.allclose(a, ra, rtol=1e-12) and abs(c - rc) <= 1e-13 * rc
+    import ctypes
+    x = np.zeros(4)
+    cc = ctypes.c_double()
+    assert g._lib.gf_sqrt_mass_rule(1.0, 0.5, 4, x.ctypes.data, x.ctypes.data, ctypes.byref(cc)) == g.GF_EINVAL
