@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + sorted(BATCH_CONFIGS))
     ap.add_argument("--apply-kind", type=int, default=0)
     ap.add_argument("--cheb", type=int, default=0)
+    ap.add_argument("--precond", choices=("vcycle", "bpx"), default="vcycle",
+                    help="multigrid preconditioner: the V-cycle or the additive BPX form")
     ap.add_argument("--split", choices=("plain", "improved"), default="plain",
                     help="split of beta: plain n + beta', or the improved split (the rule applied twice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -289,7 +291,8 @@ def main():
             reqs.append(dict(space=sp, kappa=kp, beta=bc["beta"], b=sp.white_noise(z), h=bc["h"],
                              k_minus=bc["k"], k_plus=bc["k"]))
             del z
-        kw = dict(precision=prec, rtol=rtol, max_iter=2000, cheb_degree=args.cheb, apply_kind=args.apply_kind)
+        kw = dict(precision=prec, rtol=rtol, max_iter=2000, cheb_degree=args.cheb, apply_kind=args.apply_kind,
+                  preconditioner=g.GF_PRECOND_BPX if args.precond == "bpx" else g.GF_PRECOND_VCYCLE)
 
         def step(flags=0):
             return g.sample_batch(ctx, reqs, flags=flags, **kw)
@@ -305,7 +308,8 @@ def main():
         del z
         kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
                   apply_kind=args.apply_kind,
-                  split=g.GF_SPLIT_IMPROVED if args.split == "improved" else g.GF_SPLIT_PLAIN)
+                  split=g.GF_SPLIT_IMPROVED if args.split == "improved" else g.GF_SPLIT_PLAIN,
+                  preconditioner=g.GF_PRECOND_BPX if args.precond == "bpx" else g.GF_PRECOND_VCYCLE)
 
         if args.config in GRADIENT_CONFIGS:
             pts, yv = inputs.sphere_points_and_targets(1000, seed=7)
@@ -331,6 +335,8 @@ def main():
             workload = workload_name(cfg)
         if args.split == "improved":
             workload += "; improved split (rule applied twice where beta' < 1/3 or > 2/3)"
+    if args.precond == "bpx":
+        workload += "; BPX (additive multilevel) preconditioner"
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")

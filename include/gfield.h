@@ -137,7 +137,12 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction on the finest
  * level (0: three); the coarser levels take one (two on levels of more than 50,000 patch coefficients),
  * at most cheb_degree.
- * apply_kind: GF_APPLY_STENCIL or GF_APPLY_SUMFACT for every operator application in the solver. */
+ * apply_kind: GF_APPLY_STENCIL or GF_APPLY_SUMFACT for every operator application in the solver.
+ * preconditioner (Sec. 3.5): GF_PRECOND_VCYCLE, the multiplicative V-cycle above, or GF_PRECOND_BPX,
+ * the additive multilevel preconditioner sum_l P_l D_l^-1 P_l^T with D_l the diagonal of
+ * sigma M_l + S_l on every level and the Cholesky solve on the coarsest (no operator application
+ * inside the preconditioner; more CG iterations). */
+enum { GF_PRECOND_VCYCLE = 0, GF_PRECOND_BPX = 1 };
 typedef struct {
   int32_t precision;
   double rtol;
@@ -145,6 +150,7 @@ typedef struct {
   int32_t cheb_degree;
   int32_t apply_kind;
   int32_t flags;
+  int32_t preconditioner; /* GF_PRECOND_VCYCLE (default) or GF_PRECOND_BPX */
 } gf_solve_opts;
 
 /* Statistics of the last solve (all fields written by the library). */

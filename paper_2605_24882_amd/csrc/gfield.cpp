@@ -609,6 +609,7 @@ struct SolveSpec {
   // operator M + sigma I (I the identity of the global unknowns) with a Jacobi preconditioner,
   // FP64, no multigrid plan (the shifted mass systems of the square root of M)
   bool mass_shift = false;
+  int precond = GF_PRECOND_VCYCLE;
 };
 
 struct SolveResult {
@@ -731,6 +732,39 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   return za;
 }
 
+// Additive multilevel (BPX) preconditioner: z = sum over the levels l of P_l D_l^-1 P_l^T r with
+// D_l the diagonal of sigma M_l + S_l, and the exact (Cholesky) solve on level 0.  The residual is
+// restricted level by level (knot-insertion transposes, interface sums); on the way up every level
+// adds its diagonally scaled residual to the prolongation of the coarser correction.
+template <typename T, typename TR>
+static T *bpx(gf_space *sp, Workspace &w, const SolveSpec &spec, const TR *rsrc, T *rconv, hipStream_t s) {
+  const int fi = sp->nlev() - 1;
+  const int ldb = w.ldb, nt = w.ntiles;
+  int *act = w.active.p;
+  const T *rf = (const T *)rsrc;
+  if (rconv) {
+    convert_rows<TR, T>(*sp->lev[fi], rsrc, rconv, ldb, nt, act, s);
+    rf = rconv;
+  }
+  auto resid = [&](int l) -> const T * { return l == fi ? rf : Prec<T>::r(w.lw[l]); };
+  for (int l = fi; l >= 1; --l) {
+    const Level &L = *sp->lev[l], &C = *sp->lev[l - 1];
+    T *rc = Prec<T>::r(w.lw[l - 1]);
+    restrict_residual<T>(L, C, rc, resid(l), nullptr, ldb, nt, act, s);
+    launch_interface_sum<T>(C, rc, ldb, nt, act, s);
+  }
+  T *zc = Prec<T>::za(w.lw[0]);
+  coarse_solve<T>(*sp->lev[0], sp->N0, zc, Prec<T>::r(w.lw[0]), spec.plan->Lf.p, w.node.p, ldb, nt, act, s);
+  for (int l = 1; l <= fi; ++l) {
+    const Level &L = *sp->lev[l], &C = *sp->lev[l - 1];
+    T *z = Prec<T>::za(w.lw[l]);
+    diag_scale<T>(L, z, resid(l), Prec<T>::sig(w), Prec<T>::dM(L), Prec<T>::dS(L), ldb, nt, act, s);
+    prolong_add<T>(L, C, z, zc, ldb, nt, act, s);
+    zc = z;
+  }
+  return zc;
+}
+
 // One batch of shifted systems (sigma_c M + S) x_c = r_c, one per column, on one space: on entry
 // w.r holds the right-hand sides (assembled, patch-local layout), on exit w.x the solutions.
 // prepare() and start() run eagerly; iterate() enqueues one CG iteration and is what the graph
@@ -791,6 +825,13 @@ struct BatchSolve {
       const Level &F = sp->fine();
       zd = w->lw[fi].z64a.p;
       div_diag2(F, zd, w->r.p, w->one64.p, F.dM.p, w->sig64.p, F.dI.p, w->ldb, w->ntiles, w->active.p, s);
+      return false;
+    }
+    if (spec.precond == GF_PRECOND_BPX) {
+      if (!mixed())
+        zd = bpx<double, double>(sp, *w, spec, w->r.p, nullptr, s);
+      else
+        zf = bpx<float, double>(sp, *w, spec, w->r.p, w->lw[fi].r32.p, s);
       return false;
     }
     if (!mixed())
@@ -1272,6 +1313,8 @@ static void check_common(gf_space *sp, double kappa, double beta, const gf_quad_
   if (opts->cheb_degree < 0 || opts->cheb_degree > 16) fail(GF_EINVAL, "cheb_degree must be in 0..16");
   if (opts->apply_kind != GF_APPLY_STENCIL && opts->apply_kind != GF_APPLY_SUMFACT)
     fail(GF_EINVAL, "unknown apply_kind");
+  if (opts->preconditioner != GF_PRECOND_VCYCLE && opts->preconditioner != GF_PRECOND_BPX)
+    fail(GF_EINVAL, "unknown preconditioner");
   if (nsamp < 1) fail(GF_EINVAL, "nsamp must be >= 1");
   if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
 }
@@ -1331,6 +1374,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
   base.rtol = opts->rtol;
   base.max_iter = opts->max_iter;
   base.flags = opts->flags;
+  base.precond = opts->preconditioner;
   const bool any_frac = std::any_of(items.begin(), items.end(), [](const SampleItem &it) {
     return it.beta - std::floor(it.beta) > 0.0;
   });
@@ -1557,6 +1601,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
   base.rtol = t.opts.rtol;
   base.max_iter = t.opts.max_iter;
   base.flags = t.opts.flags;
+  base.precond = t.opts.preconditioner;
   const bool use_graph = !(base.flags & (GF_FLAG_NO_GRAPH | GF_FLAG_TIME_APPLY));
   double setup_ms = 0.0;
   const Plan *chain_plan = nullptr, *frac_plan = nullptr;
@@ -2003,6 +2048,8 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     if (opts->cheb_degree < 0 || opts->cheb_degree > 16) fail(GF_EINVAL, "cheb_degree must be in 0..16");
     if (opts->apply_kind != GF_APPLY_STENCIL && opts->apply_kind != GF_APPLY_SUMFACT)
       fail(GF_EINVAL, "unknown apply_kind");
+    if (opts->preconditioner != GF_PRECOND_VCYCLE && opts->preconditioner != GF_PRECOND_BPX)
+      fail(GF_EINVAL, "unknown preconditioner");
     const bool mass = (opts->flags & GF_FLAG_MASS_SHIFT) != 0;
     // distinct shifts in order of first appearance: one multigrid plan node each
     std::vector<double> distinct;
@@ -2051,6 +2098,7 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     spec.max_iter = opts->max_iter;
     spec.flags = opts->flags;
     spec.mass_shift = mass;
+    spec.precond = opts->preconditioner;
     spec.ncols = nsys;
     spec.col_sig.assign(sigma, sigma + nsys);
     spec.col_node = node;

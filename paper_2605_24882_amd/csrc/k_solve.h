@@ -169,6 +169,9 @@ void convert_rows(const Level &L, const TS *a, TD *b, int ldb, int ntiles, const
 void div_diag(const Level &L, double *v, const double *w, const double *sig, int ldb, int ntiles, hipStream_t s);
 void div_diag2(const Level &L, double *v, const double *w, const double *ca, const double *dA, const double *cb,
                const double *dB, int ldb, int ntiles, const int *active, hipStream_t s);
+template <typename T>
+void diag_scale(const Level &L, T *z, const T *r, const T *sig, const T *dM, const T *dS, int ldb, int ntiles,
+                const int *active, hipStream_t s);
 void hash_fill(const Level &L, double *v, int ldb, int ntiles, hipStream_t s);
 template <typename T>
 void restrict_residual(const Level &F, const Level &C, T *rc, const T *r, const T *Az, int ldb, int ntiles,

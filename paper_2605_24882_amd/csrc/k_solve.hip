@@ -221,6 +221,27 @@ void div_diag2(const Level &L, double *v, const double *w, const double *ca, con
   run_rows(L, FDivDiag2{v, w, ca, dA, cb, dB, ldb}, ldb, ntiles, active, s);
 }
 
+// z = r / (sig dM + dS): the diagonal scaling of one level of the additive multilevel preconditioner
+template <typename T>
+struct FDiagScale {
+  T *z;
+  const T *r, *sig, *dM, *dS;
+  int ldb;
+  __device__ void operator()(int64_t row, int col) const {
+    const int64_t i = row * ldb + col;
+    z[i] = r[i] / (sig[col] * dM[row] + dS[row]);
+  }
+};
+template <typename T>
+void diag_scale(const Level &L, T *z, const T *r, const T *sig, const T *dM, const T *dS, int ldb, int ntiles,
+                const int *active, hipStream_t s) {
+  run_rows(L, FDiagScale<T>{z, r, sig, dM, dS, ldb}, ldb, ntiles, active, s);
+}
+template void diag_scale<double>(const Level &, double *, const double *, const double *, const double *,
+                                 const double *, int, int, const int *, hipStream_t);
+template void diag_scale<float>(const Level &, float *, const float *, const float *, const float *, const float *,
+                                int, int, const int *, hipStream_t);
+
 // deterministic start vector in [0.5, 1.5) from a hash of (row, column)
 struct FHashFill {
   double *v;

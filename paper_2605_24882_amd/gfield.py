@@ -35,6 +35,7 @@ GF_PREC_FP64, GF_PREC_MIXED = 0, 1
 GF_FLAG_TIME_APPLY = 1
 GF_FLAG_NO_GRAPH = 2
 GF_FLAG_MASS_SHIFT = 4
+GF_PRECOND_VCYCLE, GF_PRECOND_BPX = 0, 1
 GF_SPLIT_PLAIN, GF_SPLIT_IMPROVED = 0, 1
 STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ENOMEM", 3: "GF_EDEVICE", 4: "GF_ENOCONV",
                 5: "GF_EBREAKDOWN", 6: "GF_EUNSUPPORTED"}
@@ -47,7 +48,8 @@ class QuadRule(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
-                ("cheb_degree", ctypes.c_int32), ("apply_kind", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("cheb_degree", ctypes.c_int32), ("apply_kind", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("preconditioner", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -245,13 +247,14 @@ class Space:
         return b
 
     def sample(self, kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=GF_PREC_FP64, rtol=1e-10,
-               max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0, split=GF_SPLIT_PLAIN):
+               max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0, split=GF_SPLIT_PLAIN,
+               preconditioner=GF_PRECOND_VCYCLE):
         """Field samples u for loads b (nsamp, N); returns (u, stats dict)."""
         nsamp = 1 if len(b.shape) == 1 else b.shape[0]
         pb, mem, keep = _marshal_in(b, nsamp * self.ndofs)
         u = _alloc_like(b, (nsamp, self.ndofs))
         rule = QuadRule(h, k_minus, k_plus, split)
-        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
+        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags, preconditioner)
         st = SolveStats()
         status = _lib.gf_sample(self.h, kappa, beta, ctypes.byref(rule), ctypes.byref(opts), nsamp, pb, _ptr(u),
                                 mem, ctypes.byref(st))
@@ -259,13 +262,13 @@ class Space:
         return u, st.as_dict()
 
     def solve_shifted(self, sigma, b, precision=GF_PREC_FP64, rtol=1e-10, max_iter=500, cheb_degree=0,
-                      apply_kind=GF_APPLY_STENCIL, flags=0):
+                      apply_kind=GF_APPLY_STENCIL, flags=0, preconditioner=GF_PRECOND_VCYCLE):
         """x_i = (sigma_i M + S)^-1 b_i for b of shape (nsys, N); returns (x, stats dict)."""
         nsys = 1 if len(b.shape) == 1 else b.shape[0]
         sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (nsys,)))
         pb, mem, keep = _marshal_in(b, nsys * self.ndofs)
         x = _alloc_like(b, (nsys, self.ndofs))
-        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
+        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags, preconditioner)
         st = SolveStats()
         status = _lib.gf_solve_shifted(self.h, nsys, sig.ctypes.data, pb, _ptr(x), ctypes.byref(opts), mem,
                                        ctypes.byref(st))
@@ -285,13 +288,14 @@ class Space:
         return f, st.as_dict()
 
     def sample_tape(self, kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=GF_PREC_FP64, rtol=1e-10,
-                    max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0, split=GF_SPLIT_PLAIN):
+                    max_iter=500, cheb_degree=0, apply_kind=GF_APPLY_STENCIL, flags=0, split=GF_SPLIT_PLAIN,
+                    preconditioner=GF_PRECOND_VCYCLE):
         """sample() that also keeps the forward solutions; returns (u, Tape, stats dict)."""
         nsamp = 1 if len(b.shape) == 1 else b.shape[0]
         pb, mem, keep = _marshal_in(b, nsamp * self.ndofs)
         u = _alloc_like(b, (nsamp, self.ndofs))
         rule = QuadRule(h, k_minus, k_plus, split)
-        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
+        opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags, preconditioner)
         st = SolveStats()
         th = _vp()
         status = _lib.gf_sample_tape(self.h, kappa, beta, ctypes.byref(rule), ctypes.byref(opts), nsamp, pb,
@@ -372,7 +376,7 @@ class Tape:
 
 
 def sample_batch(ctx, requests, precision=GF_PREC_FP64, rtol=1e-10, max_iter=500, cheb_degree=0,
-                 apply_kind=GF_APPLY_STENCIL, flags=0):
+                 apply_kind=GF_APPLY_STENCIL, flags=0, preconditioner=GF_PRECOND_VCYCLE):
     """Several sampling requests solved together.
 
     requests: sequence of dicts with keys space, kappa, beta, b and optionally h, k_minus, k_plus,
@@ -397,7 +401,7 @@ def sample_batch(ctx, requests, precision=GF_PREC_FP64, rtol=1e-10, max_iter=500
                              QuadRule(r.get("h", 0.4), r.get("k_minus", 20), r.get("k_plus", 20),
                                       r.get("split", GF_SPLIT_PLAIN)), nsamp, pb,
                              _ptr(u))
-    opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags)
+    opts = SolveOpts(precision, rtol, max_iter, cheb_degree, apply_kind, flags, preconditioner)
     st = SolveStats()
     status = _lib.gf_sample_batch(ctx.h, len(requests), items, ctypes.byref(opts), mem0, ctypes.byref(st))
     _check(status, st.as_dict())

@@ -337,3 +337,16 @@ def test_timed_launches_do_not_change_results(ctx):
     # three smoothing steps before and after the coarse correction, minus the first (no operator)
     assert s2["smooth_launches"] == 5 * s2["apply_launches"]
     assert s2["smooth_bytes"] > s2["apply_bytes"]
+
+
+@pytest.mark.parametrize("p,j,pert,beta,prec", [(2, 3, False, 1.6, 0), (3, 3, True, 0.8, 1), (1, 3, False, 2.3, 0),
+                                                (2, 2, True, 0.75, 1)])
+def test_bpx_preconditioner_matches_oracle(ctx, p, j, pert, beta, prec):
+    """The additive multilevel preconditioner (Sec. 3.5's BPX) gives the same fields to the solver
+    tolerance."""
+    sp, d = space(ctx, p, j, pert), disc(p, j, pert)
+    b = noise.load(d, inputs.noise_vectors([6, 7], inputs.noise_length(p, j)))
+    u, st = sp.sample(3.0, beta, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13, max_iter=2000,
+                      preconditioner=g.GF_PRECOND_BPX)
+    ref = _oracle_u(d, 3.0, beta, 0.4, 10, b)
+    assert mrel(d, u, ref) <= 1e-10
