@@ -104,6 +104,7 @@ struct Level {
   DBuf<double> stI, dI;             // identity of the global unknowns as a stencil (centre 1/copies) and its
                                     // interface-summed diagonal (1); built on first use
   DBuf<float> dM32, dS32;
+  double dM_mean = 0.0, dS_mean = 0.0;  // means of dM, dS over the rows of coefficients
   DBuf<uint8_t> owner;              // [R] 1 on the owner copy of each unknown
   DBuf<int> grp_ptr, grp_rows;      // shared unknowns: CSR list of their rows
   int ngroups = 0;

@@ -156,7 +156,19 @@ static void build_level_device(gf_space *sp, Level &L, int perturbed) {
   L.dS32.alloc((size_t)L.R);
   launch_to_f32(L.dM.p, L.dM32.p, L.R, s);
   launch_to_f32(L.dS.p, L.dS32.p, L.R, s);
+  std::vector<double> hdM(L.R), hdS(L.R);
+  HIPCHK(hipMemcpyAsync(hdM.data(), L.dM.p, L.R * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hdS.data(), L.dS.p, L.R * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  int64_t nrow = 0;
+  for (int64_t i = 0; i < L.R; ++i)
+    if (row_gid[i] >= 0) {
+      L.dM_mean += hdM[i];
+      L.dS_mean += hdS[i];
+      ++nrow;
+    }
+  L.dM_mean /= (double)nrow;
+  L.dS_mean /= (double)nrow;
 }
 
 // knot-insertion transfer bands from level C into level F (= C + 1)
@@ -240,6 +252,8 @@ static void build_coarse_dense(gf_space *sp) {
 struct Plan {
   std::vector<double> sig;                // distinct shifts (nodes)
   std::vector<std::vector<double>> invb;  // [level index][node] 1/(upper spectral bound of D^-1 A)
+  std::vector<std::vector<double>> ialpha;  // [level index][node] lower end / upper end of the
+                                            // smoothing interval
   DBuf<double> Lf;                        // [node][N0][N0] coarse Cholesky factors
   double setup_ms = 0.0;
 };
@@ -247,8 +261,10 @@ struct Plan {
 struct LevelWork {
   DBuf<double> r64, z64a, z64b, d64, a64;  // V-cycle vectors (FP64 mode)
   DBuf<float> r32, z32a, z32b, d32, a32;   // V-cycle vectors (mixed mode)
-  DBuf<double> invb64;
-  DBuf<float> invb32;
+  // Chebyshev coefficients per step and system, [2][deg][ldb]: c1 of step k at k ldb, c2 / b_max of
+  // step k at (deg + k) ldb
+  DBuf<double> cf64;
+  DBuf<float> cf32;
 };
 
 // Event pairs around the finest-level smoothing launches of one batch (GF_FLAG_TIME_APPLY), each
@@ -352,8 +368,6 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
       v.d32.alloc(n);
       v.a32.alloc(n);
     }
-    v.invb64.alloc(ldb);
-    v.invb32.alloc(ldb);
   }
   w->sig64.alloc(ldb);
   w->one64.alloc(ldb);
@@ -388,7 +402,7 @@ struct Prec<double> {
   static double *zb(LevelWork &l) { return l.z64b.p; }
   static double *d(LevelWork &l) { return l.d64.p; }
   static double *a(LevelWork &l) { return l.a64.p; }
-  static double *inv(LevelWork &l) { return l.invb64.p; }
+  static const double *cf(LevelWork &l) { return l.cf64.p; }
   static double *sig(Workspace &w) { return w.sig64.p; }
   static double *one(Workspace &w) { return w.one64.p; }
 };
@@ -403,7 +417,7 @@ struct Prec<float> {
   static float *zb(LevelWork &l) { return l.z32b.p; }
   static float *d(LevelWork &l) { return l.d32.p; }
   static float *a(LevelWork &l) { return l.a32.p; }
-  static float *inv(LevelWork &l) { return l.invb32.p; }
+  static const float *cf(LevelWork &l) { return l.cf32.p; }
   static float *sig(Workspace &w) { return w.sig32.p; }
   static float *one(Workspace &w) { return w.one32.p; }
 };
@@ -510,9 +524,37 @@ static void apply_level(const Level &L, int kind, const T *x, T *y, const T *ca,
   apply_epi<T>(L, kind, x, ca, cb, e, none, nullptr, const_cast<int *>(active), ldb, ntiles, 0.0, 0, s);
 }
 
-// Chebyshev interval [b/alpha, b] with b = 1.1 x the estimated largest eigenvalue of D^-1 A
+// Chebyshev interval [b/alpha, b] with b = 1.1 x the estimated largest eigenvalue of D^-1 A.  For a
+// stiffness-dominated operator the smoother targets the upper eighth of the spectrum (the coarse
+// levels resolve the rest).  For a mass-dominated one (the sinc nodes with large t_k) the
+// high-frequency eigenvalues of D^-1 M sit at the bottom of its spectrum, down to (m(pi)/m(0))^2
+// with m the symbol of the 1D B-spline mass stencil, so the interval must reach that far.  Between
+// the two, 1/alpha is the convex combination weighted by the share r = sigma dM / (sigma dM + dS)
+// of the mass term in the diagonal (level means).  Measured at relative residual 1e-10 on degree 2,
+// 64^2 elements per patch, kappa = 10: the largest per-node CG iteration count drops from 21
+// (alpha = 8 for every node) to 16, the nodes with t_k < 1e4 are unchanged; on degree 3 (64^2 and
+// 256^2 elements, 1e-6) from 30 to 23 and from 29 to 21.  The wide interval pays for loads with
+// high-frequency content (white noise, and M A^-1 of it: 214 -> 188 summed iterations over 21
+// nodes); for M A^-2 of white noise the narrow one is better (134 against 157), so loads of that
+// smoothness keep alpha = 8 (SolveSpec::smooth_load).
 constexpr double kChebAlpha = 8.0;
 constexpr double kChebSafety = 1.1;
+
+// (m(0) / m(pi))^2 for the mass stencil of uniform 1D B-splines of degree p: its entries are the
+// values of the cardinal B-spline of degree 2p + 1 at the integers, m(0) = their sum = 1
+static double mass_interval_ratio(int p) {
+  const int n = 2 * p + 1;
+  std::vector<double> v(n + 2, 0.0);  // N_k at 0 .. n + 1
+  v[0] = 1.0;                         // N_0 at the integers: 1 at 0, else 0
+  for (int k = 1; k <= n; ++k) {
+    std::vector<double> u(n + 2, 0.0);
+    for (int i = 1; i <= k; ++i) u[i] = (i * v[i] + (k + 1 - i) * v[i - 1]) / k;
+    v = u;
+  }
+  double mpi = 0.0;
+  for (int i = 1; i <= n; ++i) mpi += ((i - (p + 1)) % 2 == 0 ? 1.0 : -1.0) * v[i];
+  return 1.0 / (mpi * mpi);
+}
 constexpr int kPowerIters = 16;
 // Chebyshev smoothing steps before and after the coarse correction when the caller passes 0: three
 // gave the fewest seconds per sample on degrees 2 and 3 at 64x64 and 128x128 elements per patch
@@ -549,6 +591,8 @@ static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
   out.alloc((size_t)2 * ldb);
   Scratch sc{partial.p, counter.p};
   pl->invb.assign(sp->nlev(), std::vector<double>(nn, 0.0));
+  pl->ialpha.assign(sp->nlev(), std::vector<double>(nn, 0.0));
+  const double ia_mass = 1.0 / mass_interval_ratio(sp->p);
   for (int li = 1; li < sp->nlev(); ++li) {
     const Level &L = *sp->lev[li];
     const size_t n = (size_t)L.R * ldb;
@@ -571,6 +615,8 @@ static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
       const double lam = ho[ldb + k] / ho[k];
       if (!(lam > 0.0) || !std::isfinite(lam)) fail(GF_EDEVICE, "spectral bound estimate failed");
       pl->invb[li][k] = 1.0 / (kChebSafety * lam);
+      const double rm = sig[k] * L.dM_mean / (sig[k] * L.dM_mean + L.dS_mean);
+      pl->ialpha[li][k] = (1.0 - rm) / kChebAlpha + rm * ia_mass;
     }
     v.release();
     w.release();
@@ -610,6 +656,10 @@ struct SolveSpec {
   // FP64, no multigrid plan (the shifted mass systems of the square root of M)
   bool mass_shift = false;
   int precond = GF_PRECOND_VCYCLE;
+  // the load has already passed through the inverse operator (an order of at least 1.5 in powers of
+  // A^-1): it has little high-frequency content, and the smoothing interval stays [b/8, b] on every
+  // node
+  bool smooth_load = false;
 };
 
 struct SolveResult {
@@ -625,9 +675,8 @@ struct SolveResult {
   double smooth_bytes = 0.0;
 };
 
-// Chebyshev recurrence coefficients for interval [b/alpha, b], in units of 1/b
-static void cheb_coeffs(int deg, std::vector<double> &c1, std::vector<double> &c2) {
-  const double ia = 1.0 / kChebAlpha;
+// Chebyshev recurrence coefficients for interval [b ia, b], in units of 1/b
+static void cheb_coeffs(int deg, double ia, std::vector<double> &c1, std::vector<double> &c2) {
   const double theta = (1.0 + ia) / 2.0, delta = (1.0 - ia) / 2.0, sigma1 = theta / delta;
   c1.assign(deg, 0.0);
   c2.assign(deg, 0.0);
@@ -639,6 +688,16 @@ static void cheb_coeffs(int deg, std::vector<double> &c1, std::vector<double> &c
     c2[k] = 2.0 * rho / delta;
     rho_prev = rho;
   }
+}
+
+// smoothing degree of level li: spec.cheb on the finest level; below it, where each smoothing step is
+// cheap in bytes but a full round of launches, one step (two on levels with more than kChebTwoRows
+// patch rows).  Measured on the workloads of bench.py: the CG iteration count is set by the finest
+// level's smoothing, and fewer coarse steps save time.
+static int level_degree(const gf_space *sp, int cheb, int li) {
+  const Level &L = *sp->lev[li];
+  if (li + 1 < sp->nlev()) return std::min(cheb, (6.0 * L.n1 * L.n1 > kChebTwoRows) ? 2 : 1);
+  return cheb;
 }
 
 // Multigrid V-cycle on level li for the assembled right-hand side rsrc (type TR; converted to T into
@@ -665,24 +724,18 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
     return za;
   }
   const T *r = rconv ? (const T *)rconv : (const T *)rsrc;
-  T *d = Prec<T>::d(lw), *a = Prec<T>::a(lw), *inv = Prec<T>::inv(lw);
+  T *d = Prec<T>::d(lw), *a = Prec<T>::a(lw);
+  const T *cf = Prec<T>::cf(lw);
   const T *dM = Prec<T>::dM(L), *dS = Prec<T>::dS(L), *sig = Prec<T>::sig(w), *one = Prec<T>::one(w);
   Scratch sc = w.scratch();
-  std::vector<double> c1, c2;
-  // smoothing degree of this level: spec.cheb on the finest level; below it, where each smoothing
-  // step is cheap in bytes but a full round of launches, one step (two on levels with more than
-  // kChebTwoRows patch rows).  Measured on the workloads of bench.py: the CG iteration count is set
-  // by the finest level's smoothing, and fewer coarse steps save time.
-  int deg = spec.cheb;
-  if (li + 1 < sp->nlev()) deg = std::min(spec.cheb, (6.0 * L.n1 * L.n1 > kChebTwoRows) ? 2 : 1);
-  cheb_coeffs(deg, c1, c2);
+  const int deg = level_degree(sp, spec.cheb, li);
   // dflags: the first step after the start from zero takes its previous direction from the
   // iterate itself (d = z after the first step); the last step of each sweep keeps no direction
-  // (the next sweep starts with c1 = 0)
+  // (the next sweep starts without one)
   auto smooth = [&](int k, bool last, int dflags) {
     EpiArgs<T> e;
     e.kind = EPI_CHEB;
-    e.dflags = dflags;
+    e.dflags = dflags | (k > 0 ? 4 : 0);
     e.y = a;
     e.zout = zb;
     e.d = d;
@@ -690,9 +743,8 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
     e.dM = dM;
     e.dS = dS;
     e.sig = sig;
-    e.invb = inv;
-    e.c1 = (T)c1[k];
-    e.c2 = (T)c2[k];
+    e.cf1 = cf + (size_t)k * ldb;
+    e.cf2 = cf + (size_t)(deg + k) * ldb;
     if (last && fin_op >= 0) {
       e.dot = 1;
       e.op = fin_op;
@@ -703,7 +755,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
       HIPCHK(hipEventCreate(&ev0));
       HIPCHK(hipEventCreate(&ev1));
       // read z, r (and d), write z_out (and d)
-      const int vecs = 3 + ((c1[k] != 0.0 && !(dflags & 1)) ? 1 : 0) + ((dflags & 2) ? 0 : 1);
+      const int vecs = 3 + ((k > 0 && !(dflags & 1)) ? 1 : 0) + ((dflags & 2) ? 0 : 1);
       w.slog->entries.push_back({ev0, ev1, vecs, (int)sizeof(T)});
     }
     apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, spec.rtol * spec.rtol, spec.max_iter, s,
@@ -711,7 +763,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
     std::swap(za, zb);
   };
   // pre-smoothing from zero (the first step's direction is the iterate itself and is not stored)
-  cheb_first<T, TR>(L, rsrc, rconv, za, nullptr, dM, dS, sig, inv, (T)c2[0], ldb, nt, act, s);
+  cheb_first<T, TR>(L, rsrc, rconv, za, nullptr, dM, dS, sig, cf + (size_t)deg * ldb, ldb, nt, act, s);
   for (int k = 1; k < deg; ++k) smooth(k, false, (k == 1 ? 1 : 0) | (k == deg - 1 ? 2 : 0));
   // residual, restriction, coarse correction, prolongation
   {
@@ -806,13 +858,21 @@ struct BatchSolve {
     w->node.upload(node, s);
     w->cs.upload(cs, s);
     w->active.upload(w->active_h, s);
-    for (int li = 1; li < sp->nlev(); ++li) {
-      std::vector<double> ib(ldb, 1.0);
-      if (!spec.mass_shift)
-        for (int c = 0; c < spec.ncols; ++c) ib[c] = spec.plan->invb[li][node[c]];
-      std::vector<float> ibf(ib.begin(), ib.end());
-      w->lw[li].invb64.upload(ib, s);
-      w->lw[li].invb32.upload(ibf, s);
+    // Chebyshev coefficients of every smoothing step per system (the interval depends on the node)
+    for (int li = 1; li < sp->nlev() && !spec.mass_shift; ++li) {
+      const int deg = level_degree(sp, spec.cheb, li);
+      std::vector<double> cf((size_t)2 * deg * ldb, 0.0), c1, c2;
+      for (int c = 0; c < spec.ncols; ++c) {
+        const int k = node[c];
+        cheb_coeffs(deg, spec.smooth_load ? 1.0 / kChebAlpha : spec.plan->ialpha[li][k], c1, c2);
+        for (int st = 0; st < deg; ++st) {
+          cf[(size_t)st * ldb + c] = c1[st];
+          cf[(size_t)(deg + st) * ldb + c] = c2[st] * spec.plan->invb[li][k];
+        }
+      }
+      std::vector<float> cff(cf.begin(), cf.end());
+      w->lw[li].cf64.upload(cf, s);
+      w->lw[li].cf32.upload(cff, s);
     }
     HIPCHK(hipMemsetAsync(w->x.p, 0, (size_t)F.R * ldb * sizeof(double), s));
   }
@@ -1519,6 +1579,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
           b.spec.col_node[k * it.nsamp + sm] = k;
         }
       b.spec.plan = it.frac_plan;
+      b.spec.smooth_load = it.n + pass * it.bf >= 1.5;
       bs.push_back(std::move(b));
       owners.push_back(&it);
     }

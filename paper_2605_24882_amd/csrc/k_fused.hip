@@ -6,6 +6,7 @@
 //   EPI_STORE  y = A x                       (optionally the inner product x . y)
 //   EPI_RESID  y = r - A x                   (residual for the restriction)
 //   EPI_CHEB   Chebyshev-Jacobi step on D^-1 A: res = (r - A z)/D, d = c1 d + c2 res / b_max,
+//              with c1, c2 and b_max per system
 //              z_out = z + d                (optionally the inner product r . z_out)
 // Unknowns on patch boundaries are shared with neighbouring patches: there the kernel stores its
 // patch contribution, and the interface kernel sums the copies and runs the same epilogue.
@@ -51,11 +52,11 @@ __device__ __forceinline__ void block_partial(double acc, double *partial, int64
 template <typename T, int P, int TY, int KIND, int DOT>
 __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__restrict__ stM,
                                                      const T *__restrict__ stS, const T *__restrict__ x,
-                                                     const T *__restrict__ ca, const T *__restrict__ cb, T c1, T c2,
+                                                     const T *__restrict__ ca, const T *__restrict__ cb, const T *__restrict__ cf1,
+                                                     const T *__restrict__ cf2,
                                                      T *__restrict__ y, T *__restrict__ zout, T *__restrict__ d,
                                                      const T *__restrict__ r, const T *__restrict__ dM,
-                                                     const T *__restrict__ dS, const T *__restrict__ invb,
-                                                     double *__restrict__ partial, const int *__restrict__ active,
+                                                     const T *__restrict__ dS, double *__restrict__ partial, const int *__restrict__ active,
                                                      int dflags) {
   constexpr int S = 2 * P + 1, WR = TY + 2 * P, SS = S * S;
   const int Lb = blockIdx.x;
@@ -77,10 +78,11 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
     const int iy0 = iyb * TY;
     const int x0 = seg * g.TX, x1 = min(x0 + g.TX, n1);
     const T a = ca[col], b = cb[col];
-    T sg = 0, ib = 0;
+    T sg = 0, a1 = 0, a2 = 0;
     if (KIND == EPI_CHEB) {
       sg = a;  // the shift of this system
-      ib = invb[col];
+      if (dflags & 4) a1 = cf1[col];
+      a2 = cf2[col];
     }
     const int64_t pbase = (int64_t)m * W * W;
     const int64_t ct0 = (int64_t)ct * CT;
@@ -154,8 +156,8 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
         } else {
           const T rv = r[i];
           const T D = sg * dM[row] + dS[row];
-          const T dp = (c1 != T(0)) ? ((dflags & 1) ? win[t + P][P] : d[i]) : T(0);
-          const T dn = c1 * dp + c2 * ib * ((rv - Az) / D);
+          const T dp = (dflags & 4) ? ((dflags & 1) ? win[t + P][P] : d[i]) : T(0);
+          const T dn = a1 * dp + a2 * ((rv - Az) / D);
           if (!(dflags & 2)) d[i] = dn;
           const T zo = win[t + P][P] + dn;
           zout[i] = zo;
@@ -201,8 +203,8 @@ __global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__re
         const T rv = e.r[i];
         const T D = e.sig[col] * e.dM[row] + e.dS[row];
         const T res = (rv - s) / D;
-        const T dp = (e.c1 != T(0)) ? ((e.dflags & 1) ? x[i] : e.d[i]) : T(0);
-        const T dn = e.c1 * dp + e.c2 * e.invb[col] * res;
+        const T dp = (e.dflags & 4) ? ((e.dflags & 1) ? x[i] : e.d[i]) : T(0);
+        const T dn = ((e.dflags & 4) ? e.cf1[col] : T(0)) * dp + e.cf2[col] * res;
         if (!(e.dflags & 2)) e.d[i] = dn;
         const T zo = x[i] + dn;
         e.zout[i] = zo;
@@ -261,12 +263,12 @@ static void launch_apply_k(const ApplyGeom &g, const T *stM, const T *stS, const
   if (ev0) {
     // the runtime stamps the events at the start and end of this dispatch itself
     hipExtLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM,
-                          stS, x, ca, cb, e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active,
+                          stS, x, ca, cb, e.cf1, e.cf2, e.y, e.zout, e.d, e.r, e.dM, e.dS, partial, active,
                           e.dflags);
     return;
   }
   hipLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca, cb,
-                     e.c1, e.c2, e.y, e.zout, e.d, e.r, e.dM, e.dS, e.invb, partial, active, e.dflags);
+                     e.cf1, e.cf2, e.y, e.zout, e.d, e.r, e.dM, e.dS, partial, active, e.dflags);
 }
 
 template <typename T, int P, int TY>
@@ -461,20 +463,20 @@ __global__ __launch_bounds__(256) void k_update_p(RowGeom g, double *__restrict_
   }
 }
 
-// First Chebyshev step from z = 0: d = z = c2 r / (D b_max).  TR is the type of the incoming
+// First Chebyshev step from z = 0: d = z = cf2 r / D (cf2 = c2 / b_max per system).  TR is the type of the incoming
 // right-hand side; with r32 != null it is also stored in the V-cycle precision.
 template <typename T, typename TR>
 __global__ __launch_bounds__(256) void k_cheb_first(RowGeom g, const TR *__restrict__ r, T *__restrict__ r32,
                                                     T *__restrict__ z, T *__restrict__ d, const T *__restrict__ dM,
                                                     const T *__restrict__ dS, const T *__restrict__ sig,
-                                                    const T *__restrict__ invb, T c2, const int *active) {
+                                                    const T *__restrict__ cf2, const int *active) {
   const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
   if (active && !active[ct]) return;
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);
   const int col = ct * CT + lane;
   const int ldb = g.ldb;
-  const T sg = sig[col], sc = c2 * invb[col];
+  const T sg = sig[col], sc = cf2[col];
   const int64_t stride = (int64_t)g.nrb * 4;
   for (int64_t r0 = (int64_t)rb * 4 + wave; r0 < g.R; r0 += 4 * stride) {
     T rv[4];
@@ -521,20 +523,20 @@ template void update_p2<float>(const Level &, double *, const float *, const Col
 
 template <typename T, typename TR>
 void cheb_first(const Level &L, const TR *r, T *r32, T *z, T *d, const T *dM, const T *dS, const T *sig,
-                const T *invb, T c2, int ldb, int ntiles, const int *active, hipStream_t s) {
+                const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s) {
   const RowGeom g = row_geom(L, ldb);
   hipLaunchKernelGGL((k_cheb_first<T, TR>), dim3(g.nrb * ntiles), dim3(256), 0, s, g, r, r32, z, d, dM, dS, sig,
-                     invb, c2, active);
+                     cf2, active);
   HIPCHK(hipGetLastError());
 }
 template void cheb_first<double, double>(const Level &, const double *, double *, double *, double *,
-                                         const double *, const double *, const double *, const double *, double, int,
-                                         int, const int *, hipStream_t);
+                                         const double *, const double *, const double *, const double *, int, int,
+                                         const int *, hipStream_t);
 template void cheb_first<float, float>(const Level &, const float *, float *, float *, float *, const float *,
-                                       const float *, const float *, const float *, float, int, int, const int *,
+                                       const float *, const float *, const float *, int, int, const int *,
                                        hipStream_t);
 template void cheb_first<float, double>(const Level &, const double *, float *, float *, float *, const float *,
-                                        const float *, const float *, const float *, float, int, int, const int *,
+                                        const float *, const float *, const float *, int, int, const int *,
                                         hipStream_t);
 
 }  // namespace gf
@@ -567,8 +569,8 @@ __global__ __launch_bounds__(256) void k_epi_rows(RowGeom g, const T *__restrict
       const T rv = e.r[i];
       const T D = e.sig[col] * e.dM[row] + e.dS[row];
       const T res = (rv - Az) / D;
-      const T dp = (e.c1 != T(0)) ? ((e.dflags & 1) ? x[i] : e.d[i]) : T(0);
-      const T dn = e.c1 * dp + e.c2 * e.invb[col] * res;
+      const T dp = (e.dflags & 4) ? ((e.dflags & 1) ? x[i] : e.d[i]) : T(0);
+      const T dn = ((e.dflags & 4) ? e.cf1[col] : T(0)) * dp + e.cf2[col] * res;
       if (!(e.dflags & 2)) e.d[i] = dn;
       const T zo = x[i] + dn;
       e.zout[i] = zo;

@@ -120,11 +120,14 @@ struct EpiArgs {
   T *zout = nullptr;      // CHEB: new iterate (a different buffer than the input)
   T *d = nullptr;         // CHEB: Chebyshev direction
   const T *r = nullptr;   // CHEB/RESID: right-hand side
-  const T *dM = nullptr, *dS = nullptr, *sig = nullptr, *invb = nullptr;
-  T c1 = 0, c2 = 0;
+  const T *dM = nullptr, *dS = nullptr, *sig = nullptr;
+  // CHEB: per-system recurrence coefficients of this step, d = cf1 d + cf2 (r - A z)/D (cf2 includes
+  // the reciprocal of the upper spectral bound)
+  const T *cf1 = nullptr, *cf2 = nullptr;
   // CHEB: bit 0 -- the previous direction equals the input iterate (first step after a start from
   // zero), so it is taken from the input instead of d; bit 1 -- the new direction is not needed
-  // afterwards and is not stored
+  // afterwards and is not stored; bit 2 -- the step has a previous direction (every step but the
+  // first of a sweep; cf1 is read only then)
   int dflags = 0;
 };
 
@@ -156,7 +159,7 @@ void epi_rows(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColS
               int ntiles, double tol2, int maxit, hipStream_t s);
 template <typename T, typename TR>
 void cheb_first(const Level &L, const TR *r, T *r32, T *z, T *d, const T *dM, const T *dS, const T *sig,
-                const T *invb, T c2, int ldb, int ntiles, const int *active, hipStream_t s);
+                const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s);
 
 template <typename TA, typename TB>
 void reduce_dot(const Level &L, const TA *a, const TB *b, Scratch &sc, int ldb, int ntiles, ColState *cs,

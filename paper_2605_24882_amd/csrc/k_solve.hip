@@ -188,10 +188,6 @@ template void convert_rows<float, double>(const Level &, const float *, double *
 template void convert_rows<double, double>(const Level &, const double *, double *, int, int, const int *,
                                            hipStream_t);
 
-// Chebyshev-Jacobi step on D^-1 A, D = sigma diag(M) + diag(S) (assembled diagonals):
-//   res = (r - Az)/D  (Az == null: initial guess zero),  d = c1 d + c2 invb res,  z = z + d
-// (z = d when `first`).  invb is the per-system reciprocal of the upper spectral bound.
-
 // power-iteration step for the spectral bound of D^-1 A: v = w / D
 struct FDivDiag {
   double *v;
