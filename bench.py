@@ -8,9 +8,15 @@ system solved by multigrid-preconditioned CG to relative residual 1e-10 in FP64.
 One step = one call of the sampler over the 64 loads, loads already resident in device memory:
 integer solves, the batch of 41 x 64 shifted systems, and the quadrature sum.
 
-Prints one JSON line.  The roofline entry is for the dominant kernel, the FP64 stencil operator
-application of the outer CG, timed with HIP events around every launch during the timed steps.
-The CPU baseline is the FP64 oracle on one of the 64 loads (single thread).
+Prints one JSON line.  The roofline entry is for the dominant kernel, the Chebyshev smoothing step
+on the finest level (the stencil operator fused with the smoother's update), timed with HIP events
+stamped by the runtime around every launch, on extra steps run after the timed ones; a second entry
+covers the FP64 operator application of the outer CG.  The CPU baseline is the FP64 oracle on one of
+the 64 loads (single thread).
+
+--load sqrtm replaces the element-wise noise factor by the paper's own load f = sqrt(M) y (Sec. 3.3,
+Khat shifted mass solves per sample, bounds estimated by the library on every call), computed inside
+every step.
 """
 import argparse
 import collections
@@ -240,6 +246,9 @@ def main():
                     help="multigrid preconditioner: the V-cycle or the additive BPX form")
     ap.add_argument("--split", choices=("plain", "improved"), default="plain",
                     help="split of beta: plain n + beta', or the improved split (the rule applied twice)")
+    ap.add_argument("--load", choices=("factor", "sqrtm"), default="factor",
+                    help="white-noise load: element-wise factor (default) or sqrt(M) y inside every step")
+    ap.add_argument("--khat", type=int, default=16, help="square-root rule size for --load sqrtm")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the one-system-per-call FP64 GPU reference timing")
@@ -289,7 +298,8 @@ def main():
             seeds = [s_ for s_ in range(nsamp) if s_ % len(combos) == i]
             z = torch.from_numpy(inputs.noise_vectors(seeds, sp.noise_length)).cuda()
             reqs.append(dict(space=sp, kappa=kp, beta=bc["beta"], b=sp.white_noise(z), h=bc["h"],
-                             k_minus=bc["k"], k_plus=bc["k"]))
+                             k_minus=bc["k"], k_plus=bc["k"],
+                             split=g.GF_SPLIT_IMPROVED if args.split == "improved" else g.GF_SPLIT_PLAIN))
             del z
         kw = dict(precision=prec, rtol=rtol, max_iter=2000, cheb_degree=args.cheb, apply_kind=args.apply_kind,
                   preconditioner=g.GF_PRECOND_BPX if args.precond == "bpx" else g.GF_PRECOND_VCYCLE)
@@ -303,9 +313,13 @@ def main():
         geo = g.Geometry(ctx, pert)
         sp = g.Space(ctx, geo, p, lev)
         space_s = time.perf_counter() - t0
-        z = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.noise_length)).cuda()
-        b = sp.white_noise(z)
-        del z
+        if args.load == "sqrtm":
+            y = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.ndofs)).cuda()
+            b = None
+        else:
+            z = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.noise_length)).cuda()
+            b = sp.white_noise(z)
+            del z
         kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
                   apply_kind=args.apply_kind,
                   split=g.GF_SPLIT_IMPROVED if args.split == "improved" else g.GF_SPLIT_PLAIN,
@@ -329,12 +343,21 @@ def main():
                 st["max_rel_resid"] = max(st1["max_rel_resid"], st2["max_rel_resid"])
                 return gk, st
             workload = workload_name(cfg) + "; plus d loss/d kappa by adjoint solves (loss over 1000 points)"
+        elif args.load == "sqrtm":
+            def step(flags=0):
+                f, st0 = sp.sqrt_mass(y, khat=args.khat, rtol=rtol, flags=flags & ~g.GF_FLAG_TIME_APPLY)
+                u, st = sp.sample(kappa, beta, f, flags=flags, **kw)
+                st = dict(st)
+                st["n_systems"] += st0["n_systems"]
+                st["max_iters"] = max(st["max_iters"], st0["max_iters"])
+                return u, st
+            workload = workload_name(cfg) + f"; load sqrt(M) y by the square-root rule with {args.khat} shifts"
         else:
             def step(flags=0):
                 return sp.sample(kappa, beta, b, flags=flags, **kw)
             workload = workload_name(cfg)
-        if args.split == "improved":
-            workload += "; improved split (rule applied twice where beta' < 1/3 or > 2/3)"
+    if args.split == "improved":
+        workload += "; improved split (rule applied twice where beta' < 1/3 or > 2/3)"
     if args.precond == "bpx":
         workload += "; BPX (additive multilevel) preconditioner"
     if args.copy_probe_mib > 0:
@@ -413,9 +436,10 @@ def main():
         "roofline": roof,
         "roofline_outer_operator": roof_outer,
     }
-    if args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_one_at_a_time:
+    if (args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_one_at_a_time
+            and args.load == "factor"):
         out["gpu_one_solve_at_a_time"] = one_at_a_time(g, sp, b, CONFIGS[args.config], kw)
-    if not args.no_cpu_baseline and args.config in CONFIGS:
+    if not args.no_cpu_baseline and args.config in CONFIGS and args.load == "factor":
         out["cpu_baseline"] = cpu_baseline(CONFIGS[args.config])
     print(json.dumps(out))
 
