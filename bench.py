@@ -39,6 +39,9 @@ CONFIGS = {
     "c1": (False, 2, 2, 4.0, 0.75, 0.4, 15, 1, 0, 1e-13),
     "c5": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-6),
     "c4": (False, 3, 6, 8.0, 0.8, 0.4, 20, 16, 1, 1e-6),
+    # NURBS multi-patch surface: the 4 x 4 patch torus R = 2, r = 1 (biquadratic rational Bezier
+    # patches, four at every corner), 32 x 32 elements per patch
+    "torus": ("torus", 2, 5, 10.0, 1.6, 0.4, 20, 64, 0, 1e-10),
 }
 # configs whose step also computes d loss / d kappa by the adjoint (loss over 1000 seeded points)
 GRADIENT_CONFIGS = {"c4"}
@@ -67,10 +70,13 @@ def batch_workload_name(bc, nreq):
 def workload_name(cfg):
     pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
     n1 = 2 ** lev + p
-    N = 6 * (n1 - 2) ** 2 + 12 * (n1 - 2) + 8
     nint = math.floor(beta)
-    surf = "perturbed sphere" if pert else "unit sphere"
-    return (f"{surf}, 6 patches, degree {p}, {2**lev}x{2**lev} elements/patch ({N} DOF); kappa={kappa:g}, "
+    if pert == "torus":
+        N, surf, npatch = 16 * (n1 - 1) ** 2, "NURBS torus R=2 r=1", 16
+    else:
+        N, npatch = 6 * (n1 - 2) ** 2 + 12 * (n1 - 2) + 8, 6
+        surf = "perturbed sphere" if pert else "unit sphere"
+    return (f"{surf}, {npatch} patches, degree {p}, {2**lev}x{2**lev} elements/patch ({N} DOF); kappa={kappa:g}, "
             f"beta={beta:g} ({nint} integer solve(s) + {2*k+1} sinc nodes, h={h:g}); {nsamp} samples; "
             f"{'FP64' if prec == 0 else 'FP32 V-cycle / FP64 CG'} MG-PCG to rel. residual {rtol:g}")
 
@@ -210,9 +216,13 @@ def cpu_baseline(cfg, nodes_timed=6):
     n, bf = fractional.split_plain(beta)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        d = assembly.Discretisation(p, lev, pert)
+        if pert == "torus":
+            from oracle import geometry
+            d = assembly.Discretisation(p, lev, geometry.NurbsSurface(*inputs.torus_patches(2.0, 1.0)))
+        else:
+            d = assembly.Discretisation(p, lev, pert)
         t1 = time.perf_counter()
-        b = noise.load(d, inputs.noise_vectors([0], inputs.noise_length(p, lev)))
+        b = noise.load(d, inputs.noise_vectors([0], inputs.noise_length(p, lev, 16 if pert == "torus" else 6)))
         t2 = time.perf_counter()
         ws = fractional.integer_chain(d.M, d.S, kappa, n, b)
         r = b if n == 0 else np.stack([d.M @ w for w in ws[-1]])
@@ -310,7 +320,10 @@ def main():
     else:
         cfg = CONFIGS[args.config]
         pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
-        geo = g.Geometry(ctx, pert)
+        if pert == "torus":
+            geo = g.Geometry.nurbs(ctx, *inputs.torus_patches(2.0, 1.0))
+        else:
+            geo = g.Geometry(ctx, pert)
         sp = g.Space(ctx, geo, p, lev)
         space_s = time.perf_counter() - t0
         if args.load == "sqrtm":

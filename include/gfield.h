@@ -6,7 +6,8 @@
  * Sonderegger and von Rickenbach, "Simulation of Gaussian random fields on surfaces
  * using the isogeometric finite element method" (arXiv 2605.24882):
  *
- *   surface      Gamma = union of six patches F_m: [0,1]^2 -> Gamma_m      (Sec. 2.2)
+ *   surface      Gamma = union of patches F_m: [0,1]^2 -> Gamma_m: the six-patch sphere
+ *                family, or rational tensor-product B-spline (NURBS) patches (Sec. 2.2)
  *   space        S^0_{j,p}: continuous, patchwise tensor B-splines of degree p on
  *                2^j x 2^j elements per patch                              (Sec. 2.3)
  *   matrices     M_ij = <phi_j, phi_i>, S_ij = <grad phi_j, grad phi_i>     (Sec. 3.1, eq. FEM;
@@ -25,7 +26,7 @@
  *     HIP stream; every call returns after that work has finished.
  *   - Vectors of unknowns are float64 in the global numbering of the space, several
  *     vectors stored one after the other: array[v * N + i] is unknown i of vector v.
- *   - Global numbering: patches 0..5, then coefficient row iy, then column ix (ix fastest),
+ *   - Global numbering: patches in order, then coefficient row iy, then column ix (ix fastest),
  *     each coefficient whose surface point has not been seen yet gets the next number.
  *   - Arguments are validated on the host before any device work: GF_EINVAL for bad sizes,
  *     null pointers, non-finite or out-of-range parameters.
@@ -76,11 +77,31 @@ void gf_context_destroy(gf_context *ctx);
  * and r(x, y, z) = 1 + 0.15 sin(3x) sin(2y) cos(z) (perturbed = 1).  The geometry holds no device
  * data; ctx may be NULL. */
 gf_status gf_geometry_sphere(gf_context *ctx, int32_t perturbed, gf_geometry **out);
+
+/* A surface given as npatch NURBS patches (Sec. 2.2, Def. of the geometry: each patch a rational
+ * tensor-product B-spline map F_m(s, t) = sum_ab N_a(s) N_b(t) w_ab X_ab / sum_ab N_a(s) N_b(t) w_ab
+ * of degrees (deg_u, deg_v), 1..4).  Per patch m: ncoef[2m], ncoef[2m+1] control points along s and
+ * t (degree+1 .. 4096); knots holds, patch after patch, the open knot vector along s
+ * (ncoef[2m] + deg_u + 1 values) and then along t (ncoef[2m+1] + deg_v + 1 values), each with
+ * deg+1 zeros, non-decreasing interior knots in (0, 1) of multiplicity at most deg, and deg+1
+ * ones; ctrl holds, patch after patch, [ncoef[2m+1]][ncoef[2m]][4] = (x, y, z, weight), weights
+ * positive.  Host arrays, copied; the geometry holds no device data (ctx may be NULL).  Patches
+ * meet conformingly: an edge shared by two patches has the same control
+ * points, weights and knots on both sides, in the same or the reverse order (relative tolerance
+ * 1e-12 of the largest coordinate); the finite element space is glued (C^0) across such edges,
+ * and any number of patches may share a corner.  An edge matched by no other edge is a boundary
+ * (natural boundary condition).  GF_EINVAL for malformed input or an edge shared by more than two
+ * patches, GF_EUNSUPPORTED for an edge collapsed to a point.  1 <= npatch <= 4096. */
+gf_status gf_geometry_nurbs(gf_context *ctx, int32_t npatch, int32_t deg_u, int32_t deg_v, const int32_t *ncoef,
+                            const double *knots, const double *ctrl, gf_geometry **out);
+/* Number of patches of a geometry (-1 for NULL). */
+int32_t gf_geometry_npatch(const gf_geometry *geom);
 void gf_geometry_destroy(gf_geometry *geom);
 
 /* Patch index and parameters of surface points, by the radial inverse of the maps above
  * (the coordinate of largest modulus picks the face).  xyz[npts][3], patch[npts],
- * st[npts][2], host arrays. */
+ * st[npts][2], host arrays.  Sphere family only (GF_EUNSUPPORTED for NURBS geometries, whose
+ * callers pass patch and parameters to gf_eval directly). */
 gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, int32_t *patch, double *st);
 
 /* S^0_{level,degree} on the geometry (Sec. 2.3): 1 <= degree <= 5, 0 <= level <= 12.
@@ -90,12 +111,14 @@ gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, in
 gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degree, int32_t level,
                           int32_t coarse_level, gf_space **out);
 void gf_space_destroy(gf_space *space);
-/* Number N of unique unknowns: 6(n-2)^2 + 12(n-2) + 8 with n = 2^level + degree. */
+/* Number N of unique unknowns: 6(n-2)^2 + 12(n-2) + 8 with n = 2^level + degree on the sphere
+ * family; on NURBS geometries the count the gluing gives (a closed surface of P quadrilateral
+ * patches with V corners and E shared edges: P(n-2)^2 + E(n-2) + V). */
 int64_t gf_space_ndofs(const gf_space *space);
-/* Length of one white-noise vector z for gf_white_noise: 6 * 4^level * (degree+1)^2. */
+/* Length of one white-noise vector z for gf_white_noise: npatch * 4^level * (degree+1)^2. */
 int64_t gf_space_noise_length(const gf_space *space);
 /* Global number of each patch coefficient: local_to_global[(m*n + iy)*n + ix], n = 2^level + degree,
- * host array of 6 n^2 entries. */
+ * host array of npatch n^2 entries. */
 gf_status gf_space_dofmap(const gf_space *space, int32_t *local_to_global);
 
 /* Operator kinds of gf_space_apply. */
@@ -270,7 +293,7 @@ void gf_tape_destroy(gf_tape *tape);
 
 /* Point evaluation (Sec. 2.3): the field with global coefficients u at the surface point F_m(s, t)
  * is sum over the (p+1)^2 B-splines that do not vanish there of B_iy(t) B_ix(s) u[gid(m, iy, ix)].
- * patch: [npts] in 0..5; st: [npts][2] = (s, t) in [0, 1]^2 (gf_locate gives both for points on the
+ * patch: [npts] in 0..npatch-1; st: [npts][2] = (s, t) in [0, 1]^2 (gf_locate gives both for points on the
  * surface); u: [nvec][N]; vals: [nvec][npts].  All arrays of the memory kind mem.  Invalid patch or
  * parameter values give GF_EINVAL before any work. */
 gf_status gf_eval(const gf_space *space, int32_t npts, const int32_t *patch, const double *st, int32_t nvec,

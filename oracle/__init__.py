@@ -15,7 +15,7 @@ blocking, fusion or reordering beyond what the cited definitions state.
 Modules
   sinc        scalar Balakrishnan / sinc quadrature rules (Sec. 3.4, eq. beta-approx)
   bspline     Cox-de Boor B-splines, Greville points, knot insertion (Sec. 2.1, 2.3)
-  geometry    six-patch cube-sphere and perturbed sphere maps (Sec. 2.2, 4.1)
+  geometry    six-patch cube-sphere, perturbed sphere, NURBS patch maps (Sec. 2.2, 4.1)
   assembly    Gauss quadrature, DOF gluing, mass and stiffness matrices (Sec. 3.1, 3.2)
   fractional  split of beta, integer chain, node solves, quadrature sum (Sec. 3.4)
   noise       element-wise factorised white-noise load b ~ N(0, M) (Sec. 3.3)

@@ -15,7 +15,7 @@ n1 = 2^j + p per direction).  Copies of one global unknown on patch interfaces
 are identified geometrically: two local coefficients are the same unknown when
 their Greville points map to the same surface point (Sec. 2.2 asks only that
 neighbouring maps agree up to a rotation, so no orientation is assumed).
-Global numbering: scan patches 0..5, then iy, then ix (ix fastest), and give
+Global numbering: scan patches in order, then iy, then ix (ix fastest), and give
 the next number to every local coefficient whose surface point is new.
 """
 import numpy as np
@@ -43,7 +43,7 @@ def dofmap(p, j, perturbed=False, tol=1e-12):
     g = bspline.greville(knots, p)
     n1 = len(g)
     pts = []
-    for m in range(geometry.NPATCH):
+    for m in range(geometry.npatch(perturbed)):
         S, T = np.meshgrid(g, g, indexing="xy")  # S[iy, ix] = g[ix], T[iy, ix] = g[iy]
         pts.append(geometry.patch_map(m, S, T, perturbed).reshape(-1, 3))
     pts = np.concatenate(pts)
@@ -58,7 +58,7 @@ def dofmap(p, j, perturbed=False, tol=1e-12):
             if k > i:
                 l2g[k] = nxt
         nxt += 1
-    return l2g.reshape(geometry.NPATCH, n1, n1), nxt
+    return l2g.reshape(geometry.npatch(perturbed), n1, n1), nxt
 
 
 class Discretisation:
@@ -87,7 +87,7 @@ class Discretisation:
         self.xq, self.wq = xs.reshape(ne, q), wg / ne  # abscissae and weights per element
         nloc = (p + 1) ** 2
         el_dofs, el_M, el_S = [], [], []
-        for m in range(geometry.NPATCH):
+        for m in range(geometry.npatch(self.perturbed)):
             for ey in range(ne):
                 for ex in range(ne):
                     iy = np.arange(ey, ey + p + 1)
@@ -133,7 +133,7 @@ class Discretisation:
 
     # ---- conversions between the global vector and the patch-local grids ----
     def to_local(self, u):
-        """Patch-local coefficient grids [6, n1, n1] of a global coefficient vector."""
+        """Patch-local coefficient grids [npatch, n1, n1] of a global coefficient vector."""
         return np.asarray(u)[..., self.l2g]
 
     def owner_of(self):
@@ -160,7 +160,7 @@ def load_vector(disc, fun, q):
     xs, ws = _patch_quadrature(disc, q)
     B = bspline.basis(disc.knots, disc.p, xs)  # (points along one direction, n1)
     f = np.zeros(disc.N)
-    for m in range(geometry.NPATCH):
+    for m in range(geometry.npatch(disc.perturbed)):
         S_, T_ = np.meshgrid(xs, xs, indexing="xy")
         X = geometry.patch_map(m, S_, T_, disc.perturbed)
         a = geometry.first_fundamental_form(m, S_, T_, disc.perturbed)[3]
@@ -175,7 +175,7 @@ def l2_error(disc, u, fun, q):
     xs, ws = _patch_quadrature(disc, q)
     B = bspline.basis(disc.knots, disc.p, xs)
     err2 = 0.0
-    for m in range(geometry.NPATCH):
+    for m in range(geometry.npatch(disc.perturbed)):
         S_, T_ = np.meshgrid(xs, xs, indexing="xy")
         X = geometry.patch_map(m, S_, T_, disc.perturbed)
         a = geometry.first_fundamental_form(m, S_, T_, disc.perturbed)[3]

@@ -56,6 +56,36 @@ def basis(knots, p, x):
     return B
 
 
+def basis_analytic(knots, p, x):
+    """b_l^p(x) for all l with x of any numeric type, complex included (shape (len(x), k)).
+
+    The same recursion as `basis`, with the knot span chosen by the real part of x and the linear
+    factors evaluated in x itself, so that the result is the polynomial piece of that span
+    continued analytically (used for complex-step derivatives of NURBS maps)."""
+    x = np.atleast_1d(np.asarray(x))
+    xr = np.real(x)
+    m = len(knots) - 1
+    B = np.zeros((x.size, m), dtype=np.result_type(x.dtype, np.float64))
+    last = max(i for i in range(m) if knots[i] < knots[i + 1])
+    for i in range(m):
+        inside = (knots[i] <= xr) & (xr < knots[i + 1])
+        if i == last:
+            inside = inside | (xr == knots[i + 1])
+        B[:, i] = inside
+    for d in range(1, p + 1):
+        m = len(knots) - 1 - d
+        Bn = np.zeros((x.size, m), dtype=B.dtype)
+        for l in range(m):
+            den1 = knots[l + d] - knots[l]
+            den2 = knots[l + d + 1] - knots[l + 1]
+            if den1 > 0.0:
+                Bn[:, l] += (x - knots[l]) / den1 * B[:, l]
+            if den2 > 0.0:
+                Bn[:, l] += (knots[l + d + 1] - x) / den2 * B[:, l + 1]
+        B = Bn
+    return B
+
+
 def basis_derivative(knots, p, x):
     """First derivatives of all b_l^p at x, shape (len(x), k).
 

@@ -1,4 +1,4 @@
-"""Six-patch sphere and perturbed sphere (oracle, test infrastructure only).
+"""Surfaces: six-patch sphere, perturbed sphere, NURBS patches (oracle, test infrastructure only).
 
 Sec. 2.2 asks for patch maps F_m: [0,1]^2 -> Gamma_m that agree on shared
 interfaces up to a rotation of the reference square.  Sec. 4.1 uses the unit
@@ -14,14 +14,60 @@ so the radial projection of the cube faces is used:
 each oriented so that dF/ds x dF/dt points outward.  The perturbed sphere
 scales the unit-sphere point xh by r(xh) = 1 + 0.15 sin(3x) sin(2y) cos(z).
 
+A NURBS surface (Sec. 2.2, definition of the geometry) is a list of rational
+tensor-product B-spline patches F_m(s, t) = sum N_a(s) N_b(t) w_ab X_ab /
+sum N_a(s) N_b(t) w_ab; `NurbsSurface` holds them, and every function below that
+takes `perturbed` also accepts a NurbsSurface in its place.
+
 Derivatives are taken by complex-step differentiation,
 dF/ds = Im F(s + i eps, t) / eps with eps = 1e-30, exact to rounding for the
-analytic maps used here; no hand-derived derivative formula is involved.
+analytic maps used here (for NURBS, inside a knot span); no hand-derived
+derivative formula is involved.
 """
 import numpy as np
 
+from . import bspline
+
 NPATCH = 6
 EPS_CS = 1e-30
+
+
+class NurbsSurface:
+    """Patches of degrees (du, dv); ncoef[m] = (control points along s, along t); knots flat, per
+    patch the s then the t knot vector; ctrl[m] of shape (nt, ns, 4) = (x, y, z, weight)."""
+
+    def __init__(self, du, dv, ncoef, knots, ctrl):
+        self.du, self.dv = int(du), int(dv)
+        self.npatch = len(ncoef)
+        self.patches = []
+        off = 0
+        for m, (ns, nt) in enumerate(np.asarray(ncoef)):
+            U = np.asarray(knots[off:off + ns + self.du + 1], dtype=np.float64)
+            off += ns + self.du + 1
+            V = np.asarray(knots[off:off + nt + self.dv + 1], dtype=np.float64)
+            off += nt + self.dv + 1
+            C = np.asarray(ctrl[m], dtype=np.float64).reshape(nt, ns, 4)
+            self.patches.append((U, V, C))
+
+    def point(self, m, s, t):
+        """F_m(s, t) of shape s.shape + (3,); analytic in s and t (complex parameters allowed)."""
+        U, V, C = self.patches[m]
+        s = np.asarray(s)
+        t = np.asarray(t)
+        shape = np.broadcast(s, t).shape
+        sf = np.broadcast_to(s, shape).reshape(-1)
+        tf = np.broadcast_to(t, shape).reshape(-1)
+        Bs = bspline.basis_analytic(U, self.du, sf)  # (npts, ns)
+        Bt = bspline.basis_analytic(V, self.dv, tf)  # (npts, nt)
+        w = C[..., 3]
+        den = np.einsum("pb,pa,ba->p", Bt, Bs, w)
+        num = np.einsum("pb,pa,bac->pc", Bt, Bs, C[..., :3] * w[..., None])
+        return (num / den[:, None]).reshape(shape + (3,))
+
+
+def npatch(surface):
+    """Number of patches of the surface (`perturbed` flag or NurbsSurface)."""
+    return surface.npatch if isinstance(surface, NurbsSurface) else NPATCH
 
 
 def cube_point(m, s, t):
@@ -51,6 +97,8 @@ def radius(xh):
 
 def patch_map(m, s, t, perturbed=False):
     """F_m(s, t) in R^3 (analytic in s, t, so it accepts complex parameters)."""
+    if isinstance(perturbed, NurbsSurface):
+        return perturbed.point(m, s, t)
     s = np.asarray(s)
     t = np.asarray(t)
     v = cube_point(m, s, t)

@@ -72,6 +72,31 @@ void gauss_legendre(int q, std::vector<double> &x, std::vector<double> &w);
 void element_basis(int p, int nel, int e, double u, double *val, double *der);
 std::vector<double> refinement_matrix(int p, int lc);
 void glue_patches(int p, int lev, std::vector<int> &l2g, int &N);
+
+// Description of the surface for the device (metric kernel): the six-patch sphere family, or
+// rational tensor-product B-spline patches of degrees (du, dv) with, per patch, pinfo[5 m ..] =
+// (control points along s, along t, offset of the s knots, offset of the t knots, offset of the
+// control points) into knots[] and ctrl[] ([nt][ns][4]: x, y, z, weight).
+enum SurfaceKind { SURF_SPHERE = 0, SURF_NURBS = 1 };
+struct SurfaceArgs {
+  int kind = SURF_SPHERE;
+  int perturbed = 0;
+  int npatch = 6;
+  int du = 0, dv = 0;
+  const int *pinfo = nullptr;
+  const double *knots = nullptr;
+  const double *ctrl = nullptr;
+};
+// host copy of a NURBS surface
+struct NurbsHost {
+  int npatch = 0, du = 0, dv = 0;
+  std::vector<int> pinfo;
+  std::vector<double> knots, ctrl;
+};
+// Interface gluing of the FEM coefficients of one level on NURBS patches: shared edges are found
+// by comparing the boundary control points, weights and knots of the patches; coefficient rows
+// along matched edges are identified (same or reversed order), corners through the edges.
+void glue_patches_nurbs(const NurbsHost &g, int p, int lev, std::vector<int> &l2g, int &N);
 // Jacobi elliptic functions sn, cn, dn of parameter q in [0, 1) and the complete elliptic integral
 // of the first kind K(q)
 void jacobi_sncndn(double u, double q, double *sn, double *cn, double *dn);
@@ -91,11 +116,12 @@ struct ApplyTune {
 // with the column (system) index fastest: element (row, c) at row*ldb + c.
 struct Level {
   int p = 0, lev = 0, nel = 0, n1 = 0, W = 0, q = 0, S = 0;  // S = 2p+1 stencil width
-  int64_t R = 0;  // padded rows 6*W*W
+  int npatch = 6;
+  int64_t R = 0;  // padded rows npatch*W*W
   int N = 0;      // unique unknowns
   std::vector<int> l2g;             // host: local (m, iy, ix) -> global id
   std::vector<int> owner_row_h;     // host: global id -> owner row
-  DBuf<double> metric;              // [6][nel][nel][q][q][4]: m, G11, G12, G22 (weights folded in)
+  DBuf<double> metric;              // [npatch][nel][nel][q][q][4]: m, G11, G12, G22 (weights folded in)
   DBuf<double> basis;               // [nel][2][q][p+1]: values, then s-derivatives
   DBuf<float> metric32, basis32;    // FP32 copies for the FP32 matrix-free apply
   DBuf<double> stM, stS;            // [R][S*S] patch stencils (FP64)
@@ -130,7 +156,11 @@ struct gf_context {
 
 struct gf_geometry {
   gf_context *ctx = nullptr;
+  int kind = gf::SURF_SPHERE;
   int perturbed = 0;
+  int npatch = 6;
+  gf::NurbsHost nurbs;                    // SURF_NURBS: the patches (host; copied to the device
+                                          // while a space is built on them)
   int refs = 1;
 };
 
@@ -148,6 +178,7 @@ struct gf_space {
   int N0 = 0;
   std::map<std::string, std::unique_ptr<gf::Plan>> plans;
   gf::Level &fine() { return *lev.back(); }
+  const gf::Level &fine() const { return *lev.back(); }
   int nlev() const { return (int)lev.size(); }
 };
 
@@ -158,7 +189,7 @@ namespace gf {
 constexpr int CT = 64;
 
 // setup kernels (k_setup.hip)
-void launch_metric(const Level &L, int perturbed, const double *gx, const double *gw, hipStream_t s);
+void launch_metric(const Level &L, const SurfaceArgs &g, const double *gx, const double *gw, hipStream_t s);
 template <typename T>
 void launch_sumfact_apply(const Level &L, const T *x, T *y, const T *ca, const T *cb, int ldb, int ntiles,
                           const int *active, hipStream_t s);

@@ -58,7 +58,7 @@ static gf_status guarded(F &&f) {
 static inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // ------------------------------------------------------------------ level construction
-static void build_level_host(Level &L, int p, int lev) {
+static void build_level_host(Level &L, int p, int lev, const gf_geometry *geom) {
   L.p = p;
   L.lev = lev;
   L.nel = 1 << lev;
@@ -66,11 +66,13 @@ static void build_level_host(Level &L, int p, int lev) {
   L.W = L.n1 + 2 * p;
   L.q = p + 1;
   L.S = 2 * p + 1;
-  L.R = (int64_t)6 * L.W * L.W;
-  glue_patches(p, lev, L.l2g, L.N);
+  L.npatch = geom->npatch;
+  L.R = (int64_t)L.npatch * L.W * L.W;
+  if (geom->kind == SURF_NURBS) glue_patches_nurbs(geom->nurbs, p, lev, L.l2g, L.N);
+  else glue_patches(p, lev, L.l2g, L.N);
 }
 
-static void build_level_device(gf_space *sp, Level &L, int perturbed) {
+static void build_level_device(gf_space *sp, Level &L, const SurfaceArgs &surf) {
   hipStream_t s = sp->ctx->stream;
   const int p = L.p, n1 = L.n1, W = L.W, nel = L.nel, q = L.q;
   // Gauss rule and per-element basis tables [nel][2][q][p+1]
@@ -90,8 +92,8 @@ static void build_level_device(gf_space *sp, Level &L, int perturbed) {
   DBuf<double> dgx, dgw;
   dgx.upload(gx, s);
   dgw.upload(gw, s);
-  L.metric.alloc((size_t)6 * nel * nel * q * q * 4);
-  launch_metric(L, perturbed, dgx.p, dgw.p, s);
+  L.metric.alloc((size_t)L.npatch * nel * nel * q * q * 4);
+  launch_metric(L, surf, dgx.p, dgw.p, s);
   L.metric32.alloc(L.metric.n);
   launch_to_f32(L.metric.p, L.metric32.p, (int64_t)L.metric.n, s);
   L.basis32.alloc(L.basis.n);
@@ -101,7 +103,7 @@ static void build_level_device(gf_space *sp, Level &L, int perturbed) {
   std::vector<int> row_gid((size_t)L.R, -1), owner_row(L.N, -1);
   std::vector<uint8_t> owner((size_t)L.R, 0);
   std::vector<std::vector<int>> copies(L.N);
-  for (int m = 0; m < 6; ++m)
+  for (int m = 0; m < L.npatch; ++m)
     for (int iy = 0; iy < n1; ++iy)
       for (int ix = 0; ix < n1; ++ix) {
         const int g = L.l2g[((size_t)m * n1 + iy) * n1 + ix];
@@ -227,7 +229,7 @@ static void build_coarse_dense(gf_space *sp) {
   HIPCHK(hipStreamSynchronize(s));
   const int N0 = C.N, p = C.p, W = C.W, n1 = C.n1, S = C.S;
   std::vector<double> M0((size_t)N0 * N0, 0.0), S0((size_t)N0 * N0, 0.0);
-  for (int m = 0; m < 6; ++m)
+  for (int m = 0; m < C.npatch; ++m)
     for (int iy = 0; iy < n1; ++iy)
       for (int ix = 0; ix < n1; ++ix) {
         const int64_t r = (int64_t)m * W * W + (int64_t)(iy + p) * W + (ix + p);
@@ -696,7 +698,7 @@ static void cheb_coeffs(int deg, double ia, std::vector<double> &c1, std::vector
 // level's smoothing, and fewer coarse steps save time.
 static int level_degree(const gf_space *sp, int cheb, int li) {
   const Level &L = *sp->lev[li];
-  if (li + 1 < sp->nlev()) return std::min(cheb, (6.0 * L.n1 * L.n1 > kChebTwoRows) ? 2 : 1);
+  if (li + 1 < sp->nlev()) return std::min(cheb, ((double)L.npatch * L.n1 * L.n1 > kChebTwoRows) ? 2 : 1);
   return cheb;
 }
 
@@ -973,11 +975,11 @@ struct BatchSolve {
       // algorithmic bytes: read x and write y for every active column of every patch row, plus the
       // two FP64 stencils of every row
       const Level &F = sp->fine();
-      const double rows = 6.0 * F.n1 * F.n1;
+      const double rows = (double)F.npatch * F.n1 * F.n1;
       res.apply_bytes += 2.0 * 8.0 * active_tiles * CT * rows + 2.0 * F.S * F.S * 8.0 * rows;
     }
     const Level &F = sp->fine();
-    const double rows = 6.0 * F.n1 * F.n1;
+    const double rows = (double)F.npatch * F.n1 * F.n1;
     for (auto &e : slog.entries) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, e.e0, e.e1));
@@ -1188,6 +1190,68 @@ gf_status gf_geometry_sphere(gf_context *ctx, int32_t perturbed, gf_geometry **o
   });
 }
 
+gf_status gf_geometry_nurbs(gf_context *ctx, int32_t npatch, int32_t deg_u, int32_t deg_v, const int32_t *ncoef,
+                            const double *knots, const double *ctrl, gf_geometry **out) {
+  return guarded([&] {
+    if (!ncoef || !knots || !ctrl || !out) fail(GF_EINVAL, "null argument");
+    *out = nullptr;
+    if (npatch < 1 || npatch > 4096) fail(GF_EINVAL, "npatch must be in 1..4096");
+    if (deg_u < 1 || deg_u > 4 || deg_v < 1 || deg_v > 4) fail(GF_EINVAL, "geometry degrees must be in 1..4");
+    std::unique_ptr<gf_geometry> g(new gf_geometry());
+    g->ctx = ctx;
+    g->kind = SURF_NURBS;
+    g->npatch = npatch;
+    NurbsHost &h = g->nurbs;
+    h.npatch = npatch;
+    h.du = deg_u;
+    h.dv = deg_v;
+    int64_t koff = 0, coff = 0;
+    // open knot vector on [0, 1]: deg+1 zeros, non-decreasing interior knots of multiplicity <= deg,
+    // deg+1 ones
+    auto check_knots = [&](const double *U, int n, int d) {
+      for (int i = 0; i < n + d + 1; ++i)
+        if (!std::isfinite(U[i])) fail(GF_EINVAL, "knot not finite");
+      for (int i = 0; i <= d; ++i)
+        if (U[i] != 0.0 || U[n + i] != 1.0) fail(GF_EINVAL, "knot vectors must be open on [0, 1]");
+      for (int i = 0; i < n + d; ++i)
+        if (U[i + 1] < U[i]) fail(GF_EINVAL, "knots must be non-decreasing");
+      if (n > d + 1 && (U[d + 1] <= 0.0 || U[n - 1] >= 1.0)) fail(GF_EINVAL, "interior knots must lie in (0, 1)");
+      for (int i = d + 1; i < n; ++i) {
+        int mult = 1;
+        while (i + mult < n && U[i + mult] == U[i]) ++mult;
+        if (mult > d) fail(GF_EINVAL, "interior knot multiplicity exceeds the degree");
+      }
+    };
+    for (int m = 0; m < npatch; ++m) {
+      const int ns = ncoef[2 * m], nt = ncoef[2 * m + 1];
+      if (ns < deg_u + 1 || nt < deg_v + 1 || ns > 4096 || nt > 4096)
+        fail(GF_EINVAL, "control points per direction must be in degree+1..4096");
+      const int64_t ku = koff, kv = koff + ns + deg_u + 1;
+      check_knots(knots + ku, ns, deg_u);
+      check_knots(knots + kv, nt, deg_v);
+      for (int64_t i = 0; i < (int64_t)ns * nt; ++i) {
+        const double *c = ctrl + 4 * (coff + i);
+        for (int k = 0; k < 4; ++k)
+          if (!std::isfinite(c[k])) fail(GF_EINVAL, "control point not finite");
+        if (!(c[3] > 0.0)) fail(GF_EINVAL, "weights must be positive");
+      }
+      h.pinfo.insert(h.pinfo.end(), {ns, nt, (int)ku, (int)kv, (int)coff});
+      koff = kv + nt + deg_v + 1;
+      coff += (int64_t)ns * nt;
+      if (koff > (int64_t)1 << 30 || coff > (int64_t)1 << 28) fail(GF_EINVAL, "geometry too large");
+    }
+    h.knots.assign(knots, knots + koff);
+    h.ctrl.assign(ctrl, ctrl + 4 * coff);
+    // the interfaces must be consistent before anything is built on them
+    std::vector<int> l2g;
+    int N = 0;
+    glue_patches_nurbs(h, 1, 0, l2g, N);
+    *out = g.release();
+  });
+}
+
+int32_t gf_geometry_npatch(const gf_geometry *g) { return g ? g->npatch : -1; }
+
 void gf_geometry_destroy(gf_geometry *g) {
   if (!g) return;
   if (--g->refs == 0) delete g;
@@ -1196,6 +1260,7 @@ void gf_geometry_destroy(gf_geometry *g) {
 gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, int32_t *patch, double *st) {
   return guarded([&] {
     if (!geom || (npts > 0 && (!xyz || !patch || !st)) || npts < 0) fail(GF_EINVAL, "bad arguments");
+    if (geom->kind != SURF_SPHERE) fail(GF_EUNSUPPORTED, "gf_locate is implemented for the sphere family only");
     for (int i = 0; i < npts; ++i) {
       const double X[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
       int ax = 0;
@@ -1234,10 +1299,27 @@ gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degr
     sp->j = level;
     sp->q = degree + 1;
     sp->lc = lc;
+    // the surface for the metric kernel; NURBS control nets on the device while the levels are built
+    SurfaceArgs surf;
+    surf.kind = geom->kind;
+    surf.perturbed = geom->perturbed;
+    surf.npatch = geom->npatch;
+    DBuf<int> d_pinfo;
+    DBuf<double> d_knots, d_ctrl;
+    if (geom->kind == SURF_NURBS) {
+      d_pinfo.upload(geom->nurbs.pinfo, ctx->stream);
+      d_knots.upload(geom->nurbs.knots, ctx->stream);
+      d_ctrl.upload(geom->nurbs.ctrl, ctx->stream);
+      surf.du = geom->nurbs.du;
+      surf.dv = geom->nurbs.dv;
+      surf.pinfo = d_pinfo.p;
+      surf.knots = d_knots.p;
+      surf.ctrl = d_ctrl.p;
+    }
     for (int l = lc; l <= level; ++l) {
       std::unique_ptr<Level> L(new Level());
-      build_level_host(*L, degree, l);
-      build_level_device(sp.get(), *L, geom->perturbed);
+      build_level_host(*L, degree, l, geom);
+      build_level_device(sp.get(), *L, surf);
       sp->lev.push_back(std::move(L));
     }
     for (int i = 1; i < sp->nlev(); ++i) build_transfer(sp.get(), *sp->lev[i], *sp->lev[i - 1]);
@@ -1258,7 +1340,7 @@ int64_t gf_space_ndofs(const gf_space *sp) { return sp ? (int64_t)sp->lev.back()
 
 int64_t gf_space_noise_length(const gf_space *sp) {
   if (!sp) return -1;
-  return (int64_t)6 * (int64_t)(1 << sp->j) * (int64_t)(1 << sp->j) * (sp->p + 1) * (sp->p + 1);
+  return (int64_t)sp->fine().npatch * (int64_t)(1 << sp->j) * (int64_t)(1 << sp->j) * (sp->p + 1) * (sp->p + 1);
 }
 
 gf_status gf_space_dofmap(const gf_space *sp, int32_t *l2g) {
@@ -1484,7 +1566,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     smooth_ms += b.res.smooth_ms;
     smooth_launches += b.res.smooth_launches;
     smooth_bytes += b.res.smooth_bytes;
-    if (b.res.apply_launches) apply_rows = 6 * b.sp->fine().n1 * b.sp->fine().n1;
+    if (b.res.apply_launches) apply_rows = b.sp->fine().npatch * b.sp->fine().n1 * b.sp->fine().n1;
   };
   const bool use_graph = !(base.flags & (GF_FLAG_NO_GRAPH | GF_FLAG_TIME_APPLY));
   // ---- integer chains: A w_1 = b, A w_i = M w_{i-1}
@@ -1784,7 +1866,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
     stats->solve_ms = ms;
     stats->apply_ms = tot.apply_ms;
     stats->apply_launches = tot.apply_launches;
-    stats->apply_rows = 6 * F.n1 * F.n1;
+    stats->apply_rows = F.npatch * F.n1 * F.n1;
     stats->apply_col_sum = tot.apply_col_sum;
     stats->apply_bytes = tot.apply_bytes;
     stats->smooth_ms = tot.smooth_ms;
@@ -1809,7 +1891,7 @@ static void check_points(const gf_space *sp, int npts, const int32_t *patch, con
     std::memcpy(sh.data(), st, 2 * (size_t)npts * sizeof(double));
   }
   for (int i = 0; i < npts; ++i) {
-    if (ph[i] < 0 || ph[i] > 5) fail(GF_EINVAL, "patch index out of 0..5");
+    if (ph[i] < 0 || ph[i] >= sp->fine().npatch) fail(GF_EINVAL, "patch index out of range");
     for (int c = 0; c < 2; ++c)
       if (!(sh[2 * i + c] >= 0.0 && sh[2 * i + c] <= 1.0)) fail(GF_EINVAL, "parameter (s, t) outside [0, 1]");
   }
@@ -1856,7 +1938,7 @@ static void ensure_identity(gf_space *sp) {
   std::vector<int> copies(F.N, 0);
   for (int v : F.l2g) copies[v] += 1;
   std::vector<double> st((size_t)F.R * SS, 0.0), di((size_t)F.R, 0.0);
-  for (int m = 0; m < 6; ++m)
+  for (int m = 0; m < F.npatch; ++m)
     for (int iy = 0; iy < n1; ++iy)
       for (int ix = 0; ix < n1; ++ix) {
         const int64_t row = (int64_t)m * W * W + (int64_t)(iy + p) * W + (ix + p);
@@ -1912,7 +1994,7 @@ static void mass_bounds(gf_space *sp, const gf_solve_opts *o, double *lo, double
   DBuf<double> ones, row, g;
   {
     std::vector<double> h((size_t)F.R * CT, 0.0);
-    for (int m = 0; m < 6; ++m)
+    for (int m = 0; m < F.npatch; ++m)
       for (int iy = 0; iy < F.n1; ++iy)
         for (int ix = 0; ix < F.n1; ++ix)
           h[((size_t)m * F.W * F.W + (size_t)(iy + F.p) * F.W + (ix + F.p)) * CT] = 1.0;
@@ -2042,7 +2124,7 @@ gf_status gf_sqrt_mass(gf_space *sp, int32_t nsamp, const double *y, double *f, 
       stats->solve_ms = ms;
       stats->apply_ms = b.res.apply_ms;
       stats->apply_launches = b.res.apply_launches;
-      stats->apply_rows = 6 * F.n1 * F.n1;
+      stats->apply_rows = F.npatch * F.n1 * F.n1;
       stats->apply_bytes = b.res.apply_bytes;
     }
     if (b.res.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
@@ -2180,7 +2262,7 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
       stats->solve_ms = ms;
       stats->apply_ms = r.apply_ms;
       stats->apply_launches = r.apply_launches;
-      stats->apply_rows = 6 * F.n1 * F.n1;
+      stats->apply_rows = F.npatch * F.n1 * F.n1;
       stats->apply_col_sum = r.apply_col_sum;
       stats->apply_bytes = r.apply_bytes;
       stats->smooth_ms = r.smooth_ms;

@@ -8,6 +8,7 @@
 // pulled-back forms; the rule is Gauss-Legendre with p+1 points per direction).
 #include "gf_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <stdexcept>
@@ -189,6 +190,113 @@ void glue_patches(int p, int lev, std::vector<int> &l2g, int &N) {
         }
         l2g[((size_t)m * n1 + iy) * n1 + ix] = g;
       }
+  }
+}
+
+// Interfaces of NURBS patches (Sec. 2.2: neighbouring patch maps agree on the shared edge up to the
+// orientation of the reference square).  Edge e of patch m: 0 is t = 0, 1 is t = 1, 2 is s = 0,
+// 3 is s = 1.  Two edges are the same curve with the same parametrisation (or its reverse) when
+// their rows of control points and weights agree point by point (relative tolerance 1e-12 of the
+// surface's extent) and their knot vectors agree (or are mirrored); such edges are glued, and the
+// coefficients along them identified in the same or the reverse order.  Corners join through the
+// edges (union-find), so any number of patches may meet at a point.  Numbering as glue_patches:
+// patches in order, then iy, then ix, the next id to every new class.
+namespace {
+struct EdgeData {
+  std::vector<double> pts;  // [k][4]
+  std::vector<double> knots;
+};
+
+EdgeData nurbs_edge(const NurbsHost &g, int m, int e) {
+  const int *pi = &g.pinfo[5 * (size_t)m];
+  const int ns = pi[0], nt = pi[1];
+  const double *U = &g.knots[pi[2]], *V = &g.knots[pi[3]], *C = &g.ctrl[4 * (size_t)pi[4]];
+  EdgeData d;
+  const bool along_s = (e < 2);
+  const int n = along_s ? ns : nt;
+  for (int k = 0; k < n; ++k) {
+    const int a = along_s ? k : (e == 2 ? 0 : ns - 1);
+    const int b = along_s ? (e == 0 ? 0 : nt - 1) : k;
+    const double *c = C + 4 * ((size_t)b * ns + a);
+    d.pts.insert(d.pts.end(), c, c + 4);
+  }
+  if (along_s) d.knots.assign(U, U + ns + g.du + 1);
+  else d.knots.assign(V, V + nt + g.dv + 1);
+  return d;
+}
+
+// 0: different curves, 1: same orientation, 2: reversed
+int edges_match(const EdgeData &x, const EdgeData &y, double tol) {
+  if (x.pts.size() != y.pts.size() || x.knots.size() != y.knots.size()) return 0;
+  const size_t n = x.pts.size() / 4, nk = x.knots.size();
+  for (int rev = 0; rev < 2; ++rev) {
+    bool ok = true;
+    for (size_t k = 0; k < n && ok; ++k) {
+      const double *a = &x.pts[4 * k], *b = &y.pts[4 * (rev ? n - 1 - k : k)];
+      for (int c = 0; c < 3; ++c) ok = ok && std::fabs(a[c] - b[c]) <= tol;
+      ok = ok && std::fabs(a[3] - b[3]) <= 1e-12 * std::max(std::fabs(a[3]), std::fabs(b[3]));
+    }
+    for (size_t k = 0; k < nk && ok; ++k) {
+      const double u = x.knots[k], v = rev ? 1.0 - y.knots[nk - 1 - k] : y.knots[k];
+      ok = std::fabs(u - v) <= 1e-14;
+    }
+    if (ok) return rev ? 2 : 1;
+  }
+  return 0;
+}
+
+int uf_find(std::vector<int> &par, int i) {
+  while (par[i] != i) {
+    par[i] = par[par[i]];
+    i = par[i];
+  }
+  return i;
+}
+}  // namespace
+
+void glue_patches_nurbs(const NurbsHost &g, int p, int lev, std::vector<int> &l2g, int &N) {
+  const int np = g.npatch, n1 = (1 << lev) + p;
+  double ext = 0.0;
+  for (size_t i = 0; i < g.ctrl.size(); i += 4)
+    for (int c = 0; c < 3; ++c) ext = std::max(ext, std::fabs(g.ctrl[i + c]));
+  const double tol = 1e-12 * std::max(ext, 1e-300);
+  std::vector<EdgeData> edges;
+  for (int m = 0; m < np; ++m)
+    for (int e = 0; e < 4; ++e) {
+      edges.push_back(nurbs_edge(g, m, e));
+      // an edge collapsed to a point (a pole) has a singular metric: not supported
+      const auto &pts = edges.back().pts;
+      bool point = true;
+      for (size_t k = 4; k < pts.size() && point; k += 4)
+        for (int c = 0; c < 3; ++c) point = point && std::fabs(pts[k + c] - pts[c]) <= tol;
+      if (point) fail(GF_EUNSUPPORTED, "a patch edge collapses to a point (degenerate patch)");
+    }
+  auto coef = [&](int m, int e, int i) -> int {
+    const int iy = e == 0 ? 0 : e == 1 ? n1 - 1 : i;
+    const int ix = e == 2 ? 0 : e == 3 ? n1 - 1 : i;
+    return (m * n1 + iy) * n1 + ix;
+  };
+  std::vector<int> par((size_t)np * n1 * n1);
+  for (size_t i = 0; i < par.size(); ++i) par[i] = (int)i;
+  std::vector<int> partners(edges.size(), 0);
+  for (size_t a = 0; a < edges.size(); ++a)
+    for (size_t b = a + 1; b < edges.size(); ++b) {
+      const int how = edges_match(edges[a], edges[b], tol);
+      if (!how) continue;
+      if (++partners[a] > 1 || ++partners[b] > 1) fail(GF_EINVAL, "a patch edge is shared by more than two patches");
+      const int ma = (int)a / 4, ea = (int)a % 4, mb = (int)b / 4, eb = (int)b % 4;
+      for (int i = 0; i < n1; ++i) {
+        const int x = uf_find(par, coef(ma, ea, i)), y = uf_find(par, coef(mb, eb, how == 2 ? n1 - 1 - i : i));
+        if (x != y) par[std::max(x, y)] = std::min(x, y);
+      }
+    }
+  l2g.assign(par.size(), -1);
+  std::vector<int> id(par.size(), -1);
+  N = 0;
+  for (size_t i = 0; i < par.size(); ++i) {
+    const int r = uf_find(par, (int)i);
+    if (id[r] < 0) id[r] = N++;
+    l2g[i] = id[r];
   }
 }
 

@@ -305,7 +305,7 @@ ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int
   g.nseg = (L.n1 + TXmax - 1) / TXmax;
   g.TX = (L.n1 + g.nseg - 1) / g.nseg;
   g.nyb = (L.n1 + g.TY - 1) / g.TY;
-  g.nstrip = 6 * g.nseg * g.nyb;
+  g.nstrip = L.npatch * g.nseg * g.nyb;
   g.nsb = (g.nstrip + 3) / 4;
   g.q = xcd_q(g.nsb * ntiles);
   return g;

@@ -45,10 +45,94 @@ __device__ void surface_derivs(int m, double s, double t, int perturbed, double 
   }
 }
 
+// ---- rational tensor-product B-spline patches (Sec. 2.2: the patch maps of a NURBS surface)
+constexpr int kMaxGeomDeg = 4;
+
+// knot span i with U[i] <= u < U[i+1] among the n basis functions of degree d (open knot vector
+// U[0 .. n+d]); u = U[n] falls into the last non-empty span
+__device__ int nurbs_span(const double *U, int n, int d, double u) {
+  if (u >= U[n]) {
+    int i = n - 1;
+    while (i > d && U[i] >= U[i + 1]) --i;
+    return i;
+  }
+  int lo = d, hi = n;  // U[lo] <= u < U[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (u < U[mid]) hi = mid;
+    else lo = mid;
+  }
+  return lo;
+}
+
+// values N[j] and first derivatives dN[j] of the d+1 basis functions span-d+j (j = 0..d) at u, by
+// the Cox-de Boor recursion over the degrees 0..d (terms with a vanishing denominator dropped)
+__device__ void nurbs_basis(const double *U, int span, int d, double u, double *N, double *dN) {
+  double tri[kMaxGeomDeg + 1][kMaxGeomDeg + 1];
+  tri[0][0] = 1.0;
+  for (int k = 1; k <= d; ++k)
+    for (int j = 0; j <= k; ++j) {
+      const int i = span - k + j;
+      double v = 0.0;
+      if (j > 0) {
+        const double den = U[i + k] - U[i];
+        if (den > 0.0) v += (u - U[i]) / den * tri[k - 1][j - 1];
+      }
+      if (j < k) {
+        const double den = U[i + k + 1] - U[i + 1];
+        if (den > 0.0) v += (U[i + k + 1] - u) / den * tri[k - 1][j];
+      }
+      tri[k][j] = v;
+    }
+  for (int j = 0; j <= d; ++j) {
+    N[j] = tri[d][j];
+    const int i = span - d + j;
+    double v = 0.0;
+    if (d > 0) {
+      if (j > 0) {
+        const double den = U[i + d] - U[i];
+        if (den > 0.0) v += d * tri[d - 1][j - 1] / den;
+      }
+      if (j < d) {
+        const double den = U[i + d + 1] - U[i + 1];
+        if (den > 0.0) v -= d * tri[d - 1][j] / den;
+      }
+    }
+    dN[j] = v;
+  }
+}
+
+// F = P / w with P = sum N_a(s) N_b(t) w_ab X_ab, w = sum N_a N_b w_ab; dF = (dP - F dw) / w
+__device__ void nurbs_derivs(const SurfaceArgs &g, int m, double s, double t, double Fs[3], double Ft[3]) {
+  const int *pi = g.pinfo + 5 * m;
+  const int ns = pi[0], nt = pi[1];
+  const double *U = g.knots + pi[2], *V = g.knots + pi[3], *C = g.ctrl + 4 * (int64_t)pi[4];
+  const int su = nurbs_span(U, ns, g.du, s), sv = nurbs_span(V, nt, g.dv, t);
+  double Nu[kMaxGeomDeg + 1], dNu[kMaxGeomDeg + 1], Nv[kMaxGeomDeg + 1], dNv[kMaxGeomDeg + 1];
+  nurbs_basis(U, su, g.du, s, Nu, dNu);
+  nurbs_basis(V, sv, g.dv, t, Nv, dNv);
+  double P[4] = {0, 0, 0, 0}, Ps[4] = {0, 0, 0, 0}, Pt[4] = {0, 0, 0, 0};  // homogeneous (x w, y w, z w, w)
+  for (int b = 0; b <= g.dv; ++b)
+    for (int a = 0; a <= g.du; ++a) {
+      const double *c = C + 4 * ((int64_t)(sv - g.dv + b) * ns + (su - g.du + a));
+      const double h[4] = {c[0] * c[3], c[1] * c[3], c[2] * c[3], c[3]};
+      for (int k = 0; k < 4; ++k) {
+        P[k] += Nu[a] * Nv[b] * h[k];
+        Ps[k] += dNu[a] * Nv[b] * h[k];
+        Pt[k] += Nu[a] * dNv[b] * h[k];
+      }
+    }
+  for (int k = 0; k < 3; ++k) {
+    const double F = P[k] / P[3];
+    Fs[k] = (Ps[k] - F * Ps[3]) / P[3];
+    Ft[k] = (Pt[k] - F * Pt[3]) / P[3];
+  }
+}
+
 // m = w a, G = w a K^-1 at every Gauss point (Sec. 3.2: K first fundamental form,
 // a = sqrt(det K)); w is the tensor Gauss weight of the element (area 1/nel^2).
-__global__ void k_metric(double *metric, int nel, int q, int perturbed, const double *gx, const double *gw) {
-  const int64_t total = (int64_t)6 * nel * nel * q * q;
+__global__ void k_metric(double *metric, int nel, int q, SurfaceArgs g, const double *gx, const double *gw) {
+  const int64_t total = (int64_t)g.npatch * nel * nel * q * q;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= total) return;
   int64_t t = id;
@@ -59,7 +143,8 @@ __global__ void k_metric(double *metric, int nel, int q, int perturbed, const do
   const int m = (int)t;
   const double s = (ex + gx[qx]) / nel, tt = (ey + gx[qy]) / nel;
   double Fs[3], Ft[3];
-  surface_derivs(m, s, tt, perturbed, Fs, Ft);
+  if (g.kind == SURF_NURBS) nurbs_derivs(g, m, s, tt, Fs, Ft);
+  else surface_derivs(m, s, tt, g.perturbed, Fs, Ft);
   const double k11 = Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2];
   const double k12 = Fs[0] * Ft[0] + Fs[1] * Ft[1] + Fs[2] * Ft[2];
   const double k22 = Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2];
@@ -73,10 +158,10 @@ __global__ void k_metric(double *metric, int nel, int q, int perturbed, const do
   o[3] = w * a * k11 / det;
 }
 
-void launch_metric(const Level &L, int perturbed, const double *gx, const double *gw, hipStream_t s) {
-  const int64_t total = (int64_t)6 * L.nel * L.nel * L.q * L.q;
-  hipLaunchKernelGGL(k_metric, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, L.metric.p, L.nel, L.q,
-                     perturbed, gx, gw);
+void launch_metric(const Level &L, const SurfaceArgs &g, const double *gx, const double *gw, hipStream_t s) {
+  const int64_t total = (int64_t)g.npatch * L.nel * L.nel * L.q * L.q;
+  hipLaunchKernelGGL(k_metric, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, L.metric.p, L.nel, L.q, g,
+                     gx, gw);
   HIPCHK(hipGetLastError());
 }
 
@@ -211,7 +296,7 @@ void launch_sumfact_apply(const Level &L, const T *x, T *y, const T *ca, const T
                           const int *active, hipStream_t s) {
   constexpr int TT = 8;
   const int ntx = (L.n1 + TT - 1) / TT;
-  dim3 grid(6 * ntx * ntx, ntiles), block(CT);
+  dim3 grid(L.npatch * ntx * ntx, ntiles), block(CT);
   const T *mt = metric_of<T>(L), *bs = basis_of<T>(L);
   switch (L.p) {
 #define GF_SF(PP)                                                                                              \
@@ -234,9 +319,9 @@ template void launch_sumfact_apply<float>(const Level &, const float *, float *,
 // Column c < S*S probes colour c = (iy mod S)*S + (ix mod S) for M, column S*S + c the same
 // colour for S.  Within the (2p+1)^2 window of any coefficient each colour occurs exactly
 // once, so (A x_c)[row] is the single stencil entry of that colour.
-__global__ void k_probe(double *x, int ldb, int n1, int W, int P, int Sw) {
+__global__ void k_probe(double *x, int ldb, int n1, int W, int P, int Sw, int64_t R) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
-  if (r >= (int64_t)6 * W * W) return;
+  if (r >= R) return;
   const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P;
   const bool inside = lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
   const int colour = inside ? (ly % Sw) * Sw + (lx % Sw) : -1;
@@ -249,13 +334,14 @@ __global__ void k_probe(double *x, int ldb, int n1, int W, int P, int Sw) {
 void launch_probe_vectors(const Level &L, double *x, int ldb, hipStream_t s) {
   dim3 block(64, 4);
   dim3 grid((unsigned)((L.R + block.y - 1) / block.y));
-  hipLaunchKernelGGL(k_probe, grid, block, 0, s, x, ldb, L.n1, L.W, L.p, L.S);
+  hipLaunchKernelGGL(k_probe, grid, block, 0, s, x, ldb, L.n1, L.W, L.p, L.S, L.R);
   HIPCHK(hipGetLastError());
 }
 
-__global__ void k_extract(const double *y, int ldb, double *stM, double *stS, int n1, int W, int P, int Sw) {
+__global__ void k_extract(const double *y, int ldb, double *stM, double *stS, int n1, int W, int P, int Sw,
+                          int64_t R) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= (int64_t)6 * W * W) return;
+  if (r >= R) return;
   const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P;
   const bool inside = lx >= 0 && lx < n1 && ly >= 0 && ly < n1;
   for (int dy = -P; dy <= P; ++dy)
@@ -275,7 +361,7 @@ __global__ void k_extract(const double *y, int ldb, double *stM, double *stS, in
 
 void launch_extract_stencil(const Level &L, const double *y, int ldb, double *stM, double *stS, hipStream_t s) {
   hipLaunchKernelGGL(k_extract, dim3((unsigned)((L.R + 255) / 256)), dim3(256), 0, s, y, ldb, stM, stS, L.n1, L.W,
-                     L.p, L.S);
+                     L.p, L.S, L.R);
   HIPCHK(hipGetLastError());
 }
 
@@ -327,9 +413,9 @@ void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s) {
 // Cholesky factor, and y_e = L_e z_e for every sample.
 template <int P>
 __global__ void k_noise_elements(const double *metric, const double *basis, const double *z, double *ye, int nel,
-                                 int nsamp) {
+                                 int nsamp, int np) {
   constexpr int Q = P + 1, NB = P + 1, NL = NB * NB;
-  const int64_t ne_tot = (int64_t)6 * nel * nel;
+  const int64_t ne_tot = (int64_t)np * nel * nel;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne_tot) return;
   const int ex = (int)(e % nel), ey = (int)((e / nel) % nel);
@@ -374,7 +460,7 @@ __global__ void k_noise_elements(const double *metric, const double *basis, cons
 // Pass 2, one thread per (coefficient row, sample): gather the element contributions of all
 // elements containing the coefficient (patch-local, before the interface sum).
 __global__ void k_noise_gather(const double *ye, double *bl, int nel, int n1, int W, int P, int nsamp, int64_t R,
-                               int ldb) {
+                               int ldb, int np) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= R * nsamp) return;
   const int64_t r = id / nsamp;
@@ -382,7 +468,7 @@ __global__ void k_noise_gather(const double *ye, double *bl, int nel, int n1, in
   const int lx = (int)(r % W) - P, ly = (int)((r / W) % W) - P, m = (int)(r / ((int64_t)W * W));
   if (lx < 0 || lx >= n1 || ly < 0 || ly >= n1) return;
   const int NB = P + 1, NL = NB * NB;
-  const int64_t ne_tot = (int64_t)6 * nel * nel;
+  const int64_t ne_tot = (int64_t)np * nel * nel;
   double v = 0.0;
   for (int b = 0; b < NB; ++b) {
     const int ey = ly - b;
@@ -398,20 +484,20 @@ __global__ void k_noise_gather(const double *ye, double *bl, int nel, int n1, in
 }
 
 void launch_white_noise(const Level &L, const double *z, int nsamp, double *ye, double *bl, int ldb, hipStream_t s) {
-  const int64_t ne_tot = (int64_t)6 * L.nel * L.nel;
+  const int64_t ne_tot = (int64_t)L.npatch * L.nel * L.nel;
   dim3 g1((unsigned)((ne_tot + 63) / 64)), b1(64);
   switch (L.p) {
-    case 1: hipLaunchKernelGGL(k_noise_elements<1>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
-    case 2: hipLaunchKernelGGL(k_noise_elements<2>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
-    case 3: hipLaunchKernelGGL(k_noise_elements<3>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
-    case 4: hipLaunchKernelGGL(k_noise_elements<4>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
-    case 5: hipLaunchKernelGGL(k_noise_elements<5>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp); break;
+    case 1: hipLaunchKernelGGL(k_noise_elements<1>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
+    case 2: hipLaunchKernelGGL(k_noise_elements<2>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
+    case 3: hipLaunchKernelGGL(k_noise_elements<3>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
+    case 4: hipLaunchKernelGGL(k_noise_elements<4>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
+    case 5: hipLaunchKernelGGL(k_noise_elements<5>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
     default: fail(GF_EUNSUPPORTED, "degree out of range");
   }
   HIPCHK(hipGetLastError());
   const int64_t tot = L.R * nsamp;
   hipLaunchKernelGGL(k_noise_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ye, bl, L.nel, L.n1, L.W,
-                     L.p, nsamp, L.R, ldb);
+                     L.p, nsamp, L.R, ldb, L.npatch);
   HIPCHK(hipGetLastError());
 }
 

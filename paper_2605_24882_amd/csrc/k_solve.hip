@@ -264,12 +264,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(T *rc, const T *r, const T *Az, const uint8_t *__restrict__ ownf,
                                                   int Wf, int Wc, int n1c, int P, int ldb,
                                                   const int *__restrict__ rs, const T *__restrict__ rcoef, int rw,
-                                                  const int *__restrict__ active, int ntiles) {
+                                                  const int *__restrict__ active, int ntiles, int np) {
   const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
   const int col = ct * CT + threadIdx.x;
   const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
-  if (id >= 6 * n1c * n1c) return;
+  if (id >= np * n1c * n1c) return;
   const int ixc = id % n1c, iyc = (id / n1c) % n1c, m = id / (n1c * n1c);
   const int64_t fbase = (int64_t)m * Wf * Wf;
   const int fy0 = rs[iyc], fx0 = rs[ixc];
@@ -293,12 +293,12 @@ __global__ __launch_bounds__(256) void k_restrict(T *rc, const T *r, const T *Az
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(T *zf, const T *zc, int Wf, int Wc, int n1f, int P, int ldb,
                                                  const int *__restrict__ ps, const T *__restrict__ pcoef, int pw,
-                                                 const int *__restrict__ active, int ntiles) {
+                                                 const int *__restrict__ active, int ntiles, int np) {
   const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
   const int col = ct * CT + threadIdx.x;
   const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
-  if (id >= 6 * n1f * n1f) return;
+  if (id >= np * n1f * n1f) return;
   const int ixf = id % n1f, iyf = (id / n1f) % n1f, m = id / (n1f * n1f);
   const int64_t cbase = (int64_t)m * Wc * Wc;
   const int cy0 = ps[iyf], cx0 = ps[ixf];
@@ -327,13 +327,13 @@ template <typename T, int P>
 __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restrict__ r, const uint8_t *__restrict__ ownf,
                                                        int Wf, int Wc, int n1f, int n1c, int ldb,
                                                        const int *__restrict__ rs, const T *__restrict__ rcoef, int rw,
-                                                       const int *__restrict__ active, int ntiles) {
+                                                       const int *__restrict__ active, int ntiles, int np) {
   constexpr int RW = P + 2;
   const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
   const int lane = threadIdx.x;
   const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
-  if (id >= 6 * n1c) return;
+  if (id >= np * n1c) return;
   const int iyc = id % n1c, m = id / n1c;
   const int64_t ct0 = (int64_t)ct * CT;
   const int64_t fbase = (int64_t)m * Wf * Wf;
@@ -381,13 +381,13 @@ template <typename T, int P>
 __global__ __launch_bounds__(256) void k_prolong_rows(T *zf, const T *__restrict__ zc, int Wf, int Wc, int n1f, int n1c,
                                                       int ldb, const int *__restrict__ ps,
                                                       const T *__restrict__ pcoef, int pw,
-                                                      const int *__restrict__ active, int ntiles) {
+                                                      const int *__restrict__ active, int ntiles, int np) {
   constexpr int PW = (P + 3) / 2;
   const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
   const int lane = threadIdx.x;
   const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
-  if (id >= 6 * n1f) return;
+  if (id >= np * n1f) return;
   const int iyf = id % n1f, m = id / n1f;
   const int64_t ct0 = (int64_t)ct * CT;
   const int64_t cbase = (int64_t)m * Wc * Wc;
@@ -443,9 +443,9 @@ const float *pro_coef<float>(const Level &F) { return F.pro_c32.p; }
 template <typename T, int P>
 static void launch_restrict_rows(const Level &F, const Level &C, T *rc, const T *r, int ldb, int ntiles,
                                  const int *active, hipStream_t s) {
-  const int n = 6 * C.n1;
+  const int n = F.npatch * C.n1;
   hipLaunchKernelGGL((k_restrict_rows<T, P>), dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, rc, r, F.owner.p, F.W,
-                     C.W, F.n1, C.n1, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles);
+                     C.W, F.n1, C.n1, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles, F.npatch);
 }
 
 template <typename T>
@@ -460,9 +460,9 @@ void restrict_residual(const Level &F, const Level &C, T *rc, const T *r, const 
       default: launch_restrict_rows<T, 5>(F, C, rc, r, ldb, ntiles, active, s); break;
     }
   } else {
-    const int n = 6 * C.n1 * C.n1;
+    const int n = F.npatch * C.n1 * C.n1;
     hipLaunchKernelGGL(k_restrict<T>, dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, rc, r, Az, F.owner.p, F.W,
-                       C.W, C.n1, F.p, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles);
+                       C.W, C.n1, F.p, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles, F.npatch);
   }
   HIPCHK(hipGetLastError());
 }
@@ -474,9 +474,9 @@ template void restrict_residual<float>(const Level &, const Level &, float *, co
 template <typename T, int P>
 static void launch_prolong_rows(const Level &F, const Level &C, T *zf, const T *zc, int ldb, int ntiles,
                                 const int *active, hipStream_t s) {
-  const int n = 6 * F.n1;
+  const int n = F.npatch * F.n1;
   hipLaunchKernelGGL((k_prolong_rows<T, P>), dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1,
-                     C.n1, ldb, F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles);
+                     C.n1, ldb, F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles, F.npatch);
 }
 
 template <typename T>
@@ -491,9 +491,9 @@ void prolong_add(const Level &F, const Level &C, T *zf, const T *zc, int ldb, in
       default: launch_prolong_rows<T, 5>(F, C, zf, zc, ldb, ntiles, active, s); break;
     }
   } else {
-    const int n = 6 * F.n1 * F.n1;
+    const int n = F.npatch * F.n1 * F.n1;
     hipLaunchKernelGGL(k_prolong<T>, dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1, F.p,
-                       ldb, F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles);
+                       ldb, F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles, F.npatch);
   }
   HIPCHK(hipGetLastError());
 }

@@ -79,6 +79,8 @@ _SIGS = {
     "gf_context_create": (_i32, [_i32, _vp, ctypes.POINTER(_vp)]),
     "gf_context_destroy": (None, [_vp]),
     "gf_geometry_sphere": (_i32, [_vp, _i32, ctypes.POINTER(_vp)]),
+    "gf_geometry_nurbs": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "gf_geometry_npatch": (_i32, [_vp]),
     "gf_geometry_destroy": (None, [_vp]),
     "gf_locate": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "gf_space_create": (_i32, [_vp, _vp, _i32, _i32, _i32, ctypes.POINTER(_vp)]),
@@ -185,11 +187,28 @@ class Context:
 
 
 class Geometry:
-    def __init__(self, ctx, perturbed=False):
-        h = _vp()
-        _check(_lib.gf_geometry_sphere(ctx.h if ctx is not None else None, 1 if perturbed else 0, ctypes.byref(h)))
+    """The six-patch sphere (perturbed or not), or NURBS patches via Geometry.nurbs."""
+
+    def __init__(self, ctx, perturbed=False, _handle=None):
+        h = _handle
+        if h is None:
+            h = _vp()
+            _check(_lib.gf_geometry_sphere(ctx.h if ctx is not None else None, 1 if perturbed else 0,
+                                           ctypes.byref(h)))
         self.h = h
         self.ctx = ctx
+        self.npatch = int(_lib.gf_geometry_npatch(h))
+
+    @classmethod
+    def nurbs(cls, ctx, deg_u, deg_v, ncoef, knots, ctrl):
+        """NURBS patches in the layout of gf_geometry_nurbs (host arrays)."""
+        nc = np.ascontiguousarray(ncoef, dtype=np.int32).reshape(-1, 2)
+        kn = np.ascontiguousarray(knots, dtype=np.float64).reshape(-1)
+        cp = np.ascontiguousarray(ctrl, dtype=np.float64).reshape(-1)
+        h = _vp()
+        _check(_lib.gf_geometry_nurbs(ctx.h if ctx is not None else None, len(nc), deg_u, deg_v, nc.ctypes.data,
+                                      kn.ctypes.data, cp.ctypes.data, ctypes.byref(h)))
+        return cls(ctx, _handle=h)
 
     def locate(self, xyz):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
@@ -225,7 +244,7 @@ class Space:
 
     def dofmap(self):
         n = 2 ** self.level + self.degree
-        out = np.empty((6, n, n), dtype=np.int32)
+        out = np.empty((self.geom.npatch, n, n), dtype=np.int32)
         _check(_lib.gf_space_dofmap(self.h, out.ctypes.data))
         return out
 

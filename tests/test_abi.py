@@ -86,3 +86,33 @@ def test_sqrt_mass_rule_matches_oracle():
     x = np.zeros(4)
     cc = ctypes.c_double()
     assert g._lib.gf_sqrt_mass_rule(1.0, 0.5, 4, x.ctypes.data, x.ctypes.data, ctypes.byref(cc)) == g.GF_EINVAL
+
+
+def test_nurbs_geometry_accepts_the_torus_and_validates_input():
+    """gf_geometry_nurbs on the host: the 4 x 4 patch torus is accepted (its interfaces glue), and
+    malformed nets are refused before any device work."""
+    from paper_2605_24882_amd import inputs
+    du, dv, nc, kn, cp = inputs.torus_patches(2.0, 1.0)
+    geo = g.Geometry.nurbs(None, du, dv, nc, kn, cp)
+    assert geo.npatch == 16
+    geo.close()
+
+    def status(du_, dv_, nc_, kn_, cp_):
+        with pytest.raises(g.GfieldError) as e:
+            g.Geometry.nurbs(None, du_, dv_, nc_, kn_, cp_)
+        return e.value.status
+
+    bad = cp.copy()
+    bad[3, 1, 1, 3] = 0.0  # a zero weight
+    assert status(du, dv, nc, kn, bad) == g.GF_EINVAL
+    bad_k = kn.copy()
+    bad_k[0] = -0.5  # not open on [0, 1]
+    assert status(du, dv, nc, bad_k, cp) == g.GF_EINVAL
+    assert status(5, dv, nc, kn, cp) == g.GF_EINVAL  # degree out of range
+    # three patches on one edge: patch 0 twice
+    assert status(du, dv, np.concatenate([nc, nc[:1]]), np.concatenate([kn, kn[:12]]),
+                  np.concatenate([cp, cp[:1]])) == g.GF_EINVAL
+    # an edge collapsed to a point
+    deg = cp.copy()
+    deg[0, 0, :, :3] = deg[0, 0, 0, :3]
+    assert status(du, dv, nc, kn, deg) == g.GF_EUNSUPPORTED

@@ -1,0 +1,139 @@
+"""GPU parity on a NURBS multi-patch surface: the 4 x 4 patch torus (R = 2, r = 1, biquadratic
+rational Bezier patches, four patches at every corner) through gf_geometry_nurbs, against the
+oracle's own NURBS evaluation (complex-step metric, Greville-point gluing).
+
+Tolerances as the sphere parity tests: operator and load 1e-13 relative, FP64 fields 1e-10 in
+the M-norm at CG rtol 1e-13, mixed precision 1e-10 with the same FP64 outer residual; at a size
+the oracle does not solve in a test, the constant-load closed form (1e-9, rtol 1e-12).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import assembly, evaluate, fractional, geometry, noise, sinc
+from paper_2605_24882_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+g = pytest.importorskip("paper_2605_24882_amd.gfield")
+
+R, RR = 2.0, 1.0
+NP = 16
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    return g.Context(0)
+
+
+@pytest.fixture(scope="module")
+def geo(ctx):
+    return g.Geometry.nurbs(ctx, *inputs.torus_patches(R, RR))
+
+
+_surf = geometry.NurbsSurface(*inputs.torus_patches(R, RR))
+_spaces, _discs = {}, {}
+
+
+def space(ctx, geo, p, j):
+    if (p, j) not in _spaces:
+        _spaces[(p, j)] = g.Space(ctx, geo, p, j)
+    return _spaces[(p, j)]
+
+
+def disc(p, j):
+    if (p, j) not in _discs:
+        _discs[(p, j)] = assembly.Discretisation(p, j, _surf)
+    return _discs[(p, j)]
+
+
+def mrel(d, u, ref):
+    out = 0.0
+    for a, b in zip(np.atleast_2d(u), np.atleast_2d(ref)):
+        e = a - b
+        out = max(out, math.sqrt(e @ (d.M @ e)) / math.sqrt(b @ (d.M @ b)))
+    return out
+
+
+CASES = [(2, 2), (3, 2), (1, 3), (2, 3)]
+
+
+@pytest.mark.parametrize("p,j", CASES)
+def test_torus_dofmap_matches_oracle(ctx, geo, p, j):
+    sp, d = space(ctx, geo, p, j), disc(p, j)
+    n = 2 ** j + p
+    assert geo.npatch == NP
+    assert sp.ndofs == d.N == NP * (n - 1) ** 2
+    assert np.array_equal(sp.dofmap(), d.l2g)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("p,j", CASES)
+def test_torus_apply_matches_oracle(ctx, geo, p, j, kind):
+    sp, d = space(ctx, geo, p, j), disc(p, j)
+    x = np.random.default_rng(11).standard_normal((3, d.N))
+    for sigma, ss in [(1.0, 0.0), (0.0, 1.0), (9.3, 1.0)]:
+        y = sp.apply(sigma, ss, x, kind)
+        ref = np.stack([(sigma * d.M + ss * d.S) @ v for v in x])
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max(), (sigma, ss)
+
+
+@pytest.mark.parametrize("p,j", [(2, 2), (3, 2)])
+def test_torus_white_noise_matches_oracle(ctx, geo, p, j):
+    sp, d = space(ctx, geo, p, j), disc(p, j)
+    assert sp.noise_length == inputs.noise_length(p, j, NP)
+    z = inputs.noise_vectors([0, 1, 2], sp.noise_length)
+    b = sp.white_noise(z)
+    ref = noise.load(d, z)
+    assert np.abs(b - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("beta", [0.7, 1.6])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_torus_sample_matches_oracle(ctx, geo, beta, prec):
+    sp, d = space(ctx, geo, 2, 3), disc(2, 3)
+    z = inputs.noise_vectors([4, 5], sp.noise_length)
+    b = noise.load(d, z)
+    u, st = sp.sample(3.0, beta, b, h=0.4, k_minus=12, k_plus=12, precision=prec, rtol=1e-13)
+    ref = fractional.sample(d.M, d.S, 3.0, beta, 0.4, 12, 12, b)
+    err = mrel(d, u, ref)
+    print(f"torus p=2 j=3 beta={beta} prec={prec}: rel. M-norm error {err:.2e}, iterations {st['max_iters']}")
+    assert err <= 1e-10
+
+
+def test_torus_eval_matches_oracle(ctx, geo):
+    sp, d = space(ctx, geo, 3, 2), disc(3, 2)
+    rng = np.random.default_rng(8)
+    patch = rng.integers(0, NP, 50).astype(np.int32)
+    st = rng.random((50, 2))
+    u = rng.standard_normal((2, d.N))
+    vals = sp.eval(patch, st, u)
+    ref = (evaluate.phi_matrix(d, patch, st[:, 0], st[:, 1]) @ u.T).T
+    assert np.abs(vals - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_torus_locate_is_unsupported(geo):
+    with pytest.raises(g.GfieldError) as e:
+        geo.locate(np.array([[3.0, 0.0, 0.0]]))
+    assert e.value.status == g.GF_EUNSUPPORTED
+
+
+def test_torus_constant_load_closed_form_at_size(ctx, geo):
+    """p = 2, 64 x 64 elements per patch (16 patches, 67,600 unknowns): u = kappa^-2n Q(kappa^2) 1."""
+    import torch
+    sp = space(ctx, geo, 2, 6)
+    assert sp.ndofs == NP * 65 ** 2
+    one = torch.ones(1, sp.ndofs, dtype=torch.float64, device="cuda")
+    b = sp.apply(1.0, 0.0, one)
+    area = b.sum().item()
+    assert abs(area - 4 * math.pi ** 2 * R * RR) <= 1e-12 * area
+    kappa, beta = 10.0, 1.6
+    u, st = sp.sample(kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=1, rtol=1e-12, max_iter=2000)
+    n, bf = fractional.split_plain(beta)
+    expect = kappa ** (-2 * n) * sinc.sinc_sum(kappa ** 2, bf, 0.4, 20, 20)
+    print(f"torus 67,600 unknowns: constant load, max abs dev {(u - expect).abs().max().item():.2e}, "
+          f"iterations {st['max_iters']}")
+    assert (u - expect).abs().max().item() <= 1e-9 * abs(expect)
