@@ -15,8 +15,9 @@
 // 64-wide column tile (lane = system).  The wavefront keeps a (TY + 2p) x (2p + 1) window of the
 // input in registers and moves it along the strip, loading one new column of TY + 2p values per
 // step (one step ahead).  The stencil coefficients are shared by every system of the row: they
-// arrive as vector loads and are broadcast from their lanes.  Linear block ids are remapped so that every XCD walks a contiguous run of strips: the
-// halo rows shared by neighbouring strips then hit the same L2.
+// arrive as vector loads and are broadcast to the wavefront through LDS.  Linear block ids are
+// remapped so that every XCD walks a contiguous run of strips: the halo rows shared by
+// neighbouring strips then hit the same L2.
 #include "gf_internal.h"
 #include "k_solve.h"
 
@@ -26,16 +27,17 @@ namespace gf {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// the value of v held by lane l (l wavefront-uniform), for every lane
-__device__ __forceinline__ double lane_bcast(double v, int l) {
-  const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
-}
-__device__ __forceinline__ float lane_bcast(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
+// (M_i, S_i) coefficient pair of one stencil tap, read from LDS in one instruction
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
 
 // reduce one double per lane over the 4 wavefronts of the block into partial[slot][col]
 __device__ __forceinline__ void block_partial(double acc, double *partial, int64_t slot, int ldb, int col) {
@@ -100,10 +102,23 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
       nxt[k] = (x + roff[k] + (int64_t)(x0 + 2 * P) * ldb)[lane];
     }
     // The (M, S) stencil pair of an output row is fetched with vector loads (lane l holds
-    // coefficient l of the concatenated pair), one output row ahead, and each coefficient is
-    // broadcast to the wavefront from its lane.  Scalar loads of the same data leave a full cache
-    // round trip per cache line exposed in every step.
+    // coefficient l of the concatenated pair), one output row ahead, staged in the wavefront's
+    // own LDS slot as (M_i, S_i) pairs, and read back with every lane at the same address (a
+    // broadcast read: one LDS instruction per tap instead of two lane reads per coefficient on
+    // the vector ALU).  Scalar loads of the same data leave a full cache round trip per cache line
+    // exposed in every step.  LDS instructions of one wavefront execute in order, so the reads
+    // see the stores of the same row and the next row's stores follow the reads.
     constexpr int NCO = 2 * SS, NV = (NCO + 63) / 64;
+    __shared__ typename Pair<T>::type lco[4][SS];
+    auto stage = [&](const T *cv) {
+      T *flat = reinterpret_cast<T *>(&lco[wave][0]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int l = v * 64 + lane;
+        if (l < NCO) flat[l < SS ? 2 * l : 2 * (l - SS) + 1] = cv[v];
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
     auto coef_load = [&](int64_t crow, T *cv) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -134,15 +149,17 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
         // next output row of this wavefront: row t+1 of this step, else row 0 of the next step
         coef_load((t + 1 < TY && iy + 1 < n1) ? row + W : pbase + (int64_t)(iy0 + P) * W + (min(ix + 1, x1 - 1) + P),
                   cvn);
+        stage(cv);
         T am = 0, as = 0;
 #pragma unroll
         for (int dy = 0; dy < S; ++dy)
 #pragma unroll
           for (int dx = 0; dx < S; ++dx) {
-            const int im = dy * S + dx, is = SS + dy * S + dx;
-            am = fma(lane_bcast(cv[im / 64], im % 64), win[t + dy][dx], am);
-            as = fma(lane_bcast(cv[is / 64], is % 64), win[t + dy][dx], as);
+            const auto c = lco[wave][dy * S + dx];
+            am = fma(c.x, win[t + dy][dx], am);
+            as = fma(c.y, win[t + dy][dx], as);
           }
+        __builtin_amdgcn_wave_barrier();
         const T Az = a * am + b * as;
         const int64_t i = row * ldb + col;
         const bool shared = (ix == 0) | (ix == n1 - 1) | (iy == 0) | (iy == n1 - 1);
