@@ -275,8 +275,10 @@ struct SmoothLog {
   struct Entry {
     hipEvent_t e0, e1;
     int vecs, elem;
+    bool first;  // launched by the first preconditioner application (before any convergence test)
   };
   std::vector<Entry> entries;
+  bool first_phase = false;
   void clear() {
     for (auto &e : entries) {
       (void)hipEventDestroy(e.e0);
@@ -758,7 +760,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
       HIPCHK(hipEventCreate(&ev1));
       // read z, r (and d), write z_out (and d)
       const int vecs = 3 + ((k > 0 && !(dflags & 1)) ? 1 : 0) + ((dflags & 2) ? 0 : 1);
-      w.slog->entries.push_back({ev0, ev1, vecs, (int)sizeof(T)});
+      w.slog->entries.push_back({ev0, ev1, vecs, (int)sizeof(T), w.slog->first_phase});
     }
     apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, spec.rtol * spec.rtol, spec.max_iter, s,
                  ev0, ev1);
@@ -905,6 +907,9 @@ struct BatchSolve {
 
   void start(hipStream_t s) {
     const Level &F = sp->fine();
+    // the smoothing launches of the first preconditioner application are timed with the others
+    w->slog = (spec.flags & GF_FLAG_TIME_APPLY) ? &slog : nullptr;
+    slog.first_phase = true;
     const int ldb = w->ldb, nt = w->ntiles;
     Scratch sc = w->scratch();
     reduce_dot<double, double>(F, w->r.p, w->r.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BB, tol2(), spec.max_iter,
@@ -957,6 +962,7 @@ struct BatchSolve {
   void new_event_pair(hipEvent_t *e0, hipEvent_t *e1) {
     *e0 = *e1 = nullptr;
     w->slog = (spec.flags & GF_FLAG_TIME_APPLY) ? &slog : nullptr;
+    slog.first_phase = false;
     if (!(spec.flags & GF_FLAG_TIME_APPLY)) return;
     HIPCHK(hipEventCreate(e0));
     HIPCHK(hipEventCreate(e1));
@@ -965,7 +971,11 @@ struct BatchSolve {
   }
 
   // read the timed pairs recorded since the last call (the stream is synchronised)
-  void harvest_events(int active_tiles) {
+  // prev_tiles: column tiles active when the iteration began (the outer operator's launches and the
+  // first preconditioner application); now_tiles: active after its convergence test (the V-cycle
+  // that follows the test skips the tiles that converged)
+  void harvest_events(int prev_tiles, int now_tiles) {
+    const int active_tiles = prev_tiles;
     for (size_t i = 0; i + 1 < evs.size(); i += 2) {
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
@@ -987,7 +997,8 @@ struct BatchSolve {
       res.smooth_launches += 1;
       // algorithmic bytes: the batch vectors read and written per active column and patch row, plus
       // the two stencils per row
-      res.smooth_bytes += (double)e.vecs * e.elem * active_tiles * CT * rows + 2.0 * F.S * F.S * e.elem * rows;
+      const int tiles = e.first ? prev_tiles : now_tiles;
+      res.smooth_bytes += (double)e.vecs * e.elem * tiles * CT * rows + 2.0 * F.S * F.S * e.elem * rows;
     }
     slog.clear();
   }
@@ -1051,7 +1062,7 @@ static void solve_all(gf_context *ctx, std::vector<BatchSolve *> &items, bool us
       items[i]->read_active(s);
     }
     HIPCHK(hipStreamSynchronize(s));
-    for (size_t i = 0; i < items.size(); ++i) items[i]->harvest_events(prev[i]);
+    for (size_t i = 0; i < items.size(); ++i) items[i]->harvest_events(prev[i], items[i]->active_tiles());
     for (auto *it : items)
       for (int t = 0; t < it->w->ntiles; ++t) any = any || it->w->active_h[t];
     return !any;
