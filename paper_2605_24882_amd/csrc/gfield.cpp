@@ -115,9 +115,16 @@ static void build_level_device(gf_space *sp, Level &L, const SurfaceArgs &surf) 
           owner[r] = 1;
         }
       }
+  // groups: every unknown on a patch boundary, with all its copies.  The fused stencil kernel
+  // leaves the epilogue of patch-boundary rows to the interface kernel, so a boundary unknown with
+  // a single copy (an edge of an open surface) forms a group of its own.
+  auto on_patch_edge = [&](int r) {
+    const int lx = r % W - p, ly = (r / W) % W - p;
+    return lx == 0 || lx == n1 - 1 || ly == 0 || ly == n1 - 1;
+  };
   std::vector<int> gp{0}, gr;
   for (int g = 0; g < L.N; ++g)
-    if (copies[g].size() > 1) {
+    if (copies[g].size() > 1 || on_patch_edge(copies[g][0])) {
       for (int r : copies[g]) gr.push_back(r);
       gp.push_back((int)gr.size());
     }

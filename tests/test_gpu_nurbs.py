@@ -137,3 +137,38 @@ def test_torus_constant_load_closed_form_at_size(ctx, geo):
     print(f"torus 67,600 unknowns: constant load, max abs dev {(u - expect).abs().max().item():.2e}, "
           f"iterations {st['max_iters']}")
     assert (u - expect).abs().max().item() <= 1e-9 * abs(expect)
+
+
+# ---- open surfaces (unmatched edges: natural boundary condition)
+from tests import open_surfaces  # noqa: E402
+
+_open = {}
+
+
+def open_case(ctx, name, p, j):
+    key = (name, p, j)
+    if key not in _open:
+        args = getattr(open_surfaces, name)()
+        geo_ = g.Geometry.nurbs(ctx, *args)
+        _open[key] = (g.Space(ctx, geo_, p, j), assembly.Discretisation(p, j, geometry.NurbsSurface(*args)))
+    return _open[key]
+
+
+@pytest.mark.parametrize("name,p,j", [("square", 2, 3), ("strip", 2, 3), ("strip", 3, 2)])
+def test_open_surface_parity(ctx, name, p, j):
+    """Dofmap, both operator kinds and FP64 / mixed fields against the oracle on open patches: the
+    rows of boundary unknowns with a single copy run the full epilogue."""
+    sp, d = open_case(ctx, name, p, j)
+    assert np.array_equal(sp.dofmap(), d.l2g)
+    x = np.random.default_rng(4).standard_normal((2, d.N))
+    for kind in (0, 1):
+        y = sp.apply(7.0, 1.0, x, kind)
+        ref = np.stack([(7.0 * d.M + d.S) @ v for v in x])
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    z = inputs.noise_vectors([1, 2], sp.noise_length)
+    b = noise.load(d, z)
+    assert np.abs(sp.white_noise(z) - b).max() <= 1e-13 * np.abs(b).max()
+    ref = fractional.sample(d.M, d.S, 2.0, 1.3, 0.4, 10, 10, b)
+    for prec in (0, 1):
+        u, st = sp.sample(2.0, 1.3, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13)
+        assert mrel(d, u, ref) <= 1e-10, prec

@@ -88,3 +88,28 @@ def test_constant_load_closed_form_on_the_torus(torus):
     n, bf = fractional.split_plain(beta)
     expect = kappa ** (-2 * n) * sinc.sinc_sum(kappa ** 2, bf, h, K, K)
     assert np.abs(u - expect).max() <= 1e-11 * abs(expect)
+
+
+# ---- open surfaces: boundary edges with the natural condition
+from tests import open_surfaces  # noqa: E402
+
+
+@pytest.mark.parametrize("name,lx", [("square", 1.0), ("strip", 2.0)])
+def test_open_flat_surfaces_have_the_neumann_spectrum(name, lx):
+    """Flat patches with unmatched edges: area, S 1 = 0, and the discrete pencil (S, M) against the
+    Neumann eigenvalues of the rectangle (error falling with refinement)."""
+    import scipy.linalg as sla
+    surf = geometry.NurbsSurface(*getattr(open_surfaces, name)())
+    exact = open_surfaces.neumann_eigenvalues(lx, 8)
+    errs = []
+    for j in (3, 4):
+        d = assembly.Discretisation(2, j, surf)
+        n1 = 2 ** j + 2
+        assert d.N == (n1 if name == "square" else 2 * n1 - 1) * n1
+        one = np.ones(d.N)
+        assert abs(one @ (d.M @ one) - lx) <= 1e-13 * lx
+        assert np.abs(d.S @ one).max() <= 1e-12
+        ev = sla.eigh(d.S.toarray(), d.M.toarray(), eigvals_only=True)[:8]
+        errs.append(np.abs(ev[1:] - exact[1:]).max() / exact[-1])
+        assert abs(ev[0]) <= 1e-10
+    assert errs[1] <= 1e-4 and errs[1] < errs[0] / 8
