@@ -159,7 +159,10 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * quadrature sum in float64.  rtol: stop a system when |r| <= rtol |b| (Euclidean, global unknowns).
  * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction on the finest
  * level (0: three); the coarser levels take one (two on levels of more than 50,000 patch coefficients),
- * at most cheb_degree.
+ * at most cheb_degree.  Each system smooths on [b ia, b] (b: 1.1 x a power estimate of the largest
+ * eigenvalue of D^-1 A), ia between 1/8 and (m(pi)/m(0))^2 of the 1D B-spline mass symbol by the
+ * share sigma dM / (sigma dM + dS) of the mass term in the diagonal; loads that have passed through
+ * the inverse operator to an order of 1.5 or more keep 1/8.
  * apply_kind: GF_APPLY_STENCIL or GF_APPLY_SUMFACT for every operator application in the solver.
  * preconditioner (Sec. 3.5): GF_PRECOND_VCYCLE, the multiplicative V-cycle above, or GF_PRECOND_BPX,
  * the additive multilevel preconditioner sum_l P_l D_l^-1 P_l^T with D_l the diagonal of
@@ -195,7 +198,9 @@ typedef struct {
   int32_t smooth_launches; /* with GF_FLAG_TIME_APPLY: number of those launches */
   double smooth_bytes;     /* with GF_FLAG_TIME_APPLY: their algorithmic bytes (the batch vectors each launch
                               reads and writes -- z, r, z_out and, where the recurrence needs it, d -- per
-                              active column and patch row, plus the two stencils per row), summed */
+                              column of the tiles the launch processes and patch row, plus the two
+                              stencils per row), summed; the launches of the first preconditioner
+                              application before the CG loop are included */
 } gf_solve_stats;
 
 /* flags */
