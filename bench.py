@@ -259,6 +259,8 @@ def main():
     ap.add_argument("--load", choices=("factor", "sqrtm"), default="factor",
                     help="white-noise load: element-wise factor (default) or sqrt(M) y inside every step")
     ap.add_argument("--khat", type=int, default=16, help="square-root rule size for --load sqrtm")
+    ap.add_argument("--coarse-level", type=int, default=-1,
+                    help="coarsest multigrid level (-1: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the one-system-per-call FP64 GPU reference timing")
@@ -299,7 +301,7 @@ def main():
         bc = BATCH_CONFIGS[args.config]
         pert, prec, rtol, nsamp, p = bc["perturbed"], bc["precision"], bc["rtol"], bc["nsamp"], max(bc["degrees"])
         geo = g.Geometry(ctx, pert)
-        spaces = {(dg, lv): g.Space(ctx, geo, dg, lv) for dg in bc["degrees"] for lv in bc["levels"]}
+        spaces = {(dg, lv): g.Space(ctx, geo, dg, lv, args.coarse_level) for dg in bc["degrees"] for lv in bc["levels"]}
         space_s = time.perf_counter() - t0
         combos = [(dg, lv, kp) for dg in bc["degrees"] for lv in bc["levels"] for kp in bc["kappas"]]
         reqs = []
@@ -324,7 +326,7 @@ def main():
             geo = g.Geometry.nurbs(ctx, *inputs.torus_patches(2.0, 1.0))
         else:
             geo = g.Geometry(ctx, pert)
-        sp = g.Space(ctx, geo, p, lev)
+        sp = g.Space(ctx, geo, p, lev, args.coarse_level)
         space_s = time.perf_counter() - t0
         if args.load == "sqrtm":
             y = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.ndofs)).cuda()

@@ -155,7 +155,7 @@ typedef struct {
 enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
 /* Solver options.  precision GF_PREC_FP64: everything in float64.  GF_PREC_MIXED: the multigrid
  * V-cycle and its operator applications in float32; the outer CG (its operator application,
- * residuals, inner products), the coarsest-level Cholesky solve, the metric terms and the
+ * residuals, inner products), the coarsest-level dense solve, the metric terms and the
  * quadrature sum in float64.  rtol: stop a system when |r| <= rtol |b| (Euclidean, global unknowns).
  * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction on the finest
  * level (0: three); the coarser levels take one (two on levels of more than 50,000 patch coefficients),
@@ -166,7 +166,7 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * apply_kind: GF_APPLY_STENCIL or GF_APPLY_SUMFACT for every operator application in the solver.
  * preconditioner (Sec. 3.5): GF_PRECOND_VCYCLE, the multiplicative V-cycle above, or GF_PRECOND_BPX,
  * the additive multilevel preconditioner sum_l P_l D_l^-1 P_l^T with D_l the diagonal of
- * sigma M_l + S_l on every level and the Cholesky solve on the coarsest (no operator application
+ * sigma M_l + S_l on every level and the dense solve on the coarsest (no operator application
  * inside the preconditioner; more CG iterations). */
 enum { GF_PRECOND_VCYCLE = 0, GF_PRECOND_BPX = 1 };
 typedef struct {

@@ -197,6 +197,7 @@ void launch_probe_vectors(const Level &L, double *x, int ldb, hipStream_t s);
 void launch_extract_stencil(const Level &L, const double *y, int ldb, double *stM, double *stS, hipStream_t s);
 void launch_stencil_diag(const Level &L, hipStream_t s);
 
+void launch_coarse_inverse(const double *Lf, int N0, int nnode, double *Ainv, hipStream_t s);
 void launch_coarse_factor(const double *M0, const double *S0, int N0, const double *sig, int nnode, double *Lf,
                           int *info, hipStream_t s);
 

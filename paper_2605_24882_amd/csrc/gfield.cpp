@@ -5,7 +5,7 @@
 // the matrix-free operator), interface gluing and knot-insertion transfers.
 // Sampling (Sec. 3.4): integer chain and one batch of all sinc nodes x samples, each system
 // solved by CG preconditioned with a multigrid V-cycle (Chebyshev-Jacobi smoothing,
-// knot-insertion transfers, dense Cholesky on the coarsest level).
+// knot-insertion transfers, a dense solve on the coarsest level).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -263,7 +263,7 @@ struct Plan {
   std::vector<std::vector<double>> invb;  // [level index][node] 1/(upper spectral bound of D^-1 A)
   std::vector<std::vector<double>> ialpha;  // [level index][node] lower end / upper end of the
                                             // smoothing interval
-  DBuf<double> Lf;                        // [node][N0][N0] coarse Cholesky factors
+  DBuf<double> Ainv;                      // [node][N0][N0] inverses of the coarse matrices
   double setup_ms = 0.0;
 };
 
@@ -636,15 +636,20 @@ static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
   // coarse factors
   DBuf<double> sn;
   sn.upload(sig, s);
-  pl->Lf.alloc((size_t)nn * sp->N0 * sp->N0);
+  DBuf<double> Lf;
+  Lf.alloc((size_t)nn * sp->N0 * sp->N0);
   DBuf<int> info;
   info.alloc(nn);
-  launch_coarse_factor(sp->M0.p, sp->S0.p, sp->N0, sn.p, nn, pl->Lf.p, info.p, s);
+  launch_coarse_factor(sp->M0.p, sp->S0.p, sp->N0, sn.p, nn, Lf.p, info.p, s);
   std::vector<int> hinfo(nn);
   HIPCHK(hipMemcpyAsync(hinfo.data(), info.p, nn * sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   for (int k = 0; k < nn; ++k)
     if (hinfo[k] != 0) fail(GF_EINVAL, "coarse matrix not positive definite (shift too small)");
+  // the solve applies the inverse (a dense matrix-vector product per system, all rows in parallel)
+  pl->Ainv.alloc((size_t)nn * sp->N0 * sp->N0);
+  launch_coarse_inverse(Lf.p, sp->N0, nn, pl->Ainv.p, s);
+  HIPCHK(hipStreamSynchronize(s));
   pl->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   Plan &ref = *pl;
   sp->plans[key] = std::move(pl);
@@ -731,7 +736,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
       convert_rows<TR, T>(L, rsrc, rconv, ldb, nt, act, s);
       r = rconv;
     }
-    coarse_solve<T>(L, sp->N0, za, r, spec.plan->Lf.p, w.node.p, ldb, nt, act, s);
+    coarse_solve<T>(L, sp->N0, za, r, spec.plan->Ainv.p, w.node.p, ldb, nt, act, s);
     return za;
   }
   const T *r = rconv ? (const T *)rconv : (const T *)rsrc;
@@ -796,7 +801,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
 }
 
 // Additive multilevel (BPX) preconditioner: z = sum over the levels l of P_l D_l^-1 P_l^T r with
-// D_l the diagonal of sigma M_l + S_l, and the exact (Cholesky) solve on level 0.  The residual is
+// D_l the diagonal of sigma M_l + S_l, and the exact (dense) solve on level 0.  The residual is
 // restricted level by level (knot-insertion transposes, interface sums); on the way up every level
 // adds its diagonally scaled residual to the prolongation of the coarser correction.
 template <typename T, typename TR>
@@ -817,7 +822,7 @@ static T *bpx(gf_space *sp, Workspace &w, const SolveSpec &spec, const TR *rsrc,
     launch_interface_sum<T>(C, rc, ldb, nt, act, s);
   }
   T *zc = Prec<T>::za(w.lw[0]);
-  coarse_solve<T>(*sp->lev[0], sp->N0, zc, Prec<T>::r(w.lw[0]), spec.plan->Lf.p, w.node.p, ldb, nt, act, s);
+  coarse_solve<T>(*sp->lev[0], sp->N0, zc, Prec<T>::r(w.lw[0]), spec.plan->Ainv.p, w.node.p, ldb, nt, act, s);
   for (int l = 1; l <= fi; ++l) {
     const Level &L = *sp->lev[l], &C = *sp->lev[l - 1];
     T *z = Prec<T>::za(w.lw[l]);

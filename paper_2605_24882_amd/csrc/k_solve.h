@@ -183,7 +183,7 @@ template <typename T>
 void prolong_add(const Level &F, const Level &C, T *zf, const T *zc, int ldb, int ntiles, const int *active,
                  hipStream_t s);
 template <typename T>
-void coarse_solve(const Level &C, int N0, T *z, const T *r, const double *Lf, const int *node, int ldb, int ntiles,
+void coarse_solve(const Level &C, int N0, T *z, const T *r, const double *Ainv, const int *node, int ldb, int ntiles,
                   const int *active, hipStream_t s);
 void global_to_local(const Level &L, double *X, const double *src, int nvec, int ldb, hipStream_t s);
 void local_to_global(const Level &L, double *dst, const double *X, int nvec, int c0, int ldb, hipStream_t s);
