@@ -58,16 +58,31 @@ BATCH_CONFIGS = {
 }
 
 
-def batch_workload_name(bc, nreq):
+def accurate_nodes(beta, kappa, level, h, eps=1e-6):
+    """(k_minus, k_plus) of the tolerance-driven node set at step h: each tail of the sinc sum for
+    beta' = beta - floor(beta) is cut where its terms, relative to the exact power, fall below eps
+    for the extreme eigenvalues of the discrete operator (lambda from kappa^2 up to
+    kappa^2 + l (l + 1) with l = sqrt(6) 2^level, the largest degree a mesh of 2^level elements
+    per patch side resolves).  Large t: terms ~ t^-beta', cut at t^-beta' = eps lambda_max^-beta';
+    small t: terms ~ t^(1-beta') / kappa^2, cut at (t / kappa^2)^(1-beta') = eps."""
+    bf = beta - math.floor(beta)
+    lmax = math.sqrt(6.0) * 2 ** level
+    lam_max = kappa * kappa + lmax * (lmax + 1.0)
+    y_lo = (math.log(eps) - bf * math.log(lam_max)) / (2.0 * bf)
+    y_hi = -(math.log(eps) + (1.0 - bf) * math.log(kappa * kappa)) / (2.0 * (1.0 - bf))
+    return math.ceil(-y_lo / h), math.ceil(y_hi / h)
+
+
+def batch_workload_name(bc, nreq, nodes_desc=None):
     surf = "perturbed sphere" if bc["perturbed"] else "unit sphere"
     lv = "/".join(f"{2**l}x{2**l}" for l in bc["levels"])
     return (f"{surf}, 6 patches, degrees {bc['degrees']}, {lv} elements/patch, kappa in {bc['kappas']}, "
-            f"beta={bc['beta']:g} ({2*bc['k']+1} sinc nodes, h={bc['h']:g}); {bc['nsamp']} samples over {nreq} "
+            f"beta={bc['beta']:g} ({nodes_desc or str(2*bc['k']+1) + ' sinc nodes'}, h={bc['h']:g}); {bc['nsamp']} samples over {nreq} "
             f"requests in one batched call; {'FP64' if bc['precision'] == 0 else 'FP32 V-cycle / FP64 CG'} MG-PCG "
             f"to rel. residual {bc['rtol']:g}")
 
 
-def workload_name(cfg):
+def workload_name(cfg, km=None, kp=None):
     pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
     n1 = 2 ** lev + p
     nint = math.floor(beta)
@@ -77,7 +92,9 @@ def workload_name(cfg):
         N, npatch = 6 * (n1 - 2) ** 2 + 12 * (n1 - 2) + 8, 6
         surf = "perturbed sphere" if pert else "unit sphere"
     return (f"{surf}, {npatch} patches, degree {p}, {2**lev}x{2**lev} elements/patch ({N} DOF); kappa={kappa:g}, "
-            f"beta={beta:g} ({nint} integer solve(s) + {2*k+1} sinc nodes, h={h:g}); {nsamp} samples; "
+            f"beta={beta:g} ({nint} integer solve(s) + "
+            f"{(2*k+1) if km is None else f'{km+kp+1} (k = -{km}..{kp}, tolerance 1e-6)'} sinc nodes, h={h:g}); "
+            f"{nsamp} samples; "
             f"{'FP64' if prec == 0 else 'FP32 V-cycle / FP64 CG'} MG-PCG to rel. residual {rtol:g}")
 
 
@@ -259,6 +276,8 @@ def main():
     ap.add_argument("--load", choices=("factor", "sqrtm"), default="factor",
                     help="white-noise load: element-wise factor (default) or sqrt(M) y inside every step")
     ap.add_argument("--khat", type=int, default=16, help="square-root rule size for --load sqrtm")
+    ap.add_argument("--nodes", choices=("fixed", "accurate"), default="fixed",
+                    help="sinc nodes: the workload's symmetric K, or the tolerance-driven set (1e-6) per request")
     ap.add_argument("--coarse-level", type=int, default=-1,
                     help="coarsest multigrid level (-1: the library's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -309,8 +328,10 @@ def main():
             sp = spaces[(dg, lv)]
             seeds = [s_ for s_ in range(nsamp) if s_ % len(combos) == i]
             z = torch.from_numpy(inputs.noise_vectors(seeds, sp.noise_length)).cuda()
+            km_, kp_ = (accurate_nodes(bc["beta"], kp, lv, bc["h"]) if args.nodes == "accurate"
+                        else (bc["k"], bc["k"]))
             reqs.append(dict(space=sp, kappa=kp, beta=bc["beta"], b=sp.white_noise(z), h=bc["h"],
-                             k_minus=bc["k"], k_plus=bc["k"],
+                             k_minus=km_, k_plus=kp_,
                              split=g.GF_SPLIT_IMPROVED if args.split == "improved" else g.GF_SPLIT_PLAIN))
             del z
         kw = dict(precision=prec, rtol=rtol, max_iter=2000, cheb_degree=args.cheb, apply_kind=args.apply_kind,
@@ -318,7 +339,10 @@ def main():
 
         def step(flags=0):
             return g.sample_batch(ctx, reqs, flags=flags, **kw)
-        workload = batch_workload_name(bc, len(combos))
+        workload = batch_workload_name(
+            bc, len(combos), None if args.nodes == "fixed" else
+            f"{min(r['k_minus'] + r['k_plus'] + 1 for r in reqs)}..{max(r['k_minus'] + r['k_plus'] + 1 for r in reqs)}"
+            f" sinc nodes per request (tolerance 1e-6)")
     else:
         cfg = CONFIGS[args.config]
         pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
@@ -335,7 +359,8 @@ def main():
             z = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.noise_length)).cuda()
             b = sp.white_noise(z)
             del z
-        kw = dict(h=h, k_minus=k, k_plus=k, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
+        km, kp = accurate_nodes(beta, kappa, lev, h) if args.nodes == "accurate" else (k, k)
+        kw = dict(h=h, k_minus=km, k_plus=kp, precision=prec, rtol=rtol, max_iter=1000, cheb_degree=args.cheb,
                   apply_kind=args.apply_kind,
                   split=g.GF_SPLIT_IMPROVED if args.split == "improved" else g.GF_SPLIT_PLAIN,
                   preconditioner=g.GF_PRECOND_BPX if args.precond == "bpx" else g.GF_PRECOND_VCYCLE)
@@ -357,7 +382,7 @@ def main():
                 st["max_iters"] = max(st1["max_iters"], st2["max_iters"])
                 st["max_rel_resid"] = max(st1["max_rel_resid"], st2["max_rel_resid"])
                 return gk, st
-            workload = workload_name(cfg) + "; plus d loss/d kappa by adjoint solves (loss over 1000 points)"
+            workload = workload_name(cfg, *((km, kp) if args.nodes == "accurate" else ())) + "; plus d loss/d kappa by adjoint solves (loss over 1000 points)"
         elif args.load == "sqrtm":
             def step(flags=0):
                 f, st0 = sp.sqrt_mass(y, khat=args.khat, rtol=rtol, flags=flags & ~g.GF_FLAG_TIME_APPLY)
@@ -366,11 +391,11 @@ def main():
                 st["n_systems"] += st0["n_systems"]
                 st["max_iters"] = max(st["max_iters"], st0["max_iters"])
                 return u, st
-            workload = workload_name(cfg) + f"; load sqrt(M) y by the square-root rule with {args.khat} shifts"
+            workload = workload_name(cfg, *((km, kp) if args.nodes == "accurate" else ())) + f"; load sqrt(M) y by the square-root rule with {args.khat} shifts"
         else:
             def step(flags=0):
                 return sp.sample(kappa, beta, b, flags=flags, **kw)
-            workload = workload_name(cfg)
+            workload = workload_name(cfg, *((km, kp) if args.nodes == "accurate" else ()))
     if args.split == "improved":
         workload += "; improved split (rule applied twice where beta' < 1/3 or > 2/3)"
     if args.precond == "bpx":
