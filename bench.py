@@ -156,6 +156,26 @@ def pmc_summary(fetch_csv, write_csv, config, probe_mib):
     return out
 
 
+def counter_summary(csvs, config):
+    """Markdown table: every counter of the given rocprofv3 --pmc runs, averaged per launch, for the
+    finest-level smoothing step and the outer operator."""
+    p = CONFIGS[config][1]
+    table = {}
+    for path in csvs:
+        names = sorted({r["Counter_Name"] for r in csv.DictReader(open(path))})
+        for n in names:
+            for kind in ("smoother", "outer"):
+                vals, _ = _kernel_rows(path, p, kind,
+                                       lambda r, n=n: float(r["Counter_Value"]) if r["Counter_Name"] == n else None)
+                vals = [v for v in vals if v is not None]
+                table.setdefault(n, {})[kind] = (sum(vals) / len(vals), len(vals)) if vals else (float("nan"), 0)
+    lines = ["| counter | smoothing step, per launch | outer operator, per launch |", "|---|---:|---:|"]
+    for n in sorted(table):
+        sm, ou = table[n]["smoother"], table[n]["outer"]
+        lines.append(f"| {n} | {sm[0]:.4g} ({sm[1]} launches) | {ou[0]:.4g} ({ou[1]} launches) |")
+    return "\n".join(lines)
+
+
 def trace_summary(trace_csv, p, top=25):
     """Text summary of a rocprofv3 kernel trace: time per kernel and grid, and the outer operator."""
     rows = list(csv.DictReader(open(trace_csv)))
@@ -288,6 +308,8 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the per-launch traffic of the outer operator from two rocprofv3 counter runs "
                          "(made with --copy-probe-mib) as JSON to stdout, then exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="COUNTER_CSV",
+                    help="print the per-launch averages of every counter in these --pmc runs and exit")
     ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
                     help="print a summary of a rocprofv3 kernel trace of this benchmark, then exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -298,6 +320,9 @@ def main():
     if args.pmc_summary:
         print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.config,
                                      args.copy_probe_mib or 512), indent=1))
+        return
+    if args.counter_summary:
+        print(counter_summary(args.counter_summary, args.config))
         return
     if args.trace_summary:
         print(trace_summary(args.trace_summary, CONFIGS[args.config][1])[0])
