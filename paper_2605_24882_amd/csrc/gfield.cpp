@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <sstream>
+#include <type_traits>
 
 #include "gf_internal.h"
 #include "k_solve.h"
@@ -303,6 +304,10 @@ struct Workspace {
   DBuf<double> sig64, one64, zero64;
   DBuf<float> sig32, one32;
   DBuf<int> node, active;
+  // outer-CG fusion: while set, the finest level's first smoothing step also performs r -= alpha q
+  // (q = fuse_q) and the convergence test, and records the tiles active before it in active0
+  const double *fuse_q = nullptr;
+  DBuf<int> active0;
   DBuf<ColState> cs;
   DBuf<double> partial;
   DBuf<int> counter;
@@ -387,6 +392,7 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
   w->one32.alloc(ldb);
   w->node.alloc(ldb);
   w->active.alloc(w->ntiles);
+  w->active0.alloc(w->ntiles);
   w->cs.alloc(ldb);
   w->partial.alloc(scratch_slots(sp, ldb, w->ntiles) * ldb);
   w->counter.alloc(w->ntiles);
@@ -778,8 +784,17 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
                  ev0, ev1);
     std::swap(za, zb);
   };
-  // pre-smoothing from zero (the first step's direction is the iterate itself and is not stored)
-  cheb_first<T, TR>(L, rsrc, rconv, za, nullptr, dM, dS, sig, cf + (size_t)deg * ldb, ldb, nt, act, s);
+  // pre-smoothing from zero (the first step's direction is the iterate itself and is not stored); in
+  // an outer-CG iteration the finest level's first step also updates the residual and tests it
+  bool fused_first = false;
+  if constexpr (std::is_same<TR, double>::value) {
+    if (w.fuse_q && li + 1 == sp->nlev()) {
+      cheb_first_cg<T>(L, w.r.p, w.fuse_q, rconv, za, dM, dS, sig, cf + (size_t)deg * ldb, sc, w.cs.p, act,
+                       w.active0.p, ldb, nt, spec.rtol * spec.rtol, spec.max_iter, s);
+      fused_first = true;
+    }
+  }
+  if (!fused_first) cheb_first<T, TR>(L, rsrc, rconv, za, nullptr, dM, dS, sig, cf + (size_t)deg * ldb, ldb, nt, act, s);
   for (int k = 1; k < deg; ++k) smooth(k, false, (k == 1 ? 1 : 0) | (k == deg - 1 ? 2 : 0));
   // residual, restriction, coarse correction, prolongation
   {
@@ -941,7 +956,8 @@ struct BatchSolve {
   }
 
   // one CG iteration: q = A p (+ p.q -> alpha), x += alpha p, r -= alpha q (+ |r|^2 -> test),
-  // z = B r (+ r.z -> beta), p = z + beta p
+  // z = B r (+ r.z -> beta), p = z + beta p.  With the V-cycle the residual update and the test run
+  // inside its first kernel and x += alpha p with the update of p (two passes over the batch fewer).
   void iterate(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const Level &F = sp->fine();
     const int ldb = w->ldb, nt = w->ntiles;
@@ -957,17 +973,31 @@ struct BatchSolve {
     else
       apply_epi<double>(F, spec.kind, w->p.p, w->sig64.p, w->one64.p, e, sc, w->cs.p, w->active.p, ldb, nt, tol2(),
                         spec.max_iter, s, e0, e1);
-    update_xr2(F, w->x.p, w->r.p, w->p.p, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, tol2(), spec.max_iter, s);
+    // (a one-level space has no smoothing step to carry the update: the coarse solve is the V-cycle)
+    const bool fuse = !spec.mass_shift && spec.precond == GF_PRECOND_VCYCLE && sp->nlev() > 1;
+    if (fuse)
+      w->fuse_q = w->q.p;
+    else
+      update_xr2(F, w->x.p, w->r.p, w->p.p, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, tol2(), spec.max_iter, s);
     if (mixed()) {
       precondition(-1, s);
+      w->fuse_q = nullptr;
       reduce_dot2<double, float, double>(F, w->r.p, zf, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BETA_FLEX,
                                          tol2(), spec.max_iter, nullptr, s);
-      update_p2<float>(F, w->p.p, zf, w->cs.p, ldb, nt, w->active.p, s);
+      if (fuse)
+        update_xp<float>(F, w->x.p, w->p.p, zf, w->cs.p, w->active0.p, ldb, nt, s);
+      else
+        update_p2<float>(F, w->p.p, zf, w->cs.p, ldb, nt, w->active.p, s);
     } else {
-      if (!precondition(OP_BETA, s))
+      const bool fused_dot = precondition(OP_BETA, s);
+      w->fuse_q = nullptr;
+      if (!fused_dot)
         reduce_dot<double, double>(F, w->r.p, zd, sc, ldb, nt, w->cs.p, w->active.p, OP_BETA, tol2(),
                                    spec.max_iter, nullptr, s);
-      update_p2<double>(F, w->p.p, zd, w->cs.p, ldb, nt, w->active.p, s);
+      if (fuse)
+        update_xp<double>(F, w->x.p, w->p.p, zd, w->cs.p, w->active0.p, ldb, nt, s);
+      else
+        update_p2<double>(F, w->p.p, zd, w->cs.p, ldb, nt, w->active.p, s);
     }
   }
 

@@ -517,6 +517,126 @@ __global__ __launch_bounds__(256) void k_cheb_first(RowGeom g, const TR *__restr
   }
 }
 
+// The outer CG's residual update fused with the first Chebyshev step of the finest level: r -= alpha q
+// in FP64 with |r|^2 over the owned unknowns into the partial sums of the convergence test (the same
+// rows in the same order as k_update_xr), then the step of k_cheb_first on the new residual.  The
+// iterate's update x += alpha p is left to k_update_xp, which runs over the column tiles that were
+// active when the iteration began (active0, written here) -- a tile that converges in this test
+// still receives its last step.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cheb_first_cg(RowGeom g, double *__restrict__ r, const double *__restrict__ q,
+                                                       T *__restrict__ r32, T *__restrict__ z,
+                                                       const T *__restrict__ dM, const T *__restrict__ dS,
+                                                       const T *__restrict__ sig, const T *__restrict__ cf2,
+                                                       const ColState *cs, double *partial, const int *active,
+                                                       int *active0) {
+  const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
+  const bool on = !active || active[ct];
+  if (rb == 0 && threadIdx.x == 0) active0[ct] = on ? 1 : 0;
+  if (!on) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int ldb = g.ldb;
+  const double al = cs[col].alpha;
+  const T sg = sig[col], sc = cf2[col];
+  const int64_t stride = (int64_t)g.nrb * 4;
+  double acc = 0.0;
+  for (int64_t r0 = (int64_t)rb * 4 + wave; r0 < g.R; r0 += 4 * stride) {
+    double rv[4], qv[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + u * stride;
+      ok[u] = row < g.R;
+      if (ok[u]) {
+        const int64_t i = row * ldb + col;
+        rv[u] = r[i];
+        qv[u] = q[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!ok[u]) continue;
+      const int64_t row = r0 + u * stride;
+      const int64_t i = row * ldb + col;
+      const double rn = rv[u] - al * qv[u];
+      r[i] = rn;
+      if (g.owner[row]) acc += rn * rn;
+      const T rt = (T)rn;
+      if (r32) r32[i] = rt;
+      z[i] = sc * rt / (sg * dM[row] + dS[row]);
+    }
+  }
+  block_partial(acc, partial, rb, ldb, col);
+}
+
+// x += alpha p, p = z + beta p over the column tiles active when the iteration began
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_update_xp(RowGeom g, double *__restrict__ x, double *__restrict__ p,
+                                                   const TZ *__restrict__ z, const ColState *cs,
+                                                   const int *active0) {
+  const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
+  if (!active0[ct]) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int ldb = g.ldb;
+  const double al = cs[col].alpha, be = cs[col].beta;
+  const int64_t stride = (int64_t)g.nrb * 4;
+  for (int64_t r0 = (int64_t)rb * 4 + wave; r0 < g.R; r0 += 4 * stride) {
+    double pv[4], xv[4], zv[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + u * stride;
+      ok[u] = row < g.R;
+      if (ok[u]) {
+        const int64_t i = row * ldb + col;
+        pv[u] = p[i];
+        xv[u] = x[i];
+        zv[u] = (double)z[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!ok[u]) continue;
+      const int64_t i = (r0 + u * stride) * ldb + col;
+      x[i] = xv[u] + al * pv[u];
+      p[i] = zv[u] + be * pv[u];
+    }
+  }
+}
+
+template <typename T>
+void cheb_first_cg(const Level &L, double *r, const double *q, T *r32, T *z, const T *dM, const T *dS, const T *sig,
+                   const T *cf2, Scratch &sc, ColState *cs, int *active, int *active0, int ldb, int ntiles,
+                   double tol2, int maxit, hipStream_t s) {
+  const RowGeom g = row_geom(L, ldb);
+  hipLaunchKernelGGL(k_cheb_first_cg<T>, dim3(g.nrb * ntiles), dim3(256), 0, s, g, r, q, r32, z, dM, dS, sig, cf2,
+                     cs, sc.partial, active, active0);
+  HIPCHK(hipGetLastError());
+  finalize(g.nrb, 1, OP_CHECK, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
+}
+template void cheb_first_cg<double>(const Level &, double *, const double *, double *, double *, const double *,
+                                    const double *, const double *, const double *, Scratch &, ColState *, int *,
+                                    int *, int, int, double, int, hipStream_t);
+template void cheb_first_cg<float>(const Level &, double *, const double *, float *, float *, const float *,
+                                   const float *, const float *, const float *, Scratch &, ColState *, int *, int *,
+                                   int, int, double, int, hipStream_t);
+
+template <typename TZ>
+void update_xp(const Level &L, double *x, double *p, const TZ *z, const ColState *cs, const int *active0, int ldb,
+               int ntiles, hipStream_t s) {
+  const RowGeom g = row_geom(L, ldb);
+  hipLaunchKernelGGL(k_update_xp<TZ>, dim3(g.nrb * ntiles), dim3(256), 0, s, g, x, p, z, cs, active0);
+  HIPCHK(hipGetLastError());
+}
+template void update_xp<double>(const Level &, double *, double *, const double *, const ColState *, const int *, int,
+                                int, hipStream_t);
+template void update_xp<float>(const Level &, double *, double *, const float *, const ColState *, const int *, int,
+                               int, hipStream_t);
+
 void update_xr2(const Level &L, double *x, double *r, const double *p, const double *q, Scratch &sc, int ldb,
                 int ntiles, ColState *cs, int *active, double tol2, int maxit, hipStream_t s) {
   const RowGeom g = row_geom(L, ldb);

@@ -161,6 +161,14 @@ template <typename T, typename TR>
 void cheb_first(const Level &L, const TR *r, T *r32, T *z, T *d, const T *dM, const T *dS, const T *sig,
                 const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s);
 
+template <typename T>
+void cheb_first_cg(const Level &L, double *r, const double *q, T *r32, T *z, const T *dM, const T *dS, const T *sig,
+                   const T *cf2, Scratch &sc, ColState *cs, int *active, int *active0, int ldb, int ntiles,
+                   double tol2, int maxit, hipStream_t s);
+template <typename TZ>
+void update_xp(const Level &L, double *x, double *p, const TZ *z, const ColState *cs, const int *active0, int ldb,
+               int ntiles, hipStream_t s);
+
 template <typename TA, typename TB>
 void reduce_dot(const Level &L, const TA *a, const TB *b, Scratch &sc, int ldb, int ntiles, ColState *cs,
                 int *active, int op, double tol2, int maxit, double *out, hipStream_t s);

@@ -351,3 +351,15 @@ def test_bpx_preconditioner_matches_oracle(ctx, p, j, pert, beta, prec):
                       preconditioner=g.GF_PRECOND_BPX)
     ref = _oracle_u(d, 3.0, beta, 0.4, 10, b)
     assert mrel(d, u, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("p,j,lc", [(1, 2, 2), (2, 3, 1), (2, 2, 0)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coarse_level_choice_matches_oracle(ctx, p, j, lc, prec):
+    """The hierarchy's coarsest level is a solver choice: a one-level space (the dense coarse solve is
+    the whole preconditioner), a coarsest level above 0 and the default give the oracle's fields."""
+    sp, d = space(ctx, p, j, False, lc), disc(p, j)
+    b = noise.load(d, inputs.noise_vectors([7, 8], inputs.noise_length(p, j)))
+    u, st = sp.sample(3.0, 1.4, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13, max_iter=1000)
+    ref = _oracle_u(d, 3.0, 1.4, 0.4, 10, b)
+    assert mrel(d, u, ref) <= 1e-10
