@@ -973,6 +973,14 @@ struct BatchSolve {
     else
       apply_epi<double>(F, spec.kind, w->p.p, w->sig64.p, w->one64.p, e, sc, w->cs.p, w->active.p, ldb, nt, tol2(),
                         spec.max_iter, s, e0, e1);
+    if (spec.mass_shift) {
+      // Jacobi CG of M + sigma I: residual update, z = r / D, the test and beta in one pass
+      zd = w->lw[sp->nlev() - 1].z64a.p;
+      jacobi_step(F, w->r.p, w->q.p, zd, w->one64.p, F.dM.p, w->sig64.p, F.dI.p, sc, w->cs.p, w->active.p,
+                  w->active0.p, ldb, nt, tol2(), spec.max_iter, s);
+      update_xp<double>(F, w->x.p, w->p.p, zd, w->cs.p, w->active0.p, ldb, nt, s);
+      return;
+    }
     // (a one-level space has no smoothing step to carry the update: the coarse solve is the V-cycle)
     const bool fuse = !spec.mass_shift && spec.precond == GF_PRECOND_VCYCLE && sp->nlev() > 1;
     if (fuse)

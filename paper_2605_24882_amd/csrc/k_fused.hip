@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ par
     return;
   }
   finalize_col(op, col, tot, cs, tol2, maxit);
-  if (op == OP_CHECK && active) {
+  if ((op == OP_CHECK || op == OP_CHECK_BETA) && active) {
     const unsigned long long any = __ballot(!cs[col].done);
     if (lane == 0) active[ct] = any ? 1 : 0;
   }
@@ -569,6 +569,73 @@ __global__ __launch_bounds__(256) void k_cheb_first_cg(RowGeom g, double *__rest
     }
   }
   block_partial(acc, partial, rb, ldb, col);
+}
+
+// Jacobi-preconditioned CG of the shifted mass systems, one pass per iteration besides the operator:
+// r -= alpha q, z = r / D with D = ca dA + cb dB per column and row, |r|^2 and r.z over the owned
+// unknowns into two sets of partial sums (slots rb and nrb + rb).
+__global__ __launch_bounds__(256) void k_jacobi_step(RowGeom g, double *__restrict__ r, const double *__restrict__ q,
+                                                     double *__restrict__ z, const double *__restrict__ ca,
+                                                     const double *__restrict__ dA, const double *__restrict__ cb,
+                                                     const double *__restrict__ dB, const ColState *cs,
+                                                     double *partial, const int *active, int *active0) {
+  __shared__ double red2[2][4][CT];
+  const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
+  const bool on = !active || active[ct];
+  if (rb == 0 && threadIdx.x == 0) active0[ct] = on ? 1 : 0;
+  if (!on) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = uni(threadIdx.x >> 6);
+  const int col = ct * CT + lane;
+  const int ldb = g.ldb;
+  const double al = cs[col].alpha, a = ca[col], b = cb[col];
+  const int64_t stride = (int64_t)g.nrb * 4;
+  double acc = 0.0, acc2 = 0.0;
+  for (int64_t r0 = (int64_t)rb * 4 + wave; r0 < g.R; r0 += 4 * stride) {
+    double rv[4], qv[4];
+    bool ok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t row = r0 + u * stride;
+      ok[u] = row < g.R;
+      if (ok[u]) {
+        const int64_t i = row * ldb + col;
+        rv[u] = r[i];
+        qv[u] = q[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (!ok[u]) continue;
+      const int64_t row = r0 + u * stride;
+      const int64_t i = row * ldb + col;
+      const double rn = rv[u] - al * qv[u];
+      const double zn = rn / (a * dA[row] + b * dB[row]);
+      r[i] = rn;
+      z[i] = zn;
+      if (g.owner[row]) {
+        acc += rn * rn;
+        acc2 += rn * zn;
+      }
+    }
+  }
+  red2[0][wave][lane] = acc;
+  red2[1][wave][lane] = acc2;
+  __syncthreads();
+  if (wave == 0)
+    for (int k = 0; k < 2; ++k)
+      partial[((int64_t)k * g.nrb + rb) * ldb + col] =
+          red2[k][0][lane] + red2[k][1][lane] + red2[k][2][lane] + red2[k][3][lane];
+}
+
+void jacobi_step(const Level &L, double *r, const double *q, double *z, const double *ca, const double *dA,
+                 const double *cb, const double *dB, Scratch &sc, ColState *cs, int *active, int *active0, int ldb,
+                 int ntiles, double tol2, int maxit, hipStream_t s) {
+  const RowGeom g = row_geom(L, ldb);
+  hipLaunchKernelGGL(k_jacobi_step, dim3(g.nrb * ntiles), dim3(256), 0, s, g, r, q, z, ca, dA, cb, dB, cs,
+                     sc.partial, active, active0);
+  HIPCHK(hipGetLastError());
+  finalize(g.nrb, 2, OP_CHECK_BETA, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
 }
 
 // x += alpha p, p = z + beta p over the column tiles active when the iteration began

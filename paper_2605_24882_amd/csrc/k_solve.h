@@ -17,7 +17,7 @@ struct ColState {
   int pad;
 };
 
-enum ReduceOp { OP_STORE = 0, OP_BB, OP_RZ0, OP_ALPHA, OP_CHECK, OP_BETA, OP_BETA_FLEX };
+enum ReduceOp { OP_STORE = 0, OP_BB, OP_RZ0, OP_ALPHA, OP_CHECK, OP_BETA, OP_BETA_FLEX, OP_CHECK_BETA };
 
 constexpr int kMaxRowBlocks = 1024;  // row blocks of the generic reduction kernels
 constexpr int kRowBlocks = 256;      // row blocks per column tile of the streaming kernels
@@ -78,6 +78,10 @@ __device__ inline void finalize_col(int op, int col, const double *tot, ColState
       // Polak-Ribiere: beta = z_new^T (r_new - r_old) / rz_old with r_new - r_old = -alpha q
       c.beta = c.done ? 0.0 : -c.alpha * tot[1] / c.rz;
       c.rz = tot[0];
+      break;
+    case OP_CHECK_BETA:  // tot[0] = |r|^2 (the test), tot[1] = r.z (beta), as OP_CHECK then OP_BETA
+      finalize_col(OP_CHECK, col, tot, cs, tol2, maxit);
+      finalize_col(OP_BETA, col, tot + 1, cs, tol2, maxit);
       break;
     default:
       break;
@@ -165,6 +169,11 @@ template <typename T>
 void cheb_first_cg(const Level &L, double *r, const double *q, T *r32, T *z, const T *dM, const T *dS, const T *sig,
                    const T *cf2, Scratch &sc, ColState *cs, int *active, int *active0, int ldb, int ntiles,
                    double tol2, int maxit, hipStream_t s);
+// Jacobi-preconditioned CG step of the shifted mass systems: r -= alpha q, z = r / (dA ca + dB cb),
+// |r|^2 and r.z into the partial sums, then the test and beta (OP_CHECK_BETA); active0 as cheb_first_cg
+void jacobi_step(const Level &L, double *r, const double *q, double *z, const double *ca, const double *dA,
+                 const double *cb, const double *dB, Scratch &sc, ColState *cs, int *active, int *active0, int ldb,
+                 int ntiles, double tol2, int maxit, hipStream_t s);
 template <typename TZ>
 void update_xp(const Level &L, double *x, double *p, const TZ *z, const ColState *cs, const int *active0, int ldb,
                int ntiles, hipStream_t s);
