@@ -537,25 +537,27 @@ void launch_coarse_factor(const double *M0, const double *S0, int N0, const doub
 // A^-1 = L^-T L^-1 from the Cholesky factor, one block per node, thread j builds column j:
 // forward substitution L y = e_j, then back substitution L^T x = y, both in place in the column.
 __global__ void k_coarse_inverse(const double *Lf, int n, int nnode, double *Ainv) {
-  const int k = blockIdx.x, j = threadIdx.x;
-  if (k >= nnode || j >= n) return;
+  const int k = blockIdx.x;
+  if (k >= nnode) return;
   const double *L = Lf + (size_t)k * n * n;
   double *X = Ainv + (size_t)k * n * n;
-  for (int i = 0; i < n; ++i) {
-    double s = (i == j) ? 1.0 : 0.0;
-    for (int t = j; t < i; ++t) s -= L[i * n + t] * X[t * n + j];
-    X[i * n + j] = (i < j) ? 0.0 : s / L[i * n + i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double s = X[i * n + j];
-    for (int t = i + 1; t < n; ++t) s -= L[t * n + i] * X[t * n + j];
-    X[i * n + j] = s / L[i * n + i];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int t = j; t < i; ++t) s -= L[(size_t)i * n + t] * X[(size_t)t * n + j];
+      X[(size_t)i * n + j] = (i < j) ? 0.0 : s / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = X[(size_t)i * n + j];
+      for (int t = i + 1; t < n; ++t) s -= L[(size_t)t * n + i] * X[(size_t)t * n + j];
+      X[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+    }
   }
 }
 
 void launch_coarse_inverse(const double *Lf, int N0, int nnode, double *Ainv, hipStream_t s) {
-  if (N0 > 1024) fail(GF_EUNSUPPORTED, "coarsest level too large for the dense coarse solve");
-  hipLaunchKernelGGL(k_coarse_inverse, dim3(nnode), dim3((N0 + 63) / 64 * 64), 0, s, Lf, N0, nnode, Ainv);
+  hipLaunchKernelGGL(k_coarse_inverse, dim3(nnode), dim3(std::min(1024, (N0 + 63) / 64 * 64)), 0, s, Lf, N0, nnode,
+                     Ainv);
   HIPCHK(hipGetLastError());
 }
 

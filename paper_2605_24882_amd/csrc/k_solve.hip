@@ -504,28 +504,31 @@ template void prolong_add<float>(const Level &, const Level &, float *, const fl
 
 // ------------------------------------------------------------------ coarse solve
 // z = (sigma M0 + S0)^-1 r on the coarsest level, in FP64 with the per-node inverse (built from the
-// Cholesky factor at plan setup): the owner copies of r are gathered into LDS (one lane per system),
-// and every copy of every unknown takes its row of the inverse times that vector; the four
-// wavefronts of the block share the rows.
-template <typename T>
+// Cholesky factor at plan setup): the owner copies of r are gathered into LDS (one lane per system;
+// read from memory instead when they do not fit), and every copy of every unknown takes its row of
+// the inverse times that vector; the four wavefronts of the block share the rows.
+template <typename T, bool STAGED>
 __global__ __launch_bounds__(256) void k_coarse(T *z, const T *r, const double *__restrict__ Ainv,
                                                 const int *__restrict__ node, int N0, const int *__restrict__ orow,
                                                 const int *__restrict__ rgid, int64_t R0, int ldb,
                                                 const int *__restrict__ active) {
-  extern __shared__ double sh[];  // right-hand sides [N0][64]
+  extern __shared__ double sh[];  // STAGED: right-hand sides [N0][64]
   const int ct = blockIdx.x;
   if (active && !active[ct]) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = ct * CT + lane;
-  for (int i = wave; i < N0; i += 4) sh[i * CT + lane] = (double)r[(int64_t)orow[i] * ldb + col];
-  __syncthreads();
+  if (STAGED) {
+    for (int i = wave; i < N0; i += 4) sh[i * CT + lane] = (double)r[(int64_t)orow[i] * ldb + col];
+    __syncthreads();
+  }
   const double *A = Ainv + (size_t)node[col] * N0 * N0;
   // every row of the level (each copy of an unknown) takes row g of A^-1 times the right-hand side
   for (int64_t rr = wave; rr < R0; rr += 4) {
     const int g = rgid[rr];
     if (g < 0) continue;
     double acc = 0.0;
-    for (int k = 0; k < N0; ++k) acc += A[(size_t)g * N0 + k] * sh[k * CT + lane];
+    for (int k = 0; k < N0; ++k)
+      acc += A[(size_t)g * N0 + k] * (STAGED ? sh[k * CT + lane] : (double)r[(int64_t)orow[k] * ldb + col]);
     z[rr * ldb + col] = (T)acc;
   }
 }
@@ -533,10 +536,14 @@ __global__ __launch_bounds__(256) void k_coarse(T *z, const T *r, const double *
 template <typename T>
 void coarse_solve(const Level &C, int N0, T *z, const T *r, const double *Ainv, const int *node, int ldb,
                   int ntiles, const int *active, hipStream_t s) {
+  // the right-hand sides of a column tile are staged in LDS when they fit, else read from memory
   const size_t shm = (size_t)N0 * CT * sizeof(double);
-  if (shm > 65536) fail(GF_EUNSUPPORTED, "coarsest level too large for the dense coarse solve; use a coarser level");
-  hipLaunchKernelGGL(k_coarse<T>, dim3(ntiles), dim3(256), shm, s, z, r, Ainv, node, N0, C.owner_row.p, C.row_gid.p,
-                     C.R, ldb, active);
+  if (shm <= 65536)
+    hipLaunchKernelGGL((k_coarse<T, true>), dim3(ntiles), dim3(256), shm, s, z, r, Ainv, node, N0, C.owner_row.p,
+                       C.row_gid.p, C.R, ldb, active);
+  else
+    hipLaunchKernelGGL((k_coarse<T, false>), dim3(ntiles), dim3(256), 0, s, z, r, Ainv, node, N0, C.owner_row.p,
+                       C.row_gid.p, C.R, ldb, active);
   HIPCHK(hipGetLastError());
 }
 template void coarse_solve<double>(const Level &, int, double *, const double *, const double *, const int *, int,

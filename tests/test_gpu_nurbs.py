@@ -172,3 +172,16 @@ def test_open_surface_parity(ctx, name, p, j):
     for prec in (0, 1):
         u, st = sp.sample(2.0, 1.3, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13)
         assert mrel(d, u, ref) <= 1e-10, prec
+
+
+@pytest.mark.parametrize("p,j,lc", [(3, 2, -1), (2, 3, 1)])
+def test_torus_large_coarse_level(ctx, geo, p, j, lc):
+    """Coarsest levels whose right-hand sides do not fit the LDS of the coarse solve (144 unknowns on
+    the 16-patch torus: degree 3 at level 0, degree 2 at level 1) read them from memory."""
+    sp = g.Space(ctx, geo, p, j, lc)
+    d = disc(p, j)
+    b = noise.load(d, inputs.noise_vectors([9], sp.noise_length))
+    ref = fractional.sample(d.M, d.S, 3.0, 1.6, 0.4, 10, 10, b)
+    for prec in (0, 1):
+        u, st = sp.sample(3.0, 1.6, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13)
+        assert mrel(d, u, ref) <= 1e-10, prec
