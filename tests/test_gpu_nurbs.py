@@ -185,3 +185,42 @@ def test_torus_large_coarse_level(ctx, geo, p, j, lc):
     for prec in (0, 1):
         u, st = sp.sample(3.0, 1.6, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13)
         assert mrel(d, u, ref) <= 1e-10, prec
+
+
+def test_torus_improved_split_bpx_sqrt_mass_and_gradient(ctx, geo):
+    """The rows built on the solver, on the NURBS torus (p = 2, 4 x 4 elements per patch): the
+    improved split, the BPX preconditioner, the sqrt(M) load and d loss / d kappa, each against the
+    oracle."""
+    import scipy.sparse as sps
+    from oracle import gradient, sqrt_mass
+    sp, d = space(ctx, geo, 2, 2), disc(2, 2)
+    b = noise.load(d, inputs.noise_vectors([3, 4], sp.noise_length))
+    # improved split: beta = 2.3 -> 1 integer solve + the rule for 0.65 twice
+    u, _ = sp.sample(3.0, 2.3, b, h=0.4, k_minus=10, k_plus=10, rtol=1e-13, split=g.GF_SPLIT_IMPROVED)
+    ref = fractional.sample(d.M, d.S, 3.0, 2.3, 0.4, 10, 10, b, mode="improved")
+    assert mrel(d, u, ref) <= 1e-10
+    # BPX, both precisions
+    ref = fractional.sample(d.M, d.S, 3.0, 1.6, 0.4, 10, 10, b)
+    for prec in (0, 1):
+        u, _ = sp.sample(3.0, 1.6, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13, max_iter=3000,
+                         preconditioner=g.GF_PRECOND_BPX)
+        assert mrel(d, u, ref) <= 1e-10, prec
+    # sqrt(M) y with the oracle's bounds
+    lo, hi = sqrt_mass.dense_bounds(d.M)
+    lo, hi = 0.99 * lo, 1.01 * hi
+    y = np.random.default_rng(21).standard_normal((2, d.N))
+    f, _ = sp.sqrt_mass(y, khat=12, lo=lo, hi=hi, rtol=1e-13)
+    fr = sqrt_mass.apply(d.M, y, 12, lo, hi)
+    assert np.abs(f - fr).max() <= 1e-10 * np.abs(fr).max()
+    # d loss / d kappa at 40 parameter points
+    rng = np.random.default_rng(22)
+    patch = rng.integers(0, NP, 40).astype(np.int32)
+    st = rng.random((40, 2))
+    yt = rng.standard_normal(40)
+    Phi = sps.csr_matrix(evaluate.phi_matrix(d, patch, st[:, 0], st[:, 1]))
+    kw = dict(h=0.4, k_minus=10, k_plus=10, rtol=1e-13)
+    u, tape, _ = sp.sample_tape(3.0, 1.6, b, **kw)
+    grad, _ = tape.grad_kappa(sp.eval_adjoint(patch, st, sp.eval(patch, st, u) - yt[None, :]))
+    tape.close()
+    gref, _ = gradient.adjoint(d.M, d.S, 3.0, 1.6, 0.4, 10, 10, b, Phi, yt)
+    assert np.abs(grad - gref).max() <= 1e-9 * np.abs(gref).max()
