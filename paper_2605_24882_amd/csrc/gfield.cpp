@@ -573,10 +573,18 @@ static double mass_interval_ratio(int p) {
   return 1.0 / (mpi * mpi);
 }
 constexpr int kPowerIters = 16;
-// Chebyshev smoothing steps before and after the coarse correction when the caller passes 0: three
-// gave the fewest seconds per sample on degrees 2 and 3 at 64x64 and 128x128 elements per patch
-// (two and four were within 5% for degree 2)
+// Chebyshev smoothing steps before and after the coarse correction when the caller passes 0, by the
+// size of the batch (columns x unknowns of the finest level).  A large batch is bound by memory
+// traffic, and three steps gave the fewest seconds per sample (degree 2, 64^2 elements per patch,
+// 2,624 systems: 962 samples/s against 873 with two and 914 with four; degree 3, 256^2, 1,952
+// systems: 59.6 against 57.7 and 55.3).  A small batch is bound by launch latency -- every CG
+// iteration is some seventy kernel launches -- and four steps, which cut the iterations, were faster
+// (degree 3, 64^2, 656 systems: 232 against 203 with three).  Batches solved together in one call
+// run as concurrent graph branches that share the GPU, each launch-latency bound: four steps for
+// all of them (the perturbed-sphere batch of 18 requests: 622 against 580 with three).
 constexpr int kDefaultCheb = 3;
+constexpr int kDefaultChebSmall = 4;
+constexpr double kSmallBatchWork = 4e7;
 constexpr double kChebTwoRows = 50000.0;
 
 static std::string plan_key(const std::vector<double> &sig) {
@@ -678,6 +686,7 @@ struct SolveSpec {
   // FP64, no multigrid plan (the shifted mass systems of the square root of M)
   bool mass_shift = false;
   int precond = GF_PRECOND_VCYCLE;
+  bool cheb_auto = false;  // the caller left the degree to the library (set by prepare from the size)
   // the load has already passed through the inverse operator (an order of at least 1.5 in powers of
   // A^-1): it has little high-frequency content, and the smoothing interval stays [b/8, b] on every
   // node
@@ -866,9 +875,12 @@ struct BatchSolve {
   bool mixed() const { return spec.prec == GF_PREC_MIXED; }
   double tol2() const { return spec.rtol * spec.rtol; }
 
+  int concurrent = 1;  // batches solved together in one call (their graph branches share the GPU)
   void prepare(hipStream_t s) {
     const Level &F = sp->fine();
     const int ldb = w->ldb;
+    if (spec.cheb_auto)
+      spec.cheb = ((double)spec.ncols * F.N < kSmallBatchWork || concurrent > 1) ? kDefaultChebSmall : kDefaultCheb;
     std::vector<double> sig(ldb, 1.0);
     std::vector<float> sigf(ldb, 1.0f);
     std::vector<int> node(ldb, 0);
@@ -1100,7 +1112,10 @@ static std::vector<hipStream_t> &side_streams(gf_context *ctx, size_t n) {
 // each launch; converged column tiles exit at the top of every kernel).
 static void solve_all(gf_context *ctx, std::vector<BatchSolve *> &items, bool use_graph) {
   hipStream_t s = ctx->stream;
-  for (auto *it : items) it->prepare(s);
+  for (auto *it : items) {
+    it->concurrent = (int)items.size();
+    it->prepare(s);
+  }
   for (auto *it : items) it->start(s);
   int max_iter = 0;
   for (auto *it : items) max_iter = std::max(max_iter, it->spec.max_iter);
@@ -1574,6 +1589,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
   base.prec = opts->precision;
   base.kind = opts->apply_kind;
   base.cheb = opts->cheb_degree > 0 ? opts->cheb_degree : kDefaultCheb;
+  base.cheb_auto = opts->cheb_degree <= 0;
   base.rtol = opts->rtol;
   base.max_iter = opts->max_iter;
   base.flags = opts->flags;
@@ -1802,6 +1818,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
   base.prec = t.opts.precision;
   base.kind = t.opts.apply_kind;
   base.cheb = t.opts.cheb_degree > 0 ? t.opts.cheb_degree : kDefaultCheb;
+  base.cheb_auto = t.opts.cheb_degree <= 0;
   base.rtol = t.opts.rtol;
   base.max_iter = t.opts.max_iter;
   base.flags = t.opts.flags;
@@ -2298,6 +2315,7 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     spec.prec = prec;
     spec.kind = mass ? GF_APPLY_STENCIL : opts->apply_kind;
     spec.cheb = opts->cheb_degree > 0 ? opts->cheb_degree : kDefaultCheb;
+    spec.cheb_auto = opts->cheb_degree <= 0;
     spec.rtol = opts->rtol;
     spec.max_iter = opts->max_iter;
     spec.flags = opts->flags;
