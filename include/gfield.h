@@ -98,10 +98,11 @@ gf_status gf_geometry_nurbs(gf_context *ctx, int32_t npatch, int32_t deg_u, int3
 int32_t gf_geometry_npatch(const gf_geometry *geom);
 void gf_geometry_destroy(gf_geometry *geom);
 
-/* Patch index and parameters of surface points, by the radial inverse of the maps above
- * (the coordinate of largest modulus picks the face).  xyz[npts][3], patch[npts],
- * st[npts][2], host arrays.  Sphere family only (GF_EUNSUPPORTED for NURBS geometries, whose
- * callers pass patch and parameters to gf_eval directly). */
+/* Patch index and parameters of points.  Sphere family: the radial inverse of the maps above
+ * (the coordinate of largest modulus picks the face).  NURBS geometries: the closest point of the
+ * surface (every patch sampled on a 17 x 17 parameter grid, the promising patches refined by
+ * Gauss-Newton steps on |F_m(s, t) - x|^2 within [0, 1]^2; the lower patch index on ties, as on
+ * shared edges).  xyz[npts][3], patch[npts], st[npts][2], host arrays; host work only. */
 gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, int32_t *patch, double *st);
 
 /* S^0_{level,degree} on the geometry (Sec. 2.3): 1 <= degree <= 5, 0 <= level <= 12.

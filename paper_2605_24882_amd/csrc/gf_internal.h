@@ -97,6 +97,10 @@ struct NurbsHost {
 // by comparing the boundary control points, weights and knots of the patches; coefficient rows
 // along matched edges are identified (same or reversed order), corners through the edges.
 void glue_patches_nurbs(const NurbsHost &g, int p, int lev, std::vector<int> &l2g, int &N);
+// surface point and parameter derivatives of patch m at (s, t), on the host
+void nurbs_eval(const NurbsHost &g, int m, double s, double t, double X[3], double Xs[3], double Xt[3]);
+// closest point of the surface to P: patch, parameters and distance
+void nurbs_locate(const NurbsHost &g, const double P[3], int *patch, double *s, double *t, double *dist);
 // Jacobi elliptic functions sn, cn, dn of parameter q in [0, 1) and the complete elliptic integral
 // of the first kind K(q)
 void jacobi_sncndn(double u, double q, double *sn, double *cn, double *dn);

@@ -1336,7 +1336,20 @@ void gf_geometry_destroy(gf_geometry *g) {
 gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, int32_t *patch, double *st) {
   return guarded([&] {
     if (!geom || (npts > 0 && (!xyz || !patch || !st)) || npts < 0) fail(GF_EINVAL, "bad arguments");
-    if (geom->kind != SURF_SPHERE) fail(GF_EUNSUPPORTED, "gf_locate is implemented for the sphere family only");
+    if (geom->kind == SURF_NURBS) {
+      for (int i = 0; i < npts; ++i) {
+        const double P[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+        if (!std::isfinite(P[0]) || !std::isfinite(P[1]) || !std::isfinite(P[2])) fail(GF_EINVAL, "point not finite");
+        double s = 0, t = 0, dist = 0;
+        int m = -1;
+        nurbs_locate(geom->nurbs, P, &m, &s, &t, &dist);
+        if (m < 0) fail(GF_EINVAL, "closest point not found (the surface evaluates to non-finite values)");
+        patch[i] = m;
+        st[2 * i] = s;
+        st[2 * i + 1] = t;
+      }
+      return;
+    }
     for (int i = 0; i < npts; ++i) {
       const double X[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
       int ax = 0;

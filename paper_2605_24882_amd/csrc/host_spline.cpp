@@ -300,6 +300,130 @@ void glue_patches_nurbs(const NurbsHost &g, int p, int lev, std::vector<int> &l2
   }
 }
 
+// ------------------------------------------------------------------ NURBS evaluation on the host
+namespace {
+// knot span of u among the n basis functions of degree d (u = 1 in the last non-empty span)
+int host_span(const double *U, int n, int d, double u) {
+  if (u >= U[n]) {
+    int i = n - 1;
+    while (i > d && U[i] >= U[i + 1]) --i;
+    return i;
+  }
+  int lo = d, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) / 2;
+    if (u < U[mid]) hi = mid;
+    else lo = mid;
+  }
+  return lo;
+}
+
+// values and first derivatives of the d+1 non-zero basis functions span-d .. span at u
+void host_basis(const double *U, int span, int d, double u, double *N, double *dN) {
+  double tri[5][5];
+  tri[0][0] = 1.0;
+  for (int k = 1; k <= d; ++k)
+    for (int j = 0; j <= k; ++j) {
+      const int i = span - k + j;
+      double v = 0.0;
+      if (j > 0 && U[i + k] > U[i]) v += (u - U[i]) / (U[i + k] - U[i]) * tri[k - 1][j - 1];
+      if (j < k && U[i + k + 1] > U[i + 1]) v += (U[i + k + 1] - u) / (U[i + k + 1] - U[i + 1]) * tri[k - 1][j];
+      tri[k][j] = v;
+    }
+  for (int j = 0; j <= d; ++j) {
+    N[j] = tri[d][j];
+    const int i = span - d + j;
+    double v = 0.0;
+    if (d > 0) {
+      if (j > 0 && U[i + d] > U[i]) v += d * tri[d - 1][j - 1] / (U[i + d] - U[i]);
+      if (j < d && U[i + d + 1] > U[i + 1]) v -= d * tri[d - 1][j] / (U[i + d + 1] - U[i + 1]);
+    }
+    dN[j] = v;
+  }
+}
+}  // namespace
+
+void nurbs_eval(const NurbsHost &g, int m, double s, double t, double X[3], double Xs[3], double Xt[3]) {
+  const int *pi = &g.pinfo[5 * (size_t)m];
+  const int ns = pi[0], nt = pi[1];
+  const double *U = &g.knots[pi[2]], *V = &g.knots[pi[3]], *C = &g.ctrl[4 * (size_t)pi[4]];
+  const int su = host_span(U, ns, g.du, s), sv = host_span(V, nt, g.dv, t);
+  double Nu[5], dNu[5], Nv[5], dNv[5];
+  host_basis(U, su, g.du, s, Nu, dNu);
+  host_basis(V, sv, g.dv, t, Nv, dNv);
+  double P[4] = {0, 0, 0, 0}, Ps[4] = {0, 0, 0, 0}, Pt[4] = {0, 0, 0, 0};
+  for (int b = 0; b <= g.dv; ++b)
+    for (int a = 0; a <= g.du; ++a) {
+      const double *c = C + 4 * ((size_t)(sv - g.dv + b) * ns + (su - g.du + a));
+      const double h[4] = {c[0] * c[3], c[1] * c[3], c[2] * c[3], c[3]};
+      for (int k = 0; k < 4; ++k) {
+        P[k] += Nu[a] * Nv[b] * h[k];
+        Ps[k] += dNu[a] * Nv[b] * h[k];
+        Pt[k] += Nu[a] * dNv[b] * h[k];
+      }
+    }
+  for (int k = 0; k < 3; ++k) {
+    X[k] = P[k] / P[3];
+    Xs[k] = (Ps[k] - X[k] * Ps[3]) / P[3];
+    Xt[k] = (Pt[k] - X[k] * Pt[3]) / P[3];
+  }
+}
+
+// Closest point on the NURBS surface: every patch is sampled on a grid of parameters, the patches
+// whose best sample lies within twice the best distance (plus a margin) are refined by Gauss-Newton
+// steps on |F_m(s, t) - P|^2 with (s, t) kept in [0, 1]^2, and the closest result wins (the lower
+// patch index on ties, as on shared edges).
+void nurbs_locate(const NurbsHost &g, const double P[3], int *patch, double *s_out, double *t_out, double *dist) {
+  constexpr int G = 17;
+  std::vector<double> best(g.npatch, 1e300), bs(g.npatch), bt(g.npatch);
+  double X[3], Xs[3], Xt[3];
+  for (int m = 0; m < g.npatch; ++m)
+    for (int a = 0; a < G; ++a)
+      for (int b = 0; b < G; ++b) {
+        const double s = a / (G - 1.0), t = b / (G - 1.0);
+        nurbs_eval(g, m, s, t, X, Xs, Xt);
+        const double d2 = (X[0] - P[0]) * (X[0] - P[0]) + (X[1] - P[1]) * (X[1] - P[1]) + (X[2] - P[2]) * (X[2] - P[2]);
+        if (d2 < best[m]) {
+          best[m] = d2;
+          bs[m] = s;
+          bt[m] = t;
+        }
+      }
+  const double gbest = *std::min_element(best.begin(), best.end());
+  double win = 1e300;
+  *patch = -1;
+  for (int m = 0; m < g.npatch; ++m) {
+    if (std::sqrt(best[m]) > 2.0 * std::sqrt(gbest) + 1e-3 * (1.0 + std::sqrt(gbest))) continue;
+    double s = bs[m], t = bt[m];
+    for (int it = 0; it < 60; ++it) {
+      nurbs_eval(g, m, s, t, X, Xs, Xt);
+      const double r[3] = {X[0] - P[0], X[1] - P[1], X[2] - P[2]};
+      const double a11 = Xs[0] * Xs[0] + Xs[1] * Xs[1] + Xs[2] * Xs[2];
+      const double a12 = Xs[0] * Xt[0] + Xs[1] * Xt[1] + Xs[2] * Xt[2];
+      const double a22 = Xt[0] * Xt[0] + Xt[1] * Xt[1] + Xt[2] * Xt[2];
+      const double g1 = Xs[0] * r[0] + Xs[1] * r[1] + Xs[2] * r[2];
+      const double g2 = Xt[0] * r[0] + Xt[1] * r[1] + Xt[2] * r[2];
+      const double det = a11 * a22 - a12 * a12;
+      if (!(det > 0.0)) break;
+      const double ds = -(a22 * g1 - a12 * g2) / det, dt = -(a11 * g2 - a12 * g1) / det;
+      const double sn = std::min(1.0, std::max(0.0, s + ds)), tn = std::min(1.0, std::max(0.0, t + dt));
+      const double step = std::fabs(sn - s) + std::fabs(tn - t);
+      s = sn;
+      t = tn;
+      if (step < 1e-15) break;
+    }
+    nurbs_eval(g, m, s, t, X, Xs, Xt);
+    const double d2 = (X[0] - P[0]) * (X[0] - P[0]) + (X[1] - P[1]) * (X[1] - P[1]) + (X[2] - P[2]) * (X[2] - P[2]);
+    if (d2 < win * (1.0 - 1e-12) - 1e-300) {
+      win = d2;
+      *patch = m;
+      *s_out = s;
+      *t_out = t;
+    }
+  }
+  *dist = std::sqrt(win);
+}
+
 // Jacobi elliptic functions by the arithmetic-geometric mean and the descending recurrence of the
 // amplitude (Abramowitz & Stegun, Sec. 16.4): with a_0 = 1, b_0 = sqrt(1-q), c_0 = sqrt(q),
 // a_n = (a_{n-1}+b_{n-1})/2, b_n = sqrt(a_{n-1} b_{n-1}), c_n = (a_{n-1}-b_{n-1})/2 until c_N is

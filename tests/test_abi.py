@@ -116,3 +116,32 @@ def test_nurbs_geometry_accepts_the_torus_and_validates_input():
     deg = cp.copy()
     deg[0, 0, :, :3] = deg[0, 0, 0, :3]
     assert status(du, dv, nc, kn, deg) == g.GF_EUNSUPPORTED
+
+
+def test_nurbs_locate_recovers_parameters():
+    """gf_locate on the NURBS torus (host work only): points made by the oracle's map from random
+    (patch, s, t) are found again -- the same patch and parameters away from patch edges, and a
+    parameter pair whose image is the point everywhere -- and a point off the surface goes to its
+    closest point."""
+    from oracle import geometry
+    from paper_2605_24882_amd import inputs
+    args = inputs.torus_patches(2.0, 1.0)
+    surf = geometry.NurbsSurface(*args)
+    geo = g.Geometry.nurbs(None, *args)
+    rng = np.random.default_rng(31)
+    m = rng.integers(0, 16, 200)
+    st = rng.uniform(0.02, 0.98, (200, 2))
+    pts = np.stack([geometry.patch_map(int(mi), s[0], s[1], surf) for mi, s in zip(m, st)])
+    patch, st2 = geo.locate(pts)
+    assert np.array_equal(patch, m)
+    assert np.abs(st2 - st).max() <= 1e-10
+    # corners and edges: any (patch, s, t) whose image is the point
+    edge = np.array([[0.0, 0.0], [1.0, 0.5], [0.5, 1.0], [1.0, 1.0]])
+    pts = np.stack([geometry.patch_map(5, s[0], s[1], surf) for s in edge])
+    patch, st2 = geo.locate(pts)
+    back = np.stack([geometry.patch_map(int(pi), s[0], s[1], surf) for pi, s in zip(patch, st2)])
+    assert np.abs(back - pts).max() <= 1e-12
+    # off the surface: (3.5, 0, 0) is 0.5 outside the outer equator
+    patch, st2 = geo.locate(np.array([[3.5, 0.0, 0.0]]))
+    x = geometry.patch_map(int(patch[0]), st2[0, 0], st2[0, 1], surf)
+    assert np.abs(x - np.array([3.0, 0.0, 0.0])).max() <= 1e-10

@@ -115,12 +115,6 @@ def test_torus_eval_matches_oracle(ctx, geo):
     assert np.abs(vals - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-def test_torus_locate_is_unsupported(geo):
-    with pytest.raises(g.GfieldError) as e:
-        geo.locate(np.array([[3.0, 0.0, 0.0]]))
-    assert e.value.status == g.GF_EUNSUPPORTED
-
-
 def test_torus_constant_load_closed_form_at_size(ctx, geo):
     """p = 2, 64 x 64 elements per patch (16 patches, 67,600 unknowns): u = kappa^-2n Q(kappa^2) 1."""
     import torch
