@@ -239,6 +239,27 @@ def one_at_a_time(g, sp, b, cfg, kw, nodes_timed=6):
                        f"node systems at {node * 1e3:.1f} ms on average")}
 
 
+def stream_probe(torch, mib=1024, reps=10):
+    """Achieved bandwidth of a plain streaming kernel on this GPU (dst = -src over `mib` MiB of FP64:
+    reads and writes that many bytes), as context for the roofline fraction of the stencil kernels."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    gbs = 2.0 * n * 8 / (us * 1e-6) / 1e9
+    del src, dst
+    return {"kernel": f"dst = -src, {mib} MiB FP64 each way", "avg_launch_us": round(us, 2),
+            "achieved": round(gbs, 1), "unit": "GB/s", "frac_of_peak": round(gbs / 8000.0, 4)}
+
+
 def cpu_baseline(cfg, nodes_timed=6):
     """The oracle (sparse LU, FP64, one thread) on the first load of the workload.
 
@@ -500,6 +521,7 @@ def main():
                    "space_setup_s": round(space_s, 3)},
         "roofline": roof,
         "roofline_outer_operator": roof_outer,
+        "stream_probe": stream_probe(torch),
     }
     if (args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_one_at_a_time
             and args.load == "factor"):
