@@ -39,12 +39,13 @@ CONFIGS = {
     "c1": (False, 2, 2, 4.0, 0.75, 0.4, 15, 1, 0, 1e-13),
     "c5": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-6),
     "c4": (False, 3, 6, 8.0, 0.8, 0.4, 20, 16, 1, 1e-6),
+    "c5-grad": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-6),
     # NURBS multi-patch surface: the 4 x 4 patch torus R = 2, r = 1 (biquadratic rational Bezier
     # patches, four at every corner), 32 x 32 elements per patch
     "torus": ("torus", 2, 5, 10.0, 1.6, 0.4, 20, 64, 0, 1e-10),
 }
 # configs whose step also computes d loss / d kappa by the adjoint (loss over 1000 seeded points)
-GRADIENT_CONFIGS = {"c4"}
+GRADIENT_CONFIGS = {"c4", "c5-grad"}
 
 
 # several sampling requests solved together (one call of the batched sampler per step): every
