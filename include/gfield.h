@@ -279,10 +279,11 @@ gf_status gf_sqrt_mass(gf_space *space, int32_t nsamp, const double *y, double *
  * not depend on kappa, sigma_k = kappa^2 + t_k).
  *
  * gf_sample_tape: gf_sample that also returns a tape holding the solutions the adjoint needs (the
- * node solutions x_{k,s} and the integer-chain solutions w_{i,s}: about (K + floor(beta)) x nsamp x N
- * doubles of device memory).  *tape is set only on GF_OK (NULL otherwise).  The tape refers to its
- * space: destroy the tape before the space.  GF_EUNSUPPORTED for a rule applied twice (improved
- * split). */
+ * node solutions x_{k,s} of every pass of the rule and the integer-chain solutions w_{i,s}: about
+ * (passes K + n) x nsamp x N doubles of device memory).  *tape is set only on GF_OK (NULL otherwise).
+ * The tape refers to its space: destroy the tape before the space.  With the improved split the
+ * adjoint runs the two passes backwards: the last takes dL/du, the first M times the weighted sum of
+ * the last pass's adjoint solutions. */
 gf_status gf_sample_tape(gf_space *space, double kappa, double beta, const gf_quad_rule *rule,
                          const gf_solve_opts *opts, int32_t nsamp, const double *b, double *u, int32_t mem,
                          gf_tape **tape, gf_solve_stats *stats);

@@ -331,7 +331,8 @@ struct gf_tape {
   int nsamp = 0, n = 0, ldc = 0, ldf = 0;
   double bf = 0;
   std::vector<double> node_sig, omega;
-  gf::DBuf<double> xk;                  // [R][ldf] node solutions, column k*nsamp + s
+  int passes = 1;                       // applications of the rule (2 for an improved split)
+  std::vector<gf::DBuf<double>> xk;     // per pass: [R][ldf] node solutions, column k*nsamp + s
   std::vector<gf::DBuf<double>> w;      // w[i-1]: [R][ldc] chain solution w_i
 };
 
@@ -1765,8 +1766,9 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
       const Level &F = it.sp->fine();
       if (it.tape) {
         const size_t nx = (size_t)F.R * it.wf->ldb;
-        it.tape->xk.alloc(nx);
-        HIPCHK(hipMemcpyAsync(it.tape->xk.p, it.wf->x.p, nx * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if ((int)it.tape->xk.size() < it.passes) it.tape->xk.resize(it.passes);
+        it.tape->xk[pass].alloc(nx);
+        HIPCHK(hipMemcpyAsync(it.tape->xk[pass].p, it.wf->x.p, nx * sizeof(double), hipMemcpyDeviceToDevice, s));
       }
       DBuf<double> om;
       om.upload(it.omega, s);
@@ -1876,45 +1878,57 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
   };
   Workspace *wc = t.n > 0 ? &get_workspace(sp, t.ldc, base.prec, 0) : nullptr;
   if (t.bf > 0.0) {
+    // the passes of the rule backwards: the last pass takes dL/du; each earlier pass takes M times
+    // the weighted sum mu of the later pass's adjoint solutions
     Workspace &wf = get_workspace(sp, t.ldf, base.prec, 1000);
-    DBuf<double> gloc;
+    DBuf<double> gloc, mloc, mu, om;
     gloc.alloc((size_t)F.R * t.ldc);
-    global_to_local(F, gloc.p, gin.p, nsamp, t.ldc, s);
-    replicate_cols(F, wf.r.p, t.ldf, gloc.p, t.ldc, nsamp, K, s);
-    BatchSolve b;
-    b.sp = sp;
-    b.w = &wf;
-    b.spec = base;
-    b.spec.ncols = K * nsamp;
-    b.spec.col_sig.resize(b.spec.ncols);
-    b.spec.col_node.resize(b.spec.ncols);
-    for (int k = 0; k < K; ++k)
-      for (int sm = 0; sm < nsamp; ++sm) {
-        b.spec.col_sig[k * nsamp + sm] = t.node_sig[k];
-        b.spec.col_node[k * nsamp + sm] = k;
-      }
-    b.spec.plan = frac_plan;
-    std::vector<BatchSolve *> ptrs{&b};
-    solve_all(ctx, ptrs, use_graph);
-    account(b);
-    // lambda^T M x per column, then the omega-weighted sum over nodes
-    Scratch sc = wf.scratch();
-    apply_level<double>(F, GF_APPLY_STENCIL, t.xk.p, wf.q.p, wf.one64.p, wf.zero64.p, t.ldf, t.ldf / CT, nullptr, s);
-    reduce_dot<double, double>(F, wf.x.p, wf.q.p, sc, t.ldf, t.ldf / CT, nullptr, nullptr, OP_STORE, 0.0, 0, dots.p,
-                               s);
-    DBuf<double> om;
+    mu.alloc((size_t)nsamp * F.N);
     om.upload(t.omega, s);
-    grad_accum(dots.p, om.p, K, nsamp, acc.p, s);
-    if (t.n > 0) {
-      // mu = sum_k omega_k lambda_k (global numbering), then the chain right-hand side M mu
-      DBuf<double> mu;
-      mu.alloc((size_t)nsamp * F.N);
-      quadrature_sum(F, mu.p, wf.x.p, om.p, K, nsamp, t.ldf, s);
-      global_to_local(F, gloc.p, mu.p, nsamp, t.ldc, s);
-      apply_level<double>(F, GF_APPLY_STENCIL, gloc.p, wc->r.p, wc->one64.p, wc->zero64.p, t.ldc, t.ldc / CT,
+    global_to_local(F, gloc.p, gin.p, nsamp, t.ldc, s);
+    const double *load = gloc.p;
+    for (int pass = t.passes - 1; pass >= 0; --pass) {
+      replicate_cols(F, wf.r.p, t.ldf, load, t.ldc, nsamp, K, s);
+      BatchSolve b;
+      b.sp = sp;
+      b.w = &wf;
+      b.spec = base;
+      b.spec.ncols = K * nsamp;
+      b.spec.col_sig.resize(b.spec.ncols);
+      b.spec.col_node.resize(b.spec.ncols);
+      for (int k = 0; k < K; ++k)
+        for (int sm = 0; sm < nsamp; ++sm) {
+          b.spec.col_sig[k * nsamp + sm] = t.node_sig[k];
+          b.spec.col_node[k * nsamp + sm] = k;
+        }
+      b.spec.plan = frac_plan;
+      std::vector<BatchSolve *> ptrs{&b};
+      solve_all(ctx, ptrs, use_graph);
+      account(b);
+      // lambda^T M x per column, then the omega-weighted sum over nodes
+      Scratch sc = wf.scratch();
+      apply_level<double>(F, GF_APPLY_STENCIL, t.xk[pass].p, wf.q.p, wf.one64.p, wf.zero64.p, t.ldf, t.ldf / CT,
                           nullptr, s);
+      reduce_dot<double, double>(F, wf.x.p, wf.q.p, sc, t.ldf, t.ldf / CT, nullptr, nullptr, OP_STORE, 0.0, 0, dots.p,
+                                 s);
+      grad_accum(dots.p, om.p, K, nsamp, acc.p, s);
+      if (pass > 0 || t.n > 0) {
+        // mu = sum_k omega_k lambda_k (global numbering), then M mu: the load of the earlier pass or
+        // of the chain
+        quadrature_sum(F, mu.p, wf.x.p, om.p, K, nsamp, t.ldf, s);
+        global_to_local(F, gloc.p, mu.p, nsamp, t.ldc, s);
+        if (pass > 0) {
+          mloc.alloc((size_t)F.R * t.ldc);
+          apply_level<double>(F, GF_APPLY_STENCIL, gloc.p, mloc.p, wf.one64.p, wf.zero64.p, t.ldc, t.ldc / CT,
+                              nullptr, s);
+          load = mloc.p;
+        } else {
+          apply_level<double>(F, GF_APPLY_STENCIL, gloc.p, wc->r.p, wc->one64.p, wc->zero64.p, t.ldc, t.ldc / CT,
+                              nullptr, s);
+        }
+      }
     }
-    HIPCHK(hipStreamSynchronize(s));  // before gloc, mu and om are released
+    HIPCHK(hipStreamSynchronize(s));  // before gloc, mloc, mu and om are released
   } else {
     global_to_local(F, wc->r.p, gin.p, nsamp, t.ldc, s);
   }
@@ -2384,11 +2398,7 @@ gf_status gf_sample_tape(gf_space *sp, double kappa, double beta, const gf_quad_
     t->rule = *rule;
     t->opts = *opts;
     t->nsamp = nsamp;
-    int passes = 1;
-    split_beta(beta, rule->split, &t->n, &t->bf, &passes);
-    if (passes != 1)
-      fail(GF_EUNSUPPORTED, "the adjoint is implemented for one pass of the rule (plain split, or an improved "
-                            "split that reduces to it)");
+    split_beta(beta, rule->split, &t->n, &t->bf, &t->passes);
     t->ldc = round_up(nsamp, CT);
     t->ldf = round_up(K * nsamp, CT);
     t->w.resize(t->n);

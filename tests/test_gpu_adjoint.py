@@ -181,3 +181,27 @@ def setup_space_only(ctx, p, j, pert=False):
         geo = g.Geometry(ctx, pert)
         _cache[key] = (geo, g.Space(ctx, geo, p, j), None)
     return _cache[key]
+
+
+@pytest.mark.parametrize("beta", [0.8, 2.3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_grad_kappa_improved_split_matches_oracle(ctx, beta, prec):
+    """The improved split applies the rule twice (beta' > 2/3 at 0.8, beta' < 1/3 at 2.3): the
+    adjoint through both passes against the oracle's two-pass adjoint."""
+    kappa, K = 8.0, 12
+    p, j = 3, 2
+    sp = g.Space(ctx, g.Geometry(ctx, False), p, j)
+    d = assembly.Discretisation(p, j)
+    b = noise.load(d, inputs.noise_vectors([0, 1, 2], inputs.noise_length(p, j)))
+    pts, y = inputs.sphere_points_and_targets(120, seed=7)
+    patch, st = sp.geom.locate(pts)
+    Phi = evaluate.phi_matrix(d, patch, st[:, 0], st[:, 1])
+    u, tape, _ = sp.sample_tape(kappa, beta, b, h=0.4, k_minus=K, k_plus=K, precision=prec, rtol=1e-13,
+                                split=g.GF_SPLIT_IMPROVED)
+    grad, stats = tape.grad_kappa(sp.eval_adjoint(patch, st, sp.eval(patch, st, u) - y[None, :]))
+    tape.close()
+    ref, u_ref = gradient.adjoint_two_pass(d.M, d.S, kappa, beta, 0.4, K, K, b, Phi, y)
+    assert np.abs(u - u_ref).max() <= 1e-10 * np.abs(u_ref).max()
+    assert np.abs(grad - ref).max() <= 1e-9 * np.abs(ref).max(), (grad, ref)
+    n = {0.8: 0, 2.3: 1}[beta]
+    assert stats["n_systems"] == 3 * (2 * (2 * K + 1) + n)

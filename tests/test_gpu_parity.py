@@ -269,7 +269,7 @@ def test_improved_split_matches_oracle(ctx, beta, prec):
         assert np.array_equal(u, u1)
 
 
-def test_improved_split_in_a_batch_and_tape_refusal(ctx):
+def test_improved_split_in_a_batch(ctx):
     sps = [space(ctx, 2, 2, True), space(ctx, 3, 2, True)]
     ds = [disc(2, 2, True), disc(3, 2, True)]
     reqs, refs = [], []
@@ -281,9 +281,6 @@ def test_improved_split_in_a_batch_and_tape_refusal(ctx):
     us, _ = g.sample_batch(ctx, reqs, rtol=1e-13)
     for d_, u, ref in zip(ds, us, refs):
         assert mrel(d_, u, ref) <= 1e-10
-    with pytest.raises(g.GfieldError) as e:
-        sps[0].sample_tape(4.0, 2.2, reqs[0]["b"], k_minus=10, k_plus=10, split=g.GF_SPLIT_IMPROVED)
-    assert e.value.status == g.GF_EUNSUPPORTED
 
 
 def test_edge_cases(ctx):
