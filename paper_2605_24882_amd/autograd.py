@@ -43,10 +43,12 @@ class EvaluateField(torch.autograd.Function):
 
 
 def sample_field(kappa, b, space, beta, h=0.4, k_minus=20, k_plus=20, precision=g.GF_PREC_FP64, rtol=1e-10,
-                 max_iter=500, cheb_degree=0, apply_kind=g.GF_APPLY_STENCIL):
-    """Field samples u(kappa) for loads b (nsamp, N) on the GPU, differentiable in kappa."""
+                 max_iter=500, cheb_degree=0, apply_kind=g.GF_APPLY_STENCIL, split=g.GF_SPLIT_PLAIN,
+                 preconditioner=g.GF_PRECOND_VCYCLE):
+    """Field samples u(kappa) for loads b (nsamp, N) on the GPU, differentiable in kappa (plain or
+    improved split)."""
     opts = dict(h=h, k_minus=k_minus, k_plus=k_plus, precision=precision, rtol=rtol, max_iter=max_iter,
-                cheb_degree=cheb_degree, apply_kind=apply_kind)
+                cheb_degree=cheb_degree, apply_kind=apply_kind, split=split, preconditioner=preconditioner)
     return SampleField.apply(kappa, b, space, beta, opts)
 
 
