@@ -218,3 +218,14 @@ def test_torus_improved_split_bpx_sqrt_mass_and_gradient(ctx, geo):
     tape.close()
     gref, _ = gradient.adjoint(d.M, d.S, 3.0, 1.6, 0.4, 10, 10, b, Phi, yt)
     assert np.abs(grad - gref).max() <= 1e-9 * np.abs(gref).max()
+
+
+def test_torus_workload_subset_matches_oracle(ctx, geo):
+    """The torus workload of bench.py at full size (p = 2, 32 x 32 elements per 16 patches, 17,424
+    unknowns, kappa = 10, beta = 1.6, 41 nodes): samples 0 and 1 of the 64 against the oracle."""
+    sp, d = space(ctx, geo, 2, 5), disc(2, 5)
+    assert sp.ndofs == 17424
+    b = noise.load(d, inputs.noise_vectors([0, 1], sp.noise_length))
+    u, st = sp.sample(10.0, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-12)
+    ref = fractional.sample(d.M, d.S, 10.0, 1.6, 0.4, 20, 20, b)
+    assert mrel(d, u, ref) <= 1e-10
