@@ -20,5 +20,7 @@ Modules
   fractional  split of beta, integer chain, node solves, quadrature sum (Sec. 3.4)
   noise       element-wise factorised white-noise load b ~ N(0, M) (Sec. 3.3)
   evaluate    point evaluation of a spline field on the surface
-  gradient    d loss / d kappa by adjoint solves, finite differences, eigen-expansion
+  gradient    d loss / d kappa by adjoint solves (one or two passes of the rule), finite
+              differences, eigen-expansion
+  sqrt_mass   the square root of the mass matrix applied to a vector (Sec. 3.3, eq. sqrt)
 """
