@@ -190,11 +190,16 @@ def trace_summary(trace_csv, p, top=25):
     for (k, g), v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
         lines.append(f"| {sum(v) / 1e3:.2f} | {100 * sum(v) / tot:.1f} | {len(v)} | {sum(v) / len(v):.2f} | `{k}` | {g[0]} |")
     d = {}
+    # the smoothing step runs in the V-cycle's precision (float in mixed mode), the outer operator in
+    # double
+    has_double_smoother = any(r["Kernel_Name"].startswith(f"void gf::k_apply_fused<double, {p}, ")
+                              and (", 1, 0>" in r["Kernel_Name"] or ", 1, 1>" in r["Kernel_Name"]) for r in rows)
     for kind in ("smoother", "outer"):
         ts = []
+        vt = "double" if kind == "outer" or has_double_smoother else "float"
         for r in rows:
             name = r["Kernel_Name"].split("(")[0]
-            if not name.startswith(f"void gf::k_apply_fused<double, {p}, "):
+            if not name.startswith(f"void gf::k_apply_fused<{vt}, {p}, "):
                 continue
             if (kind == "outer" and name.endswith(", 0, 1>")) or (kind == "smoother" and (", 1, 0>" in name or ", 1, 1>" in name)):
                 ts.append((int(r["Start_Timestamp"]), int(r["Grid_Size_X"]),
