@@ -269,8 +269,8 @@ struct Plan {
 };
 
 struct LevelWork {
-  DBuf<double> r64, z64a, z64b, d64, a64;  // V-cycle vectors (FP64 mode)
-  DBuf<float> r32, z32a, z32b, d32, a32;   // V-cycle vectors (mixed mode)
+  DBuf<double> r64, z64a, z64b, a64;  // V-cycle vectors (FP64 mode)
+  DBuf<float> r32, z32a, z32b, a32;   // V-cycle vectors (mixed mode)
   // Chebyshev coefficients per step and system, [2][deg][ldb]: c1 of step k at k ldb, c2 / b_max of
   // step k at (deg + k) ldb
   DBuf<double> cf64;
@@ -376,13 +376,11 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
       if (!finest) v.r64.alloc(n);
       v.z64a.alloc(n);
       v.z64b.alloc(n);
-      v.d64.alloc(n);
       v.a64.alloc(n);
     } else {
       v.r32.alloc(n);
       v.z32a.alloc(n);
       v.z32b.alloc(n);
-      v.d32.alloc(n);
       v.a32.alloc(n);
     }
   }
@@ -418,7 +416,6 @@ struct Prec<double> {
   static double *r(LevelWork &l) { return l.r64.p; }
   static double *za(LevelWork &l) { return l.z64a.p; }
   static double *zb(LevelWork &l) { return l.z64b.p; }
-  static double *d(LevelWork &l) { return l.d64.p; }
   static double *a(LevelWork &l) { return l.a64.p; }
   static const double *cf(LevelWork &l) { return l.cf64.p; }
   static double *sig(Workspace &w) { return w.sig64.p; }
@@ -433,7 +430,6 @@ struct Prec<float> {
   static float *r(LevelWork &l) { return l.r32.p; }
   static float *za(LevelWork &l) { return l.z32a.p; }
   static float *zb(LevelWork &l) { return l.z32b.p; }
-  static float *d(LevelWork &l) { return l.d32.p; }
   static float *a(LevelWork &l) { return l.a32.p; }
   static const float *cf(LevelWork &l) { return l.cf32.p; }
   static float *sig(Workspace &w) { return w.sig32.p; }
@@ -756,21 +752,21 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
     return za;
   }
   const T *r = rconv ? (const T *)rconv : (const T *)rsrc;
-  T *d = Prec<T>::d(lw), *a = Prec<T>::a(lw);
+  T *a = Prec<T>::a(lw);
   const T *cf = Prec<T>::cf(lw);
   const T *dM = Prec<T>::dM(L), *dS = Prec<T>::dS(L), *sig = Prec<T>::sig(w), *one = Prec<T>::one(w);
   Scratch sc = w.scratch();
   const int deg = level_degree(sp, spec.cheb, li);
-  // dflags: the first step after the start from zero takes its previous direction from the
-  // iterate itself (d = z after the first step); the last step of each sweep keeps no direction
-  // (the next sweep starts without one)
+  // Three-term recurrence: a step with a previous direction takes it as z - z_prev, z_prev being the
+  // iterate before its input, which the output buffer still holds (the two iterate buffers swap
+  // after every step); the first step after the start from zero takes it from the iterate itself
+  // (dflags bit 0)
   auto smooth = [&](int k, bool last, int dflags) {
     EpiArgs<T> e;
     e.kind = EPI_CHEB;
     e.dflags = dflags | (k > 0 ? 4 : 0);
     e.y = a;
     e.zout = zb;
-    e.d = d;
     e.r = r;
     e.dM = dM;
     e.dS = dS;
@@ -786,8 +782,8 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
     if (w.slog && li + 1 == sp->nlev()) {
       HIPCHK(hipEventCreate(&ev0));
       HIPCHK(hipEventCreate(&ev1));
-      // read z, r (and d), write z_out (and d)
-      const int vecs = 3 + ((k > 0 && !(dflags & 1)) ? 1 : 0) + ((dflags & 2) ? 0 : 1);
+      // read z, r (and z_prev), write z_out
+      const int vecs = 3 + ((k > 0 && !(dflags & 1)) ? 1 : 0);
       w.slog->entries.push_back({ev0, ev1, vecs, (int)sizeof(T), w.slog->first_phase});
     }
     apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, spec.rtol * spec.rtol, spec.max_iter, s,
@@ -804,8 +800,8 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
       fused_first = true;
     }
   }
-  if (!fused_first) cheb_first<T, TR>(L, rsrc, rconv, za, nullptr, dM, dS, sig, cf + (size_t)deg * ldb, ldb, nt, act, s);
-  for (int k = 1; k < deg; ++k) smooth(k, false, (k == 1 ? 1 : 0) | (k == deg - 1 ? 2 : 0));
+  if (!fused_first) cheb_first<T, TR>(L, rsrc, rconv, za, dM, dS, sig, cf + (size_t)deg * ldb, ldb, nt, act, s);
+  for (int k = 1; k < deg; ++k) smooth(k, false, k == 1 ? 1 : 0);
   // residual, restriction, coarse correction, prolongation
   {
     EpiArgs<T> e;
@@ -821,7 +817,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   T *zc = vcycle<T, T>(sp, w, spec, li - 1, rc, nullptr, -1, nullptr, s);
   prolong_add<T>(L, C, za, zc, ldb, nt, act, s);
   // post-smoothing
-  for (int k = 0; k < deg; ++k) smooth(k, k == deg - 1, k == deg - 1 ? 2 : 0);
+  for (int k = 0; k < deg; ++k) smooth(k, k == deg - 1, 0);
   return za;
 }
 

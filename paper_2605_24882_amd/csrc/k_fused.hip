@@ -5,9 +5,9 @@
 // product A z is never written to memory for unknowns inside a patch:
 //   EPI_STORE  y = A x                       (optionally the inner product x . y)
 //   EPI_RESID  y = r - A x                   (residual for the restriction)
-//   EPI_CHEB   Chebyshev-Jacobi step on D^-1 A: res = (r - A z)/D, d = c1 d + c2 res / b_max,
-//              with c1, c2 and b_max per system
-//              z_out = z + d                (optionally the inner product r . z_out)
+//   EPI_CHEB   Chebyshev-Jacobi step on D^-1 A in three-term form: res = (r - A z)/D,
+//              z_out = z + c1 (z - z_prev) + c2 res / b_max, with c1, c2 and b_max per system;
+//              z_out overwrites z_prev         (optionally the inner product r . z_out)
 // Unknowns on patch boundaries are shared with neighbouring patches: there the kernel stores its
 // patch contribution, and the interface kernel sums the copies and runs the same epilogue.
 //
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
                                                      const T *__restrict__ stS, const T *__restrict__ x,
                                                      const T *__restrict__ ca, const T *__restrict__ cb, const T *__restrict__ cf1,
                                                      const T *__restrict__ cf2,
-                                                     T *__restrict__ y, T *__restrict__ zout, T *__restrict__ d,
+                                                     T *__restrict__ y, T *__restrict__ zout,
                                                      const T *__restrict__ r, const T *__restrict__ dM,
                                                      const T *__restrict__ dS, double *__restrict__ partial, const int *__restrict__ active,
                                                      int dflags) {
@@ -173,10 +173,10 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
         } else {
           const T rv = r[i];
           const T D = sg * dM[row] + dS[row];
-          const T dp = (dflags & 4) ? ((dflags & 1) ? win[t + P][P] : d[i]) : T(0);
+          const T zc = win[t + P][P];
+          const T dp = (dflags & 4) ? ((dflags & 1) ? zc : zc - zout[i]) : T(0);
           const T dn = a1 * dp + a2 * ((rv - Az) / D);
-          if (!(dflags & 2)) d[i] = dn;
-          const T zo = win[t + P][P] + dn;
+          const T zo = zc + dn;
           zout[i] = zo;
           if (DOT) acc += (double)rv * (double)zo;
         }
@@ -220,10 +220,10 @@ __global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__re
         const T rv = e.r[i];
         const T D = e.sig[col] * e.dM[row] + e.dS[row];
         const T res = (rv - s) / D;
-        const T dp = (e.dflags & 4) ? ((e.dflags & 1) ? x[i] : e.d[i]) : T(0);
+        const T zc = x[i];
+        const T dp = (e.dflags & 4) ? ((e.dflags & 1) ? zc : zc - e.zout[i]) : T(0);
         const T dn = ((e.dflags & 4) ? e.cf1[col] : T(0)) * dp + e.cf2[col] * res;
-        if (!(e.dflags & 2)) e.d[i] = dn;
-        const T zo = x[i] + dn;
+        const T zo = zc + dn;
         e.zout[i] = zo;
         if (e.dot) a2 = (double)rv * (double)zo;
       }
@@ -280,12 +280,12 @@ static void launch_apply_k(const ApplyGeom &g, const T *stM, const T *stS, const
   if (ev0) {
     // the runtime stamps the events at the start and end of this dispatch itself
     hipExtLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM,
-                          stS, x, ca, cb, e.cf1, e.cf2, e.y, e.zout, e.d, e.r, e.dM, e.dS, partial, active,
+                          stS, x, ca, cb, e.cf1, e.cf2, e.y, e.zout, e.r, e.dM, e.dS, partial, active,
                           e.dflags);
     return;
   }
   hipLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca, cb,
-                     e.cf1, e.cf2, e.y, e.zout, e.d, e.r, e.dM, e.dS, partial, active, e.dflags);
+                     e.cf1, e.cf2, e.y, e.zout, e.r, e.dM, e.dS, partial, active, e.dflags);
 }
 
 template <typename T, int P, int TY>
@@ -480,11 +480,11 @@ __global__ __launch_bounds__(256) void k_update_p(RowGeom g, double *__restrict_
   }
 }
 
-// First Chebyshev step from z = 0: d = z = cf2 r / D (cf2 = c2 / b_max per system).  TR is the type of the incoming
+// First Chebyshev step from z = 0: z = cf2 r / D (cf2 = c2 / b_max per system).  TR is the type of the incoming
 // right-hand side; with r32 != null it is also stored in the V-cycle precision.
 template <typename T, typename TR>
 __global__ __launch_bounds__(256) void k_cheb_first(RowGeom g, const TR *__restrict__ r, T *__restrict__ r32,
-                                                    T *__restrict__ z, T *__restrict__ d, const T *__restrict__ dM,
+                                                    T *__restrict__ z, const T *__restrict__ dM,
                                                     const T *__restrict__ dS, const T *__restrict__ sig,
                                                     const T *__restrict__ cf2, const int *active) {
   const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
@@ -511,7 +511,6 @@ __global__ __launch_bounds__(256) void k_cheb_first(RowGeom g, const TR *__restr
       const int64_t i = row * ldb + col;
       const T v = sc * rv[u] / (sg * dM[row] + dS[row]);
       if (r32) r32[i] = rv[u];
-      if (d) d[i] = v;
       z[i] = v;
     }
   }
@@ -726,20 +725,20 @@ template void update_p2<float>(const Level &, double *, const float *, const Col
                                hipStream_t);
 
 template <typename T, typename TR>
-void cheb_first(const Level &L, const TR *r, T *r32, T *z, T *d, const T *dM, const T *dS, const T *sig,
+void cheb_first(const Level &L, const TR *r, T *r32, T *z, const T *dM, const T *dS, const T *sig,
                 const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s) {
   const RowGeom g = row_geom(L, ldb);
-  hipLaunchKernelGGL((k_cheb_first<T, TR>), dim3(g.nrb * ntiles), dim3(256), 0, s, g, r, r32, z, d, dM, dS, sig,
+  hipLaunchKernelGGL((k_cheb_first<T, TR>), dim3(g.nrb * ntiles), dim3(256), 0, s, g, r, r32, z, dM, dS, sig,
                      cf2, active);
   HIPCHK(hipGetLastError());
 }
-template void cheb_first<double, double>(const Level &, const double *, double *, double *, double *,
-                                         const double *, const double *, const double *, const double *, int, int,
-                                         const int *, hipStream_t);
-template void cheb_first<float, float>(const Level &, const float *, float *, float *, float *, const float *,
+template void cheb_first<double, double>(const Level &, const double *, double *, double *, const double *,
+                                         const double *, const double *, const double *, int, int, const int *,
+                                         hipStream_t);
+template void cheb_first<float, float>(const Level &, const float *, float *, float *, const float *,
                                        const float *, const float *, const float *, int, int, const int *,
                                        hipStream_t);
-template void cheb_first<float, double>(const Level &, const double *, float *, float *, float *, const float *,
+template void cheb_first<float, double>(const Level &, const double *, float *, float *, const float *,
                                         const float *, const float *, const float *, int, int, const int *,
                                         hipStream_t);
 
@@ -773,10 +772,10 @@ __global__ __launch_bounds__(256) void k_epi_rows(RowGeom g, const T *__restrict
       const T rv = e.r[i];
       const T D = e.sig[col] * e.dM[row] + e.dS[row];
       const T res = (rv - Az) / D;
-      const T dp = (e.dflags & 4) ? ((e.dflags & 1) ? x[i] : e.d[i]) : T(0);
+      const T zc = x[i];
+      const T dp = (e.dflags & 4) ? ((e.dflags & 1) ? zc : zc - e.zout[i]) : T(0);
       const T dn = ((e.dflags & 4) ? e.cf1[col] : T(0)) * dp + e.cf2[col] * res;
-      if (!(e.dflags & 2)) e.d[i] = dn;
-      const T zo = x[i] + dn;
+      const T zo = zc + dn;
       e.zout[i] = zo;
       if (e.dot) a2 = (double)rv * (double)zo;
     }

@@ -121,17 +121,17 @@ struct EpiArgs {
   int dot = 0;            // accumulate x.y (STORE) or r.z_out (CHEB); the interface kernel applies `op`
   int op = OP_STORE;
   T *y = nullptr;         // STORE: output; CHEB/RESID: patch contributions of shared rows; RESID: output
-  T *zout = nullptr;      // CHEB: new iterate (a different buffer than the input)
-  T *d = nullptr;         // CHEB: Chebyshev direction
+  // CHEB: new iterate, in a different buffer than the input; on entry that buffer holds the iterate
+  // before the input (read when the step takes its previous direction as their difference)
+  T *zout = nullptr;
   const T *r = nullptr;   // CHEB/RESID: right-hand side
   const T *dM = nullptr, *dS = nullptr, *sig = nullptr;
-  // CHEB: per-system recurrence coefficients of this step, d = cf1 d + cf2 (r - A z)/D (cf2 includes
-  // the reciprocal of the upper spectral bound)
+  // CHEB: per-system recurrence coefficients of this step, z_out = z + cf1 d + cf2 (r - A z)/D with the
+  // previous direction d = z - z_prev (cf2 includes the reciprocal of the upper spectral bound)
   const T *cf1 = nullptr, *cf2 = nullptr;
   // CHEB: bit 0 -- the previous direction equals the input iterate (first step after a start from
-  // zero), so it is taken from the input instead of d; bit 1 -- the new direction is not needed
-  // afterwards and is not stored; bit 2 -- the step has a previous direction (every step but the
-  // first of a sweep; cf1 is read only then)
+  // zero: z_prev = 0, zout is not read); bit 2 -- the step has a previous direction (every step but
+  // the first of a sweep; cf1 and z_prev are read only then)
   int dflags = 0;
 };
 
@@ -162,7 +162,7 @@ template <typename T>
 void epi_rows(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb,
               int ntiles, double tol2, int maxit, hipStream_t s);
 template <typename T, typename TR>
-void cheb_first(const Level &L, const TR *r, T *r32, T *z, T *d, const T *dM, const T *dS, const T *sig,
+void cheb_first(const Level &L, const TR *r, T *r32, T *z, const T *dM, const T *dS, const T *sig,
                 const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s);
 
 template <typename T>
