@@ -137,10 +137,13 @@ def pmc_summary(fetch_csv, write_csv, config, probe_mib):
     out = {"config": config, "kernel_source_sha256": source_sha(), "probe_mib": probe_mib}
     factors = {}
     for key, path in (("fetch", fetch_csv), ("write", write_csv)):
-        rows = list(csv.DictReader(open(path)))
-        probe = [float(r["Counter_Value"]) for r in rows if "neg_kernel" in r["Kernel_Name"]]
-        if not probe:
+        rows = [r for r in csv.DictReader(open(path)) if "neg_kernel" in r["Kernel_Name"]]
+        if not rows:
             raise SystemExit(f"{path}: no probe kernel dispatch")
+        # the copy probe runs before the workload; a later elementwise kernel of another size (the
+        # stream probe of a run without --copy-probe-mib) has another grid and is left out
+        first = min(rows, key=lambda r: int(r["Dispatch_Id"]))
+        probe = [float(r["Counter_Value"]) for r in rows if r["Grid_Size"] == first["Grid_Size"]]
         factors[key] = known_kib / (sum(probe) / len(probe))
         out[f"{key}_probe_kib"] = sum(probe) / len(probe)
         out[f"{key}_factor"] = round(factors[key], 4)
@@ -527,7 +530,9 @@ def main():
                    "space_setup_s": round(space_s, 3)},
         "roofline": roof,
         "roofline_outer_operator": roof_outer,
-        "stream_probe": stream_probe(torch),
+        # the counter runs (--copy-probe-mib) time no stream probe: their only elementwise kernel is
+        # the copy probe
+        "stream_probe": stream_probe(torch) if args.copy_probe_mib == 0 else None,
     }
     if (args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_one_at_a_time
             and args.load == "factor"):
