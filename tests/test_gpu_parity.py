@@ -360,3 +360,21 @@ def test_coarse_level_choice_matches_oracle(ctx, p, j, lc, prec):
     u, st = sp.sample(3.0, 1.4, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13, max_iter=1000)
     ref = _oracle_u(d, 3.0, 1.4, 0.4, 10, b)
     assert mrel(d, u, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("p,j,pert,prec", [(2, 4, False, 0), (3, 3, True, 1)])
+def test_chebyshev_degrees_match_oracle(ctx, p, j, pert, prec):
+    """Every smoothing degree gives the oracle's fields: degree 1 (no step after the first before the
+    coarse correction), 2 (only the step whose previous direction is the iterate itself), and 5 and 8
+    (steps whose previous direction is the difference of the two iterate buffers).  A higher degree
+    does not need more CG iterations than degree 1."""
+    sp, d = space(ctx, p, j, pert), disc(p, j, pert)
+    b = noise.load(d, inputs.noise_vectors([9, 10], inputs.noise_length(p, j)))
+    ref = _oracle_u(d, 3.0, 1.4, 0.4, 10, b)
+    iters = {}
+    for deg in (1, 2, 5, 8):
+        u, st = sp.sample(3.0, 1.4, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13, max_iter=1000,
+                          cheb_degree=deg)
+        assert mrel(d, u, ref) <= 1e-10, deg
+        iters[deg] = st["max_iters"]
+    assert iters[8] <= iters[5] <= iters[1], iters
