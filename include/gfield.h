@@ -159,8 +159,8 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * residuals, inner products), the coarsest-level dense solve, the metric terms and the
  * quadrature sum in float64.  rtol: stop a system when |r| <= rtol |b| (Euclidean, global unknowns).
  * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction on the finest
- * level (0: the library's choice per batch -- three when columns x unknowns exceed 4e7 and the batch
- * runs alone, where memory traffic binds; four for smaller batches and for requests of
+ * level (0: the library's choice per batch -- three when columns x unknowns exceed 5e7 and the batch
+ * runs alone, where memory traffic binds; five for smaller batches and for requests of
  * gf_sample_batch solved together, where launch latency binds and fewer iterations pay); the coarser levels
  * take one (two on levels of more than 50,000 patch coefficients), at most cheb_degree.  Each system smooths on [b ia, b] (b: 1.1 x a power estimate of the largest
  * eigenvalue of D^-1 A), ia between 1/8 and (m(pi)/m(0))^2 of the 1D B-spline mass symbol by the

@@ -573,15 +573,17 @@ constexpr int kPowerIters = 16;
 // Chebyshev smoothing steps before and after the coarse correction when the caller passes 0, by the
 // size of the batch (columns x unknowns of the finest level).  A large batch is bound by memory
 // traffic, and three steps gave the fewest seconds per sample (degree 2, 64^2 elements per patch,
-// 2,624 systems: 962 samples/s against 873 with two and 914 with four; degree 3, 256^2, 1,952
-// systems: 59.6 against 57.7 and 55.3).  A small batch is bound by launch latency -- every CG
-// iteration is some seventy kernel launches -- and four steps, which cut the iterations, were faster
-// (degree 3, 64^2, 656 systems: 232 against 203 with three).  Batches solved together in one call
-// run as concurrent graph branches that share the GPU, each launch-latency bound: four steps for
-// all of them (the perturbed-sphere batch of 18 requests: 622 against 580 with three).
+// 2,624 systems: 1016 samples/s against 981 with four and 987 with five; degree 3, 256^2, 1,952
+// systems: 63.6 against 60.1 with four).  A small batch is bound by launch latency -- every CG
+// iteration is some seventy kernel launches -- and five steps, which cut the iterations, were faster
+// (degree 3, 64^2, 656 systems: 258 against 241 with four and 208 with three; the torus of 16 NURBS
+// patches, 17,424 unknowns x 2,624 systems: 887 against 854 with three).  Batches solved together in
+// one call run as concurrent graph branches that share the GPU, each launch-latency bound: five steps
+// for all of them (the perturbed-sphere batch of 18 requests: 652-661 against 647-656 with four and
+// 630 with six).
 constexpr int kDefaultCheb = 3;
-constexpr int kDefaultChebSmall = 4;
-constexpr double kSmallBatchWork = 4e7;
+constexpr int kDefaultChebSmall = 5;
+constexpr double kSmallBatchWork = 5e7;
 constexpr double kChebTwoRows = 50000.0;
 
 static std::string plan_key(const std::vector<double> &sig) {
