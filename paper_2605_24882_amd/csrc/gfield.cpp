@@ -792,7 +792,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
                  ev0, ev1);
     std::swap(za, zb);
   };
-  // pre-smoothing from zero (the first step's direction is the iterate itself and is not stored); in
+  // pre-smoothing from zero (the second step's previous direction is the first iterate itself); in
   // an outer-CG iteration the finest level's first step also updates the residual and tests it
   bool fused_first = false;
   if constexpr (std::is_same<TR, double>::value) {
