@@ -130,10 +130,13 @@ def test_sample_eager_matches_graph(ctx):
     assert np.array_equal(u1, u2)
 
 
-def test_sample_sumfact_operator(ctx):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sample_sumfact_operator(ctx, prec):
+    """The whole solver through the matrix-free sum-factorised apply (its epilogue runs over the rows
+    after the interface sum), in FP64 and with the FP32 V-cycle."""
     sp, d = space(ctx, 3, 2), disc(3, 2)
     b = noise.load(d, inputs.noise_vectors([1], inputs.noise_length(3, 2)))
-    u, st = sp.sample(2.0, 0.6, b, h=0.4, k_minus=10, k_plus=10, rtol=1e-13, apply_kind=1)
+    u, st = sp.sample(2.0, 0.6, b, h=0.4, k_minus=10, k_plus=10, rtol=1e-13, apply_kind=1, precision=prec)
     ref = _oracle_u(d, 2.0, 0.6, 0.4, 10, b)
     assert mrel(d, u, ref) <= 1e-10
 
