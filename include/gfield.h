@@ -161,7 +161,8 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction on the finest
  * level (0: the library's choice per batch -- three when columns x unknowns exceed 5e7 and the batch
  * runs alone, where memory traffic binds; five for smaller batches and for requests of
- * gf_sample_batch solved together, where launch latency binds and fewer iterations pay); the coarser levels
+ * gf_sample_batch solved together, where launch latency binds and fewer iterations pay, and five for the
+ * first adjoint solve of gf_grad_kappa, whose load dL/du is rough); the coarser levels
  * take one (two on levels of more than 50,000 patch coefficients), at most cheb_degree.  Each system smooths on [b ia, b] (b: 1.1 x a power estimate of the largest
  * eigenvalue of D^-1 A), ia between 1/8 and (m(pi)/m(0))^2 of the 1D B-spline mass symbol by the
  * share sigma dM / (sigma dM + dS) of the mass term in the diagonal; loads that have passed through

@@ -690,6 +690,9 @@ struct SolveSpec {
   // A^-1): it has little high-frequency content, and the smoothing interval stays [b/8, b] on every
   // node
   bool smooth_load = false;
+  // the load is dL/du of a loss over point values (the first adjoint solve): rough, with much
+  // high-frequency content; the automatic degree is the higher one of small batches
+  bool rough_load = false;
 };
 
 struct SolveResult {
@@ -879,7 +882,8 @@ struct BatchSolve {
     const Level &F = sp->fine();
     const int ldb = w->ldb;
     if (spec.cheb_auto)
-      spec.cheb = ((double)spec.ncols * F.N < kSmallBatchWork || concurrent > 1) ? kDefaultChebSmall : kDefaultCheb;
+      spec.cheb = ((double)spec.ncols * F.N < kSmallBatchWork || concurrent > 1 || spec.rough_load) ? kDefaultChebSmall
+                                                                                                    : kDefaultCheb;
     std::vector<double> sig(ldb, 1.0);
     std::vector<float> sigf(ldb, 1.0f);
     std::vector<int> node(ldb, 0);
@@ -1900,6 +1904,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
           b.spec.col_node[k * nsamp + sm] = k;
         }
       b.spec.plan = frac_plan;
+      b.spec.rough_load = (pass == t.passes - 1);
       std::vector<BatchSolve *> ptrs{&b};
       solve_all(ctx, ptrs, use_graph);
       account(b);
@@ -1940,6 +1945,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
     b.spec.col_sig.assign(nsamp, t.kappa * t.kappa);
     b.spec.col_node.assign(nsamp, 0);
     b.spec.plan = chain_plan;
+    b.spec.rough_load = (t.bf == 0.0 && i == t.n);
     std::vector<BatchSolve *> ptrs{&b};
     solve_all(ctx, ptrs, use_graph);
     account(b);
