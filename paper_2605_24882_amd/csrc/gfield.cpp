@@ -262,8 +262,9 @@ static void build_coarse_dense(gf_space *sp) {
 struct Plan {
   std::vector<double> sig;                // distinct shifts (nodes)
   std::vector<std::vector<double>> invb;  // [level index][node] 1/(upper spectral bound of D^-1 A)
-  std::vector<std::vector<double>> ialpha;  // [level index][node] lower end / upper end of the
-                                            // smoothing interval
+  std::vector<std::vector<double>> mshare;  // [level index][node] share of the mass term in the
+                                            // diagonal, sigma dM / (sigma dM + dS) (level means)
+  double ia_mass = 0.0;                     // (m(pi)/m(0))^2 of the 1D B-spline mass symbol
   DBuf<double> Ainv;                      // [node][N0][N0] inverses of the coarse matrices
   double setup_ms = 0.0;
 };
@@ -615,8 +616,8 @@ static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
   out.alloc((size_t)2 * ldb);
   Scratch sc{partial.p, counter.p};
   pl->invb.assign(sp->nlev(), std::vector<double>(nn, 0.0));
-  pl->ialpha.assign(sp->nlev(), std::vector<double>(nn, 0.0));
-  const double ia_mass = 1.0 / mass_interval_ratio(sp->p);
+  pl->mshare.assign(sp->nlev(), std::vector<double>(nn, 0.0));
+  pl->ia_mass = 1.0 / mass_interval_ratio(sp->p);
   for (int li = 1; li < sp->nlev(); ++li) {
     const Level &L = *sp->lev[li];
     const size_t n = (size_t)L.R * ldb;
@@ -639,8 +640,7 @@ static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
       const double lam = ho[ldb + k] / ho[k];
       if (!(lam > 0.0) || !std::isfinite(lam)) fail(GF_EDEVICE, "spectral bound estimate failed");
       pl->invb[li][k] = 1.0 / (kChebSafety * lam);
-      const double rm = sig[k] * L.dM_mean / (sig[k] * L.dM_mean + L.dS_mean);
-      pl->ialpha[li][k] = (1.0 - rm) / kChebAlpha + rm * ia_mass;
+      pl->mshare[li][k] = sig[k] * L.dM_mean / (sig[k] * L.dM_mean + L.dS_mean);
     }
     v.release();
     w.release();
@@ -709,6 +709,22 @@ struct SolveResult {
 };
 
 // Chebyshev recurrence coefficients for interval [b ia, b], in units of 1/b
+// alpha of the stiffness-dominated nodes by the degree of the smoothing polynomial: a polynomial of
+// degree five or more damps a wider part of the spectrum, and [b/32, b] gave the fewest seconds per
+// sample (degree 3, 64^2 elements per patch, 656 systems: 276 samples/s against 259 with alpha = 8
+// and 283 / 267 with 48 / 64; the perturbed-sphere batch of 18 requests: 706 against 656; the
+// torus: 1076 against 885); for degrees up to four alpha = 8 stays (degree 2, 64^2, 2,624 systems
+// at degree four: 968 against 834 with 32; at degree three alpha = 16 gave 924 against 1023)
+constexpr double kChebAlphaWide = 32.0;
+constexpr int kChebWideFrom = 5;
+static double alpha_for_degree(int deg) { return deg >= kChebWideFrom ? kChebAlphaWide : kChebAlpha; }
+
+// lower end / upper end of the smoothing interval of node k on level li for a polynomial of degree deg
+static double interval_ia(const Plan &pl, int li, int k, int deg) {
+  const double rm = pl.mshare[li][k];
+  return (1.0 - rm) / alpha_for_degree(deg) + rm * pl.ia_mass;
+}
+
 static void cheb_coeffs(int deg, double ia, std::vector<double> &c1, std::vector<double> &c2) {
   const double theta = (1.0 + ia) / 2.0, delta = (1.0 - ia) / 2.0, sigma1 = theta / delta;
   c1.assign(deg, 0.0);
@@ -910,7 +926,7 @@ struct BatchSolve {
       std::vector<double> cf((size_t)2 * deg * ldb, 0.0), c1, c2;
       for (int c = 0; c < spec.ncols; ++c) {
         const int k = node[c];
-        cheb_coeffs(deg, spec.smooth_load ? 1.0 / kChebAlpha : spec.plan->ialpha[li][k], c1, c2);
+        cheb_coeffs(deg, spec.smooth_load ? 1.0 / kChebAlpha : interval_ia(*spec.plan, li, k, deg), c1, c2);
         for (int st = 0; st < deg; ++st) {
           cf[(size_t)st * ldb + c] = c1[st];
           cf[(size_t)(deg + st) * ldb + c] = c2[st] * spec.plan->invb[li][k];
