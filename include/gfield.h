@@ -160,10 +160,9 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * quadrature sum in float64.  rtol: stop a system when |r| <= rtol |b| (Euclidean, global unknowns).
  * cheb_degree: Chebyshev-Jacobi smoothing steps before and after the coarse correction on the finest
  * level (0: the library's choice per batch -- three when columns x unknowns exceed 5e7 and the batch
- * runs alone, where memory traffic binds; five for smaller batches and for requests of
- * gf_sample_batch solved together, where launch latency binds and fewer iterations pay, and five for the
- * first adjoint solve of gf_grad_kappa, whose load dL/du is rough); the coarser levels
- * take one (two on levels of more than 50,000 patch coefficients), at most cheb_degree.  Each system smooths on [b ia, b] (b: 1.1 x a power estimate of the largest
+ * runs alone, where memory traffic binds; nine for smaller batches, where launch latency binds and
+ * fewer iterations pay, and for the first adjoint solve of gf_grad_kappa, whose load dL/du is rough;
+ * seven for the requests of gf_sample_batch solved together); the coarser levels take one (two on levels of more than 50,000 patch coefficients), at most cheb_degree.  Each system smooths on [b ia, b] (b: 1.1 x a power estimate of the largest
  * eigenvalue of D^-1 A), ia between 1/8 (1/32 for five steps or more) and (m(pi)/m(0))^2 of the 1D B-spline mass symbol by the
  * share sigma dM / (sigma dM + dS) of the mass term in the diagonal; loads that have passed through
  * the inverse operator to an order of 1.5 or more keep 1/8.

@@ -574,16 +574,18 @@ constexpr int kPowerIters = 16;
 // Chebyshev smoothing steps before and after the coarse correction when the caller passes 0, by the
 // size of the batch (columns x unknowns of the finest level).  A large batch is bound by memory
 // traffic, and three steps gave the fewest seconds per sample (degree 2, 64^2 elements per patch,
-// 2,624 systems: 1016 samples/s against 981 with four and 987 with five; degree 3, 256^2, 1,952
-// systems: 63.6 against 60.1 with four).  A small batch is bound by launch latency -- every CG
-// iteration is some seventy kernel launches -- and five steps, which cut the iterations, were faster
-// (degree 3, 64^2, 656 systems: 258 against 241 with four and 208 with three; the torus of 16 NURBS
-// patches, 17,424 unknowns x 2,624 systems: 887 against 854 with three).  Batches solved together in
-// one call run as concurrent graph branches that share the GPU, each launch-latency bound: five steps
-// for all of them (the perturbed-sphere batch of 18 requests: 652-661 against 647-656 with four and
-// 630 with six).
+// 2,624 systems: 1016 samples/s against 981 with four, 874 with five and 881 with nine; degree 3,
+// 256^2, 1,952 systems: 66.5 against 60.1 with four and 56.7 with nine).  A small batch is bound by
+// launch latency -- every CG iteration is some seventy kernel launches -- and a high degree on the
+// wide interval of degrees five and up cuts the iterations (degree 3, 64^2, 656 systems: 340 with
+// nine steps against 320 with seven, 283 with five and 208 with three; the torus of 16 NURBS
+// patches, 17,424 unknowns x 2,624 systems: 1176 with nine against 1074 with five and 854 with
+// three).  Batches solved together in one call run as concurrent graph branches that share the GPU:
+// seven steps (the perturbed-sphere batch of 18 requests: 727-750 against 709 with five and 715 with
+// nine; in FP64 495 against 496 and 473).
 constexpr int kDefaultCheb = 3;
-constexpr int kDefaultChebSmall = 5;
+constexpr int kDefaultChebSmall = 9;
+constexpr int kDefaultChebConcurrent = 7;
 constexpr double kSmallBatchWork = 5e7;
 constexpr double kChebTwoRows = 50000.0;
 
@@ -898,8 +900,9 @@ struct BatchSolve {
     const Level &F = sp->fine();
     const int ldb = w->ldb;
     if (spec.cheb_auto)
-      spec.cheb = ((double)spec.ncols * F.N < kSmallBatchWork || concurrent > 1 || spec.rough_load) ? kDefaultChebSmall
-                                                                                                    : kDefaultCheb;
+      spec.cheb = concurrent > 1 ? kDefaultChebConcurrent
+                  : ((double)spec.ncols * F.N < kSmallBatchWork || spec.rough_load) ? kDefaultChebSmall
+                                                                                     : kDefaultCheb;
     std::vector<double> sig(ldb, 1.0);
     std::vector<float> sigf(ldb, 1.0f);
     std::vector<int> node(ldb, 0);
