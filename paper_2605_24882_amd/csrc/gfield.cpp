@@ -744,11 +744,15 @@ static void cheb_coeffs(int deg, double ia, std::vector<double> &c1, std::vector
 // smoothing degree of level li: spec.cheb on the finest level; below it, where each smoothing step is
 // cheap in bytes but a full round of launches, one step (two on levels with more than kChebTwoRows
 // patch rows).  Measured on the workloads of bench.py: the CG iteration count is set by the finest
-// level's smoothing, and fewer coarse steps save time.
-static int level_degree(const gf_space *sp, int cheb, int li) {
+// level's smoothing, and fewer coarse steps save time (degree 2, 64^2 elements per patch: 1017
+// samples/s against 962 with two steps on every level).  A smooth load (SolveSpec::smooth_load) leaves
+// an error made mostly of low frequencies, which the coarse levels carry: two steps on every level
+// there (degree 3, 256^2 elements, beta = 2.3: 71.6 samples/s against 65.2).
+static int level_degree(const gf_space *sp, const SolveSpec &spec, int li) {
   const Level &L = *sp->lev[li];
-  if (li + 1 < sp->nlev()) return std::min(cheb, ((double)L.npatch * L.n1 * L.n1 > kChebTwoRows) ? 2 : 1);
-  return cheb;
+  if (li + 1 < sp->nlev())
+    return std::min(spec.cheb, ((double)L.npatch * L.n1 * L.n1 > kChebTwoRows || spec.smooth_load) ? 2 : 1);
+  return spec.cheb;
 }
 
 // Multigrid V-cycle on level li for the assembled right-hand side rsrc (type TR; converted to T into
@@ -779,7 +783,7 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   const T *cf = Prec<T>::cf(lw);
   const T *dM = Prec<T>::dM(L), *dS = Prec<T>::dS(L), *sig = Prec<T>::sig(w), *one = Prec<T>::one(w);
   Scratch sc = w.scratch();
-  const int deg = level_degree(sp, spec.cheb, li);
+  const int deg = level_degree(sp, spec, li);
   // Three-term recurrence: a step with a previous direction takes it as z - z_prev, z_prev being the
   // iterate before its input, which the output buffer still holds (the two iterate buffers swap
   // after every step); the first step after the start from zero takes it from the iterate itself
@@ -925,7 +929,7 @@ struct BatchSolve {
     w->active.upload(w->active_h, s);
     // Chebyshev coefficients of every smoothing step per system (the interval depends on the node)
     for (int li = 1; li < sp->nlev() && !spec.mass_shift; ++li) {
-      const int deg = level_degree(sp, spec.cheb, li);
+      const int deg = level_degree(sp, spec, li);
       std::vector<double> cf((size_t)2 * deg * ldb, 0.0), c1, c2;
       for (int c = 0; c < spec.ncols; ++c) {
         const int k = node[c];
