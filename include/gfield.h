@@ -162,10 +162,13 @@ enum { GF_PREC_FP64 = 0, GF_PREC_MIXED = 1 };
  * level (0: the library's choice per batch -- three when columns x unknowns exceed 5e7 and the batch
  * runs alone, where memory traffic binds; nine for smaller batches, where launch latency binds and
  * fewer iterations pay, and for the first adjoint solve of gf_grad_kappa, whose load dL/du is rough;
- * seven for the requests of gf_sample_batch solved together); the coarser levels take one (two on levels of more than 50,000 patch coefficients), at most cheb_degree.  Each system smooths on [b ia, b] (b: 1.1 x a power estimate of the largest
- * eigenvalue of D^-1 A), ia between 1/8 (1/32 for five steps or more) and (m(pi)/m(0))^2 of the 1D B-spline mass symbol by the
- * share sigma dM / (sigma dM + dS) of the mass term in the diagonal; loads that have passed through
- * the inverse operator to an order of 1.5 or more keep 1/8.
+ * seven for the requests of gf_sample_batch solved together); the coarser levels take one (two on
+ * levels of more than 50,000 patch coefficients, and on every level for loads that have passed
+ * through the inverse operator to an order of 1.5 or more), at most cheb_degree.  Each system
+ * smooths on [b ia, b] (b: 1.1 x a power estimate of the largest eigenvalue of D^-1 A), ia between
+ * 1/8 (1/32 for five steps or more) and (m(pi)/m(0))^2 of the 1D B-spline mass symbol by the share
+ * sigma dM / (sigma dM + dS) of the mass term in the diagonal; loads that have passed through the
+ * inverse operator to an order of 1.5 or more keep 1/8.
  * apply_kind: GF_APPLY_STENCIL or GF_APPLY_SUMFACT for every operator application in the solver.
  * preconditioner (Sec. 3.5): GF_PRECOND_VCYCLE, the multiplicative V-cycle above, or GF_PRECOND_BPX,
  * the additive multilevel preconditioner sum_l P_l D_l^-1 P_l^T with D_l the diagonal of
