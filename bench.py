@@ -360,8 +360,8 @@ def main():
     if args.apply_shape:
         os.environ["GF_APPLY_SHAPE"] = args.apply_shape
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the sampler shards by "
-              f"sample with no communication, but this build measures one GPU)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (samples are independent: "
+              f"several GPUs would each solve their own samples, with no communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
