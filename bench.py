@@ -533,6 +533,11 @@ def main():
         # the counter runs (--copy-probe-mib) time no stream probe: their only elementwise kernel is
         # the copy probe
         "stream_probe": stream_probe(torch) if args.copy_probe_mib == 0 else None,
+        # the vector multiply-add rates the stencil kernels' ALU use is compared with (library probe:
+        # independent multiply-add chains, no memory traffic)
+        "fma_probe": ({"fp64": round(ctx.probe_fma(g.GF_PREC_FP64), 1), "fp32": round(ctx.probe_fma(g.GF_PREC_MIXED), 1),
+                       "unit": "TFLOP/s", "fp32_kind": "scalar FMA (no packed FP32 instructions)"}
+                      if args.copy_probe_mib == 0 else None),
     }
     if (args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_one_at_a_time
             and args.load == "factor"):

@@ -70,6 +70,14 @@ typedef struct gf_tape gf_tape;
 gf_status gf_context_create(int32_t device, void *hip_stream, gf_context **out);
 void gf_context_destroy(gf_context *ctx);
 
+/* Measurement support, not part of the method: the achieved rate of the vector ALU's fused
+ * multiply-add on the context's device, in TFLOP/s (2 flops per multiply-add), for precision
+ * GF_PREC_FP64 (float64) or GF_PREC_MIXED (float32, scalar instructions as in the library's
+ * kernels).  One kernel of independent multiply-add chains with no memory traffic, timed with
+ * events on the context's stream; synchronous, a few milliseconds.  *tflops is a host pointer.
+ * GF_EINVAL for a null argument or an unknown precision. */
+gf_status gf_probe_fma(gf_context *ctx, int32_t precision, double *tflops);
+
 /* The closed surface as six patches (Sec. 2.2): the radial projection of the faces of the
  * cube [-1,1]^3 with a = 2s-1, b = 2t-1,
  *   patch 0: ( 1, a, b)  1: (-1, b, a)  2: ( b, 1, a)  3: ( a,-1, b)  4: ( a, b, 1)  5: ( b, a,-1),

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgfield.so")
-SOURCES = ["gfield.cpp", "host_spline.cpp", "k_setup.hip", "k_solve.hip", "k_fused.hip", "k_adjoint.hip"]
+SOURCES = ["gfield.cpp", "host_spline.cpp", "k_setup.hip", "k_solve.hip", "k_fused.hip", "k_adjoint.hip",
+           "k_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wno-unused-command-line-argument",

@@ -202,6 +202,8 @@ void launch_extract_stencil(const Level &L, const double *y, int ldb, double *st
 void launch_stencil_diag(const Level &L, hipStream_t s);
 
 void launch_coarse_inverse(const double *Lf, int N0, int nnode, double *Ainv, hipStream_t s);
+// achieved vector fused multiply-add rate in TFLOP/s (FP64 or FP32), measured on the current device
+double fma_probe(bool fp64, hipStream_t s);
 void launch_coarse_factor(const double *M0, const double *S0, int N0, const double *sig, int nnode, double *Lf,
                           int *info, hipStream_t s);
 

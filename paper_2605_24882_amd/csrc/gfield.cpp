@@ -1256,6 +1256,15 @@ extern "C" {
 const char *gf_last_error(void) { return g_last_error.c_str(); }
 int gf_abi_version(void) { return GF_ABI_VERSION; }
 
+gf_status gf_probe_fma(gf_context *ctx, int32_t precision, double *tflops) {
+  return guarded([&] {
+    if (!ctx || !tflops) fail(GF_EINVAL, "null argument");
+    if (precision != GF_PREC_FP64 && precision != GF_PREC_MIXED) fail(GF_EINVAL, "unknown precision");
+    HIPCHK(hipSetDevice(ctx->device));
+    *tflops = fma_probe(precision == GF_PREC_FP64, ctx->stream);
+  });
+}
+
 gf_status gf_context_create(int32_t device, void *hip_stream, gf_context **out) {
   return guarded([&] {
     if (!out) fail(GF_EINVAL, "out is null");

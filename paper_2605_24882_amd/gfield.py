@@ -78,6 +78,7 @@ _SIGS = {
     "gf_abi_version": (ctypes.c_int, []),
     "gf_context_create": (_i32, [_i32, _vp, ctypes.POINTER(_vp)]),
     "gf_context_destroy": (None, [_vp]),
+    "gf_probe_fma": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double)]),
     "gf_geometry_sphere": (_i32, [_vp, _i32, ctypes.POINTER(_vp)]),
     "gf_geometry_nurbs": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "gf_geometry_npatch": (_i32, [_vp]),
@@ -173,6 +174,13 @@ class Context:
         _check(_lib.gf_context_create(device, s, ctypes.byref(h)))
         self.h = h
         self.device = device
+
+    def probe_fma(self, precision=GF_PREC_FP64):
+        """Achieved vector multiply-add rate of the device in TFLOP/s (FP64, or FP32 for
+        GF_PREC_MIXED): measurement support for the roofline of the stencil kernels."""
+        out = ctypes.c_double(0.0)
+        _check(_lib.gf_probe_fma(self.h, precision, ctypes.byref(out)))
+        return out.value
 
     def close(self):
         if self.h:

@@ -388,3 +388,13 @@ def test_chebyshev_degrees_match_oracle(ctx, p, j, pert, prec):
         assert mrel(d, u, ref) <= 1e-10, deg
         iters[deg] = st["max_iters"]
     assert iters[8] <= iters[5] <= iters[1], iters
+
+
+def test_fma_probe(ctx):
+    """The vector multiply-add probe reports a positive rate below the chip's vector peak (78.6
+    TFLOP/s in FP64; FP32 without packed instructions has the same per-lane rate)."""
+    for prec in (g.GF_PREC_FP64, g.GF_PREC_MIXED):
+        r = ctx.probe_fma(prec)
+        assert 1.0 < r < 160.0, (prec, r)
+    with pytest.raises(g.GfieldError):
+        ctx.probe_fma(7)
