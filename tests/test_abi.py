@@ -59,6 +59,8 @@ def test_null_handles_are_einval():
                             x.ctypes.data, g.GF_HOST, ctypes.byref(st)) == g.GF_EINVAL
     items = (g.BatchItem * 1)()
     assert g._lib.gf_sample_batch(None, 1, items, ctypes.byref(opts), g.GF_HOST, ctypes.byref(st)) == g.GF_EINVAL
+    rate = ctypes.c_double(0.0)
+    assert g._lib.gf_probe_fma(None, g.GF_PREC_FP64, ctypes.byref(rate)) == g.GF_EINVAL
 
 
 def test_locate_matches_oracle_inversion():
