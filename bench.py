@@ -112,13 +112,17 @@ def source_sha():
 
 
 def _kernel_rows(path, p, kind, value_key):
-    """values of every launch of the FP64 stencil kernel with epilogue `kind` ("outer": EPI_STORE with
-    the inner product, "smoother": EPI_CHEB) at the finest level (the largest grid of that kernel)."""
+    """values of every launch of the stencil kernel with epilogue `kind` ("outer": EPI_STORE with the
+    inner product, FP64; "smoother": EPI_CHEB in the V-cycle's precision, FP32 when no FP64 smoothing
+    step was launched) at the finest level (the largest grid of that kernel)."""
     rows = list(csv.DictReader(open(path)))
+    has_double_smoother = any(r["Kernel_Name"].startswith(f"void gf::k_apply_fused<double, {p}, ")
+                              and (", 1, 0>" in r["Kernel_Name"] or ", 1, 1>" in r["Kernel_Name"]) for r in rows)
+    vt = "double" if kind == "outer" or has_double_smoother else "float"
     out = []
     for r in rows:
         name = r["Kernel_Name"].split("(")[0]
-        if not name.startswith(f"void gf::k_apply_fused<double, {p}, "):
+        if not name.startswith(f"void gf::k_apply_fused<{vt}, {p}, "):
             continue
         if (kind == "outer" and name.endswith(", 0, 1>")) or (kind == "smoother" and (", 1, 0>" in name or ", 1, 1>" in name)):
             grid = int(r.get("Grid_Size") or r.get("Grid_Size_X"))
