@@ -258,8 +258,12 @@ typedef struct {
 /* Several gf_sample requests solved together (Sec. 3.4 for each request).  The integer solves of
  * all requests advance step by step (step i batches every request with floor(beta) >= i); then the
  * sinc-node systems of all requests (nodes x samples each) iterate together, one CG iteration of
- * every request captured as one HIP graph with one branch per request.  Each request's u equals
- * what gf_sample returns for it alone: the same kernels run on the same columns in the same order.
+ * every node batch captured as one HIP graph with one branch per batch.  Requests on one space with
+ * the same rule and split (and no tape) share one node batch: their columns side by side, each with
+ * its own shift, under one plan for the union of their shifts.  Each request's u agrees with what
+ * gf_sample returns for it alone to the solver tolerance (bit for bit when it has a batch of its own
+ * and the smoothing degree is given: the same kernels then run on the same columns in the same
+ * order).
  * 1 <= nitems <= 4096.  Errors as gf_sample; validation of every request precedes any work.  stats
  * aggregates over all requests (n_systems summed, max_iters and max_rel_resid maxima). */
 gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *items,

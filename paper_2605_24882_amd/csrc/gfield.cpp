@@ -1666,6 +1666,55 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     }
     if (built) setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
   }
+  // requests on one space with the same rule and split share one node batch (their columns side by
+  // side, each with its own shift, under one plan for the union of their shifts); a request with a
+  // tape keeps a batch of its own
+  struct NodeGroup {
+    gf_space *sp = nullptr;
+    std::vector<SampleItem *> its;
+    std::vector<int> off;  // first column of each request
+    int ncols = 0;
+    const Plan *plan = nullptr;
+  };
+  std::vector<NodeGroup> groups;
+  {
+    auto c0 = std::chrono::steady_clock::now();
+    bool built = false;
+    for (auto &it : items) {
+      if (it.bf <= 0.0) continue;
+      int gi = -1;
+      if (!it.tape)
+        for (size_t q = 0; q < groups.size(); ++q) {
+          const SampleItem &h = *groups[q].its[0];
+          if (groups[q].sp == it.sp && !h.tape && h.n == it.n && h.bf == it.bf && h.passes == it.passes &&
+              h.omega == it.omega) {
+            gi = (int)q;
+            break;
+          }
+        }
+      if (gi < 0) {
+        groups.emplace_back();
+        groups.back().sp = it.sp;
+        gi = (int)groups.size() - 1;
+      }
+      NodeGroup &gr = groups[gi];
+      gr.its.push_back(&it);
+      gr.off.push_back(gr.ncols);
+      gr.ncols += (int)it.node_sig.size() * it.nsamp;
+    }
+    for (auto &gr : groups) {
+      if (gr.its.size() == 1) {
+        gr.plan = gr.its[0]->frac_plan;
+        continue;
+      }
+      std::vector<double> usig;
+      for (auto *it : gr.its) usig.insert(usig.end(), it->node_sig.begin(), it->node_sig.end());
+      const size_t np = gr.sp->plans.size();
+      gr.plan = &get_plan(gr.sp, usig);
+      built = built || gr.sp->plans.size() != np;
+    }
+    if (built) setup_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+  }
   for (auto &it : items) {
     const size_t nv = (size_t)it.nsamp * it.sp->fine().N;
     stage_in(it.bin, it.b, nv, mem, s);
@@ -1740,55 +1789,64 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
       if (i == it.n && it.bf == 0.0) local_to_global(F, it.uout.p, it.wc->x.p, it.nsamp, 0, ldc, s);
     }
   }
-  // ---- sinc nodes: all nodes x samples of every request, one batch per request, one graph.  The
+  // ---- sinc nodes: all nodes x samples of every request, one batch per group of requests, one graph.  The
   // improved split applies the rule a second time, to M times the first result.
   int max_pass = 0;
   for (auto &it : items)
     if (it.bf > 0.0) max_pass = std::max(max_pass, it.passes);
   for (int pass = 0; pass < max_pass; ++pass) {
     std::vector<BatchSolve> bs;
-    std::vector<SampleItem *> owners;
-    bs.reserve(items.size());
-    for (size_t idx = 0; idx < items.size(); ++idx) {
-      auto &it = items[idx];
-      if (it.bf <= 0.0 || pass >= it.passes) continue;
-      const Level &F = it.sp->fine();
-      const int K = (int)it.node_sig.size();
-      const int ncols = K * it.nsamp;
-      const int ldc = round_up(it.nsamp, CT);
-      const int ldf = round_up(ncols, CT);
-      const double *rsrc;
-      int ldr;
-      if (pass > 0) {
-        rsrc = it.rloc.p;  // M v of the previous pass
-        ldr = ldc;
-      } else if (it.n > 0) {
-        rsrc = it.wc->r.p;
-        ldr = it.wc->ldb;
-      } else {
-        it.rloc.alloc((size_t)F.R * ldc);
-        global_to_local(F, it.rloc.p, it.bin.p, it.nsamp, ldc, s);
-        rsrc = it.rloc.p;
-        ldr = ldc;
-      }
-      it.wf = &get_workspace(it.sp, ldf, base.prec, 1000 + (int)idx);
-      replicate_cols(F, it.wf->r.p, ldf, rsrc, ldr, it.nsamp, K, s);
+    std::vector<NodeGroup *> owners;
+    bs.reserve(groups.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      NodeGroup &gr = groups[gi];
+      if (pass >= gr.its[0]->passes) continue;
+      const Level &F = gr.sp->fine();
+      const int ldf = round_up(gr.ncols, CT);
+      Workspace *wf = &get_workspace(gr.sp, ldf, base.prec, 1000 + (int)gi);
       BatchSolve b;
-      b.sp = it.sp;
-      b.w = it.wf;
+      b.sp = gr.sp;
+      b.w = wf;
       b.spec = base;
-      b.spec.ncols = ncols;
-      b.spec.col_sig.resize(ncols);
-      b.spec.col_node.resize(ncols);
-      for (int k = 0; k < K; ++k)
-        for (int sm = 0; sm < it.nsamp; ++sm) {
-          b.spec.col_sig[k * it.nsamp + sm] = it.node_sig[k];
-          b.spec.col_node[k * it.nsamp + sm] = k;
+      b.spec.ncols = gr.ncols;
+      b.spec.col_sig.resize(gr.ncols);
+      b.spec.col_node.resize(gr.ncols);
+      int node0 = 0;  // first node of the request in the group's plan
+      for (size_t q = 0; q < gr.its.size(); ++q) {
+        SampleItem &it = *gr.its[q];
+        const int K = (int)it.node_sig.size();
+        const int ldc = round_up(it.nsamp, CT);
+        const double *rsrc;
+        int ldr;
+        if (pass > 0) {
+          rsrc = it.rloc.p;  // M v of the previous pass
+          ldr = ldc;
+        } else if (it.n > 0) {
+          rsrc = it.wc->r.p;
+          ldr = it.wc->ldb;
+        } else {
+          it.rloc.alloc((size_t)F.R * ldc);
+          global_to_local(F, it.rloc.p, it.bin.p, it.nsamp, ldc, s);
+          rsrc = it.rloc.p;
+          ldr = ldc;
         }
-      b.spec.plan = it.frac_plan;
-      b.spec.smooth_load = it.n + pass * it.bf >= 1.5;
+        it.wf = wf;
+        // this request's K nsamp columns only: the writes stay inside its column range
+        replicate_cols(F, wf->r.p + gr.off[q], ldf, rsrc, ldr, it.nsamp, K, s, K * it.nsamp);
+        for (int k = 0; k < K; ++k)
+          for (int sm = 0; sm < it.nsamp; ++sm) {
+            b.spec.col_sig[gr.off[q] + k * it.nsamp + sm] = it.node_sig[k];
+            b.spec.col_node[gr.off[q] + k * it.nsamp + sm] = node0 + k;
+          }
+        node0 += K;
+      }
+      if (ldf > gr.ncols)  // zero padding columns after the last request
+        replicate_cols(F, wf->r.p + gr.ncols, ldf, nullptr, 0, 1, 0, s, ldf - gr.ncols);
+      const SampleItem &h = *gr.its[0];
+      b.spec.plan = gr.plan;
+      b.spec.smooth_load = h.n + pass * h.bf >= 1.5;
       bs.push_back(std::move(b));
-      owners.push_back(&it);
+      owners.push_back(&gr);
     }
     if (bs.empty()) continue;
     std::vector<BatchSolve *> ptrs;
@@ -1796,30 +1854,33 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     solve_all(ctx, ptrs, use_graph);
     for (size_t q = 0; q < bs.size(); ++q) {
       account(bs[q]);
-      SampleItem &it = *owners[q];
-      const Level &F = it.sp->fine();
-      if (it.tape) {
-        const size_t nx = (size_t)F.R * it.wf->ldb;
-        if ((int)it.tape->xk.size() < it.passes) it.tape->xk.resize(it.passes);
-        it.tape->xk[pass].alloc(nx);
-        HIPCHK(hipMemcpyAsync(it.tape->xk[pass].p, it.wf->x.p, nx * sizeof(double), hipMemcpyDeviceToDevice, s));
+      NodeGroup &gr = *owners[q];
+      for (size_t m = 0; m < gr.its.size(); ++m) {
+        SampleItem &it = *gr.its[m];
+        const Level &F = it.sp->fine();
+        if (it.tape) {  // alone in its group: the node solutions start at column 0
+          const size_t nx = (size_t)F.R * it.wf->ldb;
+          if ((int)it.tape->xk.size() < it.passes) it.tape->xk.resize(it.passes);
+          it.tape->xk[pass].alloc(nx);
+          HIPCHK(hipMemcpyAsync(it.tape->xk[pass].p, it.wf->x.p, nx * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        DBuf<double> om;
+        om.upload(it.omega, s);
+        // the sum lands in u; before a further pass it becomes that pass's right-hand side M u
+        quadrature_sum(F, it.uout.p, it.wf->x.p + gr.off[m], om.p, (int)it.omega.size(), it.nsamp, it.wf->ldb, s);
+        if (pass + 1 < it.passes) {
+          const int ldc = round_up(it.nsamp, CT);
+          DBuf<double> vloc;
+          vloc.alloc((size_t)F.R * ldc);
+          global_to_local(F, vloc.p, it.uout.p, it.nsamp, ldc, s);
+          it.rloc.alloc((size_t)F.R * ldc);
+          Workspace &wv = *it.wf;
+          apply_level<double>(F, GF_APPLY_STENCIL, vloc.p, it.rloc.p, wv.one64.p, wv.zero64.p, ldc, ldc / CT, nullptr,
+                              s);
+          HIPCHK(hipStreamSynchronize(s));  // before vloc is released
+        }
+        HIPCHK(hipStreamSynchronize(s));
       }
-      DBuf<double> om;
-      om.upload(it.omega, s);
-      // the sum lands in u; before a further pass it becomes that pass's right-hand side M u
-      quadrature_sum(F, it.uout.p, it.wf->x.p, om.p, (int)it.omega.size(), it.nsamp, it.wf->ldb, s);
-      if (pass + 1 < it.passes) {
-        const int ldc = round_up(it.nsamp, CT);
-        DBuf<double> vloc;
-        vloc.alloc((size_t)F.R * ldc);
-        global_to_local(F, vloc.p, it.uout.p, it.nsamp, ldc, s);
-        it.rloc.alloc((size_t)F.R * ldc);
-        Workspace &wv = *it.wf;
-        apply_level<double>(F, GF_APPLY_STENCIL, vloc.p, it.rloc.p, wv.one64.p, wv.zero64.p, ldc, ldc / CT, nullptr,
-                            s);
-        HIPCHK(hipStreamSynchronize(s));  // before vloc is released
-      }
-      HIPCHK(hipStreamSynchronize(s));
     }
   }
   HIPCHK(hipEventRecord(t1, s));

@@ -204,7 +204,10 @@ void coarse_solve(const Level &C, int N0, T *z, const T *r, const double *Ainv, 
                   const int *active, hipStream_t s);
 void global_to_local(const Level &L, double *X, const double *src, int nvec, int ldb, hipStream_t s);
 void local_to_global(const Level &L, double *dst, const double *X, int nvec, int c0, int ldb, hipStream_t s);
-void replicate_cols(const Level &L, double *Y, int ldy, const double *X, int ldx, int S, int K, hipStream_t s);
+// Y[r][c] = X[r][c mod S] for c < K S and 0 up to column ncw (ncw < 0: the whole row, ldy columns);
+// Y may point at a column offset within its rows when ncw keeps the writes inside them
+void replicate_cols(const Level &L, double *Y, int ldy, const double *X, int ldx, int S, int K, hipStream_t s,
+                    int ncw = -1);
 void quadrature_sum(const Level &L, double *u, const double *X, const double *omega, int K, int S, int ldb,
                     hipStream_t s);
 void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s);

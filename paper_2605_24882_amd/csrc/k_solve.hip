@@ -582,13 +582,17 @@ void local_to_global(const Level &L, double *dst, const double *X, int nvec, int
 }
 
 // Y[row][k*S + s] = X[row][s]: the same right-hand side for every node
-__global__ void k_replicate(double *Y, int ldy, const double *X, int ldx, int S, int K, int64_t R) {
+// Y[r][c] = X[r][c mod S] for c < K S, 0 for K S <= c < ncw (ncw <= ldy minus the column offset of Y)
+__global__ void k_replicate(double *Y, int ldy, const double *X, int ldx, int S, int K, int ncw, int64_t R) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.y + threadIdx.y;
   if (r >= R) return;
-  for (int c = threadIdx.x; c < ldy; c += blockDim.x) Y[r * ldy + c] = (c < K * S) ? X[r * ldx + (c % S)] : 0.0;
+  for (int c = threadIdx.x; c < ncw; c += blockDim.x) Y[r * ldy + c] = (c < K * S) ? X[r * ldx + (c % S)] : 0.0;
 }
-void replicate_cols(const Level &L, double *Y, int ldy, const double *X, int ldx, int S, int K, hipStream_t s) {
-  hipLaunchKernelGGL(k_replicate, dim3((unsigned)((L.R + 3) / 4)), dim3(64, 4), 0, s, Y, ldy, X, ldx, S, K, L.R);
+void replicate_cols(const Level &L, double *Y, int ldy, const double *X, int ldx, int S, int K, hipStream_t s,
+                    int ncw) {
+  if (ncw < 0) ncw = ldy;
+  hipLaunchKernelGGL(k_replicate, dim3((unsigned)((L.R + 3) / 4)), dim3(64, 4), 0, s, Y, ldy, X, ldx, S, K, ncw,
+                     L.R);
   HIPCHK(hipGetLastError());
 }
 
