@@ -398,3 +398,20 @@ def test_fma_probe(ctx):
         assert 1.0 < r < 160.0, (prec, r)
     with pytest.raises(g.GfieldError):
         ctx.probe_fma(7)
+
+
+def test_sample_batch_shared_node_batch(ctx):
+    """Requests on one space with the same rule share one node batch (their columns side by side, of
+    ragged widths, under one plan for the union of their shifts); a request with another rule keeps a
+    batch of its own.  Every field matches the oracle, in FP64 and with the FP32 V-cycle."""
+    sp, d = space(ctx, 2, 3, True), disc(2, 3, True)
+    reqs, refs = [], []
+    for kappa, seeds, K in [(3.0, [1], 10), (7.0, [2, 3, 4], 10), (5.0, [5, 6], 8)]:
+        b = noise.load(d, inputs.noise_vectors(seeds, inputs.noise_length(2, 3)))
+        reqs.append(dict(space=sp, kappa=kappa, beta=0.7, b=b, h=0.4, k_minus=K, k_plus=K))
+        refs.append(_oracle_u(d, kappa, 0.7, 0.4, K, b))
+    for prec in (0, 1):
+        us, st = g.sample_batch(ctx, reqs, precision=prec, rtol=1e-13, max_iter=1000)
+        assert st["n_systems"] == 21 * 4 + 17 * 2
+        for u, ref in zip(us, refs):
+            assert mrel(d, u, ref) <= 1e-10
