@@ -131,19 +131,6 @@ class Discretisation:
         self.M = sp.csr_matrix((self.el_M.reshape(-1), (rows, cols)), shape=(self.N, self.N))
         self.S = sp.csr_matrix((self.el_S.reshape(-1), (rows, cols)), shape=(self.N, self.N))
 
-    # ---- conversions between the global vector and the patch-local grids ----
-    def to_local(self, u):
-        """Patch-local coefficient grids [npatch, n1, n1] of a global coefficient vector."""
-        return np.asarray(u)[..., self.l2g]
-
-    def owner_of(self):
-        """For each global unknown, the first local position (m, iy, ix) in scan order."""
-        flat = self.l2g.reshape(-1)
-        first = np.full(self.N, -1, dtype=np.int64)
-        for i in range(len(flat) - 1, -1, -1):
-            first[flat[i]] = i
-        return first
-
 
 def _patch_quadrature(disc, q):
     """Abscissae and weights of a q-point Gauss rule on every element, flattened per direction."""
