@@ -1,18 +1,23 @@
 """Throughput benchmark: Whittle-Matern field samples per second on one MI355X.
 
-Workload (default): unit sphere as six cube-face patches, degree-2 B-splines, 64 x 64 elements per
-patch (25,352 unknowns); kappa = 10, beta = 1.6 split into one integer solve plus the sinc rule for
-0.6 with h = 0.4 and 41 nodes; 64 independent white-noise loads (seeds 0..63); every shifted
-system solved by multigrid-preconditioned CG to relative residual 1e-10 in FP64.
+Workload (default, the largest configuration of the measured metric): unit sphere as six cube-face
+patches, degree-3 B-splines, 256 x 256 elements per patch (399,386 unknowns); kappa = 30, beta = 2.3
+split into two integer solves plus the sinc rule for 0.3 with h = 0.4 and 61 nodes; 32 independent
+white-noise loads (seeds 0..31); the multigrid V-cycle and its operator in FP32, the outer CG in FP64,
+every shifted system to relative residual 1e-6.
 
-One step = one call of the sampler over the 64 loads, loads already resident in device memory:
-integer solves, the batch of 41 x 64 shifted systems, and the quadrature sum.
+One step = one call of the sampler over the 32 loads, loads already resident in device memory:
+integer solves, the batch of 61 x 32 shifted systems, and the quadrature sum.  After the timed steps
+the field error of two of the timed samples is measured against the FP64 path (rtol 1e-11) in the
+M-norm, and the derivative d loss / d kappa (loss over 1000 seeded surface points, adjoint solves) is
+timed on the same workload (gradients_per_s).
 
 Prints one JSON line.  The roofline entry is for the dominant kernel, the Chebyshev smoothing step
 on the finest level (the stencil operator fused with the smoother's update), timed with HIP events
 stamped by the runtime around every launch, on extra steps run after the timed ones; a second entry
-covers the FP64 operator application of the outer CG.  The CPU baseline is the FP64 oracle on one of
-the 64 loads (single thread).
+covers the FP64 operator application of the outer CG.  The CPU baseline is the FP64 oracle (sparse
+LU, one thread) on one load; for meshes above 64 x 64 elements per patch its per-system cost is
+measured at two coarser levels of the same workload and extrapolated (stated in the line).
 
 --load sqrtm replaces the element-wise noise factor by the paper's own load f = sqrt(M) y (Sec. 3.3,
 Khat shifted mass solves per sample, bounds estimated by the library on every call), computed inside
@@ -99,7 +104,7 @@ def workload_name(cfg, km=None, kp=None):
             f"{'FP64' if prec == 0 else 'FP32 V-cycle / FP64 CG'} MG-PCG to rel. residual {rtol:g}")
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_24882_amd", "csrc", "k_fused.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_24882_amd", "csrc", f) for f in ("k_fused.hip", "k_stencil.h")]
 
 
 def traffic_file(config):
@@ -107,8 +112,27 @@ def traffic_file(config):
 
 
 def source_sha():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 of the stencil kernels' sources (the traffic counters are valid only for these)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _stencil_kind(name, p, kind, vt):
+    """Whether a kernel name is the finest-level operator launch of `kind`: "outer" (EPI_STORE with the
+    inner product, FP64) or "smoother" (EPI_CHEB in type vt), in the combined-stencil kernel
+    k_stencil<T, P, TY, KIND, DOT, MODE> or the separate-stencil kernel k_apply_fused<T, P, TY, KIND, DOT>."""
+    for k in ("k_stencil", "k_apply_fused"):
+        pre = f"void gf::{k}<{vt}, {p}, "
+        if not name.startswith(pre):
+            continue
+        args = [a.strip() for a in name[len(pre):].rstrip(">").split(",")]  # TY, KIND, DOT[, MODE]
+        if len(args) < 3:
+            return False
+        return (args[1], args[2]) == ("0", "1") if kind == "outer" else args[1] == "1"
+    return False
 
 
 def _kernel_rows(path, p, kind, value_key):
@@ -116,15 +140,12 @@ def _kernel_rows(path, p, kind, value_key):
     inner product, FP64; "smoother": EPI_CHEB in the V-cycle's precision, FP32 when no FP64 smoothing
     step was launched) at the finest level (the largest grid of that kernel)."""
     rows = list(csv.DictReader(open(path)))
-    has_double_smoother = any(r["Kernel_Name"].startswith(f"void gf::k_apply_fused<double, {p}, ")
-                              and (", 1, 0>" in r["Kernel_Name"] or ", 1, 1>" in r["Kernel_Name"]) for r in rows)
+    has_double_smoother = any(_stencil_kind(r["Kernel_Name"].split("(")[0], p, "smoother", "double") for r in rows)
     vt = "double" if kind == "outer" or has_double_smoother else "float"
     out = []
     for r in rows:
         name = r["Kernel_Name"].split("(")[0]
-        if not name.startswith(f"void gf::k_apply_fused<{vt}, {p}, "):
-            continue
-        if (kind == "outer" and name.endswith(", 0, 1>")) or (kind == "smoother" and (", 1, 0>" in name or ", 1, 1>" in name)):
+        if _stencil_kind(name, p, kind, vt):
             grid = int(r.get("Grid_Size") or r.get("Grid_Size_X"))
             out.append((grid, value_key(r)))
     big = max(g for g, _ in out)
@@ -199,16 +220,13 @@ def trace_summary(trace_csv, p, top=25):
     d = {}
     # the smoothing step runs in the V-cycle's precision (float in mixed mode), the outer operator in
     # double
-    has_double_smoother = any(r["Kernel_Name"].startswith(f"void gf::k_apply_fused<double, {p}, ")
-                              and (", 1, 0>" in r["Kernel_Name"] or ", 1, 1>" in r["Kernel_Name"]) for r in rows)
+    has_double_smoother = any(_stencil_kind(r["Kernel_Name"].split("(")[0], p, "smoother", "double") for r in rows)
     for kind in ("smoother", "outer"):
         ts = []
         vt = "double" if kind == "outer" or has_double_smoother else "float"
         for r in rows:
             name = r["Kernel_Name"].split("(")[0]
-            if not name.startswith(f"void gf::k_apply_fused<{vt}, {p}, "):
-                continue
-            if (kind == "outer" and name.endswith(", 0, 1>")) or (kind == "smoother" and (", 1, 0>" in name or ", 1, 1>" in name)):
+            if _stencil_kind(name, p, kind, vt):
                 ts.append((int(r["Start_Timestamp"]), int(r["Grid_Size_X"]),
                            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
         big = max(g for _, g, _ in ts)
@@ -273,46 +291,88 @@ def stream_probe(torch, mib=1024, reps=10):
             "achieved": round(gbs, 1), "unit": "GB/s", "frac_of_peak": round(gbs / 8000.0, 4)}
 
 
-def cpu_baseline(cfg, nodes_timed=6):
-    """The oracle (sparse LU, FP64, one thread) on the first load of the workload.
+def cpu_model():
+    """(model name, logical CPUs) of the host."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
 
-    Bounded sample: the integer solves and `nodes_timed` of the sinc-node solves (evenly spaced in k)
-    are timed; the per-sample time adds the remaining nodes at the measured average per node (every
-    node solve is one SuperLU factorisation of the same sparsity plus one triangular solve)."""
-    from threadpoolctl import threadpool_limits
+
+def _oracle_system_times(pert, p, lev, kappa, beta, h, k, nsys_nodes):
+    """Oracle on one load at one level: assembly time, and the times of its integer solves and of
+    `nsys_nodes` node solves (evenly spaced in k), each a SuperLU factorisation plus a solve."""
     import numpy as np
     from oracle import assembly, fractional, noise
     from paper_2605_24882_amd import inputs
-    pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
     n, bf = fractional.split_plain(beta)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        if pert == "torus":
-            from oracle import geometry
-            d = assembly.Discretisation(p, lev, geometry.NurbsSurface(*inputs.torus_patches(2.0, 1.0)))
-        else:
-            d = assembly.Discretisation(p, lev, pert)
-        t1 = time.perf_counter()
-        b = noise.load(d, inputs.noise_vectors([0], inputs.noise_length(p, lev, 16 if pert == "torus" else 6)))
-        t2 = time.perf_counter()
-        ws = fractional.integer_chain(d.M, d.S, kappa, n, b)
-        r = b if n == 0 else np.stack([d.M @ w for w in ws[-1]])
-        t3 = time.perf_counter()
-        sigma, omega, _ = fractional.nodes(kappa, bf, h, k, k)
-        pick = np.linspace(0, len(sigma) - 1, nodes_timed).round().astype(int)
+    t0 = time.perf_counter()
+    if pert == "torus":
+        from oracle import geometry
+        d = assembly.Discretisation(p, lev, geometry.NurbsSurface(*inputs.torus_patches(2.0, 1.0)))
+    else:
+        d = assembly.Discretisation(p, lev, pert)
+    t1 = time.perf_counter()
+    b = noise.load(d, inputs.noise_vectors([0], inputs.noise_length(p, lev, 16 if pert == "torus" else 6)))
+    t2 = time.perf_counter()
+    ws = fractional.integer_chain(d.M, d.S, kappa, n, b)
+    r = b if n == 0 else np.stack([d.M @ w for w in ws[-1]])
+    t3 = time.perf_counter()
+    sigma, omega, _ = fractional.nodes(kappa, bf, h, k, k)
+    pick = np.linspace(0, len(sigma) - 1, nsys_nodes).round().astype(int) if bf > 0 else []
+    if len(pick):
         fractional.node_solutions(d.M, d.S, sigma[pick], r)
-        t4 = time.perf_counter()
-    per_node = (t4 - t3) / nodes_timed
-    per_sample = (t3 - t2) + per_node * len(sigma)
-    return {
-        "value": 1.0 / per_sample,
-        "unit": "samples/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"1 of the {nsamp} loads (seed 0): its {n} integer solve(s) ({t3 - t2:.2f} s) and {nodes_timed} of "
-                   f"the {len(sigma)} node solves ({per_node:.2f} s each) by SuperLU on one thread, extrapolated to all "
-                   f"{len(sigma)} nodes; assembly of M and S ({t1 - t0:.2f} s) excluded"),
-    }
+    t4 = time.perf_counter()
+    return dict(N=d.N, assembly=t1 - t0, chain=t3 - t2, n=n, nodes=len(sigma) if bf > 0 else 0,
+                per_node=(t4 - t3) / max(1, len(pick)), timed_nodes=len(pick))
+
+
+def cpu_baseline(cfg, nodes_timed=6):
+    """The oracle (sparse LU, FP64, one thread) on the first load of the workload.
+
+    Bounded sample.  Up to 64 x 64 elements per patch: the integer solves and `nodes_timed` of the
+    sinc-node solves (evenly spaced in k) are timed at the workload's level; the per-sample time adds
+    the remaining nodes at the measured average per node (every node solve is one SuperLU
+    factorisation of the same sparsity plus one triangular solve).  Finer meshes (one factorisation
+    alone would take minutes): the time per system is measured at the two levels three and two below
+    the workload's (same degree, kappa and nodes: the integer solves and one to three node solves),
+    and extrapolated to the workload's unknowns with the power law those two levels give."""
+    from threadpoolctl import threadpool_limits
+    pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
+    model, ncpu = cpu_model()
+    with threadpool_limits(limits=1):
+        if lev <= 6:
+            m = _oracle_system_times(pert, p, lev, kappa, beta, h, k, nodes_timed)
+            per_sample = m["chain"] + m["per_node"] * m["nodes"]
+            sample = (f"1 of the {nsamp} loads (seed 0): its {m['n']} integer solve(s) ({m['chain']:.2f} s) and "
+                      f"{m['timed_nodes']} of the {m['nodes']} node solves ({m['per_node']:.2f} s each) by SuperLU on "
+                      f"one thread, extrapolated to all {m['nodes']} nodes; assembly of M and S "
+                      f"({m['assembly']:.2f} s) excluded")
+        else:
+            lo = _oracle_system_times(pert, p, lev - 3, kappa, beta, h, k, 3)
+            hi = _oracle_system_times(pert, p, lev - 2, kappa, beta, h, k, 1)
+            per_sys = []
+            for m in (lo, hi):
+                tsys = (m["chain"] + m["per_node"] * m["timed_nodes"]) / (m["n"] + m["timed_nodes"])
+                per_sys.append(tsys)
+            n1 = 2 ** lev + p
+            N = 6 * (n1 - 2) ** 2 + 12 * (n1 - 2) + 8
+            expo = math.log(per_sys[1] / per_sys[0]) / math.log(hi["N"] / lo["N"])
+            t_sys = per_sys[1] * (N / hi["N"]) ** expo
+            per_sample = (hi["n"] + hi["nodes"]) * t_sys
+            sample = (f"1 of the {nsamp} loads (seed 0) at levels {lev - 3} and {lev - 2} of the same workload "
+                      f"({lo['N']} and {hi['N']} unknowns): the integer solves and 3 resp. 1 node solves by SuperLU "
+                      f"on one thread, {per_sys[0]:.3f} s and {per_sys[1]:.2f} s per system (factorisation + solve); "
+                      f"extrapolated as N^{expo:.2f} to {N} unknowns ({t_sys:.0f} s per system) times "
+                      f"{hi['n']} + {hi['nodes']} systems per sample; assembly excluded")
+    return {"value": 1.0 / per_sample, "unit": "samples/s", "cores": 1, "kind": "oracle", "sample": sample,
+            "host_cpu": model, "host_logical_cpus": ncpu}
 
 
 def main():
@@ -320,7 +380,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS) + sorted(BATCH_CONFIGS))
+    ap.add_argument("--config", default="c5", choices=sorted(CONFIGS) + sorted(BATCH_CONFIGS))
     ap.add_argument("--apply-kind", type=int, default=0)
     ap.add_argument("--cheb", type=int, default=0)
     ap.add_argument("--precond", choices=("vcycle", "bpx"), default="vcycle",
@@ -332,9 +392,13 @@ def main():
     ap.add_argument("--khat", type=int, default=16, help="square-root rule size for --load sqrtm")
     ap.add_argument("--nodes", choices=("fixed", "accurate"), default="fixed",
                     help="sinc nodes: the workload's symmetric K, or the tolerance-driven set (1e-6) per request")
-    ap.add_argument("--coarse-level", type=int, default=-1,
-                    help="coarsest multigrid level (-1: the library's choice)")
+    ap.add_argument("--mg-levels", type=int, default=0,
+                    help="levels of the multigrid hierarchy (0: the library's choice, all levels down to 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip the d loss / d kappa timing that follows the sampling steps")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the field error of two timed samples against the FP64 path")
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the one-system-per-call FP64 GPU reference timing")
     ap.add_argument("--apply-shape", default="",
@@ -379,7 +443,8 @@ def main():
         bc = BATCH_CONFIGS[args.config]
         pert, prec, rtol, nsamp, p = bc["perturbed"], bc["precision"], bc["rtol"], bc["nsamp"], max(bc["degrees"])
         geo = g.Geometry(ctx, pert)
-        spaces = {(dg, lv): g.Space(ctx, geo, dg, lv, args.coarse_level) for dg in bc["degrees"] for lv in bc["levels"]}
+        spaces = {(dg, lv): g.Space(ctx, geo, dg, lv, mg_levels=args.mg_levels) for dg in bc["degrees"]
+                  for lv in bc["levels"]}
         space_s = time.perf_counter() - t0
         combos = [(dg, lv, kp) for dg in bc["degrees"] for lv in bc["levels"] for kp in bc["kappas"]]
         reqs = []
@@ -409,7 +474,7 @@ def main():
             geo = g.Geometry.nurbs(ctx, *inputs.torus_patches(2.0, 1.0))
         else:
             geo = g.Geometry(ctx, pert)
-        sp = g.Space(ctx, geo, p, lev, args.coarse_level)
+        sp = g.Space(ctx, geo, p, lev, mg_levels=args.mg_levels)
         space_s = time.perf_counter() - t0
         if args.load == "sqrtm":
             y = torch.from_numpy(inputs.noise_vectors(range(nsamp), sp.ndofs)).cuda()
@@ -424,12 +489,14 @@ def main():
                   split=g.GF_SPLIT_IMPROVED if args.split == "improved" else g.GF_SPLIT_PLAIN,
                   preconditioner=g.GF_PRECOND_BPX if args.precond == "bpx" else g.GF_PRECOND_VCYCLE)
 
-        if args.config in GRADIENT_CONFIGS:
+        grad_step = None
+        if pert != "torus" and args.load == "factor":
             pts, yv = inputs.sphere_points_and_targets(1000, seed=7)
             patch, stp = geo.locate(pts)
             yt = torch.from_numpy(yv).cuda()
 
-            def step(flags=0):
+            def grad_step(flags=0):
+                """forward samples and d loss / d kappa per sample (loss over 1000 seeded points)"""
                 u, tape, st1 = sp.sample_tape(kappa, beta, b, flags=flags, **kw)
                 vals = sp.eval(patch, stp, u)
                 gk, st2 = tape.grad_kappa(sp.eval_adjoint(patch, stp, vals - yt[None, :]))
@@ -441,6 +508,8 @@ def main():
                 st["max_iters"] = max(st1["max_iters"], st2["max_iters"])
                 st["max_rel_resid"] = max(st1["max_rel_resid"], st2["max_rel_resid"])
                 return gk, st
+        if args.config in GRADIENT_CONFIGS:
+            step = grad_step
             workload = workload_name(cfg, *((km, kp) if args.nodes == "accurate" else ())) + "; plus d loss/d kappa by adjoint solves (loss over 1000 points)"
         elif args.load == "sqrtm":
             def step(flags=0):
@@ -481,6 +550,38 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = nsamp * args.steps / elapsed
+    # field error of two timed samples against the FP64 path at rtol 1e-11 (M-norm, the L2 norm of the
+    # field on the surface)
+    accuracy = None
+    if (args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and args.load == "factor"
+            and not args.no_accuracy):
+        kw64 = dict(kw)
+        kw64.update(precision=0, rtol=1e-11, max_iter=4000)
+        nchk = min(2, nsamp)
+        uref, st64 = sp.sample(kappa, beta, b[:nchk].contiguous(), **kw64)
+        err = u[:nchk] - uref
+        num = (err * sp.apply(1.0, 0.0, err)).sum(dim=1)
+        den = (uref * sp.apply(1.0, 0.0, uref)).sum(dim=1)
+        rel = torch.sqrt(num / den)
+        accuracy = {"rel_l2_vs_fp64": float(rel.max()), "samples_checked": nchk,
+                    "reference": "the library's FP64 path at rtol 1e-11 on the same loads (M-norm)",
+                    "reference_cg_iters": st64["max_iters"]}
+    # derivative throughput: forward samples and d loss / d kappa per sample by the adjoint solves
+    gradients = None
+    if (args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_gradient
+            and grad_step is not None):
+        gsteps = max(1, min(3, args.steps))
+        grad_step()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(gsteps):
+            gk, gst = grad_step()
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - tg
+        gradients = {"value": round(nsamp * gsteps / tg, 3), "unit": "gradients/s", "steps": gsteps,
+                     "ms_per_step": round(1e3 * tg / gsteps, 3), "max_cg_iters": gst["max_iters"],
+                     "what": (f"{nsamp} forward samples and d loss/d kappa of each (loss over 1000 seeded surface "
+                              f"points; adjoint solves by the same batched solver) per step")}
     # dominant-kernel timing: the same steps once more with HIP events stamped around every outer
     # operator launch of the node batch (events need the eagerly enqueued loop; kernels and launch
     # shapes are the same)
@@ -511,10 +612,10 @@ def main():
 
     vt = "double" if prec == 0 else "float"
     roof = roof_entry(agg["smooth_ms"], agg["smooth_launches"], agg["smooth_bytes"],
-                      f"k_apply_fused<{vt},p,*,EPI_CHEB,*> (Chebyshev smoothing step on the finest level, stencil form)",
+                      f"k_stencil<{vt},p,*,EPI_CHEB,*,*> (Chebyshev smoothing step on the finest level, stencil form)",
                       "smoother")
     roof_outer = roof_entry(agg["apply_ms"], agg["apply_launches"], agg["apply_bytes"],
-                            "k_apply_fused<double,p,*,EPI_STORE,dot> (outer CG operator, stencil form)", "outer")
+                            "k_stencil<double,p,*,EPI_STORE,dot,*> (outer CG operator, stencil form)", "outer")
 
     out = {
         "metric": "field samples/sec at rel-L2 err <=1e-6 vs FP64 oracle; operator-apply HBM GB/s",
@@ -531,7 +632,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "samples_per_step": nsamp, "systems_per_step": st["n_systems"],
                    "max_cg_iters": agg["max_iters"], "max_rel_resid": agg["max_rel_resid"],
-                   "space_setup_s": round(space_s, 3)},
+                   "space_setup_s": round(space_s, 3),
+                   **({"accuracy": accuracy} if accuracy else {})},
         "roofline": roof,
         "roofline_outer_operator": roof_outer,
         # the counter runs (--copy-probe-mib) time no stream probe: their only elementwise kernel is
@@ -546,6 +648,8 @@ def main():
     if (args.config in CONFIGS and args.config not in GRADIENT_CONFIGS and not args.no_one_at_a_time
             and args.load == "factor"):
         out["gpu_one_solve_at_a_time"] = one_at_a_time(g, sp, b, CONFIGS[args.config], kw)
+    if gradients:
+        out["gradients_per_s"] = gradients
     if not args.no_cpu_baseline and args.config in CONFIGS and args.load == "factor":
         out["cpu_baseline"] = cpu_baseline(CONFIGS[args.config])
     print(json.dumps(out))

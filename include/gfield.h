@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GF_ABI_VERSION 1
+#define GF_ABI_VERSION 2
 
 typedef enum {
   GF_OK = 0,
@@ -81,10 +81,11 @@ gf_status gf_probe_fma(gf_context *ctx, int32_t precision, double *tflops);
 /* The closed surface as six patches (Sec. 2.2): the radial projection of the faces of the
  * cube [-1,1]^3 with a = 2s-1, b = 2t-1,
  *   patch 0: ( 1, a, b)  1: (-1, b, a)  2: ( b, 1, a)  3: ( a,-1, b)  4: ( a, b, 1)  5: ( b, a,-1),
- * F_m = v/|v| (perturbed = 0, the unit sphere of Sec. 4.1), or F_m = r(xh) xh with xh = v/|v|
- * and r(x, y, z) = 1 + 0.15 sin(3x) sin(2y) cos(z) (perturbed = 1).  The geometry holds no device
- * data; ctx may be NULL. */
-gf_status gf_geometry_sphere(gf_context *ctx, int32_t perturbed, gf_geometry **out);
+ * xh = v/|v| and F_m = r(xh) xh with r(x, y, z) = 1 + perturb_amp sin(3x) sin(2y) cos(z):
+ * perturb_amp = 0 is the unit sphere of Sec. 4.1, 0.15 the perturbed sphere of the batching workload.
+ * GF_EINVAL unless perturb_amp is finite with |perturb_amp| < 1 (so that r > 0).  The geometry holds
+ * no device data; ctx may be NULL. */
+gf_status gf_geometry_cubesphere(gf_context *ctx, double perturb_amp, gf_geometry **out);
 
 /* A surface given as npatch NURBS patches (Sec. 2.2, Def. of the geometry: each patch a rational
  * tensor-product B-spline map F_m(s, t) = sum_ab N_a(s) N_b(t) w_ab X_ab / sum_ab N_a(s) N_b(t) w_ab
@@ -114,11 +115,15 @@ void gf_geometry_destroy(gf_geometry *geom);
 gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, int32_t *patch, double *st);
 
 /* S^0_{level,degree} on the geometry (Sec. 2.3): 1 <= degree <= 5, 0 <= level <= 12.
- * coarse_level (-1: automatic) is the coarsest level of the multigrid hierarchy, 0 <= coarse_level
- * <= level.  Builds the metric terms m = w a, G = w a K^-1 at the (p+1)^2 Gauss points of every
- * element (Sec. 3.2), the patch operators and the level hierarchy.  GF_EINVAL out of range. */
-gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degree, int32_t level,
-                          int32_t coarse_level, gf_space **out);
+ * nquad: Gauss-Legendre points per direction and element for every integral of the space (Sec. 3.2
+ * leaves the quadrature open): 0 selects degree + 1; degree + 1 and degree + 2 are supported (a
+ * larger value gives GF_EUNSUPPORTED, a smaller non-zero one GF_EINVAL).
+ * mg_levels: levels of the multigrid hierarchy, the finest being `level` (0: all levels down to 0;
+ * 1 <= mg_levels <= level + 1 otherwise; the coarsest level is solved densely).
+ * Builds the metric terms m = w a, G = w a K^-1 at the nquad^2 Gauss points of every element
+ * (Sec. 3.2), the patch operators and the level hierarchy.  GF_EINVAL out of range. */
+gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degree, int32_t level, int32_t nquad,
+                          int32_t mg_levels, gf_space **out);
 void gf_space_destroy(gf_space *space);
 /* Number N of unique unknowns: 6(n-2)^2 + 12(n-2) + 8 with n = 2^level + degree on the sphere
  * family; on NURBS geometries the count the gluing gives (a closed surface of P quadrilateral

@@ -12,7 +12,8 @@ so the radial projection of the cube faces is used:
     F_m(s, t) = v / |v|,
 
 each oriented so that dF/ds x dF/dt points outward.  The perturbed sphere
-scales the unit-sphere point xh by r(xh) = 1 + 0.15 sin(3x) sin(2y) cos(z).
+scales the unit-sphere point xh by r(xh) = 1 + amp sin(3x) sin(2y) cos(z) (amp = 0.15 for
+the perturbed sphere of the workloads; `perturbed` may also be a number, the amplitude).
 
 A NURBS surface (Sec. 2.2, definition of the geometry) is a list of rational
 tensor-product B-spline patches F_m(s, t) = sum N_a(s) N_b(t) w_ab X_ab /
@@ -90,9 +91,19 @@ def cube_point(m, s, t):
     raise ValueError("patch index out of range")
 
 
-def radius(xh):
-    """r(x, y, z) = 1 + 0.15 sin(3x) sin(2y) cos(z) at the unit-sphere point xh."""
-    return 1.0 + 0.15 * np.sin(3.0 * xh[..., 0]) * np.sin(2.0 * xh[..., 1]) * np.cos(xh[..., 2])
+def amplitude(perturbed):
+    """Perturbation amplitude of the sphere family: False -> 0 (the unit sphere), True -> 0.15 (the
+    perturbed sphere of the workloads), a number -> that amplitude."""
+    if perturbed is True:
+        return 0.15
+    if perturbed is False or perturbed is None:
+        return 0.0
+    return float(perturbed)
+
+
+def radius(xh, amp=0.15):
+    """r(x, y, z) = 1 + amp sin(3x) sin(2y) cos(z) at the unit-sphere point xh."""
+    return 1.0 + amp * np.sin(3.0 * xh[..., 0]) * np.sin(2.0 * xh[..., 1]) * np.cos(xh[..., 2])
 
 
 def patch_map(m, s, t, perturbed=False):
@@ -104,8 +115,9 @@ def patch_map(m, s, t, perturbed=False):
     v = cube_point(m, s, t)
     nrm = np.sqrt(np.sum(v * v, axis=-1))  # no conjugation: keeps the map analytic
     xh = v / nrm[..., None]
-    if perturbed:
-        return radius(xh)[..., None] * xh
+    amp = amplitude(perturbed)
+    if amp != 0.0:
+        return radius(xh, amp)[..., None] * xh
     return xh
 
 

@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gfield.h"
@@ -80,7 +81,7 @@ void glue_patches(int p, int lev, std::vector<int> &l2g, int &N);
 enum SurfaceKind { SURF_SPHERE = 0, SURF_NURBS = 1 };
 struct SurfaceArgs {
   int kind = SURF_SPHERE;
-  int perturbed = 0;
+  double amp = 0.0;  // sphere family: amplitude of the radial perturbation (0: unit sphere)
   int npatch = 6;
   int du = 0, dv = 0;
   const int *pinfo = nullptr;
@@ -110,6 +111,8 @@ double complete_k(double q);
 // wavefront strip (1, 2 or 4) and at most TX coefficients along the strip
 struct ApplyTune {
   int TY = 1, TX = 32, NC = 1;  // NC: 64-column tiles per wavefront
+  int algo = 1;                 // 0: M and S stencils applied separately; 1: one combined stencil per
+                                // distinct shift of the column tile, loads one step ahead
   float us = 0.f;               // measured duration of one launch
 };
 
@@ -145,8 +148,8 @@ struct Level {
   DBuf<int> pro_start, res_start;   // per fine index: first coarse index; per coarse index: first fine index
   DBuf<double> pro_c, res_c;        // [n1f][pw], [n1c][rw]
   DBuf<float> pro_c32, res_c32;
-  // autotuned launch shapes, keyed by (element size, column stride)
-  mutable std::map<std::pair<int, int>, ApplyTune> tune;
+  // autotuned launch shapes, keyed by (element size, column stride, epilogue kind, stencil mode)
+  mutable std::map<std::tuple<int, int, int, int>, ApplyTune> tune;
 };
 
 }  // namespace gf
@@ -161,7 +164,7 @@ struct gf_context {
 struct gf_geometry {
   gf_context *ctx = nullptr;
   int kind = gf::SURF_SPHERE;
-  int perturbed = 0;
+  double amp = 0.0;  // sphere family: amplitude of the radial perturbation
   int npatch = 6;
   gf::NurbsHost nurbs;                    // SURF_NURBS: the patches (host; copied to the device
                                           // while a space is built on them)

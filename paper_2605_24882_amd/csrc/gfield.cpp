@@ -59,13 +59,13 @@ static gf_status guarded(F &&f) {
 static inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // ------------------------------------------------------------------ level construction
-static void build_level_host(Level &L, int p, int lev, const gf_geometry *geom) {
+static void build_level_host(Level &L, int p, int lev, int q, const gf_geometry *geom) {
   L.p = p;
   L.lev = lev;
   L.nel = 1 << lev;
   L.n1 = L.nel + p;
   L.W = L.n1 + 2 * p;
-  L.q = p + 1;
+  L.q = q;
   L.S = 2 * p + 1;
   L.npatch = geom->npatch;
   L.R = (int64_t)L.npatch * L.W * L.W;
@@ -300,6 +300,9 @@ struct SmoothLog {
 struct Workspace {
   SmoothLog *slog = nullptr;  // set while a timed batch runs
   int ldb = 0, ntiles = 0, prec = 0;
+  // structure of the columns' shifts in the current batch: the most distinct shifts in one column tile,
+  // and whether every aligned group of 16 columns has one shift (see EpiArgs::nslot, rows16)
+  int nslot = 0, rows16 = 0;
   DBuf<double> x, r, p, q;  // outer CG (FP64)
   std::vector<LevelWork> lw;
   DBuf<double> sig64, one64, zero64;
@@ -437,68 +440,95 @@ struct Prec<float> {
   static float *one(Workspace &w) { return w.one32.p; }
 };
 
-// Autotuner of the fused stencil apply: on first use for a (level, precision, column stride) every
-// candidate launch shape is timed with HIP events on the caller's buffers (one warm-up and three
-// timed launches, all column tiles active) and the fastest is kept for the lifetime of the space.
+// Autotuner of the fused stencil apply: on first use for a (level, precision, column stride, epilogue
+// kind, stencil mode) every candidate launch shape of the combined-stencil kernel is timed with HIP
+// events (one warm-up and three timed launches, all column tiles active) and the fastest is kept for the
+// lifetime of the space.  The candidates write into scratch vectors of their own, so tuning leaves the
+// caller's buffers untouched; the shape changes neither the operations nor their order for any output,
+// so the choice cannot change results.  A level whose strips exceed the kernel's 32-bit buffer offsets
+// takes the separate-stencil kernel (same launch shapes).
 static bool g_autotune = true;
 
+static int stencil_mode_class(int nslot, int rows16) { return rows16 ? 2 : (nslot >= 1 && nslot <= 8 ? 0 : 1); }
+
 template <typename T>
-static const ApplyTune &get_tune(const Level &L, int ldb, int ntiles, const T *x, T *y, const T *ca, const T *cb,
-                                 hipStream_t s) {
-  const auto key = std::make_pair((int)sizeof(T), ldb);
+static const ApplyTune &get_tune(const Level &L, int ldb, int ntiles, const T *x, const T *ca, const T *cb,
+                                 const EpiArgs<T> &ecall, hipStream_t s) {
+  const auto key = std::make_tuple((int)sizeof(T), ldb, ecall.kind, stencil_mode_class(ecall.nslot, ecall.rows16));
   auto it = L.tune.find(key);
   if (it != L.tune.end()) return it->second;
   ApplyTune best;
+  const bool fits2 = stencil_offsets_fit(L, ldb, 2, (int)sizeof(T));
   // GF_APPLY_SHAPE="TY,TX" fixes the launch shape (reproducible profiling runs)
   if (const char *fixed = std::getenv("GF_APPLY_SHAPE")) {
     int ty = 0, tx = 0;
-    if (std::sscanf(fixed, "%d,%d", &ty, &tx) != 2 || ty < 1 || ty > 2 || tx < 1)
-      fail(GF_EINVAL, "GF_APPLY_SHAPE must be \"TY,TX\" with TY in {1,2} and TX >= 1");
+    if (std::sscanf(fixed, "%d,%d", &ty, &tx) != 2 || (ty != 1 && ty != 2 && ty != 4) || tx < 1)
+      fail(GF_EINVAL, "GF_APPLY_SHAPE must be \"TY,TX\" with TY in {1,2,4} and TX >= 1");
     best.TY = ty;
     best.TX = tx;
     return L.tune.emplace(key, best).first->second;
   }
   if (g_autotune && L.n1 >= 8) {
-    const int tys[2] = {1, 2}, txs[3] = {16, 32, 64}, ncs[1] = {1};
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    EpiArgs<T> e;
-    e.kind = EPI_STORE;
-    e.y = y;
-    Scratch none;
-    float best_us = 1e30f;
-    for (int ty : tys)
-      for (int nc : ncs)
-      for (int tx : txs) {
-        if (tx > 2 * L.n1 && tx != 16) continue;
-        if (nc > 1 && (L.p >= 4 || nc > ntiles)) continue;
+    std::vector<ApplyTune> cand;
+    for (int ty : {1, 2, 4}) {
+      if (ty == 4 && (sizeof(T) != 4 || L.p > 3)) continue;
+      if (ty > 1 && L.p >= 4) continue;
+      for (int tx : {32, 64}) {
+        if (tx > 2 * L.n1 && tx != 32) continue;
         ApplyTune t;
         t.TY = ty;
         t.TX = tx;
-        t.NC = nc;
+        t.algo = stencil_offsets_fit(L, ldb, ty, (int)sizeof(T)) ? 1 : 0;
+        if (t.algo == 0 && ty == 4) continue;
+        cand.push_back(t);
+      }
+    }
+    // scratch outputs and inputs of the candidate launches
+    const size_t n = (size_t)L.R * ldb;
+    DBuf<T> ty_, tz, tr;
+    ty_.alloc(n);
+    EpiArgs<T> e = ecall;
+    e.dot = 0;
+    e.y = ty_.p;
+    if (e.kind != EPI_STORE) {
+      tr.alloc(n);
+      e.r = tr.p;
+    }
+    if (e.kind == EPI_CHEB) {
+      tz.alloc(n);
+      e.zout = tz.p;
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    Scratch none;
+    float best_us = 1e30f;
+    for (const ApplyTune &t : cand) {
+      apply_fused<T>(L, Prec<T>::stM(L), Prec<T>::stS(L), x, ca, cb, e, none, nullptr, nullptr, ldb, ntiles, 0.0, 0,
+                     s, t);
+      HIPCHK(hipEventRecord(e0, s));
+      for (int k = 0; k < 3; ++k)
         apply_fused<T>(L, Prec<T>::stM(L), Prec<T>::stS(L), x, ca, cb, e, none, nullptr, nullptr, ldb, ntiles, 0.0,
                        0, s, t);
-        HIPCHK(hipEventRecord(e0, s));
-        for (int k = 0; k < 3; ++k)
-          apply_fused<T>(L, Prec<T>::stM(L), Prec<T>::stS(L), x, ca, cb, e, none, nullptr, nullptr, ldb, ntiles, 0.0,
-                         0, s, t);
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        const float us = ms * 1e3f / 3.f;
-        if (std::getenv("GF_TUNE_LOG"))
-          std::fprintf(stderr, "tune p=%d lev=%d T=%d ldb=%d TY=%d NC=%d TX=%d: %.1f us\n", L.p, L.lev,
-                       (int)sizeof(T), ldb, ty, nc, tx, us);
-        if (us < best_us) {
-          best_us = us;
-          best = t;
-          best.us = us;
-        }
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      const float us = ms * 1e3f / 3.f;
+      if (std::getenv("GF_TUNE_LOG"))
+        std::fprintf(stderr, "tune p=%d lev=%d T=%d ldb=%d kind=%d mode=%d algo=%d TY=%d TX=%d: %.1f us\n", L.p, L.lev,
+                     (int)sizeof(T), ldb, e.kind, stencil_mode_class(e.nslot, e.rows16), t.algo, t.TY, t.TX, us);
+      if (us < best_us) {
+        best_us = us;
+        best = t;
+        best.us = us;
       }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+  } else {
+    best.TY = fits2 ? 2 : 1;
+    best.algo = stencil_offsets_fit(L, ldb, best.TY, (int)sizeof(T)) ? 1 : 0;
   }
   return L.tune.emplace(key, best).first->second;
 }
@@ -511,7 +541,7 @@ static void apply_epi(const Level &L, int kind, const T *x, const T *ca, const T
                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                       const T *stB = nullptr) {
   if (stB) {  // second operator given as a stencil (stencil path only)
-    const ApplyTune &t = get_tune<T>(L, ldb, ntiles, x, e.y, ca, cb, s);
+    const ApplyTune &t = get_tune<T>(L, ldb, ntiles, x, ca, cb, e, s);
     apply_fused<T>(L, Prec<T>::stM(L), stB, x, ca, cb, e, sc, cs, active, ldb, ntiles, tol2, maxit, s, t, ev0, ev1);
     return;
   }
@@ -522,19 +552,22 @@ static void apply_epi(const Level &L, int kind, const T *x, const T *ca, const T
     launch_interface_sum<T>(L, e.y, ldb, ntiles, active, s);
     if (e.kind != EPI_STORE || e.dot) epi_rows<T>(L, x, e, sc, cs, active, ldb, ntiles, tol2, maxit, s);
   } else {
-    const ApplyTune &t = get_tune<T>(L, ldb, ntiles, x, e.y, ca, cb, s);
+    const ApplyTune &t = get_tune<T>(L, ldb, ntiles, x, ca, cb, e, s);
     apply_fused<T>(L, Prec<T>::stM(L), Prec<T>::stS(L), x, ca, cb, e, sc, cs, active, ldb, ntiles, tol2, maxit, s,
                    t, ev0, ev1);
   }
 }
 
-// y = (ca M + cb S) x, assembled (interface sums included)
+// y = (ca M + cb S) x, assembled (interface sums included); uniform: ca and cb hold one value each over
+// all columns (one combined stencil for the whole batch)
 template <typename T>
 static void apply_level(const Level &L, int kind, const T *x, T *y, const T *ca, const T *cb, int ldb, int ntiles,
-                        const int *active, hipStream_t s) {
+                        const int *active, hipStream_t s, bool uniform = true) {
   EpiArgs<T> e;
   e.kind = EPI_STORE;
   e.y = y;
+  e.nslot = uniform ? 1 : 0;
+  e.rows16 = uniform ? 1 : 0;
   Scratch none;
   apply_epi<T>(L, kind, x, ca, cb, e, none, nullptr, const_cast<int *>(active), ldb, ntiles, 0.0, 0, s);
 }
@@ -628,7 +661,7 @@ static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
     v2.alloc(n);
     hash_fill(L, v.p, ldb, nt, s);
     for (int itp = 0; itp < kPowerIters; ++itp) {
-      apply_level<double>(L, GF_APPLY_STENCIL, v.p, w.p, dsig.p, one.p, ldb, nt, nullptr, s);
+      apply_level<double>(L, GF_APPLY_STENCIL, v.p, w.p, dsig.p, one.p, ldb, nt, nullptr, s, false);
       div_diag(L, v2.p, w.p, dsig.p, ldb, nt, s);
       if (itp + 1 < kPowerIters) std::swap(v.p, v2.p);
     }
@@ -791,6 +824,8 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   auto smooth = [&](int k, bool last, int dflags) {
     EpiArgs<T> e;
     e.kind = EPI_CHEB;
+    e.nslot = w.nslot;
+    e.rows16 = w.rows16;
     e.dflags = dflags | (k > 0 ? 4 : 0);
     e.y = a;
     e.zout = zb;
@@ -833,6 +868,8 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
   {
     EpiArgs<T> e;
     e.kind = EPI_RESID;
+    e.nslot = w.nslot;
+    e.rows16 = w.rows16;
     e.y = a;
     e.r = r;
     apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, 0.0, 0, s);
@@ -922,6 +959,17 @@ struct BatchSolve {
     }
     std::fill(w->active_h.begin(), w->active_h.end(), 0);
     for (int c = 0; c < spec.ncols; ++c) w->active_h[c / CT] = 1;
+    // shift structure of the column tiles (padding columns carry the shift 1)
+    w->nslot = 0;
+    w->rows16 = 1;
+    for (int t = 0; t < w->ntiles; ++t) {
+      std::vector<double> d;
+      for (int c = t * CT; c < (t + 1) * CT; ++c) {
+        if (std::find(d.begin(), d.end(), sig[c]) == d.end()) d.push_back(sig[c]);
+        if (c % 16 != 0 && sig[c] != sig[c - 1]) w->rows16 = 0;
+      }
+      w->nslot = std::max(w->nslot, (int)d.size());
+    }
     w->sig64.upload(sig, s);
     w->sig32.upload(sigf, s);
     w->node.upload(node, s);
@@ -1002,6 +1050,8 @@ struct BatchSolve {
     Scratch sc = w->scratch();
     EpiArgs<double> e;
     e.kind = EPI_STORE;
+    e.nslot = w->nslot;
+    e.rows16 = w->rows16;
     e.y = w->q.p;
     e.dot = 1;
     e.op = OP_ALPHA;
@@ -1290,13 +1340,15 @@ void gf_context_destroy(gf_context *ctx) {
   delete ctx;
 }
 
-gf_status gf_geometry_sphere(gf_context *ctx, int32_t perturbed, gf_geometry **out) {
+gf_status gf_geometry_cubesphere(gf_context *ctx, double perturb_amp, gf_geometry **out) {
   return guarded([&] {
     if (!out) fail(GF_EINVAL, "null argument");
-    if (perturbed != 0 && perturbed != 1) fail(GF_EINVAL, "perturbed must be 0 or 1");
+    *out = nullptr;
+    if (!std::isfinite(perturb_amp) || !(std::fabs(perturb_amp) < 1.0))
+      fail(GF_EINVAL, "perturb_amp must be finite with |perturb_amp| < 1");
     gf_geometry *g = new gf_geometry();
     g->ctx = ctx;
-    g->perturbed = perturbed;
+    g->amp = perturb_amp;
     *out = g;
   });
 }
@@ -1405,28 +1457,30 @@ gf_status gf_locate(const gf_geometry *geom, int32_t npts, const double *xyz, in
   });
 }
 
-gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degree, int32_t level,
-                          int32_t coarse_level, gf_space **out) {
+gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degree, int32_t level, int32_t nquad,
+                          int32_t mg_levels, gf_space **out) {
   return guarded([&] {
     if (!ctx || !geom || !out) fail(GF_EINVAL, "null argument");
     *out = nullptr;
     if (degree < 1 || degree > 5) fail(GF_EINVAL, "degree must be in 1..5");
     if (level < 0 || level > 12) fail(GF_EINVAL, "level must be in 0..12");
-    if (coarse_level > level) fail(GF_EINVAL, "coarse_level must not exceed level");
-    int lc = coarse_level;
-    if (lc < 0) lc = 0;
+    if (nquad == 0) nquad = degree + 1;
+    if (nquad < degree + 1) fail(GF_EINVAL, "nquad must be 0 or at least degree + 1");
+    if (nquad > degree + 2) fail(GF_EUNSUPPORTED, "nquad above degree + 2 is not supported");
+    if (mg_levels < 0 || mg_levels > level + 1) fail(GF_EINVAL, "mg_levels must be in 0..level+1");
+    const int lc = mg_levels == 0 ? 0 : level + 1 - mg_levels;
     HIPCHK(hipSetDevice(ctx->device));
     std::unique_ptr<gf_space> sp(new gf_space());
     sp->ctx = ctx;
     sp->geom = const_cast<gf_geometry *>(geom);
     sp->p = degree;
     sp->j = level;
-    sp->q = degree + 1;
+    sp->q = nquad;
     sp->lc = lc;
     // the surface for the metric kernel; NURBS control nets on the device while the levels are built
     SurfaceArgs surf;
     surf.kind = geom->kind;
-    surf.perturbed = geom->perturbed;
+    surf.amp = geom->amp;
     surf.npatch = geom->npatch;
     DBuf<int> d_pinfo;
     DBuf<double> d_knots, d_ctrl;
@@ -1442,7 +1496,7 @@ gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degr
     }
     for (int l = lc; l <= level; ++l) {
       std::unique_ptr<Level> L(new Level());
-      build_level_host(*L, degree, l, geom);
+      build_level_host(*L, degree, l, nquad, geom);
       build_level_device(sp.get(), *L, surf);
       sp->lev.push_back(std::move(L));
     }

@@ -20,33 +20,11 @@
 // neighbouring strips then hit the same L2.
 #include "gf_internal.h"
 #include "k_solve.h"
+#include "k_stencil.h"
 
 #include <hip/hip_ext.h>
 
 namespace gf {
-
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// (M_i, S_i) coefficient pair of one stencil tap, read from LDS in one instruction
-template <typename T>
-struct Pair;
-template <>
-struct Pair<double> {
-  using type = double2;
-};
-template <>
-struct Pair<float> {
-  using type = float2;
-};
-
-// reduce one double per lane over the 4 wavefronts of the block into partial[slot][col]
-__device__ __forceinline__ void block_partial(double acc, double *partial, int64_t slot, int ldb, int col) {
-  __shared__ double red[4][CT];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  red[w][lane] = acc;
-  __syncthreads();
-  if (w == 0) partial[slot * ldb + col] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-}
 
 // The stencil coefficients of the current row (wavefront-uniform) are scalar loads; the window of x
 // shifts by one column per step.  The epilogue kind and the inner-product flag are compile-time
@@ -274,41 +252,67 @@ void finalize(int nslot, int nd, int op, Scratch &sc, ColState *cs, int *active,
 static int xcd_q(int total) { return (total + 7) / 8; }
 
 template <typename T, int P, int TY, int KIND, int DOT>
-static void launch_apply_k(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
-                           const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s, hipEvent_t ev0,
-                           hipEvent_t ev1) {
-  if (ev0) {
-    // the runtime stamps the events at the start and end of this dispatch itself
-    hipExtLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM,
-                          stS, x, ca, cb, e.cf1, e.cf2, e.y, e.zout, e.r, e.dM, e.dS, partial, active,
-                          e.dflags);
+static void launch_apply_k(const ApplyGeom &g, int algo, const T *stM, const T *stS, const T *x, const T *ca,
+                           const T *cb, const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1) {
+  // with events the runtime stamps them at the start and end of this dispatch itself
+  if (algo == 1) {
+    auto kern = e.rows16 ? k_stencil<T, P, TY, KIND, DOT, SM_DPP>
+                : (e.nslot >= 1 && e.nslot <= StencilSlots<T, P, TY>::value) ? k_stencil<T, P, TY, KIND, DOT, SM_COMB>
+                                                                            : k_stencil<T, P, TY, KIND, DOT, SM_PAIR>;
+    if (ev0)
+      hipExtLaunchKernelGGL(kern, dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM, stS, x, ca, cb, e.cf1, e.cf2,
+                            e.y, e.zout, e.r, partial, active, e.dflags);
+    else
+      hipLaunchKernelGGL(kern, dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca, cb, e.cf1, e.cf2, e.y, e.zout,
+                         e.r, partial, active, e.dflags);
     return;
   }
-  hipLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca, cb,
-                     e.cf1, e.cf2, e.y, e.zout, e.r, e.dM, e.dS, partial, active, e.dflags);
+  if constexpr (TY <= 2) {
+    if (ev0)
+      hipExtLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g,
+                            stM, stS, x, ca, cb, e.cf1, e.cf2, e.y, e.zout, e.r, e.dM, e.dS, partial, active,
+                            e.dflags);
+    else
+      hipLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca,
+                         cb, e.cf1, e.cf2, e.y, e.zout, e.r, e.dM, e.dS, partial, active, e.dflags);
+  }
 }
 
 template <typename T, int P, int TY>
-static void launch_apply_pt(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
-                            const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s, hipEvent_t ev0,
-                            hipEvent_t ev1) {
+static void launch_apply_pt(const ApplyGeom &g, int algo, const T *stM, const T *stS, const T *x, const T *ca,
+                            const T *cb, const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s,
+                            hipEvent_t ev0, hipEvent_t ev1) {
   if (e.kind == EPI_STORE) {
-    if (e.dot) launch_apply_k<T, P, TY, EPI_STORE, 1>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
-    else launch_apply_k<T, P, TY, EPI_STORE, 0>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    if (e.dot) launch_apply_k<T, P, TY, EPI_STORE, 1>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    else launch_apply_k<T, P, TY, EPI_STORE, 0>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
   } else if (e.kind == EPI_CHEB) {
-    if (e.dot) launch_apply_k<T, P, TY, EPI_CHEB, 1>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
-    else launch_apply_k<T, P, TY, EPI_CHEB, 0>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    if (e.dot) launch_apply_k<T, P, TY, EPI_CHEB, 1>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    else launch_apply_k<T, P, TY, EPI_CHEB, 0>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
   } else {
-    launch_apply_k<T, P, TY, EPI_RESID, 0>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    launch_apply_k<T, P, TY, EPI_RESID, 0>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
   }
 }
 
+// four rows per strip only for float and degrees up to 3 (the window of a double strip would not fit
+// the registers), and only in the combined-stencil kernel
 template <typename T, int P>
-static void launch_apply_p(const ApplyGeom &g, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
-                           const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s, hipEvent_t ev0,
-                           hipEvent_t ev1) {
-  if (g.TY == 1 || P >= 4) launch_apply_pt<T, P, 1>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
-  else launch_apply_pt<T, P, 2>(g, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+static void launch_apply_p(const ApplyGeom &g, int algo, const T *stM, const T *stS, const T *x, const T *ca,
+                           const T *cb, const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1) {
+  if constexpr (P <= 3) {
+    if (g.TY == 2) {
+      launch_apply_pt<T, P, 2>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+      return;
+    }
+    if constexpr (sizeof(T) == 4) {
+      if (g.TY == 4) {
+        launch_apply_pt<T, P, 4>(g, 1, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+        return;
+      }
+    }
+  }
+  launch_apply_pt<T, P, 1>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
 }
 
 ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int NC) {
@@ -317,7 +321,7 @@ ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int
   g.n1 = L.n1;
   g.ldb = ldb;
   g.ntiles = ntiles;
-  g.TY = (L.p >= 4 || TY < 2) ? 1 : 2;
+  g.TY = (L.p >= 4 || TY < 2) ? 1 : (TY < 4 ? 2 : 4);
   g.NC = 1;
   g.nseg = (L.n1 + TXmax - 1) / TXmax;
   g.TX = (L.n1 + g.nseg - 1) / g.nseg;
@@ -326,6 +330,16 @@ ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int
   g.nsb = (g.nstrip + 3) / 4;
   g.q = xcd_q(g.nsb * ntiles);
   return g;
+}
+
+// The combined-stencil kernel reads and writes through buffer descriptors based at the first row of
+// its strip, with 32-bit offsets below 2^31 bytes: the window (TY + 2p rows of the padded patch and one
+// more row of columns), the output rows and the stencils of the strip must fit that range.
+bool stencil_offsets_fit(const Level &L, int ldb, int TY, int elem) {
+  const int64_t lim = ((int64_t)1 << 31) - 1;
+  const int64_t win = (int64_t)(TY + 2 * L.p + 1) * L.W * ldb * elem;
+  const int64_t st = (int64_t)(TY + 1) * L.W * L.S * L.S * elem;
+  return win < lim && st < lim;
 }
 
 int partial_slots(const Level &L, int ldb, int ntiles) {
@@ -338,13 +352,19 @@ template <typename T>
 void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
                  const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
                  int maxit, hipStream_t s, const ApplyTune &tune, hipEvent_t ev0, hipEvent_t ev1) {
-  const ApplyGeom g = apply_geom(L, ldb, ntiles, tune.TY, tune.TX, tune.NC);
+  ApplyGeom g = apply_geom(L, ldb, ntiles, tune.TY, tune.TX, tune.NC);
+  int algo = tune.algo;
+  if (algo == 1 && !stencil_offsets_fit(L, ldb, g.TY, (int)sizeof(T))) {
+    // the combined-stencil kernel addresses vectors by 32-bit offsets from the strip's first row
+    algo = 0;
+    g = apply_geom(L, ldb, ntiles, std::min(g.TY, 2), tune.TX, tune.NC);
+  }
   switch (L.p) {
-    case 1: launch_apply_p<T, 1>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
-    case 2: launch_apply_p<T, 2>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
-    case 3: launch_apply_p<T, 3>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
-    case 4: launch_apply_p<T, 4>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
-    case 5: launch_apply_p<T, 5>(g, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 1: launch_apply_p<T, 1>(g, algo, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 2: launch_apply_p<T, 2>(g, algo, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 3: launch_apply_p<T, 3>(g, algo, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 4: launch_apply_p<T, 4>(g, algo, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 5: launch_apply_p<T, 5>(g, algo, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
     default: fail(GF_EUNSUPPORTED, "degree out of range");
   }
   HIPCHK(hipGetLastError());

@@ -10,9 +10,9 @@ __constant__ int c_frames[6][4] = {{0, 1, 1, 2}, {0, -1, 2, 1}, {1, 1, 2, 0},
                                    {1, -1, 0, 2}, {2, 1, 0, 1}, {2, -1, 1, 0}};
 
 // Surface point and its parameter derivatives for patch m at (s, t) (Sec. 2.2 maps).
-// xh = v/|v| has d xh = (dv - xh (xh . dv))/|v|; the perturbed surface r(xh) xh has
-// d(r xh) = (grad r . d xh) xh + r d xh.
-__device__ void surface_derivs(int m, double s, double t, int perturbed, double Fs[3], double Ft[3]) {
+// xh = v/|v| has d xh = (dv - xh (xh . dv))/|v|; the perturbed surface r(xh) xh with
+// r = 1 + amp sin(3x) sin(2y) cos(z) has d(r xh) = (grad r . d xh) xh + r d xh.
+__device__ void surface_derivs(int m, double s, double t, double amp, double Fs[3], double Ft[3]) {
   const int fa = c_frames[m][0], fs = c_frames[m][1], aa = c_frames[m][2], ba = c_frames[m][3];
   double v[3], vs[3] = {0, 0, 0}, vt[3] = {0, 0, 0};
   v[fa] = (double)fs;
@@ -29,14 +29,14 @@ __device__ void surface_derivs(int m, double s, double t, int perturbed, double 
     xs[i] = (vs[i] - xh[i] * ps) / nv;
     xt[i] = (vt[i] - xh[i] * pt) / nv;
   }
-  if (!perturbed) {
+  if (amp == 0.0) {
     for (int i = 0; i < 3; ++i) { Fs[i] = xs[i]; Ft[i] = xt[i]; }
     return;
   }
   const double X = xh[0], Y = xh[1], Z = xh[2];
-  const double r = 1.0 + 0.15 * sin(3.0 * X) * sin(2.0 * Y) * cos(Z);
-  const double gr[3] = {0.45 * cos(3.0 * X) * sin(2.0 * Y) * cos(Z), 0.30 * sin(3.0 * X) * cos(2.0 * Y) * cos(Z),
-                        -0.15 * sin(3.0 * X) * sin(2.0 * Y) * sin(Z)};
+  const double r = 1.0 + amp * sin(3.0 * X) * sin(2.0 * Y) * cos(Z);
+  const double gr[3] = {3.0 * amp * cos(3.0 * X) * sin(2.0 * Y) * cos(Z),
+                        2.0 * amp * sin(3.0 * X) * cos(2.0 * Y) * cos(Z), -amp * sin(3.0 * X) * sin(2.0 * Y) * sin(Z)};
   const double rs = gr[0] * xs[0] + gr[1] * xs[1] + gr[2] * xs[2];
   const double rt = gr[0] * xt[0] + gr[1] * xt[1] + gr[2] * xt[2];
   for (int i = 0; i < 3; ++i) {
@@ -144,7 +144,7 @@ __global__ void k_metric(double *metric, int nel, int q, SurfaceArgs g, const do
   const double s = (ex + gx[qx]) / nel, tt = (ey + gx[qy]) / nel;
   double Fs[3], Ft[3];
   if (g.kind == SURF_NURBS) nurbs_derivs(g, m, s, tt, Fs, Ft);
-  else surface_derivs(m, s, tt, g.perturbed, Fs, Ft);
+  else surface_derivs(m, s, tt, g.amp, Fs, Ft);
   const double k11 = Fs[0] * Fs[0] + Fs[1] * Fs[1] + Fs[2] * Fs[2];
   const double k12 = Fs[0] * Ft[0] + Fs[1] * Ft[1] + Fs[2] * Ft[2];
   const double k22 = Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2];
@@ -178,12 +178,12 @@ void launch_metric(const Level &L, const SurfaceArgs &g, const double *gx, const
 //   y[b][a] += sum_qx V0 Bx + V1 Dx
 // Basis tables and metric terms are uniform over the wavefront.  Accumulators live in
 // LDS, one column per lane, so no barrier is needed.
-template <typename T, int P, int TT>
+template <typename T, int P, int Q, int TT>
 __global__ __launch_bounds__(64) void k_sumfact(const T *__restrict__ metric, const T *__restrict__ basis,
                                                 const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ ca,
                                                 const T *__restrict__ cb, int nel, int n1, int W, int ldb,
                                                 const int *__restrict__ active, int ntx) {
-  constexpr int Q = P + 1, NB = P + 1;
+  constexpr int NB = P + 1;
   const int ct = blockIdx.y;
   if (active && !active[ct]) return;
   const int lane = threadIdx.x;
@@ -298,11 +298,17 @@ void launch_sumfact_apply(const Level &L, const T *x, T *y, const T *ca, const T
   const int ntx = (L.n1 + TT - 1) / TT;
   dim3 grid(L.npatch * ntx * ntx, ntiles), block(CT);
   const T *mt = metric_of<T>(L), *bs = basis_of<T>(L);
+  if (L.q != L.p + 1 && L.q != L.p + 2) fail(GF_EUNSUPPORTED, "quadrature order out of range");
+  const bool q2 = L.q == L.p + 2;
   switch (L.p) {
-#define GF_SF(PP)                                                                                              \
-  case PP:                                                                                                     \
-    hipLaunchKernelGGL((k_sumfact<T, PP, TT>), grid, block, 0, s, mt, bs, x, y, ca, cb, L.nel, L.n1, L.W, ldb, \
-                       active, ntx);                                                                           \
+#define GF_SF(PP)                                                                                                \
+  case PP:                                                                                                       \
+    if (q2)                                                                                                      \
+      hipLaunchKernelGGL((k_sumfact<T, PP, PP + 2, TT>), grid, block, 0, s, mt, bs, x, y, ca, cb, L.nel, L.n1, L.W, \
+                         ldb, active, ntx);                                                                      \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_sumfact<T, PP, PP + 1, TT>), grid, block, 0, s, mt, bs, x, y, ca, cb, L.nel, L.n1, L.W, \
+                         ldb, active, ntx);                                                                      \
     break;
     GF_SF(1) GF_SF(2) GF_SF(3) GF_SF(4) GF_SF(5)
 #undef GF_SF
@@ -411,10 +417,10 @@ void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s) {
 // ------------------------------------------------------------------ white noise (Sec. 3.3)
 // Pass 1, one thread per element: element mass matrix M_e = sum_q m_q phi_i phi_j, its lower
 // Cholesky factor, and y_e = L_e z_e for every sample.
-template <int P>
+template <int P, int Q>
 __global__ void k_noise_elements(const double *metric, const double *basis, const double *z, double *ye, int nel,
                                  int nsamp, int np) {
-  constexpr int Q = P + 1, NB = P + 1, NL = NB * NB;
+  constexpr int NB = P + 1, NL = NB * NB;
   const int64_t ne_tot = (int64_t)np * nel * nel;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne_tot) return;
@@ -486,12 +492,20 @@ __global__ void k_noise_gather(const double *ye, double *bl, int nel, int n1, in
 void launch_white_noise(const Level &L, const double *z, int nsamp, double *ye, double *bl, int ldb, hipStream_t s) {
   const int64_t ne_tot = (int64_t)L.npatch * L.nel * L.nel;
   dim3 g1((unsigned)((ne_tot + 63) / 64)), b1(64);
+  if (L.q != L.p + 1 && L.q != L.p + 2) fail(GF_EUNSUPPORTED, "quadrature order out of range");
+  const bool q2 = L.q == L.p + 2;
   switch (L.p) {
-    case 1: hipLaunchKernelGGL(k_noise_elements<1>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
-    case 2: hipLaunchKernelGGL(k_noise_elements<2>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
-    case 3: hipLaunchKernelGGL(k_noise_elements<3>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
-    case 4: hipLaunchKernelGGL(k_noise_elements<4>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
-    case 5: hipLaunchKernelGGL(k_noise_elements<5>, g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, L.npatch); break;
+#define GF_NE(PP)                                                                                            \
+  case PP:                                                                                                   \
+    if (q2)                                                                                                  \
+      hipLaunchKernelGGL((k_noise_elements<PP, PP + 2>), g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, \
+                         L.npatch);                                                                          \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_noise_elements<PP, PP + 1>), g1, b1, 0, s, L.metric.p, L.basis.p, z, ye, L.nel, nsamp, \
+                         L.npatch);                                                                          \
+    break;
+    GF_NE(1) GF_NE(2) GF_NE(3) GF_NE(4) GF_NE(5)
+#undef GF_NE
     default: fail(GF_EUNSUPPORTED, "degree out of range");
   }
   HIPCHK(hipGetLastError());

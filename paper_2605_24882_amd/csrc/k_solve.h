@@ -133,6 +133,12 @@ struct EpiArgs {
   // zero: z_prev = 0, zout is not read); bit 2 -- the step has a previous direction (every step but
   // the first of a sweep; cf1 and z_prev are read only then)
   int dflags = 0;
+  // the largest number of distinct (ca, cb) pairs in one 64-column tile, as the caller knows it
+  // (0: unknown); the combined-stencil kernel applies one stencil per pair when they fit its slots
+  int nslot = 0;
+  // 1: (ca, cb) is the same within every aligned group of 16 columns (the combined stencil can be
+  // broadcast within 16-lane rows)
+  int rows16 = 0;
 };
 
 struct ApplyGeom {
@@ -145,6 +151,7 @@ struct IfaceGeom {
 
 ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int NC);
 int partial_slots(const Level &L, int ldb, int ntiles);
+bool stencil_offsets_fit(const Level &L, int ldb, int TY, int elem);
 template <typename T>
 void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
                  const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,

@@ -79,12 +79,12 @@ _SIGS = {
     "gf_context_create": (_i32, [_i32, _vp, ctypes.POINTER(_vp)]),
     "gf_context_destroy": (None, [_vp]),
     "gf_probe_fma": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double)]),
-    "gf_geometry_sphere": (_i32, [_vp, _i32, ctypes.POINTER(_vp)]),
+    "gf_geometry_cubesphere": (_i32, [_vp, _dbl, ctypes.POINTER(_vp)]),
     "gf_geometry_nurbs": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
     "gf_geometry_npatch": (_i32, [_vp]),
     "gf_geometry_destroy": (None, [_vp]),
     "gf_locate": (_i32, [_vp, _i32, _vp, _vp, _vp]),
-    "gf_space_create": (_i32, [_vp, _vp, _i32, _i32, _i32, ctypes.POINTER(_vp)]),
+    "gf_space_create": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, ctypes.POINTER(_vp)]),
     "gf_space_destroy": (None, [_vp]),
     "gf_space_ndofs": (_i64, [_vp]),
     "gf_space_noise_length": (_i64, [_vp]),
@@ -194,15 +194,20 @@ class Context:
             pass
 
 
-class Geometry:
-    """The six-patch sphere (perturbed or not), or NURBS patches via Geometry.nurbs."""
+# perturbation amplitude of the perturbed sphere of the batching workload
+PERTURBED_AMP = 0.15
 
-    def __init__(self, ctx, perturbed=False, _handle=None):
+
+class Geometry:
+    """The six-patch sphere family (gf_geometry_cubesphere; perturb_amp True stands for PERTURBED_AMP),
+    or NURBS patches via Geometry.nurbs."""
+
+    def __init__(self, ctx, perturb_amp=0.0, _handle=None):
         h = _handle
         if h is None:
+            amp = PERTURBED_AMP if perturb_amp is True else float(perturb_amp)
             h = _vp()
-            _check(_lib.gf_geometry_sphere(ctx.h if ctx is not None else None, 1 if perturbed else 0,
-                                           ctypes.byref(h)))
+            _check(_lib.gf_geometry_cubesphere(ctx.h if ctx is not None else None, amp, ctypes.byref(h)))
         self.h = h
         self.ctx = ctx
         self.npatch = int(_lib.gf_geometry_npatch(h))
@@ -241,9 +246,9 @@ class Geometry:
 class Space:
     """S^0_{level,degree} on a geometry, with its multigrid hierarchy."""
 
-    def __init__(self, ctx, geom, degree, level, coarse_level=-1):
+    def __init__(self, ctx, geom, degree, level, nquad=0, mg_levels=0):
         h = _vp()
-        _check(_lib.gf_space_create(ctx.h, geom.h, degree, level, coarse_level, ctypes.byref(h)))
+        _check(_lib.gf_space_create(ctx.h, geom.h, degree, level, nquad, mg_levels, ctypes.byref(h)))
         self.h = h
         self.ctx, self.geom = ctx, geom
         self.degree, self.level = degree, level

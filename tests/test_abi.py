@@ -26,7 +26,7 @@ def test_every_declared_symbol_is_exported_and_bound():
 
 
 def test_abi_version():
-    assert g.abi_version() == 1
+    assert g.abi_version() == 2
 
 
 def _has_gpu():
@@ -50,8 +50,9 @@ def test_null_handles_are_einval():
     assert g._lib.gf_space_apply(None, 1.0, 1.0, 1, x.ctypes.data, x.ctypes.data, g.GF_HOST, 0) == g.GF_EINVAL
     assert b"null" in g._lib.gf_last_error()
     out = ctypes.c_void_p()
-    assert g._lib.gf_space_create(None, None, 2, 2, -1, ctypes.byref(out)) == g.GF_EINVAL
-    assert g._lib.gf_geometry_sphere(None, 3, ctypes.byref(out)) == g.GF_EINVAL
+    assert g._lib.gf_space_create(None, None, 2, 2, 0, 0, ctypes.byref(out)) == g.GF_EINVAL
+    for amp in (1.0, -1.5, float("nan"), float("inf")):
+        assert g._lib.gf_geometry_cubesphere(None, amp, ctypes.byref(out)) == g.GF_EINVAL
     rule = g.QuadRule(0.4, 15, 15)
     opts = g.SolveOpts(0, 1e-10, 100, 0, 0, 0)
     st = g.SolveStats()
@@ -67,7 +68,7 @@ def test_locate_matches_oracle_inversion():
     from oracle import geometry
     from paper_2605_24882_amd import inputs
     pts, _ = inputs.sphere_points_and_targets(1000, seed=7)
-    geo = g.Geometry(None, perturbed=False)
+    geo = g.Geometry(None, perturb_amp=0.0)
     patch, st = geo.locate(pts)
     op, os_, ot = geometry.invert(pts)
     assert np.array_equal(patch, op)

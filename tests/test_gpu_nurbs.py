@@ -172,7 +172,7 @@ def test_open_surface_parity(ctx, name, p, j):
 def test_torus_large_coarse_level(ctx, geo, p, j, lc):
     """Coarsest levels whose right-hand sides do not fit the LDS of the coarse solve (144 unknowns on
     the 16-patch torus: degree 3 at level 0, degree 2 at level 1) read them from memory."""
-    sp = g.Space(ctx, geo, p, j, lc)
+    sp = g.Space(ctx, geo, p, j, mg_levels=0 if lc < 0 else j - lc + 1)
     d = disc(p, j)
     b = noise.load(d, inputs.noise_vectors([9], sp.noise_length))
     ref = fractional.sample(d.M, d.S, 3.0, 1.6, 0.4, 10, 10, b)

@@ -34,7 +34,7 @@ def space(ctx, p, j, perturbed=False, lc=-1):
     key = (p, j, perturbed, lc)
     if key not in _spaces:
         geo = g.Geometry(ctx, perturbed)
-        _spaces[key] = g.Space(ctx, geo, p, j, lc)
+        _spaces[key] = g.Space(ctx, geo, p, j, mg_levels=0 if lc < 0 else j - lc + 1)
     return _spaces[key]
 
 
