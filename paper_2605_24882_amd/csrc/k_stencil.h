@@ -156,11 +156,7 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
                                                 const T *sab, int slot, int nd, T a, T b, T a1, T a2, int dflags) {
   constexpr int S = 2 * P + 1, SS = S * S, WR = TY + 2 * P, NH = (SS + 63) / 64, NCH = (SS + 15) / 16;
   constexpr bool PAIR = MODE != SM_COMB;
-#ifdef GF_EXP_NOUNROLL
-  constexpr int U = 1;
-#else
   constexpr int U = (P <= 3) ? S : 1;
-#endif
   constexpr int MAXD = StencilSlots<T, P, TY>::value;
   const int W = g.W, n1 = g.n1;
   const int64_t ldb = g.ldb;
@@ -302,9 +298,6 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
           for (int dy = 0; dy < S; ++dy) {
 #pragma unroll
             for (int dx = 0; dx < S; ++dx) ac = fma(lc[dy * S + dx], win[t + dy][(U == S) ? (u + dx) % S : dx], ac);
-#ifdef GF_EXP_SCHED
-            __builtin_amdgcn_sched_barrier(0);
-#endif
           }
           return ac;
         };
