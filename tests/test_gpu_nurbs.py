@@ -102,6 +102,8 @@ def test_torus_sample_matches_oracle(ctx, geo, beta, prec):
     err = mrel(d, u, ref)
     print(f"torus p=2 j=3 beta={beta} prec={prec}: rel. M-norm error {err:.2e}, iterations {st['max_iters']}")
     assert err <= 1e-10
+    # multigrid on a surface with four patches at every corner: measured 7-8 iterations
+    assert st["max_iters"] <= 10, st["max_iters"]
 
 
 def test_torus_eval_matches_oracle(ctx, geo):
@@ -229,3 +231,4 @@ def test_torus_workload_subset_matches_oracle(ctx, geo):
     u, st = sp.sample(10.0, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-12)
     ref = fractional.sample(d.M, d.S, 10.0, 1.6, 0.4, 20, 20, b)
     assert mrel(d, u, ref) <= 1e-10
+    assert st["max_iters"] <= 9, st["max_iters"]  # measured 7

@@ -99,6 +99,15 @@ def _oracle_u(d, kappa, beta, h, K, b):
     return fractional.sample(d.M, d.S, kappa, beta, h, K, K, b)
 
 
+# CG iteration ceilings of the multigrid-preconditioned solver: the counts measured on these cases plus
+# about a quarter.  The fields converge to the oracle's whatever the preconditioner, so a wrong
+# knot-insertion transfer, smoothing interval or coarse solve shows only as more iterations; these
+# bounds make it fail.
+ITER_CEIL = {"c1": 10, "split": {0.75: 9, 1.6: 9, 2.3: 15, 2.0: 7}, "sumfact": 21, "c2_mesh": 8,
+             "one_level": 2, "coarse": 9,
+             "cheb": {(2, 4): {1: 48, 2: 27, 5: 13, 8: 9}, (3, 3): {1: 140, 2: 72, 5: 32, 8: 21}}}
+
+
 def test_sample_c1_fp64(ctx):
     """Unit sphere, p = 2, 4 x 4 elements per patch, kappa = 4, beta = 0.75, h = 0.4, 31 nodes, 1 sample."""
     sp, d = space(ctx, 2, 2), disc(2, 2)
@@ -108,6 +117,7 @@ def test_sample_c1_fp64(ctx):
     ref = _oracle_u(d, 4.0, 0.75, 0.4, 15, b)
     assert st["n_systems"] == 31
     assert mrel(d, u, ref) <= 1e-10
+    assert st["max_iters"] <= ITER_CEIL["c1"], st["max_iters"]
 
 
 @pytest.mark.parametrize("beta", [0.75, 1.6, 2.3, 2.0])
@@ -118,6 +128,7 @@ def test_sample_split_and_precision(ctx, beta, prec):
     u, st = sp.sample(3.0, beta, b, h=0.4, k_minus=12, k_plus=12, precision=prec, rtol=1e-13)
     ref = _oracle_u(d, 3.0, beta, 0.4, 12, b)
     assert mrel(d, u, ref) <= 1e-10
+    assert st["max_iters"] <= ITER_CEIL["split"][beta], st["max_iters"]
 
 
 def test_sample_eager_matches_graph(ctx):
@@ -139,6 +150,7 @@ def test_sample_sumfact_operator(ctx, prec):
     u, st = sp.sample(2.0, 0.6, b, h=0.4, k_minus=10, k_plus=10, rtol=1e-13, apply_kind=1, precision=prec)
     ref = _oracle_u(d, 2.0, 0.6, 0.4, 10, b)
     assert mrel(d, u, ref) <= 1e-10
+    assert st["max_iters"] <= ITER_CEIL["sumfact"], st["max_iters"]
 
 
 @pytest.mark.parametrize("beta", [0.75, 1.6, 2.3])
@@ -161,6 +173,7 @@ def test_c2_mesh_subset(ctx):
     u, st = sp.sample(10.0, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-12)
     ref = _oracle_u(d, 10.0, 1.6, 0.4, 20, b)
     assert mrel(d, u, ref) <= 1e-10
+    assert st["max_iters"] <= ITER_CEIL["c2_mesh"], st["max_iters"]
 
 
 BATCH = [
@@ -370,6 +383,8 @@ def test_coarse_level_choice_matches_oracle(ctx, p, j, lc, prec):
     u, st = sp.sample(3.0, 1.4, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13, max_iter=1000)
     ref = _oracle_u(d, 3.0, 1.4, 0.4, 10, b)
     assert mrel(d, u, ref) <= 1e-10
+    # a one-level space: the dense coarse solve is the whole preconditioner (exact up to rounding)
+    assert st["max_iters"] <= ITER_CEIL["one_level" if lc == j else "coarse"], st["max_iters"]
 
 
 @pytest.mark.parametrize("p,j,pert,prec", [(2, 4, False, 0), (3, 3, True, 1)])
@@ -388,6 +403,8 @@ def test_chebyshev_degrees_match_oracle(ctx, p, j, pert, prec):
         assert mrel(d, u, ref) <= 1e-10, deg
         iters[deg] = st["max_iters"]
     assert iters[8] <= iters[5] <= iters[1], iters
+    for deg, n in iters.items():
+        assert n <= ITER_CEIL["cheb"][(p, j)][deg], iters
 
 
 def test_fma_probe(ctx):

@@ -52,6 +52,8 @@ def test_c5_mixed_precision_error(c5):
     print(f"C5 mixed precision (rtol 1e-6) vs FP64 (rtol 1e-11): rel. M-norm error {err:.3e}; "
           f"iterations {st1['max_iters']} vs {st0['max_iters']}")
     assert err <= 1e-6
+    # measured: 8 iterations (mixed, 1e-6) and 35 (FP64, 1e-11)
+    assert st1["max_iters"] <= 10 and st0["max_iters"] <= 42, (st1["max_iters"], st0["max_iters"])
 
 
 def test_c5_constant_load_closed_form(c5):
