@@ -144,6 +144,19 @@ enum { GF_APPLY_STENCIL = 0, GF_APPLY_SUMFACT = 1 };
 gf_status gf_space_apply(const gf_space *space, double sigma, double s_scale, int32_t nvec, const double *x,
                          double *y, int32_t mem, int32_t kind);
 
+/* gf_space_apply for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  The same operator, y = (sigma M + s_scale S) x
+ * for nvec vectors (kind GF_APPLY_STENCIL or GF_APPLY_SUMFACT), on device arrays x, y ([nvec][N], on
+ * the space's device); no host staging.  The patch-local work vectors live in a per-device static work
+ * space of 256 MiB that the library reserves when it is loaded on a device (registered by
+ * gf_context_create): GF_EINVAL when 2 R L + 2 L doubles exceed it, R the padded patch rows of the
+ * space (npatch (2^level + 3 degree)^2) and L = nvec rounded up to a multiple of 64.  The stencil kind
+ * runs with a fixed launch shape (no tuning pass).  The call returns once the work is queued on the
+ * context's stream (it does not synchronise, so it may be captured); calls that overlap on one GPU
+ * share the work space and race. */
+gf_status gf_space_apply_noalloc(const gf_space *space, double sigma, double s_scale, int32_t nvec,
+                                 const double *x, double *y, int32_t kind);
+
 /* Discrete white noise b = sum_e R_e^T L_e z_e with M_e = L_e L_e^T the lower Cholesky factor of the
  * element mass matrix, so that b ~ N(0, M) when z ~ N(0, I) (Sec. 3.3).  z: [nsamp][noise_length],
  * elements in the order patch, ey, ex (ex fastest), each block of (p+1)^2 entries in element-local

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <sstream>
 #include <type_traits>
 
@@ -1296,6 +1297,43 @@ static SolveResult solve_batch(gf_space *sp, Workspace &w, const SolveSpec &spec
   return b.res;
 }
 
+// ------------------------------------------------------------------ allocation-free operator apply
+// Work space of gf_space_apply_noalloc: a file-scope device array (each GPU holds its own copy, at its
+// own address, for the life of the process).  Host code never uses the array's name as a device
+// address: the device address is looked up once per device (noalloc_register, from gf_context_create,
+// with that device current) and passed to the kernels.  It holds the patch-local input and output
+// batches [R][ldb] and the per-column coefficients; every call overwrites what it reads.
+constexpr size_t kNoAllocBytes = (size_t)256 << 20;
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (device index `device`), looked up once
+static void noalloc_register(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(GF_EDEVICE, "device index above the supported range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  double *ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) fail(GF_EDEVICE, "no device address for the allocation-free work space");
+  g_scratch_ptr[device] = ptr;
+}
+
+static double *noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
+
+__global__ void k_fill2(double *a, double va, double *b, double vb, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    a[i] = va;
+    b[i] = vb;
+  }
+}
+
 }  // namespace gf
 
 using namespace gf;
@@ -1327,6 +1365,7 @@ gf_status gf_context_create(int32_t device, void *hip_stream, gf_context **out) 
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
       fail(GF_EDEVICE, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
     HIPCHK(hipSetDevice(device));
+    noalloc_register(device);
     std::unique_ptr<gf_context> c(new gf_context());
     c->device = device;
     c->stream = (hipStream_t)hip_stream;  // NULL: the device's null stream
@@ -1590,6 +1629,52 @@ gf_status gf_space_apply(const gf_space *csp, double sigma, double s_scale, int3
     apply_level<double>(F, kind, X.p, Y.p, ca.p, cb.p, ldb, nt, nullptr, s);
     local_to_global(F, yout.p, Y.p, nvec, 0, ldb, s);
     finish_out(yout, s);
+  });
+}
+
+gf_status gf_space_apply_noalloc(const gf_space *csp, double sigma, double s_scale, int32_t nvec, const double *x,
+                                 double *y, int32_t kind) {
+  return guarded([&] {
+    gf_space *sp = const_cast<gf_space *>(csp);
+    if (!sp || !x || !y) fail(GF_EINVAL, "null argument");
+    if (nvec < 1) fail(GF_EINVAL, "nvec must be >= 1");
+    if (kind != GF_APPLY_STENCIL && kind != GF_APPLY_SUMFACT) fail(GF_EINVAL, "unknown operator kind");
+    if (!std::isfinite(sigma) || !std::isfinite(s_scale)) fail(GF_EINVAL, "sigma and s_scale must be finite");
+    const Level &F = sp->fine();
+    const int ldb = round_up(nvec, CT), nt = ldb / CT;
+    const size_t need = 2 * (size_t)F.R * ldb + 2 * (size_t)ldb;
+    if (need * sizeof(double) > kNoAllocBytes) {
+      std::ostringstream os;
+      os << "nvec " << nvec << " needs " << need * sizeof(double) << " bytes of work space on this space; the "
+         << "allocation-free apply has " << kNoAllocBytes << " (at most "
+         << (kNoAllocBytes / sizeof(double) - 2 * CT) / (2 * (size_t)F.R + 2) / CT * CT << " vectors)";
+      fail(GF_EINVAL, os.str());
+    }
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    double *base = noalloc_scratch(sp->ctx->device);
+    if (!base) fail(GF_EDEVICE, "allocation-free work space not registered for this device");
+    hipStream_t s = sp->ctx->stream;
+    double *X = base, *Y = base + (size_t)F.R * ldb, *ca = Y + (size_t)F.R * ldb, *cb = ca + ldb;
+    hipLaunchKernelGGL(k_fill2, dim3((ldb + 255) / 256), dim3(256), 0, s, ca, sigma, cb, s_scale, ldb);
+    HIPCHK(hipGetLastError());
+    global_to_local(F, X, x, nvec, ldb, s);
+    if (kind == GF_APPLY_SUMFACT) {
+      launch_sumfact_apply<double>(F, X, Y, ca, cb, ldb, nt, nullptr, s);
+      launch_interface_sum<double>(F, Y, ldb, nt, nullptr, s);
+    } else {
+      // a fixed launch shape: the autotuner would time candidates into buffers of its own
+      ApplyTune t;
+      t.TY = 2;
+      t.TX = 32;
+      EpiArgs<double> e;
+      e.kind = EPI_STORE;
+      e.y = Y;
+      e.nslot = 1;
+      e.rows16 = 1;
+      Scratch none;
+      apply_fused<double>(F, F.stM.p, F.stS.p, X, ca, cb, e, none, nullptr, nullptr, ldb, nt, 0.0, 0, s, t);
+    }
+    local_to_global(F, y, Y, nvec, 0, ldb, s);
   });
 }
 

@@ -90,6 +90,7 @@ _SIGS = {
     "gf_space_noise_length": (_i64, [_vp]),
     "gf_space_dofmap": (_i32, [_vp, _vp]),
     "gf_space_apply": (_i32, [_vp, _dbl, _dbl, _i32, _vp, _vp, _i32, _i32]),
+    "gf_space_apply_noalloc": (_i32, [_vp, _dbl, _dbl, _i32, _vp, _vp, _i32]),
     "gf_white_noise": (_i32, [_vp, _i32, _vp, _vp, _i32]),
     "gf_sample": (_i32, [_vp, _dbl, _dbl, ctypes.POINTER(QuadRule), ctypes.POINTER(SolveOpts), _i32, _vp, _vp,
                          _i32, ctypes.POINTER(SolveStats)]),
@@ -268,6 +269,18 @@ class Space:
         px, mem, keep = _marshal_in(x, nvec * self.ndofs)
         y = _alloc_like(x, x.shape)
         _check(_lib.gf_space_apply(self.h, sigma, s_scale, nvec, px, _ptr(y), mem, kind))
+        return y
+
+    def apply_noalloc(self, sigma, s_scale, x, y, kind=GF_APPLY_STENCIL):
+        """y = (sigma M + s_scale S) x into the preallocated device tensor y (nvec, N), queued on the
+        context's stream without any device allocation."""
+        if not (_is_torch(x) and _is_torch(y)):
+            raise TypeError("x and y must be float64 CUDA tensors")
+        nvec = 1 if len(x.shape) == 1 else x.shape[0]
+        px, mem, keep = _marshal_in(x, nvec * self.ndofs)
+        if y.dtype != x.dtype or not y.is_contiguous() or y.numel() != nvec * self.ndofs or y.device != x.device:
+            raise ValueError("y must be a contiguous float64 tensor of the shape of x on its device")
+        _check(_lib.gf_space_apply_noalloc(self.h, sigma, s_scale, nvec, px, y.data_ptr(), kind))
         return y
 
     def white_noise(self, z):
