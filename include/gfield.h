@@ -340,8 +340,9 @@ void gf_tape_destroy(gf_tape *tape);
  * parameter values give GF_EINVAL before any work. */
 gf_status gf_eval(const gf_space *space, int32_t npts, const int32_t *patch, const double *st, int32_t nvec,
                   const double *u, double *vals, int32_t mem);
-/* Transpose of gf_eval: out = Phi^T r, r: [nvec][npts], out: [nvec][N].  Points that share a
- * coefficient add into it atomically, so the last bits of out may differ between runs. */
+/* Transpose of gf_eval: out = Phi^T r, r: [nvec][npts], out: [nvec][N].  Each coefficient sums the
+ * contributions of the points that touch it in ascending point order (no atomics): the result is the
+ * same bit for bit on every run. */
 gf_status gf_eval_adjoint(const gf_space *space, int32_t npts, const int32_t *patch, const double *st,
                           int32_t nvec, const double *r, double *out, int32_t mem);
 

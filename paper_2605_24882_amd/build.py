@@ -1,7 +1,8 @@
 """Build libgfield.so (HIP for gfx950) in-tree with hipcc.
 
 Usage: python -m paper_2605_24882_amd.build   (or call build()).
-Objects go to paper_2605_24882_amd/_build/, the library to paper_2605_24882_amd/libgfield.so.
+Objects go to paper_2605_24882_amd/_build/, the library to paper_2605_24882_amd/libgfield.so, and the
+operator-kernel timing tool (csrc/kbench.hip, linked against the library) to paper_2605_24882_amd/kbench.
 """
 import concurrent.futures
 import os
@@ -12,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgfield.so")
+KBENCH = os.path.join(HERE, "kbench")  # operator-kernel timing tool (measurement support)
 SOURCES = ["gfield.cpp", "host_spline.cpp", "k_setup.hip", "k_solve.hip", "k_fused.hip", "k_adjoint.hip",
            "k_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -46,6 +48,12 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    cmd = [HIPCC] + COMMON + [os.path.join(CSRC, "kbench.hip"), "-o", KBENCH + ".tmp", "-L" + HERE, "-lgfield",
+                              "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"kbench build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(KBENCH + ".tmp", KBENCH)
     return LIB
 
 

@@ -2261,11 +2261,37 @@ static void run_eval(const gf_space *csp, int npts, const int32_t *patch, const 
   stage_in(a, in, nin, mem, s);
   OutArray o;
   stage_out(o, out, nout, mem);
-  if (adjoint)
-    launch_eval_adjoint(F, npts, pd.p, sd.p, nvec, a.p, o.p, s);
-  else
+  if (adjoint) {
+    // per global coefficient, the (point, basis function) entries that touch it, in ascending point
+    // order: the gather then sums them in that order (no atomics, the same result on every run).  The
+    // element of a point is the one the device's basis evaluation picks (floor(u nel), clamped).
+    const int p = F.p, nb = p + 1, nel = F.nel, n1 = F.n1;
+    std::vector<int> cnt((size_t)F.N + 1, 0);
+    std::vector<int> gids((size_t)npts * nb * nb);
+    for (int i = 0; i < npts; ++i) {
+      const int ex = std::min(std::max((int)std::floor(sh[2 * i] * nel), 0), nel - 1);
+      const int ey = std::min(std::max((int)std::floor(sh[2 * i + 1] * nel), 0), nel - 1);
+      for (int aa = 0; aa < nb; ++aa)
+        for (int bb = 0; bb < nb; ++bb) {
+          const int gid = F.l2g[((size_t)ph[i] * n1 + ey + aa) * n1 + ex + bb];
+          gids[(size_t)i * nb * nb + aa * nb + bb] = gid;
+          cnt[(size_t)gid + 1] += 1;
+        }
+    }
+    for (int gi = 0; gi < F.N; ++gi) cnt[(size_t)gi + 1] += cnt[gi];
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1), ent(std::max<size_t>(1, gids.size()));
+    for (size_t k = 0; k < gids.size(); ++k) ent[fill[gids[k]]++] = (int)k;
+    DBuf<int> dptr, dent;
+    DBuf<double> w;
+    dptr.upload(cnt, s);
+    dent.upload(ent, s);
+    w.alloc(std::max<size_t>(1, gids.size()));
+    launch_eval_adjoint(F, npts, sd.p, dptr.p, dent.p, w.p, nvec, a.p, o.p, s);
+    finish_out(o, s);  // synchronises before the work arrays are released
+  } else {
     launch_eval(F, npts, pd.p, sd.p, nvec, a.p, o.p, s);
-  finish_out(o, s);
+    finish_out(o, s);
+  }
 }
 
 // The identity of the global unknowns as a patch stencil: centre coefficient 1/(number of copies)

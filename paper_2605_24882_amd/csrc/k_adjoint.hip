@@ -71,27 +71,36 @@ __global__ __launch_bounds__(256) void k_eval(EvalGeom g, const int *__restrict_
   }
 }
 
-// out[v][gid] += B(s_i, t_i) r[v][i] over all points (out zeroed by the caller).  Several points
-// can share a coefficient, so the additions are atomic: the summation order, and with it the last
-// bits of the result, may vary from run to run.
-__global__ __launch_bounds__(256) void k_eval_adjoint(EvalGeom g, const int *__restrict__ patch,
-                                                      const double *__restrict__ st, const int *__restrict__ row_gid,
-                                                      const double *__restrict__ r, double *out) {
+// The transpose Phi^T r without atomics, in two passes.  Pass 1: the (p+1)^2 basis products of every
+// point, w[i][a (p+1) + b] = B_a(t_i) B_b(s_i).  Pass 2: one thread per (global coefficient, vector)
+// sums w r over the entries the host listed for that coefficient, in ascending point order: the
+// result does not depend on the scheduling and is the same bit for bit on every run.
+__global__ __launch_bounds__(256) void k_eval_weights(EvalGeom g, const double *__restrict__ st, double *__restrict__ w) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.npts) return;
   double bs[6], bt[6];
-  const int ex = span_basis<5>(st[2 * i], g.p, g.nel, bs);
-  const int ey = span_basis<5>(st[2 * i + 1], g.p, g.nel, bt);
-  const int64_t base = (int64_t)patch[i] * g.W * g.W;
-  for (int v = 0; v < g.nvec; ++v) {
-    const double rv = r[(int64_t)v * g.npts + i];
-    double *ov = out + (int64_t)v * g.N;
-    for (int a = 0; a <= g.p; ++a)
-      for (int b = 0; b <= g.p; ++b) {
-        const int gid = row_gid[base + (int64_t)(ey + a + g.p) * g.W + (ex + b + g.p)];
-        atomicAdd(ov + gid, bt[a] * bs[b] * rv);
-      }
+  span_basis<5>(st[2 * i], g.p, g.nel, bs);
+  span_basis<5>(st[2 * i + 1], g.p, g.nel, bt);
+  const int nb = g.p + 1;
+  for (int a = 0; a <= g.p; ++a)
+    for (int b = 0; b <= g.p; ++b) w[(int64_t)i * nb * nb + a * nb + b] = bt[a] * bs[b];
+}
+
+// out[v][gid] = sum over the entries e of gid (ptr[gid] .. ptr[gid+1], ascending point order) of
+// w[ent[e]] r[v][ent[e] / (p+1)^2]; coefficients no point touches get 0
+__global__ __launch_bounds__(256) void k_eval_gather(EvalGeom g, const int *__restrict__ ptr, const int *__restrict__ ent,
+                                                     const double *__restrict__ w, const double *__restrict__ r,
+                                                     double *__restrict__ out) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)g.N * g.nvec) return;
+  const int gid = (int)(id % g.N), v = (int)(id / g.N);
+  const int nb2 = (g.p + 1) * (g.p + 1);
+  double acc = 0.0;
+  for (int e = ptr[gid]; e < ptr[gid + 1]; ++e) {
+    const int k = ent[e];
+    acc += w[k] * r[(int64_t)v * g.npts + k / nb2];
   }
+  out[(int64_t)v * g.N + gid] = acc;
 }
 
 void launch_eval(const Level &L, int npts, const int *patch, const double *st, int nvec, const double *u,
@@ -102,12 +111,13 @@ void launch_eval(const Level &L, int npts, const int *patch, const double *st, i
   HIPCHK(hipGetLastError());
 }
 
-void launch_eval_adjoint(const Level &L, int npts, const int *patch, const double *st, int nvec, const double *r,
-                         double *out, hipStream_t s) {
-  HIPCHK(hipMemsetAsync(out, 0, (size_t)nvec * L.N * sizeof(double), s));
-  if (npts == 0 || nvec == 0) return;
+void launch_eval_adjoint(const Level &L, int npts, const double *st, const int *ptr, const int *ent, double *w,
+                         int nvec, const double *r, double *out, hipStream_t s) {
+  if (nvec == 0) return;
   EvalGeom g{L.p, L.nel, L.W, L.N, npts, nvec};
-  hipLaunchKernelGGL(k_eval_adjoint, dim3((npts + 255) / 256), dim3(256), 0, s, g, patch, st, L.row_gid.p, r, out);
+  if (npts > 0) hipLaunchKernelGGL(k_eval_weights, dim3((npts + 255) / 256), dim3(256), 0, s, g, st, w);
+  const int64_t tot = (int64_t)L.N * nvec;
+  hipLaunchKernelGGL(k_eval_gather, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g, ptr, ent, w, r, out);
   HIPCHK(hipGetLastError());
 }
 

@@ -166,116 +166,153 @@ void launch_metric(const Level &L, const SurfaceArgs &g, const double *gx, const
 }
 
 // ------------------------------------------------------------------ matrix-free apply
-// y = (ca M + cb S) x per column, patch by patch (no interface sum), evaluating the
-// element integrals of eq. mass / eq. stiffness at the q x q Gauss points on the fly.
-// One wavefront per block; lane = column of a 64-wide column tile.  A block owns a
-// TT x TT tile of output coefficients and visits every element touching it.  Per element
-// (sum factorisation, q = p+1):
+// y = (ca M + cb S) x per column, patch by patch (no interface sum), evaluating the element integrals of
+// eq. mass / eq. stiffness at the Q x Q Gauss points on the fly (sum factorisation).  Per element
+// (NB = p+1 basis functions per direction, coefficients c[b][a], b along t, a along s):
 //   U0[b][qx] = sum_a c[b][a] Bx[qx][a],  U1[b][qx] = sum_a c[b][a] Dx[qx][a]
-//   u = sum_b U0 By, us = sum_b U1 By, ut = sum_b U0 Dy                     (at each qy, qx)
+//   u = sum_b U0 By, us = sum_b U1 By, ut = sum_b U0 Dy                        (at each qy, qx)
 //   v = ca m u,  gs = cb (G11 us + G12 ut),  gt = cb (G12 us + G22 ut)
 //   V0[b][qx] = sum_qy v By + gt Dy,  V1[b][qx] = sum_qy gs By
-//   y[b][a] += sum_qx V0 Bx + V1 Dx
-// Basis tables and metric terms are uniform over the wavefront.  Accumulators live in
-// LDS, one column per lane, so no barrier is needed.
-template <typename T, int P, int Q, int TT>
-__global__ __launch_bounds__(64) void k_sumfact(const T *__restrict__ metric, const T *__restrict__ basis,
-                                                const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ ca,
-                                                const T *__restrict__ cb, int nel, int n1, int W, int ldb,
-                                                const int *__restrict__ active, int ntx) {
-  constexpr int NB = P + 1;
-  const int ct = blockIdx.y;
-  if (active && !active[ct]) return;
-  const int lane = threadIdx.x;
-  const int col = ct * CT + lane;
-  const int tile = blockIdx.x;
-  const int tx = tile % ntx;
-  const int ty = (tile / ntx) % ntx;
-  const int m = tile / (ntx * ntx);
-  const int x0 = tx * TT, y0 = ty * TT;
-  __shared__ T acc[TT * TT][CT];
-#pragma unroll
-  for (int i = 0; i < TT * TT; ++i) acc[i][lane] = T(0);
-  const T sig = ca[col], ss = cb[col];
+//   y_e[b][a] = sum_qx V0 Bx + V1 Dx
+// (evaluated one quadrature column qx at a time: only NB-long intermediates are live)
+// Every element is evaluated once.  Element rows are coloured by ey mod NB: the rows of one colour
+// touch disjoint coefficient rows (ey .. ey+p), so one launch per colour adds them into y (zeroed
+// first) without atomics, in a fixed order.  A block runs one element row of one patch for four column
+// tiles (one wavefront each, lane = column): the four share each element's metric terms and basis
+// tables Bx, Dx, staged in LDS a chunk of elements at a time (the row's By, Dy are uniform loads).  Along the row a wavefront keeps the NB x NB
+// coefficients of the current element and an NB-column ring of output sums in registers; column ex
+// is complete once element ex is done and is added to y.
+constexpr int kSfChunk = 16;  // elements staged per LDS chunk
+
+template <typename T, int P, int Q>
+__global__ __launch_bounds__(256) void k_sumfact(const T *__restrict__ metric, const T *__restrict__ basis,
+                                                 const T *__restrict__ x, T *__restrict__ y, const T *__restrict__ ca,
+                                                 const T *__restrict__ cb, int nel, int n1, int W, int ldb, int ntiles,
+                                                 const int *__restrict__ active, int colour, int nrow, int np) {
+  constexpr int NB = P + 1, QQ = Q * Q, BT = Q * NB;  // BT: one basis table (Q points x NB functions)
+  constexpr int CHUNK = kSfChunk;
+  __shared__ T sm[CHUNK][QQ * 4];       // metric terms of the chunk's elements
+  __shared__ T sb[CHUNK][2 * BT];       // Bx, Dx of the chunk's elements
+  const int ntg = (ntiles + 3) / 4;
+  const int tg = blockIdx.x % ntg, rr = (blockIdx.x / ntg) % nrow, m = blockIdx.x / (ntg * nrow);
+  if (m >= np) return;
+  const int ey = colour + rr * NB;
+  if (ey >= nel) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int ct = tg * 4 + wave;
+  const bool on = ct < ntiles && (!active || active[ct]);
+  const int64_t col = (int64_t)ct * CT + lane;
+  // the row's basis tables By, Dy are the same for every element of the row: uniform loads (scalar
+  // registers); the metric terms and Bx, Dx change per element and are staged in LDS
+  const T *By = basis + (size_t)ey * 2 * BT, *Dy = By + BT;
+  const T sig = on ? ca[col] : T(0), ss = on ? cb[col] : T(0);
   const int64_t prow = (int64_t)m * W * W;
-  const int ey0 = max(0, y0 - P), ey1 = min(nel - 1, y0 + TT - 1);
-  const int ex0 = max(0, x0 - P), ex1 = min(nel - 1, x0 + TT - 1);
-  for (int ey = ey0; ey <= ey1; ++ey) {
-    const T *By = basis + (size_t)ey * 2 * Q * NB;
-    const T *Dy = By + Q * NB;
-    for (int ex = ex0; ex <= ex1; ++ex) {
-      const T *Bx = basis + (size_t)ex * 2 * Q * NB;
-      const T *Dx = Bx + Q * NB;
-      T c[NB][NB];
+  // coefficient rows ey .. ey+p of the patch (padded rows ey+P .. ey+2P, columns shifted by P)
+  auto xat = [&](int b, int a) { return x[(prow + (int64_t)(ey + b + P) * W + (a + P)) * ldb + col]; };
+  auto yadd = [&](int b, int a, T v) {
+    T *py = y + (prow + (int64_t)(ey + b + P) * W + (a + P)) * ldb + col;
+    *py += v;
+  };
+  T c[NB][NB], ring[NB][NB];  // ring[b][k]: output column (ex + k) mod NB of coefficient row ey + b
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+  for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int a = 0; a < NB; ++a)
-          c[b][a] = x[(prow + (int64_t)(ey + b + P) * W + (ex + a + P)) * ldb + col];
-      T U0[NB][Q], U1[NB][Q];
+    for (int k = 0; k < NB; ++k) ring[b][k] = T(0);
+  if (on) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int qx = 0; qx < Q; ++qx) {
+      for (int a = 0; a < P; ++a) c[b][a + 1] = xat(b, a);  // columns 0 .. P-1, shifted in below
+  }
+  for (int e0 = 0; e0 < nel; e0 += CHUNK) {
+    const int ne = min(CHUNK, nel - e0);
+    __syncthreads();  // the previous chunk's reads are done
+    for (int k = threadIdx.x; k < ne * QQ * 4; k += 256)
+      sm[k / (QQ * 4)][k % (QQ * 4)] = metric[((((size_t)m * nel + ey) * nel + e0) * QQ) * 4 + k];
+    for (int k = threadIdx.x; k < ne * 2 * BT; k += 256)
+      sb[k / (2 * BT)][k % (2 * BT)] = basis[(size_t)e0 * 2 * BT + k];
+    __syncthreads();
+    if (!on) continue;
+    for (int el = 0; el < ne; ++el) {
+      const int ex = e0 + el;
+      // the element's coefficient window: shift by one column, load column ex + P
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int a = 0; a < P; ++a) c[b][a] = c[b][a + 1];
+        c[b][P] = xat(b, ex + P);
+      }
+      const T *Bx = sb[el], *Dx = sb[el] + BT, *mt = sm[el];
+      // one quadrature column qx at a time (only NB-long intermediates live); local column a of the
+      // element is output column ex + a, ring slot a
+#pragma unroll 1
+      for (int qx = 0; qx < Q; ++qx) {
+        T U0[NB], U1[NB], V0[NB], V1[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
           T s0 = 0, s1 = 0;
 #pragma unroll
           for (int a = 0; a < NB; ++a) {
-            s0 += c[b][a] * Bx[qx * NB + a];
-            s1 += c[b][a] * Dx[qx * NB + a];
+            s0 = fma(c[b][a], Bx[qx * NB + a], s0);
+            s1 = fma(c[b][a], Dx[qx * NB + a], s1);
           }
-          U0[b][qx] = s0;
-          U1[b][qx] = s1;
+          U0[b] = s0;
+          U1[b] = s1;
+          V0[b] = 0;
+          V1[b] = 0;
         }
-      const T *mt = metric + ((((size_t)m * nel + ey) * nel + ex) * Q * Q) * 4;
-      T V0[NB][Q], V1[NB][Q];
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int qx = 0; qx < Q; ++qx) { V0[b][qx] = 0; V1[b][qx] = 0; }
-#pragma unroll
-      for (int qy = 0; qy < Q; ++qy)
-#pragma unroll
-        for (int qx = 0; qx < Q; ++qx) {
+        for (int qy = 0; qy < Q; ++qy) {
           T u = 0, us = 0, ut = 0;
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            u += U0[b][qx] * By[qy * NB + b];
-            us += U1[b][qx] * By[qy * NB + b];
-            ut += U0[b][qx] * Dy[qy * NB + b];
+            u = fma(U0[b], By[qy * NB + b], u);
+            us = fma(U1[b], By[qy * NB + b], us);
+            ut = fma(U0[b], Dy[qy * NB + b], ut);
           }
-          const T *g = mt + (qy * Q + qx) * 4;
-          const T v = sig * g[0] * u;
-          const T gs = ss * (g[1] * us + g[2] * ut);
-          const T gt = ss * (g[2] * us + g[3] * ut);
+          const T *gq = mt + (qy * Q + qx) * 4;
+          const T v = sig * gq[0] * u;
+          const T gs = ss * (gq[1] * us + gq[2] * ut);
+          const T gt = ss * (gq[2] * us + gq[3] * ut);
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            V0[b][qx] += v * By[qy * NB + b] + gt * Dy[qy * NB + b];
-            V1[b][qx] += gs * By[qy * NB + b];
+            V0[b] = fma(v, By[qy * NB + b], fma(gt, Dy[qy * NB + b], V0[b]));
+            V1[b] = fma(gs, By[qy * NB + b], V1[b]);
           }
         }
 #pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+            ring[b][a] = fma(V0[b], Bx[qx * NB + a], fma(V1[b], Dx[qx * NB + a], ring[b][a]));
+      }
+      // output column ex is complete: add it to y and rotate the ring by one column
+#pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const int iy = ey + b - y0;
-        if (iy < 0 || iy >= TT) continue;
+        yadd(b, ex, ring[b][0]);
 #pragma unroll
-        for (int a = 0; a < NB; ++a) {
-          const int ix = ex + a - x0;
-          if (ix < 0 || ix >= TT) continue;
-          T r = 0;
-#pragma unroll
-          for (int qx = 0; qx < Q; ++qx) r += V0[b][qx] * Bx[qx * NB + a] + V1[b][qx] * Dx[qx * NB + a];
-          acc[iy * TT + ix][lane] += r;
-        }
+        for (int k = 0; k < P; ++k) ring[b][k] = ring[b][k + 1];
+        ring[b][P] = T(0);
       }
     }
   }
-  for (int iy = 0; iy < TT; ++iy) {
-    if (y0 + iy >= n1) break;
-    for (int ix = 0; ix < TT; ++ix) {
-      if (x0 + ix >= n1) break;
-      y[(prow + (int64_t)(y0 + iy + P) * W + (x0 + ix + P)) * ldb + col] = acc[iy * TT + ix][lane];
-    }
+  if (on) {
+    // the row's last P output columns nel .. nel+P-1
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int k = 0; k < P; ++k) yadd(b, nel + k, ring[b][k]);
   }
+}
+
+// y = 0 on the rows of the patches, active column tiles
+template <typename T>
+__global__ void k_zero_rows(T *y, int64_t R, int ldb, int ntiles, const int *active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * ldb) return;
+  const int ct = (int)(i % ldb) / CT;
+  if (active && !active[ct]) return;
+  y[i] = T(0);
 }
 
 template <typename T>
@@ -294,25 +331,30 @@ const float *basis_of<float>(const Level &L) { return L.basis32.p; }
 template <typename T>
 void launch_sumfact_apply(const Level &L, const T *x, T *y, const T *ca, const T *cb, int ldb, int ntiles,
                           const int *active, hipStream_t s) {
-  constexpr int TT = 8;
-  const int ntx = (L.n1 + TT - 1) / TT;
-  dim3 grid(L.npatch * ntx * ntx, ntiles), block(CT);
   const T *mt = metric_of<T>(L), *bs = basis_of<T>(L);
   if (L.q != L.p + 1 && L.q != L.p + 2) fail(GF_EUNSUPPORTED, "quadrature order out of range");
   const bool q2 = L.q == L.p + 2;
-  switch (L.p) {
-#define GF_SF(PP)                                                                                                \
-  case PP:                                                                                                       \
-    if (q2)                                                                                                      \
-      hipLaunchKernelGGL((k_sumfact<T, PP, PP + 2, TT>), grid, block, 0, s, mt, bs, x, y, ca, cb, L.nel, L.n1, L.W, \
-                         ldb, active, ntx);                                                                      \
-    else                                                                                                         \
-      hipLaunchKernelGGL((k_sumfact<T, PP, PP + 1, TT>), grid, block, 0, s, mt, bs, x, y, ca, cb, L.nel, L.n1, L.W, \
-                         ldb, active, ntx);                                                                      \
+  const int64_t tot = L.R * ldb;
+  hipLaunchKernelGGL(k_zero_rows<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, y, L.R, ldb, ntiles,
+                     active);
+  const int NB = L.p + 1, ntg = (ntiles + 3) / 4;
+  for (int colour = 0; colour < NB && colour < L.nel; ++colour) {
+    const int nrow = (L.nel - colour + NB - 1) / NB;
+    const dim3 grid((unsigned)(L.npatch * nrow * ntg)), block(256);
+    switch (L.p) {
+#define GF_SF(PP)                                                                                              \
+  case PP:                                                                                                     \
+    if (q2)                                                                                                    \
+      hipLaunchKernelGGL((k_sumfact<T, PP, PP + 2>), grid, block, 0, s, mt, bs, x, y, ca, cb, L.nel, L.n1, L.W, \
+                         ldb, ntiles, active, colour, nrow, L.npatch);                                         \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_sumfact<T, PP, PP + 1>), grid, block, 0, s, mt, bs, x, y, ca, cb, L.nel, L.n1, L.W, \
+                         ldb, ntiles, active, colour, nrow, L.npatch);                                         \
     break;
-    GF_SF(1) GF_SF(2) GF_SF(3) GF_SF(4) GF_SF(5)
+      GF_SF(1) GF_SF(2) GF_SF(3) GF_SF(4) GF_SF(5)
 #undef GF_SF
-    default: fail(GF_EUNSUPPORTED, "degree out of range");
+      default: fail(GF_EUNSUPPORTED, "degree out of range");
+    }
   }
   HIPCHK(hipGetLastError());
 }

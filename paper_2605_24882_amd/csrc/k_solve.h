@@ -39,7 +39,12 @@ __device__ inline void finalize_col(int op, int col, const double *tot, ColState
       c.flag = 0;
       c.alpha = 0;
       c.beta = 0;
-      c.done = (c.done || !(tot[0] > 0.0)) ? 1 : 0;
+      if (!isfinite(tot[0])) {  // a load that is not finite: CG cannot start
+        c.flag |= 2;
+        c.done = 1;
+      } else {
+        c.done = (c.done || !(tot[0] > 0.0)) ? 1 : 0;
+      }
       break;
     case OP_RZ0:
       c.rz = tot[0];
@@ -219,11 +224,13 @@ void quadrature_sum(const Level &L, double *u, const double *X, const double *om
                     hipStream_t s);
 void launch_to_f32(const double *a, float *b, int64_t n, hipStream_t s);
 void launch_white_noise(const Level &L, const double *z, int nsamp, double *ye, double *bl, int ldb, hipStream_t s);
-// point evaluation Phi u (vals [nvec][npts]) and its transpose Phi^T r (out [nvec][N], zeroed first)
+// point evaluation Phi u (vals [nvec][npts]) and its transpose Phi^T r (out [nvec][N], every entry
+// written): ptr [N+1] / ent list, per global coefficient in ascending point order, the entries
+// i (p+1)^2 + a (p+1) + b of the points whose basis functions (a, b) it is; w [npts (p+1)^2] is work space
 void launch_eval(const Level &L, int npts, const int *patch, const double *st, int nvec, const double *u,
                  double *vals, hipStream_t s);
-void launch_eval_adjoint(const Level &L, int npts, const int *patch, const double *st, int nvec, const double *r,
-                         double *out, hipStream_t s);
+void launch_eval_adjoint(const Level &L, int npts, const double *st, const int *ptr, const int *ent, double *w,
+                         int nvec, const double *r, double *out, hipStream_t s);
 // acc[s] += sum_k w[k] dots[k*nsamp + s];  out[s] = c acc[s]
 void grad_accum(const double *dots, const double *w, int K, int nsamp, double *acc, hipStream_t s);
 void grad_scale(const double *acc, int nsamp, double c, double *out, hipStream_t s);

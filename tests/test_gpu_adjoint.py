@@ -65,6 +65,27 @@ def test_eval_and_adjoint_match_oracle(ctx, p, j, pert):
     out = sp.eval_adjoint(patch, st, r)
     ref_t = np.stack([Phi.T @ v for v in r])
     assert np.abs(out - ref_t).max() <= 1e-13 * np.abs(ref_t).max()
+    # the transpose sums each coefficient's points in a fixed order: identical on every call
+    for _ in range(3):
+        assert np.array_equal(sp.eval_adjoint(patch, st, r), out)
+
+
+def test_grad_kappa_is_reproducible(ctx):
+    """dL/dkappa from the same tape and loss is the same bit for bit on every call (no atomics in the
+    transpose of the point evaluation, fixed-order reductions in the solver)."""
+    import torch
+    geo, sp, d = setup(ctx, 3, 3)
+    pts, y, patch, st = points(geo, 500)
+    z = torch.from_numpy(inputs.noise_vectors([3, 4, 5], sp.noise_length)).cuda()
+    b = sp.white_noise(z)
+    yt = torch.from_numpy(y).cuda()
+    grads = []
+    for _ in range(3):
+        u, tape, _ = sp.sample_tape(4.0, 1.6, b, h=0.4, k_minus=10, k_plus=10, precision=1, rtol=1e-8)
+        gk, _ = tape.grad_kappa(sp.eval_adjoint(patch, st, sp.eval(patch, st, u) - yt[None, :]))
+        tape.close()
+        grads.append(gk.cpu().numpy())
+    assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[0], grads[2])
 
 
 def test_eval_rejects_bad_points(ctx):
