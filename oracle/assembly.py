@@ -100,28 +100,27 @@ class Discretisation:
             W = np.outer(np.tile(self.wq, ne), np.tile(self.wq, ne))  # [t-point, s-point]
             det = k11 * k22 - k12 * k12
             g11, g12, g22 = k22 / det, -k12 / det, k11 / det  # K^{-1}
-            for ey in range(ne):
-                for ex in range(ne):
-                    sl_t = slice(ey * q, (ey + 1) * q)
-                    sl_s = slice(ex * q, (ex + 1) * q)
-                    wa = (W * a)[sl_t, sl_s]  # (qy, qx)
-                    G11, G12, G22 = g11[sl_t, sl_s], g12[sl_t, sl_s], g22[sl_t, sl_s]
-                    Bx, Dx = self.B1[ex], self.D1[ex]  # (qx, a)
-                    By, Dy = self.B1[ey], self.D1[ey]  # (qy, b)
-                    # phi_(b,a)(qy,qx) = By[qy,b] Bx[qx,a]; d/ds and d/dt of it
-                    phi = np.einsum("yb,xa->yxba", By, Bx).reshape(q, q, nloc)
-                    phs = np.einsum("yb,xa->yxba", By, Dx).reshape(q, q, nloc)
-                    pht = np.einsum("yb,xa->yxba", Dy, Bx).reshape(q, q, nloc)
-                    Me = np.einsum("yx,yxi,yxj->ij", wa, phi, phi)
-                    Se = (np.einsum("yx,yxi,yxj->ij", wa * G11, phs, phs)
-                          + np.einsum("yx,yxi,yxj->ij", wa * G12, phs, pht)
-                          + np.einsum("yx,yxi,yxj->ij", wa * G12, pht, phs)
-                          + np.einsum("yx,yxi,yxj->ij", wa * G22, pht, pht))
-                    el_M.append(Me)
-                    el_S.append(Se)
+            # the same element integrals for all elements of the patch at once: quadrature arrays
+            # reshaped to [ey, ex, qy, qx], basis tables By[ey, qy, b], Bx[ex, qx, a] (eq. mass and
+            # eq. stiffness with phi_(b,a) = By Bx, d/ds phi = By Dx, d/dt phi = Dy Bx)
+            def per_el(f):
+                return f.reshape(ne, q, ne, q).transpose(0, 2, 1, 3)
+
+            wa = per_el(W * a)
+            G11, G12, G22 = per_el(g11), per_el(g12), per_el(g22)
+            B, D = self.B1, self.D1
+
+            def form(w, Ly, Lx, Ry, Rx):
+                """sum over (qy, qx) of w Ly[ey,qy,b] Lx[ex,qx,a] Ry[ey,qy,c] Rx[ex,qx,d] -> [(ey,ex),(b,a),(c,d)]"""
+                t = np.einsum("EXyx,Eyb,Xxa,Eyc,Xxd->EXbacd", w, Ly, Lx, Ry, Rx, optimize=True)
+                return t.reshape(ne * ne, nloc, nloc)
+
+            el_M.append(form(wa, B, B, B, B))
+            el_S.append(form(wa * G11, B, D, B, D) + form(wa * G12, B, D, D, B) + form(wa * G12, D, B, B, D)
+                        + form(wa * G22, D, B, D, B))
         self.el_dofs = np.array(el_dofs)
-        self.el_M = np.array(el_M)
-        self.el_S = np.array(el_S)
+        self.el_M = np.concatenate(el_M)
+        self.el_S = np.concatenate(el_S)
 
     def _assemble(self):
         """Sum element matrices into sparse global M and S (eq. FEM)."""
