@@ -233,13 +233,17 @@ typedef struct {
                               column of the tiles the launch processes and patch row, plus the two
                               stencils per row), summed; the launches of the first preconditioner
                               application before the CG loop are included */
+  int32_t host_syncs;      /* times the host waited for the stream inside the CG loops of the call (one per
+                              replayed chunk of CG iterations, one per iteration when eager) */
 } gf_solve_stats;
 
 /* flags */
 #define GF_FLAG_MASS_SHIFT 4 /* gf_solve_shifted: the operator is M + sigma I (I the identity of the global
                                  unknowns), sigma >= 0, solved by Jacobi-preconditioned CG in FP64 (the
                                  shifted mass systems of gf_sqrt_mass) */
-#define GF_FLAG_NO_GRAPH 2   /* enqueue every CG iteration eagerly instead of replaying a captured HIP graph */
+#define GF_FLAG_NO_GRAPH 2   /* enqueue every CG iteration eagerly instead of replaying captured HIP graphs
+                                 (by default chunks of four CG iterations of every batch of the call are
+                                 captured as one graph, kept for later calls with the same batches) */
 #define GF_FLAG_TIME_APPLY 1 /* bracket each outer-CG operator launch and each finest-level smoothing
                                  launch of the dominant batch (the sinc nodes; the integer solves when
                                  beta is an integer) with HIP events; iterations are then enqueued

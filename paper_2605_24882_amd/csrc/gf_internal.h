@@ -159,6 +159,19 @@ struct gf_context {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // Instantiated HIP graphs of chunks of CG iterations, by batch configuration (kept across calls; a
+  // graph is dropped when a space it uses is destroyed, the least recently used beyond a bound)
+  struct Graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> spaces;
+    uint64_t last = 0;
+  };
+  std::map<std::string, Graph> graphs;
+  uint64_t graph_clock = 0;
+  int *flag_dev = nullptr;   // 1 while some column tile of the last chunk's batches is still active
+  int *flag_host = nullptr;  // its pinned host copy
+  int64_t host_syncs = 0;    // host synchronisations with the stream inside CG loops (statistics)
 };
 
 struct gf_geometry {

@@ -1182,11 +1182,66 @@ static std::vector<hipStream_t> &side_streams(gf_context *ctx, size_t n) {
   return v;
 }
 
-// Runs the CG iterations of all batches together.  The first iteration is enqueued eagerly (it
-// also runs the launch-shape autotuner); then one iteration of every batch is captured into a single
-// HIP graph -- one branch per batch, forked from and joined back into the context stream -- and the
-// graph is launched until every system of every batch has converged (active tiles are read back after
-// each launch; converged column tiles exit at the top of every kernel).
+// "some column tile still active" into one word: zeroed at the start of a chunk, set by any tile
+__global__ void k_flag_zero(int *flag) { *flag = 0; }
+__global__ void k_flag_any(const int *active, int n, int *flag) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x)
+    if (active[t]) *flag = 1;
+}
+
+constexpr int kGraphChunk = 4;    // CG iterations per captured graph
+constexpr size_t kMaxGraphs = 32;  // instantiated graphs kept per context
+
+// Identity of a captured chunk: everything its kernels take as arguments -- the batches' spaces,
+// plans, workspaces and their buffers, and the solver settings baked into the launches.
+static std::string graph_key(const std::vector<BatchSolve *> &items, int chunk) {
+  std::ostringstream os;
+  os.precision(17);
+  os << chunk;
+  for (const BatchSolve *it : items) {
+    const Workspace &w = *it->w;
+    const SolveSpec &sp = it->spec;
+    os << "|" << (const void *)it->sp << "," << (const void *)sp.plan << "," << (const void *)&w << "," << w.ldb
+       << "," << sp.prec << "," << sp.kind << "," << sp.cheb << "," << sp.rtol << "," << sp.max_iter << ","
+       << sp.flags << "," << sp.precond << "," << sp.mass_shift << "," << sp.smooth_load << "," << w.nslot << ","
+       << w.rows16 << "," << (const void *)w.x.p << "," << (const void *)w.r.p << "," << (const void *)w.p.p << ","
+       << (const void *)w.q.p << "," << (const void *)w.cs.p << "," << (const void *)w.partial.p << ","
+       << (const void *)w.active.p << "," << (const void *)w.sig64.p;
+    if (sp.plan) os << "," << (const void *)sp.plan->Ainv.p;
+    for (const LevelWork &l : w.lw)
+      os << "," << (const void *)l.z64a.p << (const void *)l.z32a.p << (const void *)l.cf64.p << (const void *)l.cf32.p;
+  }
+  return os.str();
+}
+
+static void graph_destroy(gf_context::Graph &gr) {
+  if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+  if (gr.graph) (void)hipGraphDestroy(gr.graph);
+  gr.exec = nullptr;
+  gr.graph = nullptr;
+}
+
+// drop the cached graphs that use space sp (its workspaces are about to be freed)
+static void drop_graphs_of(gf_context *ctx, const gf_space *sp) {
+  if (!ctx) return;
+  for (auto it = ctx->graphs.begin(); it != ctx->graphs.end();) {
+    if (std::find(it->second.spaces.begin(), it->second.spaces.end(), (const void *)sp) != it->second.spaces.end()) {
+      graph_destroy(it->second);
+      it = ctx->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+// Runs the CG iterations of all batches together.  The first iteration is enqueued eagerly (it also
+// runs the launch-shape autotuner).  Then kGraphChunk iterations of every batch are captured into one
+// HIP graph -- one branch per batch, forked from and joined back into the capture stream, each branch
+// running its batch's iterations in sequence -- followed by the reduction of every batch's active-tile
+// flags into one word.  The graph is replayed until no tile is active: one read-back of that word and
+// one host synchronisation per chunk.  Converged column tiles exit at the top of every kernel, so the
+// iterations of a chunk after convergence cost only their launches.  Instantiated graphs are kept in
+// the context, keyed by everything their launches take as arguments, and reused by later calls.
 static void solve_all(gf_context *ctx, std::vector<BatchSolve *> &items, bool use_graph) {
   hipStream_t s = ctx->stream;
   for (auto *it : items) {
@@ -1204,6 +1259,7 @@ static void solve_all(gf_context *ctx, std::vector<BatchSolve *> &items, bool us
       items[i]->read_active(s);
     }
     HIPCHK(hipStreamSynchronize(s));
+    ctx->host_syncs += 1;
     for (size_t i = 0; i < items.size(); ++i) items[i]->harvest_events(prev[i], items[i]->active_tiles());
     for (auto *it : items)
       for (int t = 0; t < it->w->ntiles; ++t) any = any || it->w->active_h[t];
@@ -1240,48 +1296,68 @@ static void solve_all(gf_context *ctx, std::vector<BatchSolve *> &items, bool us
     for (auto *it : items) it->collect();
     return;
   }
-  // capture one iteration of every batch
-  std::vector<hipEvent_t> evpairs(2 * items.size(), nullptr);
-  for (size_t i = 0; i < items.size(); ++i) items[i]->new_event_pair(&evpairs[2 * i], &evpairs[2 * i + 1]);
-  std::vector<hipEvent_t> joins(items.size());
-  hipEvent_t fork;
-  HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-  for (auto &j : joins) HIPCHK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
-  // capture on a side stream (the context stream may be the null stream, which cannot capture);
-  // the graph is launched on the context stream, after all of its earlier work
-  std::vector<hipStream_t> &side = side_streams(ctx, items.size() + 1);
-  hipStream_t cap = side[0];
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
-  try {
-    if (items.size() == 1) {
-      items[0]->iterate(cap, evpairs[0], evpairs[1]);
-    } else {
+  if (!ctx->flag_dev) {
+    HIPCHK(hipMalloc((void **)&ctx->flag_dev, sizeof(int)));
+    HIPCHK(hipHostMalloc((void **)&ctx->flag_host, sizeof(int), hipHostMallocDefault));
+  }
+  const std::string key = graph_key(items, kGraphChunk);
+  auto found = ctx->graphs.find(key);
+  if (found == ctx->graphs.end()) {
+    for (auto *it : items) it->w->slog = nullptr;
+    // capture on a side stream (the context stream may be the null stream, which cannot capture); the
+    // graph is launched on the context stream, after all of its earlier work
+    std::vector<hipStream_t> &side = side_streams(ctx, items.size() + 1);
+    hipStream_t cap = side[0];
+    std::vector<hipEvent_t> joins(items.size());
+    hipEvent_t fork;
+    HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    for (auto &j : joins) HIPCHK(hipEventCreateWithFlags(&j, hipEventDisableTiming));
+    gf_context::Graph gr;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+    try {
+      hipLaunchKernelGGL(k_flag_zero, dim3(1), dim3(1), 0, cap, ctx->flag_dev);
       HIPCHK(hipEventRecord(fork, cap));
       for (size_t i = 0; i < items.size(); ++i) {
         HIPCHK(hipStreamWaitEvent(side[i + 1], fork, 0));
-        items[i]->iterate(side[i + 1], evpairs[2 * i], evpairs[2 * i + 1]);
+        for (int k = 0; k < kGraphChunk; ++k) items[i]->iterate(side[i + 1], nullptr, nullptr);
         HIPCHK(hipEventRecord(joins[i], side[i + 1]));
         HIPCHK(hipStreamWaitEvent(cap, joins[i], 0));
       }
+      for (auto *it : items)
+        hipLaunchKernelGGL(k_flag_any, dim3(1), dim3(256), 0, cap, it->w->active.p, it->w->ntiles, ctx->flag_dev);
+      HIPCHK(hipGetLastError());
+    } catch (...) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(cap, &g2);
+      if (g2) (void)hipGraphDestroy(g2);
+      (void)hipEventDestroy(fork);
+      for (auto j : joins) (void)hipEventDestroy(j);
+      throw;
     }
-  } catch (...) {
-    hipGraph_t g2 = nullptr;
-    (void)hipStreamEndCapture(cap, &g2);
-    if (g2) (void)hipGraphDestroy(g2);
-    throw;
+    HIPCHK(hipStreamEndCapture(cap, &gr.graph));
+    (void)hipEventDestroy(fork);
+    for (auto j : joins) (void)hipEventDestroy(j);
+    HIPCHK(hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0));
+    for (auto *it : items)
+      if (std::find(gr.spaces.begin(), gr.spaces.end(), (const void *)it->sp) == gr.spaces.end())
+        gr.spaces.push_back(it->sp);
+    if (ctx->graphs.size() >= kMaxGraphs) {  // drop the least recently used
+      auto lru = ctx->graphs.begin();
+      for (auto g = ctx->graphs.begin(); g != ctx->graphs.end(); ++g)
+        if (g->second.last < lru->second.last) lru = g;
+      graph_destroy(lru->second);
+      ctx->graphs.erase(lru);
+    }
+    found = ctx->graphs.emplace(key, gr).first;
   }
-  HIPCHK(hipStreamEndCapture(cap, &graph));
-  HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  for (int k = 1; k < max_iter; ++k) {
-    HIPCHK(hipGraphLaunch(exec, s));
-    if (all_done()) break;
+  found->second.last = ++ctx->graph_clock;
+  for (int k = 1; k < max_iter; k += kGraphChunk) {
+    HIPCHK(hipGraphLaunch(found->second.exec, s));
+    HIPCHK(hipMemcpyAsync(ctx->flag_host, ctx->flag_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->host_syncs += 1;
+    if (*ctx->flag_host == 0) break;
   }
-  (void)hipGraphExecDestroy(exec);
-  (void)hipGraphDestroy(graph);
-  (void)hipEventDestroy(fork);
-  for (auto j : joins) (void)hipEventDestroy(j);
   for (auto *it : items) it->collect();
 }
 
@@ -1375,6 +1451,10 @@ gf_status gf_context_create(int32_t device, void *hip_stream, gf_context **out) 
 
 void gf_context_destroy(gf_context *ctx) {
   if (!ctx) return;
+  for (auto &g : ctx->graphs) graph_destroy(g.second);
+  ctx->graphs.clear();
+  if (ctx->flag_dev) (void)hipFree(ctx->flag_dev);
+  if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -1548,6 +1628,7 @@ gf_status gf_space_create(gf_context *ctx, const gf_geometry *geom, int32_t degr
 
 void gf_space_destroy(gf_space *sp) {
   if (!sp) return;
+  drop_graphs_of(sp->ctx, sp);
   ws_registry().erase(sp);
   gf_geometry_destroy(sp->geom);
   delete sp;
@@ -1863,6 +1944,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
   HIPCHK(hipEventRecord(t0, s));
+  const int64_t sync0 = ctx->host_syncs;
   int max_it = 0, flags = 0, nsys = 0;
   double max_rel = 0.0, apply_ms = 0.0, apply_col_sum = 0.0, apply_bytes = 0.0, smooth_ms = 0.0, smooth_bytes = 0.0;
   int smooth_launches = 0;
@@ -2042,6 +2124,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
     stats->smooth_ms = smooth_ms;
     stats->smooth_launches = smooth_launches;
     stats->smooth_bytes = smooth_bytes;
+    stats->host_syncs = (int32_t)(ctx->host_syncs - sync0);
   }
   if (flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
   if (flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
@@ -2091,6 +2174,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
   HIPCHK(hipEventRecord(t0, s));
+  const int64_t sync0 = ctx->host_syncs;
   DBuf<double> acc, dots, one;
   acc.alloc(nsamp);
   dots.alloc((size_t)2 * std::max(t.ldf, t.ldc));
@@ -2213,6 +2297,7 @@ static void run_grad(gf_tape &t, const double *g_in, double *grad, int mem, gf_s
     stats->smooth_ms = tot.smooth_ms;
     stats->smooth_launches = tot.smooth_launches;
     stats->smooth_bytes = tot.smooth_bytes;
+    stats->host_syncs = (int32_t)(ctx->host_syncs - sync0);
   }
   if (tot.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some adjoint system");
   if (tot.flags & 1) fail(GF_ENOCONV, "some adjoint system did not reach rtol within max_iter");
@@ -2456,6 +2541,7 @@ gf_status gf_sqrt_mass(gf_space *sp, int32_t nsamp, const double *y, double *f, 
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
     HIPCHK(hipEventRecord(t0, s));
+    const int64_t sync0 = sp->ctx->host_syncs;
     const int ldc = round_up(nsamp, CT), ncols = khat * nsamp, ldf = round_up(ncols, CT);
     DBuf<double> yl;
     yl.alloc((size_t)F.R * ldc);
@@ -2493,6 +2579,7 @@ gf_status gf_sqrt_mass(gf_space *sp, int32_t nsamp, const double *y, double *f, 
       stats->apply_launches = b.res.apply_launches;
       stats->apply_rows = F.npatch * F.n1 * F.n1;
       stats->apply_bytes = b.res.apply_bytes;
+      stats->host_syncs = (int32_t)(sp->ctx->host_syncs - sync0);
     }
     if (b.res.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
     if (b.res.flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");
@@ -2599,6 +2686,7 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     HIPCHK(hipEventCreate(&t0));
     HIPCHK(hipEventCreate(&t1));
     HIPCHK(hipEventRecord(t0, s));
+    const int64_t sync0 = sp->ctx->host_syncs;
     global_to_local(F, w.r.p, bin.p, nsys, ldb, s);
     SolveSpec spec;
     spec.prec = prec;
@@ -2636,6 +2724,7 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
       stats->smooth_ms = r.smooth_ms;
       stats->smooth_launches = r.smooth_launches;
       stats->smooth_bytes = r.smooth_bytes;
+      stats->host_syncs = (int32_t)(sp->ctx->host_syncs - sync0);
     }
     if (r.flags & 2) fail(GF_EBREAKDOWN, "conjugate gradients broke down in some system");
     if (r.flags & 1) fail(GF_ENOCONV, "some system did not reach rtol within max_iter");

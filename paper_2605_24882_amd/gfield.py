@@ -58,7 +58,7 @@ class SolveStats(ctypes.Structure):
                 ("apply_launches", ctypes.c_int32), ("apply_rows", ctypes.c_int32),
                 ("apply_col_sum", ctypes.c_double), ("apply_bytes", ctypes.c_double),
                 ("smooth_ms", ctypes.c_double), ("smooth_launches", ctypes.c_int32),
-                ("smooth_bytes", ctypes.c_double)]
+                ("smooth_bytes", ctypes.c_double), ("host_syncs", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -132,13 +132,17 @@ def test_sample_split_and_precision(ctx, beta, prec):
 
 
 def test_sample_eager_matches_graph(ctx):
-    """The graph-replayed iteration loop and the eagerly enqueued one give identical fields."""
+    """The graph-replayed iteration loop (chunks of four CG iterations per graph, the instantiated graph
+    kept for the next call with the same batches) and the eagerly enqueued one give identical fields;
+    the graph loop waits for the stream once per chunk instead of once per iteration."""
     sp, d = space(ctx, 2, 3), disc(2, 3)
     b = noise.load(d, inputs.noise_vectors([7, 8], inputs.noise_length(2, 3)))
     u1, s1 = sp.sample(3.0, 1.6, b, h=0.4, k_minus=12, k_plus=12, rtol=1e-12)
     u2, s2 = sp.sample(3.0, 1.6, b, h=0.4, k_minus=12, k_plus=12, rtol=1e-12, flags=g.GF_FLAG_NO_GRAPH)
-    assert s1["max_iters"] == s2["max_iters"]
-    assert np.array_equal(u1, u2)
+    u3, s3 = sp.sample(3.0, 1.6, b, h=0.4, k_minus=12, k_plus=12, rtol=1e-12)  # the cached graphs again
+    assert s1["max_iters"] == s2["max_iters"] == s3["max_iters"]
+    assert np.array_equal(u1, u2) and np.array_equal(u1, u3)
+    assert s1["host_syncs"] == s3["host_syncs"] < s2["host_syncs"], (s1["host_syncs"], s2["host_syncs"])
 
 
 @pytest.mark.parametrize("prec", [0, 1])
