@@ -329,6 +329,7 @@ ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int
   g.nstrip = L.npatch * g.nseg * g.nyb;
   g.nsb = (g.nstrip + 3) / 4;
   g.q = xcd_q(g.nsb * ntiles);
+  g.grp = 1;
   return g;
 }
 
@@ -353,6 +354,7 @@ void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T
                  const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
                  int maxit, hipStream_t s, const ApplyTune &tune, hipEvent_t ev0, hipEvent_t ev1) {
   ApplyGeom g = apply_geom(L, ldb, ntiles, tune.TY, tune.TX, tune.NC);
+  g.grp = std::max(1, std::min(tune.grp, g.nsb));
   int algo = tune.algo;
   if (algo == 1 && !stencil_offsets_fit(L, ldb, g.TY, (int)sizeof(T))) {
     // the combined-stencil kernel addresses vectors by 32-bit offsets from the strip's first row

@@ -148,6 +148,7 @@ struct EpiArgs {
 
 struct ApplyGeom {
   int W, n1, ldb, ntiles, TY, NC, nseg, TX, nyb, nstrip, nsb, q;
+  int grp;  // strip blocks of one column tile dispatched back to back (1: column tile fastest)
 };
 
 struct IfaceGeom {

@@ -3,6 +3,8 @@
 #include "gf_internal.h"
 #include "k_solve.h"
 
+#include <type_traits>
+
 namespace gf {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -103,18 +105,47 @@ __device__ __forceinline__ double row_bcast(double v) {
   return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + J, 0xf, 0xf, true);
 }
 
-// acc[t] += sum over the S x S taps (tap = dy S + dx, in chunk tap / 16 at lane tap % 16) of the window
-// column (u + dx) mod U of row t + dy, for the NT rows of a step; the rows' chains are interleaved tap
-// by tap (independent multiply-adds back to back), each chain summed in tap order
-template <typename T, int S, int U, int NT, int TAP = 0, typename Win>
+// In DPP mode the taps are summed column by column: the o-th multiply-add of a row's chain takes tap
+// (dy, dx) = (o mod S, o / S), tap index dy S + dx.  The window's leftmost column (dx = 0) is then dead
+// after the first S multiply-adds of every row, and the next column is loaded into its registers while
+// the other columns are summed (no staging registers for it).  The LDS modes sum row by row (tap
+// order), which lets the compiler read the coefficients of consecutive taps in wide LDS reads.
+template <int S>
+constexpr int tap_at(int o) {
+  return (o % S) * S + o / S;
+}
+// whether the o-th multiply-add is the first to read its 16-tap chunk register
+template <int S>
+constexpr bool chunk_first(int o) {
+  for (int k = 0; k < o; ++k)
+    if (tap_at<S>(k) / 16 == tap_at<S>(o) / 16) return false;
+  return true;
+}
+
+// acc[t] += the multiply-adds o in [O, O1) of the NT rows of a step, in DPP mode: tap (dy, dx) takes its
+// coefficient from chunk tap / 16, lane tap % 16, and the window column (u + dx) mod U of row t + dy;
+// the rows' chains are interleaved (independent multiply-adds back to back)
+template <typename T, int S, int U, int NT, int O, int O1, typename Win>
 __device__ __forceinline__ void dpp_taps(T (&acc)[NT], const T (&c)[NT][(S * S + 15) / 16], const Win &win, int u) {
-  if constexpr (TAP < S * S) {
-    constexpr int dy = TAP / S, dx = TAP % S;
+  if constexpr (O < O1) {
+    constexpr int tap = tap_at<S>(O), dy = tap / S, dx = tap % S;
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-      fma_row_bcast<TAP % 16, TAP % 16 == 0>(acc[t], c[t][TAP / 16], win[t + dy][(U == S) ? (u + dx) % S : dx]);
-    dpp_taps<T, S, U, NT, TAP + 1>(acc, c, win, u);
+      fma_row_bcast<tap % 16, chunk_first<S>(O)>(acc[t], c[t][tap / 16], win[t + dy][(U == S) ? (u + dx) % S : dx]);
+    dpp_taps<T, S, U, NT, O + 1, O1>(acc, c, win, u);
   }
+}
+
+// the stencil sum of row t with coefficients from a stencil in LDS (lc[tap]), in tap order
+template <typename T, int S, int U, typename Win>
+__device__ __forceinline__ T lds_taps(const T *lc, const Win &win, int t, int u) {
+  T acc = 0;
+#pragma unroll
+  for (int o = 0; o < S * S; ++o) {
+    const int dy = o / S, dx = o % S;
+    acc = fma(lc[o], win[t + dy][(U == S) ? (u + dx) % S : dx], acc);
+  }
+  return acc;
 }
 
 // Raw buffer accesses: a wavefront-uniform 128-bit descriptor (base address in scalar registers) plus a
@@ -184,16 +215,22 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
 #pragma unroll
   for (int t = 0; t < TY; ++t) ooff[t] = (uint32_t)((min(iy0 + t, n1 - 1) - iy0) * W);  // in rows
 
-  // columns x0 .. x0 + 2P - 1 of the window: in slots 0 .. S-2 for the rotating window (the first step
-  // puts column x0 + 2P into slot S-1), in slots 1 .. S-1 for the shifting one (the first step shifts
-  // them down by one and appends column x0 + 2P)
-  constexpr int C0 = (U == S) ? 0 : 1;
+  // columns x0 .. x0 + 2P of the window.  Rotating window (U = S): column x0 + c in slot c; in step u the
+  // window's column dx sits in slot (u + dx) mod S, and the column of the next step is loaded into the
+  // slot of column dx = 0 once that column's multiply-adds are issued.  Shifting window (U = 1): columns
+  // x0 .. x0 + 2P - 1 in slots 1 .. S-1, column x0 + 2P in nxt; each step shifts the slots down by one,
+  // appends nxt and loads the next column into nxt before its arithmetic.
   T win[WR][S], nxt[WR];
 #pragma unroll
   for (int k = 0; k < WR; ++k) {
+    if constexpr (U == S) {
 #pragma unroll
-    for (int c = 0; c < S - 1; ++c) win[k][c + C0] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(x0 + c) * colb);
-    nxt[k] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(x0 + 2 * P) * colb);
+      for (int c = 0; c < S; ++c) win[k][c] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(x0 + c) * colb);
+    } else {
+#pragma unroll
+      for (int c = 0; c < S - 1; ++c) win[k][c + 1] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(x0 + c) * colb);
+      nxt[k] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(x0 + 2 * P) * colb);
+    }
   }
   T cmn[TY][NH], csn[TY][NH], rvn[TY], zpn[TY];
   uint32_t vst[NH];  // this lane's stencil tap, in bytes
@@ -220,35 +257,19 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
     for (int u = 0; u < U; ++u) {
       const int ix = ixb + u;
       if (ix >= x1) break;
-      // the newest column enters the window
-      if (U == S) {
-#pragma unroll
-        for (int k = 0; k < WR; ++k) win[k][(u + S - 1) % S] = nxt[k];
-      } else {
+      const int ixn = min(ix + 1, x1 - 1);
+      if constexpr (U != S) {
+        // shift the window, append the column loaded during the previous step, load the next one
 #pragma unroll
         for (int k = 0; k < WR; ++k) {
 #pragma unroll
           for (int c = 0; c < S - 1; ++c) win[k][c] = win[k][c + 1];
           win[k][S - 1] = nxt[k];
+          nxt[k] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(ixn + 2 * P) * colb);
         }
       }
-      T cm[TY][NH], cs[TY][NH], rv[TY], zp[TY];
-#pragma unroll
-      for (int t = 0; t < TY; ++t) {
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          cm[t][h] = cmn[t][h];
-          cs[t][h] = csn[t][h];
-        }
-        rv[t] = rvn[t];
-        zp[t] = zpn[t];
-      }
-      // everything the next step reads, issued before this step's arithmetic
-      const int ixn = min(ix + 1, x1 - 1);
-#pragma unroll
-      for (int k = 0; k < WR; ++k) nxt[k] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(ixn + 2 * P) * colb);
-      load_step(ixn);
-      // stage this step's stencils: lane l holds tap l of M_i and S_i
+      // stage this step's stencils (loaded during the previous step; lane l holds tap l of M_i and
+      // S_i), then reuse their registers for the next step's loads
 #pragma unroll
       for (int t = 0; t < TY; ++t) {
         T *lt = lds + t * MAXD * SS;
@@ -257,14 +278,21 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
           const int l = h * 64 + lane;
           if (l < SS) {
             if (PAIR) {
-              lt[l] = cm[t][h];
-              lt[SS + l] = cs[t][h];
+              lt[l] = cmn[t][h];
+              lt[SS + l] = csn[t][h];
             } else {
-              for (int d = 0; d < nd; ++d) lt[d * SS + l] = sab[2 * d] * cm[t][h] + sab[2 * d + 1] * cs[t][h];
+              for (int d = 0; d < nd; ++d) lt[d * SS + l] = sab[2 * d] * cmn[t][h] + sab[2 * d + 1] * csn[t][h];
             }
           }
         }
       }
+      T rv[TY], zp[TY];
+#pragma unroll
+      for (int t = 0; t < TY; ++t) {
+        rv[t] = rvn[t];
+        zp[t] = zpn[t];
+      }
+      load_step(ixn);
       __builtin_amdgcn_wave_barrier();
       // DPP mode: chunk k of row t holds taps 16k .. 16k+15 of this lane's combined stencil in the
       // lanes of every 16-lane row
@@ -279,38 +307,41 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
                                                    : T(0);
           }
       }
-      T accd[TY];
-      if (MODE == SM_DPP) {
+      // DPP mode: the stencil sums of all TY rows before the epilogue, column dx = 0 first, then the
+      // next step's newest column into that column's slot.  LDS modes: the next column into nxt now,
+      // each row's sum in the epilogue (one row's coefficient reads in flight), nxt into the freed
+      // slot after it.
+      T ac[TY];
+      if constexpr (MODE == SM_DPP) {
 #pragma unroll
-        for (int t = 0; t < TY; ++t) accd[t] = 0;
-        dpp_taps<T, S, U, TY>(accd, cc, win, u);
+        for (int t = 0; t < TY; ++t) ac[t] = 0;
+        if constexpr (U == S) {
+          dpp_taps<T, S, U, TY, 0, S>(ac, cc, win, u);
+#pragma unroll
+          for (int k = 0; k < WR; ++k) win[k][u % S] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(ixn + 2 * P) * colb);
+          dpp_taps<T, S, U, TY, S, S * S>(ac, cc, win, u);
+        } else {
+          dpp_taps<T, S, U, TY, 0, S * S>(ac, cc, win, u);
+        }
+      } else if constexpr (U == S) {
+#pragma unroll
+        for (int k = 0; k < WR; ++k) nxt[k] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(ixn + 2 * P) * colb);
       }
 #pragma unroll
       for (int t = 0; t < TY; ++t) {
         const int iy = iy0 + t;
         if (iy >= n1) break;
         const T *lt = lds + t * MAXD * SS;
-        // sum over the taps of the staged stencil in slot d
-        auto taps = [&](int d) {
-          const T *lc = lt + d * SS;
-          T ac = 0;
-#pragma unroll
-          for (int dy = 0; dy < S; ++dy) {
-#pragma unroll
-            for (int dx = 0; dx < S; ++dx) ac = fma(lc[dy * S + dx], win[t + dy][(U == S) ? (u + dx) % S : dx], ac);
-          }
-          return ac;
-        };
         T Az, D;
         if (MODE == SM_DPP) {
-          Az = accd[t];
+          Az = ac[t];
           D = row_bcast<(P * S + P) % 16>(cc[t][(P * S + P) / 16]);
         } else if (PAIR) {  // slot 0 holds M_i, slot 1 S_i
-          const T am = taps(0);
-          Az = a * am + b * taps(1);
+          const T am = lds_taps<T, S, U>(lt, win, t, u);
+          Az = a * am + b * lds_taps<T, S, U>(lt + SS, win, t, u);
           D = a * lt[P * S + P] + b * lt[SS + P * S + P];
         } else {
-          Az = taps(slot);
+          Az = lds_taps<T, S, U>(lt + slot * SS, win, t, u);
           D = lt[slot * SS + P * S + P];
         }
         const uint32_t so = (ooff[t] + (uint32_t)ix) * colb;
@@ -331,6 +362,10 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
           if (DOT) acc += (double)rv[t] * (double)zo;
         }
       }
+      if constexpr (MODE != SM_DPP && U == S) {
+#pragma unroll
+        for (int k = 0; k < WR; ++k) win[k][u % S] = nxt[k];
+      }
       // the next step's staging overwrites this step's stencils only after these reads (LDS
       // instructions of one wavefront execute in order)
       __builtin_amdgcn_wave_barrier();
@@ -339,8 +374,15 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
   return acc;
 }
 
+// waves per SIMD the register allocation of a stencil kernel is held to (0: the compiler's choice)
+template <typename T, int P, int TY, int KIND, int MODE>
+struct StencilWaves {
+  static constexpr int value = (sizeof(T) == 8 && P == 3 && TY == 2 && KIND == EPI_STORE && MODE == SM_DPP) ? 3 : 0;
+};
+
 template <typename T, int P, int TY, int KIND, int DOT, int MODE>
-__global__ __launch_bounds__(256) void k_stencil(ApplyGeom g, const T *__restrict__ stM, const T *__restrict__ stS,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StencilWaves<T, P, TY, KIND, MODE>::value)))
+void k_stencil(ApplyGeom g, const T *__restrict__ stM, const T *__restrict__ stS,
                                                  const T *__restrict__ x, const T *__restrict__ ca,
                                                  const T *__restrict__ cb, const T *__restrict__ cf1,
                                                  const T *__restrict__ cf2, T *__restrict__ y, T *__restrict__ zout,
@@ -353,7 +395,16 @@ __global__ __launch_bounds__(256) void k_stencil(ApplyGeom g, const T *__restric
   const int Lb = blockIdx.x;
   const int bl = (Lb & 7) * g.q + (Lb >> 3);
   if (bl >= g.nsb * g.ntiles) return;
-  const int ct = bl % g.ntiles, sb = bl / g.ntiles;  // column tile fastest: contiguous rows in memory
+  // groups of grp vertically adjacent strip blocks (the last group may be shorter); within a group the
+  // blocks of one column tile run back to back (they share halo rows), then those of the next tile
+  // (the tiles share the group's stencil rows).  grp = 1: column tile fastest
+  int ct, sb;
+  {
+    const int per = g.grp * g.ntiles, gi = bl / per, rem = bl - gi * per;
+    const int gs = min(g.grp, g.nsb - gi * g.grp);
+    ct = rem / gs;
+    sb = gi * g.grp + (rem - ct * gs);
+  }
   if (active && !active[ct]) return;
   const int lane = threadIdx.x & 63;
   const int wave = uni(threadIdx.x >> 6);

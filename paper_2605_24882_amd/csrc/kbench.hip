@@ -3,9 +3,12 @@
 //
 // Usage: kbench <p> <lev> <nnode> <nsamp> <f32|f64> <kinds> [algos] [shapes]
 //   kinds  comma-separated: cheb (smoothing step with a previous direction), chebdot, store, storedot,
-//          resid (the fused stencil kernels), sumfact (the matrix-free sum-factorised apply)
+//          resid (the fused stencil kernels), sumfact (the matrix-free sum-factorised apply), copy
+//          (y = -x over the whole batch: reads and writes exactly R * ldb elements; the known-size
+//          reference for the memory-traffic counters)
 //   algos  digits: 0 separate-stencil kernel, 1 combined-stencil kernel (default 01)
-//   shapes comma-separated TY:TX launch shapes (default 1:32,2:32,1:64,2:64,4:32,4:64)
+//   shapes comma-separated TY:TX or TY:TX:G launch shapes (default 1:32,2:32,1:64,2:64,4:32,4:64); G:
+//          strip blocks of one column tile dispatched back to back (default: the library's)
 // Columns: nnode shifts of nsamp systems each (node-major, as the sampler lays them out).  Stencils,
 // metric terms and vectors are seeded pseudo-random numbers (timing does not depend on the values);
 // every configuration after the first of a kind is compared with the first (relative max deviation).
@@ -77,15 +80,25 @@ __global__ void k_cmp(const T *a, const T *b, int64_t R, int ldb, int ncols, int
 }
 
 template <typename T>
+__global__ void k_neg(const T *__restrict__ a, T *__restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = -a[i];
+}
+
+template <typename T>
 static T *dalloc(size_t n) {
   T *p = nullptr;
   CK(hipMalloc((void **)&p, n * sizeof(T)));
   return p;
 }
 
+struct Shape {
+  int TY, TX, G;
+};
+
 template <typename T>
 static void run(int p, int lev, int nnode, int nsamp, const std::vector<std::string> &kinds,
-                const std::vector<int> &algos, const std::vector<std::pair<int, int>> &shapes) {
+                const std::vector<int> &algos, const std::vector<Shape> &shapes) {
   hipStream_t s = nullptr;
   Level L;
   L.p = p;
@@ -191,6 +204,23 @@ static void run(int p, int lev, int nnode, int nsamp, const std::vector<std::str
   CK(hipEventCreate(&e1));
   const double rows = 6.0 * n1 * n1;
   for (const auto &kind : kinds) {
+    if (kind == "copy") {
+      float tot = 0.f;
+      for (int k = 0; k < 4; ++k) {
+        CK(hipEventRecord(e0, s));
+        hipLaunchKernelGGL(k_neg<T>, dim3(g1), dim3(256), 0, s, x, y, (int64_t)nv);
+        CK(hipEventRecord(e1, s));
+        CK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        if (k > 0) tot += ms;
+      }
+      const double us = tot * 1e3 / 3.0, bytes = 2.0 * sizeof(T) * nv;
+      std::printf("copy     %9.1f us  %7.1f GB/s (%.3g B read, %.3g B written)\n", us, bytes / (us * 1e-6) / 1e9,
+                  bytes / 2, bytes / 2);
+      std::fflush(stdout);
+      continue;
+    }
     if (kind == "sumfact") {
       // matrix-free sum-factorised apply (all colours and the zero fill), 1 warm-up + 3 timed
       float tot = 0.f;
@@ -249,11 +279,12 @@ static void run(int p, int lev, int nnode, int nsamp, const std::vector<std::str
     for (int algo : algos)
       for (int slotmode = 0; slotmode < (algo == 1 ? 3 : 1); ++slotmode)
         for (auto sh : shapes) {
-          if (sh.first == 4 && (sizeof(T) == 8 || p > 3)) continue;
-          if (sh.first == 4 && algo == 0) continue;
+          if (sh.TY == 4 && (sizeof(T) == 8 || p > 3)) continue;
+          if (sh.TY == 4 && algo == 0) continue;
           ApplyTune tu;
-          tu.TY = sh.first;
-          tu.TX = sh.second;
+          tu.TY = sh.TY;
+          tu.TX = sh.TX;
+          tu.grp = sh.G;
           tu.algo = algo;
           e.nslot = slotmode == 0 ? nslot : 0;  // 0: pair fallback
           e.rows16 = slotmode == 2 ? 1 : 0;
@@ -291,8 +322,8 @@ static void run(int p, int lev, int nnode, int nsamp, const std::vector<std::str
               (w ? errz : erry) = m > 0 ? d / m : d;
             }
           }
-          std::printf("%-8s algo=%d %s TY=%d TX=%-3d %9.1f us %7.1f GB/s (%.1f%%)  rel.err y %.2e z %.2e  nslot=%d\n",
-                      kind.c_str(), algo, slotmode == 2 ? "dpp " : slotmode ? "pair" : "comb", sh.first, sh.second, us, bytes / (us * 1e-6) / 1e9,
+          std::printf("%-8s algo=%d %s TY=%d TX=%-3d G=%-2d %9.1f us %7.1f GB/s (%.1f%%)  rel.err y %.2e z %.2e  nslot=%d\n",
+                      kind.c_str(), algo, slotmode == 2 ? "dpp " : slotmode ? "pair" : "comb", sh.TY, sh.TX, sh.G, us, bytes / (us * 1e-6) / 1e9,
                       100.0 * bytes / (us * 1e-6) / 8e12, erry, errz, e.nslot);
           std::fflush(stdout);
         }
@@ -324,14 +355,15 @@ int main(int argc, char **argv) {
     for (char c : std::string(argv[7]))
       if (c >= '0' && c <= '9') algos.push_back(c - '0');
   }
-  std::vector<std::pair<int, int>> shapes{{1, 32}, {2, 32}, {1, 64}, {2, 64}, {4, 32}, {4, 64}};
+  const int G0 = ApplyTune().grp;
+  std::vector<Shape> shapes{{1, 32, G0}, {2, 32, G0}, {1, 64, G0}, {2, 64, G0}, {4, 32, G0}, {4, 64, G0}};
   if (argc > 8) {
     shapes.clear();
     std::string k = std::string(argv[8]) + ",", cur;
     for (char c : k) {
       if (c == ',') {
-        int a = 0, b = 0;
-        if (std::sscanf(cur.c_str(), "%d:%d", &a, &b) == 2) shapes.push_back({a, b});
+        int a = 0, b = 0, c = G0;
+        if (std::sscanf(cur.c_str(), "%d:%d:%d", &a, &b, &c) >= 2) shapes.push_back({a, b, c < 1 ? 1 : c});
         cur.clear();
       } else cur += c;
     }
