@@ -1,0 +1,43 @@
+"""Bounded caches: the library keeps multigrid plans (one per list of shifts) and workspaces (one per
+batch width, precision and slot) for later calls, least recently used first out beyond a bound.  A
+loop over new values of kappa -- central differences, or an optimiser stepping kappa -- builds new
+plans on every call and must not grow device memory without bound."""
+import pytest
+
+from paper_2605_24882_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+g = pytest.importorskip("paper_2605_24882_amd.gfield")
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    return g.Context(0)
+
+
+def test_device_memory_flat_over_varying_kappa(ctx):
+    # one-level space: the coarse solve is the dense inverse of every node's matrix on this level
+    # (488 unknowns, 1.9 MB per node, 80 MB per call's plans), so a cache that kept every plan would
+    # grow by that much per call
+    sp = g.Space(ctx, g.Geometry(ctx, False), 2, 3, mg_levels=1)
+    z = torch.from_numpy(inputs.noise_vectors([0, 1], sp.noise_length)).cuda()
+    b = sp.white_noise(z)
+    free = []
+    fields = []
+    for i in range(24):
+        kappa = 1.0 + 0.25 * i
+        u, st = sp.sample(kappa, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-8)
+        torch.cuda.synchronize()
+        free.append(torch.cuda.mem_get_info()[0])
+        if i in (0, 23):
+            fields.append(u.clone())
+    late = free[8:]
+    growth = max(late) - min(late)
+    print(f"device memory over calls 8..23: spread {growth / 2**20:.1f} MiB")
+    assert growth < 32 * 2**20, [f / 2**20 for f in free]
+    # a plan evicted and built again gives the same field
+    u0, _ = sp.sample(1.0, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-8)
+    assert torch.equal(u0, fields[0])
