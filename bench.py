@@ -43,14 +43,18 @@ CONFIGS = {
     "c2-mixed": (False, 2, 6, 10.0, 1.6, 0.4, 20, 64, 1, 1e-10),
     "c1": (False, 2, 2, 4.0, 0.75, 0.4, 15, 1, 0, 1e-13),
     "c5": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-6),
-    "c4": (False, 3, 6, 8.0, 0.8, 0.4, 20, 16, 1, 1e-6),
-    "c5-grad": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-6),
+    "c4": (False, 3, 6, 8.0, 0.8, 0.4, 20, 16, 1, 1e-7),
+    "c5-grad": (False, 3, 8, 30.0, 2.3, 0.4, 30, 32, 1, 1e-7),
     # NURBS multi-patch surface: the 4 x 4 patch torus R = 2, r = 1 (biquadratic rational Bezier
     # patches, four at every corner), 32 x 32 elements per patch
     "torus": ("torus", 2, 5, 10.0, 1.6, 0.4, 20, 64, 0, 1e-10),
 }
 # configs whose step also computes d loss / d kappa by the adjoint (loss over 1000 seeded points)
 GRADIENT_CONFIGS = {"c4", "c5-grad"}
+# relative residual of the forward and adjoint solves of a gradient: at 1e-6 the mixed-precision
+# d loss / d kappa deviates from the FP64 adjoint by up to 1.4e-6 (degree 3, 64 x 64 mesh), at 1e-7
+# by a tenth of that, inside the 1e-6 stated for gradients
+GRAD_RTOL = 1e-7
 
 
 # several sampling requests solved together (one call of the batched sampler per step): every
@@ -135,11 +139,15 @@ def _stencil_kind(name, p, kind, vt):
     return False
 
 
-def _kernel_rows(path, p, kind, value_key):
+def _kernel_rows(path, p, kind, value_key, last=None):
+    # `path`: a CSV file or its rows
     """values of every launch of the stencil kernel with epilogue `kind` ("outer": EPI_STORE with the
     inner product, FP64; "smoother": EPI_CHEB in the V-cycle's precision, FP32 when no FP64 smoothing
-    step was launched) at the finest level (the largest grid of that kernel)."""
-    rows = list(csv.DictReader(open(path)))
+    step was launched) at the finest level (the largest grid of that kernel), in dispatch order; with
+    `last`, only the last that many of them (the launches of the event-timed step, which ends the run)."""
+    rows = list(csv.DictReader(open(path))) if isinstance(path, str) else list(path)
+    if rows and "Dispatch_Id" in rows[0]:
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
     has_double_smoother = any(_stencil_kind(r["Kernel_Name"].split("(")[0], p, "smoother", "double") for r in rows)
     vt = "double" if kind == "outer" or has_double_smoother else "float"
     out = []
@@ -147,41 +155,84 @@ def _kernel_rows(path, p, kind, value_key):
         name = r["Kernel_Name"].split("(")[0]
         if _stencil_kind(name, p, kind, vt):
             grid = int(r.get("Grid_Size") or r.get("Grid_Size_X"))
-            out.append((grid, value_key(r)))
+            v = value_key(r)
+            if v is not None:
+                out.append((grid, v))
     big = max(g for g, _ in out)
-    return [v for g, v in out if g == big], big
+    vals = [v for g, v in out if g == big]
+    return (vals[-last:] if last else vals), big
 
 
-def pmc_summary(fetch_csv, write_csv, config, probe_mib):
+def _events(path):
+    """launch counts, algorithmic bytes and event-timed durations per launch of the two operator
+    kinds from a bench.py JSON line (its event-timed step is the last part of the run)"""
+    if not path:
+        return None
+    with open(path) as f:
+        d = json.loads(f.read().strip().splitlines()[-1])
+    return {"smoother": d["roofline"], "outer": d["roofline_outer_operator"]}
+
+
+READ_REQ = {"TCC_EA0_RDREQ_32B_sum": 32, "TCC_EA0_RDREQ_64B_sum": 64, "TCC_EA0_RDREQ_128B_sum": 128}
+
+
+def _dispatch_counters(path):
+    """rows of a rocprofv3 counter CSV merged per dispatch: {dispatch id: row with a "counters" dict}"""
+    out = {}
+    for r in csv.DictReader(open(path)):
+        d = out.setdefault(int(r["Dispatch_Id"]), dict(r, counters={}))
+        d["counters"][r["Counter_Name"]] = float(r["Counter_Value"])
+    return [out[k] for k in sorted(out)]
+
+
+def _read_bytes(counters):
+    """bytes an L2 channel fetched from memory, from the request counts by size"""
+    return sum(counters[n] * b for n, b in READ_REQ.items())
+
+
+def pmc_summary(fetch_csv, write_csv, config, probe_mib, events=None):
     """Per-launch HBM traffic of the finest-level smoothing launches and of the outer operator from
-    two counter runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the counter reads
-    for the plain elementwise probe kernel (dst = -src over probe_mib MiB, which reads and writes
-    exactly that many bytes)."""
+    two counter runs, KiB per dispatch.  Reads: either FETCH_SIZE, scaled by what it reads for the
+    plain elementwise probe kernel (dst = -src over probe_mib MiB, which reads and writes exactly that
+    many bytes), or the memory read requests of the L2 by size (TCC_EA0_RDREQ_{32B,64B,128B}_sum: bytes
+    counted directly; the probe is then a check).  Writes: WRITE_SIZE, scaled by the probe.  With
+    `events` (the JSON line of a run with the same launch sequence), only the launches of the
+    event-timed step are averaged and set against their algorithmic bytes."""
     p = CONFIGS[config][1]
     known_kib = probe_mib * 1024.0
     out = {"config": config, "kernel_source_sha256": source_sha(), "probe_mib": probe_mib}
-    factors = {}
     for key, path in (("fetch", fetch_csv), ("write", write_csv)):
-        rows = [r for r in csv.DictReader(open(path)) if "neg_kernel" in r["Kernel_Name"]]
-        if not rows:
+        rows = _dispatch_counters(path)
+        by_req = key == "fetch" and all(n in rows[0]["counters"] for n in READ_REQ)
+        if by_req:
+            val = lambda r: _read_bytes(r["counters"]) / 1024.0
+            out["fetch_counters"] = "TCC_EA0_RDREQ_32B/64B/128B (request counts x size)"
+        else:
+            name = "FETCH_SIZE" if key == "fetch" else "WRITE_SIZE"
+            val = lambda r, name=name: r["counters"][name]
+            out[f"{key}_counters"] = name
+        probe = [r for r in rows if "neg_kernel" in r["Kernel_Name"]]
+        if not probe:
             raise SystemExit(f"{path}: no probe kernel dispatch")
         # the copy probe runs before the workload; a later elementwise kernel of another size (the
         # stream probe of a run without --copy-probe-mib) has another grid and is left out
-        first = min(rows, key=lambda r: int(r["Dispatch_Id"]))
-        probe = [float(r["Counter_Value"]) for r in rows if r["Grid_Size"] == first["Grid_Size"]]
-        factors[key] = known_kib / (sum(probe) / len(probe))
-        out[f"{key}_probe_kib"] = sum(probe) / len(probe)
-        out[f"{key}_factor"] = round(factors[key], 4)
-    for kind in ("smoother", "outer"):
-        e = {}
-        for key, path in (("fetch", fetch_csv), ("write", write_csv)):
-            vals, grid = _kernel_rows(path, p, kind, lambda r: float(r["Counter_Value"]))
+        pv = [val(r) for r in probe if r["Grid_Size"] == probe[0]["Grid_Size"]]
+        factor = 1.0 if by_req else known_kib / (sum(pv) / len(pv))
+        out[f"{key}_probe_kib"] = sum(pv) / len(pv)
+        out[f"{key}_factor"] = round(factor, 4)
+        for kind in ("smoother", "outer"):
+            e = out.setdefault(kind, {})
+            vals, grid = _kernel_rows(rows, p, kind, val, last=events[kind]["launches"] if events else None)
             e[f"{key}_kib_per_launch"] = sum(vals) / len(vals)
             e[f"{key}_launches"] = len(vals)
             e[f"{key}_grid"] = grid
-            e[f"{key}_bytes_per_launch"] = sum(vals) / len(vals) * 1024.0 * factors[key]
+            e[f"{key}_bytes_per_launch"] = sum(vals) / len(vals) * 1024.0 * factor
+    for kind in ("smoother", "outer"):
+        e = out[kind]
         e["traffic_bytes_per_launch"] = e["fetch_bytes_per_launch"] + e["write_bytes_per_launch"]
-        out[kind] = e
+        if events:
+            e["algorithmic_bytes_per_launch"] = events[kind]["bytes_per_launch"]
+            e["traffic_over_algorithmic"] = round(e["traffic_bytes_per_launch"] / events[kind]["bytes_per_launch"], 4)
     return out
 
 
@@ -205,8 +256,10 @@ def counter_summary(csvs, config):
     return "\n".join(lines)
 
 
-def trace_summary(trace_csv, p, top=25):
-    """Text summary of a rocprofv3 kernel trace: time per kernel and grid, and the outer operator."""
+def trace_summary(trace_csv, p, top=25, events=None):
+    """Text summary of a rocprofv3 kernel trace: time per kernel and grid, and the two operator kinds;
+    with `events` (the JSON line the traced run printed) also the trace's average over the launches of
+    the event-timed step (the last launches of each kind) beside the events' average."""
     rows = list(csv.DictReader(open(trace_csv)))
     agg = collections.defaultdict(list)
     for r in rows:
@@ -233,6 +286,14 @@ def trace_summary(trace_csv, p, top=25):
         d[kind] = [x for _, g, x in sorted(ts) if g == big]
         lines += ["", f"{kind} ({'finest-level Chebyshev smoothing step' if kind == 'smoother' else 'outer CG operator'}, "
                       f"grid {big}): {len(d[kind])} launches, avg {sum(d[kind]) / len(d[kind]):.2f} us"]
+        if events:
+            n = events[kind]["launches"]
+            tail = d[kind][-n:]
+            ev = events[kind]["avg_launch_us"]
+            tr = sum(tail) / len(tail)
+            lines.append(f"  event-timed step: last {n} launches, trace avg {tr:.2f} us, events avg {ev:.2f} us "
+                         f"(ratio {ev / tr:.4f}); algorithmic {events[kind]['bytes_per_launch']:.4e} B per launch "
+                         f"-> {events[kind]['bytes_per_launch'] / tr / 1e3:.1f} GB/s by the trace")
     return "\n".join(lines), d
 
 
@@ -410,6 +471,9 @@ def main():
                     help="print the per-launch averages of every counter in these --pmc runs and exit")
     ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
                     help="print a summary of a rocprofv3 kernel trace of this benchmark, then exit")
+    ap.add_argument("--events-json", metavar="BENCH_JSON",
+                    help="with --trace-summary / --pmc-summary: the JSON line of a run of this benchmark with the same "
+                         "launch sequence; restricts the averages to the launches of its event-timed step")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the timed steps, stream this many MiB through a plain elementwise kernel "
                          "(dst = -src: reads and writes exactly that many bytes; the known-size reference for "
@@ -417,13 +481,13 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.config,
-                                     args.copy_probe_mib or 512), indent=1))
+                                     args.copy_probe_mib or 512, _events(args.events_json)), indent=1))
         return
     if args.counter_summary:
         print(counter_summary(args.counter_summary, args.config))
         return
     if args.trace_summary:
-        print(trace_summary(args.trace_summary, CONFIGS[args.config][1])[0])
+        print(trace_summary(args.trace_summary, CONFIGS[args.config][1], events=_events(args.events_json))[0])
         return
     if args.apply_shape:
         os.environ["GF_APPLY_SHAPE"] = args.apply_shape
@@ -495,9 +559,12 @@ def main():
             patch, stp = geo.locate(pts)
             yt = torch.from_numpy(yv).cuda()
 
+            kwg = dict(kw)
+            kwg["rtol"] = min(kw["rtol"], GRAD_RTOL)
+
             def grad_step(flags=0):
                 """forward samples and d loss / d kappa per sample (loss over 1000 seeded points)"""
-                u, tape, st1 = sp.sample_tape(kappa, beta, b, flags=flags, **kw)
+                u, tape, st1 = sp.sample_tape(kappa, beta, b, flags=flags, **kwg)
                 vals = sp.eval(patch, stp, u)
                 gk, st2 = tape.grad_kappa(sp.eval_adjoint(patch, stp, vals - yt[None, :]))
                 tape.close()
@@ -580,6 +647,7 @@ def main():
         tg = time.perf_counter() - tg
         gradients = {"value": round(nsamp * gsteps / tg, 3), "unit": "gradients/s", "steps": gsteps,
                      "ms_per_step": round(1e3 * tg / gsteps, 3), "max_cg_iters": gst["max_iters"],
+                     "rtol": kwg["rtol"],
                      "what": (f"{nsamp} forward samples and d loss/d kappa of each (loss over 1000 seeded surface "
                               f"points; adjoint solves by the same batched solver) per step")}
     # dominant-kernel timing: the same steps once more with HIP events stamped around every outer

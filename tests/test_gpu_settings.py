@@ -1,0 +1,196 @@
+"""Accuracy of the settings the throughput workloads run at, and of the degrees the paper covers.
+
+  * the batching workload's finest meshes (128 x 128 elements, degrees 2 and 3, perturbed sphere) and
+    the perturbed degree-3 64 x 64 mesh: FP32 V-cycle / FP64 CG at relative residual 1e-6 against the
+    FP64 path at 1e-11 (itself pinned to the oracle element by element on smaller meshes), relative
+    M-norm error at most 1e-6;
+  * a full-size FP64 pin against the oracle's sparse LU on the degree-3 128 x 128 mesh (101,402
+    unknowns; the 256 x 256 mesh of the scale workload is beyond a direct factorisation in a test):
+    two shifted systems, kappa^2 and the largest shift of the scale workload's rule, rtol 1e-13;
+  * degrees 4 and 5 (the top of the paper's range): fields against the oracle;
+  * the mixed-precision gradient at the benched setting (forward and adjoint solves to relative
+    residual 1e-7) against the FP64 adjoint on the differentiation workload's mesh, at most 1e-6;
+  * the continuous eigen-expansion: on the unit sphere with a band-limited load f = sum c_lm Y_lm the
+    sinc-rule field is sum c_lm lambda_l^-n Q(lambda_l) Y_lm (lambda_l = kappa^2 + l(l+1)), and its
+    kappa-derivative follows in closed form; the discrete field and d loss / d kappa on the
+    differentiation workload's mesh agree with them to the discretisation error;
+  * the degree-2 workload at the relative residual it is benchmarked at (1e-10): field error against
+    the oracle on four samples;
+  * the quadrature order (Sec. 3.2 leaves it open; q = p + 1 Gauss points per direction is the
+    default reading): with q = p + 2 the fields match the oracle built with the same rule, and the
+    difference between the two rules is reported on the first two workloads' meshes.
+"""
+import numpy as np
+import pytest
+
+import math
+
+from oracle import assembly, fractional, noise
+from paper_2605_24882_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+g = pytest.importorskip("paper_2605_24882_amd.gfield")
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    return g.Context(0)
+
+
+def mrel(sp, u, ref):
+    """max over samples of |u - ref|_M / |ref|_M, with M applied by the library (device tensors)"""
+    d = u - ref
+    return ((d * sp.apply(1.0, 0.0, d)).sum(dim=1).sqrt() / (ref * sp.apply(1.0, 0.0, ref)).sum(dim=1).sqrt()).max().item()
+
+
+def mrel_host(disc, u, ref):
+    """max over samples of |u - ref|_M / |ref|_M with the oracle's mass matrix"""
+    u, ref = np.atleast_2d(u), np.atleast_2d(ref)
+    out = 0.0
+    for a, b in zip(u, ref):
+        e = a - b
+        out = max(out, math.sqrt(e @ (disc.M @ e)) / math.sqrt(b @ (disc.M @ b)))
+    return out
+
+
+@pytest.mark.parametrize("p,j,kappa", [(2, 7, 20.0), (3, 7, 5.0), (3, 6, 10.0)])
+def test_batching_meshes_mixed_precision(ctx, p, j, kappa):
+    sp = g.Space(ctx, g.Geometry(ctx, True), p, j)
+    z = torch.from_numpy(inputs.noise_vectors([0, 1], sp.noise_length)).cuda()
+    b = sp.white_noise(z)
+    kw = dict(h=0.4, k_minus=20, k_plus=20, max_iter=2000)
+    ref, st0 = sp.sample(kappa, 0.9, b, precision=0, rtol=1e-11, **kw)
+    u, st1 = sp.sample(kappa, 0.9, b, precision=1, rtol=1e-6, **kw)
+    err = mrel(sp, u, ref)
+    print(f"perturbed p={p} level={j} kappa={kappa}: mixed 1e-6 vs FP64 1e-11 rel. M-norm error {err:.3e} "
+          f"({st1['max_iters']} / {st0['max_iters']} iterations)")
+    assert err <= 1e-6
+
+
+def test_full_size_fp64_pin_against_sparse_lu(ctx):
+    import scipy.sparse.linalg as spla
+    p, j = 3, 7
+    d = assembly.Discretisation(p, j)
+    sp = g.Space(ctx, g.Geometry(ctx, False), p, j)
+    assert sp.ndofs == d.N == 101402
+    rng = np.random.default_rng(31)
+    b = rng.standard_normal((2, d.N))
+    sig = np.array([30.0 ** 2, 30.0 ** 2 + np.exp(2 * 30 * 0.4)])  # kappa^2 and the largest shift (k = -30)
+    x, st = sp.solve_shifted(sig, b, precision=0, rtol=1e-13, max_iter=2000)
+    for i in range(2):
+        ref = spla.splu((sig[i] * d.M + d.S).tocsc(), permc_spec="MMD_AT_PLUS_A").solve(b[i])
+        e = x[i] - ref
+        rel = np.sqrt(e @ (d.M @ e)) / np.sqrt(ref @ (d.M @ ref))
+        print(f"p=3 level=7 shift {sig[i]:.4g}: FP64 vs sparse LU rel. M-norm {rel:.3e}")
+        assert rel <= 1e-10
+
+
+@pytest.mark.parametrize("p,j", [(4, 2), (5, 1)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_high_degree_fields_match_oracle(ctx, p, j, prec):
+    sp = g.Space(ctx, g.Geometry(ctx, True), p, j)
+    d = assembly.Discretisation(p, j, True)
+    b = noise.load(d, inputs.noise_vectors([5, 6], inputs.noise_length(p, j)))
+    u, st = sp.sample(3.0, 1.3, b, h=0.4, k_minus=10, k_plus=10, precision=prec, rtol=1e-13, max_iter=1000)
+    ref = fractional.sample(d.M, d.S, 3.0, 1.3, 0.4, 10, 10, b)
+    e = u - ref
+    rel = np.max(np.sqrt(np.einsum("si,si->s", e, (d.M @ e.T).T) / np.einsum("si,si->s", ref, (d.M @ ref.T).T)))
+    assert rel <= 1e-10, rel
+
+
+def _loss_grad(sp, geo, b, prec, rtol, kappa=8.0, beta=0.8):
+    pts, y = inputs.sphere_points_and_targets(1000, seed=7)
+    patch, st = geo.locate(pts)
+    yt = torch.from_numpy(y).cuda()
+    u, tape, _ = sp.sample_tape(kappa, beta, b, h=0.4, k_minus=20, k_plus=20, precision=prec, rtol=rtol,
+                                max_iter=2000)
+    vals = sp.eval(patch, st, u)
+    grad, _ = tape.grad_kappa(sp.eval_adjoint(patch, st, vals - yt[None, :]))
+    tape.close()
+    return grad, vals, pts, y
+
+
+def test_mixed_gradient_against_fp64_adjoint(ctx):
+    geo = g.Geometry(ctx, False)
+    sp = g.Space(ctx, geo, 3, 6)
+    z = torch.from_numpy(inputs.noise_vectors([0, 1, 2, 3], sp.noise_length)).cuda()
+    b = sp.white_noise(z)
+    g64, _, _, _ = _loss_grad(sp, geo, b, 0, 1e-12)
+    g32, _, _, _ = _loss_grad(sp, geo, b, 1, 1e-7)
+    err = ((g32 - g64).abs() / g64.abs()).max().item()
+    print(f"differentiation mesh: mixed (1e-7) vs FP64 (1e-12) d loss/d kappa, max rel. deviation {err:.3e}")
+    assert err <= 1e-6
+
+
+def _harmonics(X):
+    """l, and the real harmonics of degree 0, 1, 2 used for the load, at unit vectors X"""
+    x, y, z = X[..., 0], X[..., 1], X[..., 2]
+    return [(0, 0.7 * np.ones_like(x)), (1, 1.3 * x - 0.4 * z), (2, 0.9 * x * y + 0.5 * (3 * z * z - 1))]
+
+
+def test_continuous_eigen_expansion_gradient(ctx):
+    kappa, beta, h, K = 8.0, 0.8, 0.4, 20
+    p, j = 3, 6
+    d = assembly.Discretisation(p, j)
+    f = lambda X: sum(v for _, v in _harmonics(X))
+    b = assembly.load_vector(d, f, p + 3)[None, :]
+    geo = g.Geometry(ctx, False)
+    sp = g.Space(ctx, geo, p, j)
+    grad, vals, pts, y = _loss_grad(sp, geo, torch.from_numpy(b).cuda(), 0, 1e-13, kappa, beta)
+    n, bf = fractional.split_plain(beta)
+    _, omega, t = fractional.nodes(kappa, bf, h, K, K)
+    X = pts / np.linalg.norm(pts, axis=1, keepdims=True)
+    uq = np.zeros(len(X))
+    du = np.zeros(len(X))
+    for l, v in _harmonics(X):
+        lam = kappa ** 2 + l * (l + 1)
+        Q = np.sum(omega / (t + lam))
+        dQ = -np.sum(omega / (t + lam) ** 2)
+        gl = lam ** (-n) * Q
+        dg = -n * lam ** (-n - 1) * Q + lam ** (-n) * dQ
+        uq += gl * v
+        du += 2 * kappa * dg * v
+    gcont = np.sum((uq - y) * du)
+    vrel = np.abs(vals.cpu().numpy()[0] - uq).max() / np.abs(uq).max()
+    grel = abs(grad.item() - gcont) / abs(gcont)
+    print(f"eigen-expansion: point values rel. deviation {vrel:.3e}, d loss/d kappa {grad.item():.10e} vs "
+          f"{gcont:.10e} (rel. {grel:.3e})")
+    assert vrel <= 1e-6 and grel <= 1e-6
+
+
+def test_c2_benchmarked_tolerance(ctx):
+    """Unit sphere, p = 2, 64 x 64 elements per patch, kappa = 10, beta = 1.6, 41 nodes: the FP64 solver
+    at relative residual 1e-10 (the benchmarked setting) against the oracle, samples 0..3."""
+    d = assembly.Discretisation(2, 6)
+    sp = g.Space(ctx, g.Geometry(ctx, False), 2, 6)
+    b = noise.load(d, inputs.noise_vectors(range(4), inputs.noise_length(2, 6)))
+    u, st = sp.sample(10.0, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-10)
+    ref = fractional.sample(d.M, d.S, 10.0, 1.6, 0.4, 20, 20, b)
+    err = mrel_host(d, u, ref)
+    print(f"degree-2 workload mesh, FP64 at rtol 1e-10: rel. M-norm error against the oracle {err:.3e} "
+          f"({st['max_iters']} iterations)")
+    assert err <= 1e-9
+
+
+@pytest.mark.parametrize("p,j,kappa,beta,K,seeds", [(2, 2, 4.0, 0.75, 15, [0]), (2, 6, 10.0, 1.6, 20, [0, 1])])
+def test_quadrature_order_sensitivity(ctx, p, j, kappa, beta, K, seeds):
+    geo = g.Geometry(ctx, False)
+    z = inputs.noise_vectors(seeds, inputs.noise_length(p, j))
+    fields = {}
+    for q in (p + 1, p + 2):
+        d = assembly.Discretisation(p, j, nquad=q)
+        sp = g.Space(ctx, geo, p, j, nquad=q)
+        b = noise.load(d, z)
+        u, st = sp.sample(kappa, beta, b, h=0.4, k_minus=K, k_plus=K, rtol=1e-13, max_iter=1000)
+        ref = fractional.sample(d.M, d.S, kappa, beta, 0.4, K, K, b)
+        assert mrel_host(d, u, ref) <= 1e-10, q
+        fields[q] = (d, u)
+    d2, u2 = fields[p + 2]
+    diff = mrel_host(d2, fields[p + 1][1], u2)
+    print(f"p={p} level={j}: fields with q = p+1 and q = p+2 Gauss points differ by {diff:.3e} (rel. M-norm)")
+    # the two rules integrate the same polynomial-times-metric integrands to within the quadrature
+    # error: a difference far below the discretisation error, but not zero
+    assert 1e-14 < diff < 1e-2
