@@ -353,7 +353,9 @@ template <typename T>
 void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
                  const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
                  int maxit, hipStream_t s, const ApplyTune &tune, hipEvent_t ev0, hipEvent_t ev1) {
-  ApplyGeom g = apply_geom(L, ldb, ntiles, tune.TY, tune.TX, tune.NC);
+  // four-row strips exist for FP32 only (the FP64 window would not fit the registers)
+  const int ty = (sizeof(T) == 8 && tune.TY > 2) ? 2 : tune.TY;
+  ApplyGeom g = apply_geom(L, ldb, ntiles, ty, tune.TX, tune.NC);
   g.grp = std::max(1, std::min(tune.grp, g.nsb));
   int algo = tune.algo;
   if (algo == 1 && !stencil_offsets_fit(L, ldb, g.TY, (int)sizeof(T))) {
