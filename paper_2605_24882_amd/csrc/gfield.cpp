@@ -9,7 +9,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -269,7 +268,6 @@ struct Plan {
   double ia_mass = 0.0;                     // (m(pi)/m(0))^2 of the 1D B-spline mass symbol
   DBuf<double> Ainv;                      // [node][N0][N0] inverses of the coarse matrices
   double setup_ms = 0.0;
-  uint64_t last = 0;                      // number of the last call that used the plan
 };
 
 struct LevelWork {
@@ -303,8 +301,6 @@ struct SmoothLog {
 struct Workspace {
   SmoothLog *slog = nullptr;  // set while a timed batch runs
   int ldb = 0, ntiles = 0, prec = 0;
-  uint64_t last = 0;          // number of the last call that used the workspace
-  size_t bytes = 0;           // device memory of its batch vectors
   // structure of the columns' shifts in the current batch: the most distinct shifts in one column tile,
   // and whether every aligned group of 16 columns has one shift (see EpiArgs::nslot, rows16)
   int nslot = 0, rows16 = 0;
@@ -352,72 +348,6 @@ static std::map<const gf_space *, std::unique_ptr<gf_workspaces>> &ws_registry()
   return r;
 }
 
-static void drop_graphs_of(gf_context *ctx, const gf_space *sp);
-
-// ------------------------------------------------------------------ cache bounds
-// Plans (per shift list) and workspaces (per batch width, precision and slot) are cached per space
-// and reused by later calls.  Each public solver call has a number; what it uses is stamped with it,
-// and at its end the plans beyond kMaxPlans and the workspaces beyond kMaxWorkspaces of each space it
-// touched are released, least recently used first and never one the call itself used; so are
-// workspaces while those of the space hold more than half the device's memory.  Releasing either
-// drops the space's cached graphs first (their launches hold the buffers' addresses).
-constexpr size_t kMaxPlans = 8;
-constexpr size_t kMaxWorkspaces = 8;
-static std::atomic<uint64_t> g_call{0};
-static thread_local int g_call_depth = 0;
-
-static void trim_caches(gf_space *sp) {
-  const uint64_t now = g_call.load();
-  auto &reg = ws_registry()[sp];
-  std::vector<std::string> plan_out;
-  std::vector<std::tuple<int, int, int>> ws_out;
-  {
-    std::vector<std::pair<uint64_t, std::string>> v;
-    for (auto &kv : sp->plans)
-      if (kv.second->last != now) v.push_back({kv.second->last, kv.first});
-    std::sort(v.begin(), v.end());
-    for (size_t i = 0; i < v.size() && sp->plans.size() - plan_out.size() > kMaxPlans; ++i) plan_out.push_back(v[i].second);
-  }
-  if (reg) {
-    size_t fr = 0, total = 0, held = 0;
-    HIPCHK(hipMemGetInfo(&fr, &total));
-    std::vector<std::pair<uint64_t, std::tuple<int, int, int>>> v;
-    for (auto &kv : reg->m) {
-      held += kv.second->bytes;
-      if (kv.second->last != now) v.push_back({kv.second->last, kv.first});
-    }
-    std::sort(v.begin(), v.end());
-    for (size_t i = 0; i < v.size() && (reg->m.size() - ws_out.size() > kMaxWorkspaces || held > total / 2); ++i) {
-      held -= reg->m[v[i].second]->bytes;
-      ws_out.push_back(v[i].second);
-    }
-  }
-  if (plan_out.empty() && ws_out.empty()) return;
-  HIPCHK(hipStreamSynchronize(sp->ctx->stream));
-  drop_graphs_of(sp->ctx, sp);
-  for (auto &k : plan_out) sp->plans.erase(k);
-  for (auto &k : ws_out) reg->m.erase(k);
-}
-
-// One public solver call: numbers the call and bounds the caches of the spaces it used at its end
-// (the outermost scope of a thread does both)
-struct CallScope {
-  std::vector<gf_space *> spaces;
-  CallScope() {
-    if (g_call_depth++ == 0) ++g_call;
-  }
-  void use(gf_space *sp) {
-    if (sp && std::find(spaces.begin(), spaces.end(), sp) == spaces.end()) spaces.push_back(sp);
-  }
-  ~CallScope() {
-    if (--g_call_depth != 0) return;
-    try {
-      for (gf_space *sp : spaces) trim_caches(sp);
-    } catch (...) {
-    }
-  }
-};
-
 static size_t scratch_slots(gf_space *sp, int ldb, int ntiles) {
   size_t slots = 2 * (size_t)kMaxRowBlocks;
   for (auto &L : sp->lev) slots = std::max(slots, (size_t)partial_slots(*L, ldb, ntiles));
@@ -430,12 +360,8 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
   if (!reg) reg.reset(new gf_workspaces());
   auto key = std::make_tuple(ldb, prec, slot);
   auto it = reg->m.find(key);
-  if (it != reg->m.end()) {
-    it->second->last = g_call.load();
-    return *it->second;
-  }
+  if (it != reg->m.end()) return *it->second;
   std::unique_ptr<Workspace> w(new Workspace());
-  w->last = g_call.load();
   w->ldb = ldb;
   w->ntiles = ldb / CT;
   w->prec = prec;
@@ -445,12 +371,10 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
   w->r.alloc(nf);
   w->p.alloc(nf);
   w->q.alloc(nf);
-  w->bytes = 4 * nf * sizeof(double);
   w->lw.resize(sp->nlev());
   for (int li = 0; li < sp->nlev(); ++li) {
     const Level &L = *sp->lev[li];
     const size_t n = (size_t)L.R * ldb;
-    w->bytes += 4 * n * (prec == GF_PREC_FP64 ? sizeof(double) : sizeof(float));
     LevelWork &v = w->lw[li];
     const bool finest = (li == sp->nlev() - 1);
     if (prec == GF_PREC_FP64) {
@@ -709,15 +633,11 @@ static std::string plan_key(const std::vector<double> &sig) {
 static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
   const std::string key = plan_key(sig);
   auto it = sp->plans.find(key);
-  if (it != sp->plans.end()) {
-    it->second->last = g_call.load();
-    return *it->second;
-  }
+  if (it != sp->plans.end()) return *it->second;
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = sp->ctx->stream;
   std::unique_ptr<Plan> pl(new Plan());
   pl->sig = sig;
-  pl->last = g_call.load();
   const int nn = (int)sig.size();
   const int ldb = round_up(nn, CT), nt = ldb / CT;
   DBuf<double> dsig, one, v, w, v2, out;
@@ -1921,7 +1841,7 @@ struct SampleItem {
   double bf = 0;   // order of the sinc rule
   int passes = 1;  // applications of the rule (2 for the improved split)
   std::vector<double> node_sig, omega;
-  const Plan *chain_plan = nullptr;
+  const Plan *chain_plan = nullptr, *frac_plan = nullptr;
   InArray bin;
   OutArray uout;
   DBuf<double> rloc;
@@ -1960,6 +1880,7 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
           it.node_sig.push_back(it.kappa * it.kappa + t);
           it.omega.push_back(2.0 * it.rule.h * std::sin(M_PI * it.bf) / M_PI * std::pow(t, 1.0 - it.bf));
         }
+        it.frac_plan = &get_plan(it.sp, it.node_sig);
       }
       built = built || it.sp->plans.size() != np;
     }
@@ -2001,9 +1922,11 @@ static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_
       gr.off.push_back(gr.ncols);
       gr.ncols += (int)it.node_sig.size() * it.nsamp;
     }
-    // a request alone in its group solves under the plan of its own shifts, a group under the plan of
-    // the union of its requests' shifts (no per-request plan is built for a grouped request)
     for (auto &gr : groups) {
+      if (gr.its.size() == 1) {
+        gr.plan = gr.its[0]->frac_plan;
+        continue;
+      }
       std::vector<double> usig;
       for (auto *it : gr.its) usig.insert(usig.end(), it->node_sig.begin(), it->node_sig.end());
       const size_t np = gr.sp->plans.size();
@@ -2594,8 +2517,6 @@ gf_status gf_sqrt_mass(gf_space *sp, int32_t nsamp, const double *y, double *f, 
     if (nsamp < 1) fail(GF_EINVAL, "nsamp must be >= 1");
     if (khat < 1 || khat > 4096) fail(GF_EINVAL, "khat must be in 1..4096");
     if ((int64_t)khat * nsamp > (int64_t)1 << 20) fail(GF_EINVAL, "too many systems in one batch");
-    CallScope scope;
-    scope.use(sp);
     if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
     if (!(opts->rtol > 0.0) || !(opts->rtol < 1.0)) fail(GF_EINVAL, "rtol must be in (0, 1)");
     if (opts->max_iter < 1) fail(GF_EINVAL, "max_iter must be >= 1");
@@ -2682,8 +2603,6 @@ gf_status gf_sample(gf_space *sp, double kappa, double beta, const gf_quad_rule 
     items[0].nsamp = nsamp;
     items[0].b = b;
     items[0].u = u;
-    CallScope scope;
-    scope.use(sp);
     run_items(sp->ctx, items, opts, mem, stats);
   });
 }
@@ -2710,8 +2629,6 @@ gf_status gf_sample_batch(gf_context *ctx, int32_t nitems, const gf_batch_item *
       items[i].b = in.b;
       items[i].u = in.u;
     }
-    CallScope scope;
-    for (auto &it : items) scope.use(it.sp);
     run_items(ctx, items, opts, mem, stats);
   });
 }
@@ -2731,8 +2648,6 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     if (opts->preconditioner != GF_PRECOND_VCYCLE && opts->preconditioner != GF_PRECOND_BPX)
       fail(GF_EINVAL, "unknown preconditioner");
     const bool mass = (opts->flags & GF_FLAG_MASS_SHIFT) != 0;
-    CallScope scope;
-    scope.use(sp);
     // distinct shifts in order of first appearance: one multigrid plan node each
     std::vector<double> distinct;
     std::vector<int> node(nsys);
@@ -2847,8 +2762,6 @@ gf_status gf_sample_tape(gf_space *sp, double kappa, double beta, const gf_quad_
     items[0].b = b;
     items[0].u = u;
     items[0].tape = t.get();
-    CallScope scope;
-    scope.use(sp);
     run_items(sp->ctx, items, opts, mem, stats);
     t->node_sig = items[0].node_sig;
     t->omega = items[0].omega;
@@ -2861,8 +2774,6 @@ gf_status gf_grad_kappa(gf_tape *tape, const double *dl_du, double *dl_dkappa, i
     if (!tape || !dl_du || !dl_dkappa) fail(GF_EINVAL, "null argument");
     if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
     HIPCHK(hipSetDevice(tape->sp->ctx->device));
-    CallScope scope;
-    scope.use(tape->sp);
     run_grad(*tape, dl_du, dl_dkappa, mem, stats);
   });
 }
