@@ -30,6 +30,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -366,74 +367,101 @@ def cpu_model():
     return name, os.cpu_count()
 
 
-def _oracle_system_times(pert, p, lev, kappa, beta, h, k, nsys_nodes):
-    """Oracle on one load at one level: assembly time, and the times of its integer solves and of
-    `nsys_nodes` node solves (evenly spaced in k), each a SuperLU factorisation plus a solve."""
+_POOL = {}  # the matrices and load of the pool's node solves (inherited by the forked workers)
+
+
+def _pool_node_solve(i):
+    """one sinc-node system of the pooled oracle run: the oracle's own node solve (SuperLU
+    factorisation + solve) on one thread; returns its duration"""
+    from threadpoolctl import threadpool_limits
+    from oracle import fractional
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        fractional.node_solutions(_POOL["M"], _POOL["S"], _POOL["sig"][i:i + 1], _POOL["r"])
+        return time.perf_counter() - t0
+
+
+def _oracle_pool_rate(pert, p, lev, kappa, beta, h, k, cores):
+    """The oracle on one load at one level: its integer chain on one thread, then `cores` of its node
+    solves (evenly spaced in k) run by `cores` forked worker processes at once.  Returns the unknowns,
+    the chain time, the node count and the wall time of the pooled node solves."""
+    import multiprocessing
+
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import assembly, fractional, noise
     from paper_2605_24882_amd import inputs
     n, bf = fractional.split_plain(beta)
-    t0 = time.perf_counter()
     if pert == "torus":
         from oracle import geometry
         d = assembly.Discretisation(p, lev, geometry.NurbsSurface(*inputs.torus_patches(2.0, 1.0)))
     else:
         d = assembly.Discretisation(p, lev, pert)
-    t1 = time.perf_counter()
     b = noise.load(d, inputs.noise_vectors([0], inputs.noise_length(p, lev, 16 if pert == "torus" else 6)))
-    t2 = time.perf_counter()
-    ws = fractional.integer_chain(d.M, d.S, kappa, n, b)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ws = fractional.integer_chain(d.M, d.S, kappa, n, b)
+        chain = time.perf_counter() - t0
     r = b if n == 0 else np.stack([d.M @ w for w in ws[-1]])
-    t3 = time.perf_counter()
-    sigma, omega, _ = fractional.nodes(kappa, bf, h, k, k)
-    pick = np.linspace(0, len(sigma) - 1, nsys_nodes).round().astype(int) if bf > 0 else []
-    if len(pick):
-        fractional.node_solutions(d.M, d.S, sigma[pick], r)
-    t4 = time.perf_counter()
-    return dict(N=d.N, assembly=t1 - t0, chain=t3 - t2, n=n, nodes=len(sigma) if bf > 0 else 0,
-                per_node=(t4 - t3) / max(1, len(pick)), timed_nodes=len(pick))
+    sigma, _, _ = fractional.nodes(kappa, bf, h, k, k)
+    pick = np.linspace(0, len(sigma) - 1, cores).round().astype(int)
+    _POOL.update(M=d.M, S=d.S, r=r, sig=sigma[pick])
+    with multiprocessing.get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        single = pool.map(_pool_node_solve, range(cores), chunksize=1)
+        wall = time.perf_counter() - t0
+    _POOL.clear()
+    return dict(N=d.N, n=n, chain=chain, nodes=len(sigma) if bf > 0 else 0, wall=wall,
+                single=sum(single) / len(single))
 
 
-def cpu_baseline(cfg, nodes_timed=6):
-    """The oracle (sparse LU, FP64, one thread) on the first load of the workload.
+def cpu_baseline(cfg):
+    """The oracle (sparse LU, FP64) on the first load of the workload, its node solves spread over a
+    pool of worker processes (one per core of the host's share, one thread each).
 
-    Bounded sample.  Up to 64 x 64 elements per patch: the integer solves and `nodes_timed` of the
-    sinc-node solves (evenly spaced in k) are timed at the workload's level; the per-sample time adds
-    the remaining nodes at the measured average per node (every node solve is one SuperLU
-    factorisation of the same sparsity plus one triangular solve).  Finer meshes (one factorisation
-    alone would take minutes): the time per system is measured at the two levels three and two below
-    the workload's (same degree, kappa and nodes: the integer solves and one to three node solves),
-    and extrapolated to the workload's unknowns with the power law those two levels give."""
-    from threadpoolctl import threadpool_limits
+    Bounded sample.  Per level measured: the integer chain of the load on one thread, then as many node
+    solves as there are workers, all at once (evenly spaced in k).  Every node solve is one SuperLU
+    factorisation plus a solve; the pool's wall time gives the core-seconds one node solve costs with
+    every core busy, t = wall x cores / solves (memory contention included).  A sample costs its
+    chain plus its nodes, in node-solve units c = nodes + chain time / single-solve time, so the pool
+    completes cores / (c t) samples per second.  Up to 64 x 64 elements per patch the workload's level
+    is measured; finer meshes (one factorisation alone would take minutes) at the two levels three and
+    two below, t extrapolated to the workload's unknowns by the power law of those two levels."""
     pert, p, lev, kappa, beta, h, k, nsamp, prec, rtol = cfg
     model, ncpu = cpu_model()
-    with threadpool_limits(limits=1):
-        if lev <= 6:
-            m = _oracle_system_times(pert, p, lev, kappa, beta, h, k, nodes_timed)
-            per_sample = m["chain"] + m["per_node"] * m["nodes"]
-            sample = (f"1 of the {nsamp} loads (seed 0): its {m['n']} integer solve(s) ({m['chain']:.2f} s) and "
-                      f"{m['timed_nodes']} of the {m['nodes']} node solves ({m['per_node']:.2f} s each) by SuperLU on "
-                      f"one thread, extrapolated to all {m['nodes']} nodes; assembly of M and S "
-                      f"({m['assembly']:.2f} s) excluded")
-        else:
-            lo = _oracle_system_times(pert, p, lev - 3, kappa, beta, h, k, 3)
-            hi = _oracle_system_times(pert, p, lev - 2, kappa, beta, h, k, 1)
-            per_sys = []
-            for m in (lo, hi):
-                tsys = (m["chain"] + m["per_node"] * m["timed_nodes"]) / (m["n"] + m["timed_nodes"])
-                per_sys.append(tsys)
-            n1 = 2 ** lev + p
-            N = 6 * (n1 - 2) ** 2 + 12 * (n1 - 2) + 8
-            expo = math.log(per_sys[1] / per_sys[0]) / math.log(hi["N"] / lo["N"])
-            t_sys = per_sys[1] * (N / hi["N"]) ** expo
-            per_sample = (hi["n"] + hi["nodes"]) * t_sys
-            sample = (f"1 of the {nsamp} loads (seed 0) at levels {lev - 3} and {lev - 2} of the same workload "
-                      f"({lo['N']} and {hi['N']} unknowns): the integer solves and 3 resp. 1 node solves by SuperLU "
-                      f"on one thread, {per_sys[0]:.3f} s and {per_sys[1]:.2f} s per system (factorisation + solve); "
-                      f"extrapolated as N^{expo:.2f} to {N} unknowns ({t_sys:.0f} s per system) times "
-                      f"{hi['n']} + {hi['nodes']} systems per sample; assembly excluded")
-    return {"value": 1.0 / per_sample, "unit": "samples/s", "cores": 1, "kind": "oracle", "sample": sample,
+    cores = max(1, min(16, ncpu or 1))
+    levels = [lev] if lev <= 6 else [lev - 3, lev - 2]
+    ms = [_oracle_pool_rate(pert, p, lv, kappa, beta, h, k, cores) for lv in levels]
+    t_eff = [m["wall"] for m in ms]  # core-seconds per node solve with every core busy (cores solves, cores workers)
+    m = ms[-1]
+    if lev <= 6:
+        t = t_eff[0]
+        extra = ""
+    else:
+        n1 = 2 ** lev + p
+        N = 6 * (n1 - 2) ** 2 + 12 * (n1 - 2) + 8
+        expo = math.log(t_eff[1] / t_eff[0]) / math.log(ms[1]["N"] / ms[0]["N"])
+        t = t_eff[1] * (N / ms[1]["N"]) ** expo
+        extra = (f"; {t_eff[0]:.3f} s and {t_eff[1]:.2f} s per node solve at levels {levels[0]} and {levels[1]} "
+                 f"({ms[0]['N']} and {ms[1]['N']} unknowns), extrapolated as N^{expo:.2f} to {N} unknowns: {t:.0f} s")
+    c = m["nodes"] + m["chain"] / m["single"]
+    value = cores / (c * t)
+    sample = (f"1 of the {nsamp} loads (seed 0) at level{'s' if len(levels) > 1 else ''} "
+              f"{' and '.join(str(v) for v in levels)}: its {m['n']} integer solve(s) on one thread "
+              f"({m['chain']:.2f} s), then {cores} of its {m['nodes']} node solves at once in {cores} worker "
+              f"processes ({m['wall']:.2f} s wall; {m['single']:.2f} s per solve): {t:.2f} core-s per node "
+              f"solve with every core busy{extra}; {c:.1f} node-solve units per sample; assembly excluded")
+    return {"value": value, "unit": "samples/s", "cores": cores, "kind": "oracle", "sample": sample,
             "host_cpu": model, "host_logical_cpus": ncpu}
+
+
+def cpu_baseline_child(config):
+    """cpu_baseline in a child process that never touches the GPU (its worker pool forks it)"""
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--config", config, "--cpu-baseline-only"],
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed:\n{r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
@@ -456,6 +484,8 @@ def main():
     ap.add_argument("--mg-levels", type=int, default=0,
                     help="levels of the multigrid hierarchy (0: the library's choice, all levels down to 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="time the oracle's bounded sample of the workload on the host (no GPU), print it as JSON")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the d loss / d kappa timing that follows the sampling steps")
     ap.add_argument("--no-accuracy", action="store_true",
@@ -479,6 +509,9 @@ def main():
                          "(dst = -src: reads and writes exactly that many bytes; the known-size reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(CONFIGS[args.config])))
+        return
     if args.pmc_summary:
         print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.config,
                                      args.copy_probe_mib or 512, _events(args.events_json)), indent=1))
@@ -719,7 +752,7 @@ def main():
     if gradients:
         out["gradients_per_s"] = gradients
     if not args.no_cpu_baseline and args.config in CONFIGS and args.load == "factor":
-        out["cpu_baseline"] = cpu_baseline(CONFIGS[args.config])
+        out["cpu_baseline"] = cpu_baseline_child(args.config)
     print(json.dumps(out))
 
 
