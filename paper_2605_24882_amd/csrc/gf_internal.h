@@ -113,9 +113,8 @@ struct ApplyTune {
   int TY = 1, TX = 32, NC = 1;  // NC: 64-column tiles per wavefront
   int algo = 1;                 // 0: M and S stencils applied separately; 1: one combined stencil per
                                 // distinct shift of the column tile, loads one step ahead
-  int grp = 4;                  // dispatch order of the combined-stencil kernel: groups of grp
-                                // vertically adjacent strip blocks per column tile (1: tiles fastest;
-                                // 4 was never slower at degrees 2 and 3 and 5 % faster in LDS mode)
+  int grp = 1;                  // dispatch order of the combined-stencil kernel: groups of grp
+                                // vertically adjacent strip blocks per column tile (1: tiles fastest)
   float us = 0.f;               // measured duration of one launch
 };
 
