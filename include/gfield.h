@@ -144,6 +144,20 @@ enum { GF_APPLY_STENCIL = 0, GF_APPLY_SUMFACT = 1 };
 gf_status gf_space_apply(const gf_space *space, double sigma, double s_scale, int32_t nvec, const double *x,
                          double *y, int32_t mem, int32_t kind);
 
+/* Directions of gf_space_transfer. */
+enum { GF_PROLONG = 0, GF_RESTRICT = 1 };
+/* Transfer between two consecutive levels of the space's multigrid hierarchy: the spline spaces are
+ * nested (Sec. 2.3: the knots of level j-1 are a subset of those of level j), so every spline of level
+ * j-1 is exactly a spline of level j, with coefficients P x (knot insertion, tensor product per patch).
+ * level: the finer level j of the pair, lc+1 <= j <= the space's level, where lc is the coarsest level of
+ * the hierarchy (the space's level + 1 - mg_levels; 0 with mg_levels = 0).
+ * GF_PROLONG: y = P x, x of the coarse level [nvec][N(j-1)], y [nvec][N(j)].
+ * GF_RESTRICT: y = P^T x, x [nvec][N(j)], y [nvec][N(j-1)] (the transpose the multigrid cycle applies to
+ * residuals).  Unknown counts N(j) as gf_space_ndofs gives for a space of level j.  mem: GF_HOST or
+ * GF_DEVICE for x and y; GF_EINVAL for a level outside the hierarchy or an unknown direction. */
+gf_status gf_space_transfer(const gf_space *space, int32_t level, int32_t direction, int32_t nvec, const double *x,
+                            double *y, int32_t mem);
+
 /* gf_space_apply for callers that cannot allocate device memory: code under HIP graph capture,
  * tight serving loops, harnesses that forbid allocation.  The same operator, y = (sigma M + s_scale S) x
  * for nvec vectors (kind GF_APPLY_STENCIL or GF_APPLY_SUMFACT), on device arrays x, y ([nvec][N], on

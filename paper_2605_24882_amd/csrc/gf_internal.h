@@ -166,6 +166,7 @@ struct gf_context {
   struct Graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> events;  // the fork and join events of the capture, kept while the graph lives
     std::vector<const void *> spaces;
     uint64_t last = 0;
   };

@@ -1217,8 +1217,10 @@ static std::string graph_key(const std::vector<BatchSolve *> &items, int chunk) 
 static void graph_destroy(gf_context::Graph &gr) {
   if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
   if (gr.graph) (void)hipGraphDestroy(gr.graph);
+  for (hipEvent_t e : gr.events) (void)hipEventDestroy(e);
   gr.exec = nullptr;
   gr.graph = nullptr;
+  gr.events.clear();
 }
 
 // drop the cached graphs that use space sp (its workspaces are about to be freed)
@@ -1335,8 +1337,9 @@ static void solve_all(gf_context *ctx, std::vector<BatchSolve *> &items, bool us
       throw;
     }
     HIPCHK(hipStreamEndCapture(cap, &gr.graph));
-    (void)hipEventDestroy(fork);
-    for (auto j : joins) (void)hipEventDestroy(j);
+    // the events recorded during the capture live as long as the graph (released in graph_destroy)
+    gr.events.push_back(fork);
+    gr.events.insert(gr.events.end(), joins.begin(), joins.end());
     HIPCHK(hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0));
     for (auto *it : items)
       if (std::find(gr.spaces.begin(), gr.spaces.end(), (const void *)it->sp) == gr.spaces.end())
@@ -1756,6 +1759,41 @@ gf_status gf_space_apply_noalloc(const gf_space *csp, double sigma, double s_sca
       apply_fused<double>(F, F.stM.p, F.stS.p, X, ca, cb, e, none, nullptr, nullptr, ldb, nt, 0.0, 0, s, t);
     }
     local_to_global(F, y, Y, nvec, 0, ldb, s);
+  });
+}
+
+gf_status gf_space_transfer(const gf_space *csp, int32_t level, int32_t direction, int32_t nvec, const double *x,
+                            double *y, int32_t mem) {
+  return guarded([&] {
+    gf_space *sp = const_cast<gf_space *>(csp);
+    if (!sp || !x || !y) fail(GF_EINVAL, "null argument");
+    if (nvec < 1) fail(GF_EINVAL, "nvec must be >= 1");
+    if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
+    if (direction != GF_PROLONG && direction != GF_RESTRICT) fail(GF_EINVAL, "unknown direction");
+    const int li = level - sp->lc;  // index of the finer level in the hierarchy
+    if (li < 1 || li >= sp->nlev()) fail(GF_EINVAL, "level must be in lc+1 .. the space's level");
+    HIPCHK(hipSetDevice(sp->ctx->device));
+    hipStream_t s = sp->ctx->stream;
+    const Level &F = *sp->lev[li], &C = *sp->lev[li - 1];
+    const Level &In = direction == GF_PROLONG ? C : F, &Out = direction == GF_PROLONG ? F : C;
+    InArray xin;
+    stage_in(xin, x, (size_t)nvec * In.N, mem, s);
+    OutArray yout;
+    stage_out(yout, y, (size_t)nvec * Out.N, mem);
+    const int ldb = round_up(nvec, CT), nt = ldb / CT;
+    DBuf<double> XL, YL;  // patch-local layouts, zero-filled (ghost rows stay zero)
+    XL.alloc((size_t)In.R * ldb);
+    YL.alloc((size_t)Out.R * ldb);
+    global_to_local(In, XL.p, xin.p, nvec, ldb, s);  // every copy of an unknown holds its value
+    if (direction == GF_PROLONG) {
+      prolong_add<double>(F, C, YL.p, XL.p, ldb, nt, nullptr, s);
+    } else {
+      // each fine unknown contributes once (owner copies), per patch; the coarse copies are summed
+      restrict_residual<double>(F, C, YL.p, XL.p, nullptr, ldb, nt, nullptr, s);
+      launch_interface_sum<double>(C, YL.p, ldb, nt, nullptr, s);
+    }
+    local_to_global(Out, yout.p, YL.p, nvec, 0, ldb, s);
+    finish_out(yout, s);
   });
 }
 

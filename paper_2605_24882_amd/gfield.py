@@ -31,6 +31,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 GF_OK, GF_EINVAL, GF_ENOMEM, GF_EDEVICE, GF_ENOCONV, GF_EBREAKDOWN, GF_EUNSUPPORTED = range(7)
 GF_HOST, GF_DEVICE = 0, 1
 GF_APPLY_STENCIL, GF_APPLY_SUMFACT = 0, 1
+GF_PROLONG, GF_RESTRICT = 0, 1
 GF_PREC_FP64, GF_PREC_MIXED = 0, 1
 GF_FLAG_TIME_APPLY = 1
 GF_FLAG_NO_GRAPH = 2
@@ -90,6 +91,7 @@ _SIGS = {
     "gf_space_noise_length": (_i64, [_vp]),
     "gf_space_dofmap": (_i32, [_vp, _vp]),
     "gf_space_apply": (_i32, [_vp, _dbl, _dbl, _i32, _vp, _vp, _i32, _i32]),
+    "gf_space_transfer": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _i32]),
     "gf_space_apply_noalloc": (_i32, [_vp, _dbl, _dbl, _i32, _vp, _vp, _i32]),
     "gf_white_noise": (_i32, [_vp, _i32, _vp, _vp, _i32]),
     "gf_sample": (_i32, [_vp, _dbl, _dbl, ctypes.POINTER(QuadRule), ctypes.POINTER(SolveOpts), _i32, _vp, _vp,
@@ -269,6 +271,16 @@ class Space:
         px, mem, keep = _marshal_in(x, nvec * self.ndofs)
         y = _alloc_like(x, x.shape)
         _check(_lib.gf_space_apply(self.h, sigma, s_scale, nvec, px, _ptr(y), mem, kind))
+        return y
+
+    def transfer(self, level, direction, x, n_out):
+        """Prolongation (GF_PROLONG: y = P x) or restriction (GF_RESTRICT: y = P^T x) between levels
+        level-1 and level of the space's hierarchy; x of shape (nvec, n_in), n_out unknowns out."""
+        single = len(x.shape) == 1
+        nvec = 1 if single else x.shape[0]
+        px, mem, keep = _marshal_in(x, nvec * x.shape[-1])
+        y = _alloc_like(x, (n_out,) if single else (nvec, n_out))
+        _check(_lib.gf_space_transfer(self.h, level, direction, nvec, px, _ptr(y), mem))
         return y
 
     def apply_noalloc(self, sigma, s_scale, x, y, kind=GF_APPLY_STENCIL):
