@@ -647,6 +647,7 @@ def main():
         agg["max_iters"] = max(agg["max_iters"], st["max_iters"])
         agg["max_rel_resid"] = max(agg["max_rel_resid"], st["max_rel_resid"])
     torch.cuda.synchronize()
+    host_syncs = st.get("host_syncs")  # host waits inside the CG loops of one timed step
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = nsamp * args.steps / elapsed
@@ -733,6 +734,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "samples_per_step": nsamp, "systems_per_step": st["n_systems"],
                    "max_cg_iters": agg["max_iters"], "max_rel_resid": agg["max_rel_resid"],
+                   "host_syncs_per_step": host_syncs,
                    "space_setup_s": round(space_s, 3),
                    **({"accuracy": accuracy} if accuracy else {})},
         "roofline": roof,
