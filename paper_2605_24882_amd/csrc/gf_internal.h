@@ -200,6 +200,8 @@ struct gf_space {
   gf::DBuf<double> M0, S0;
   int N0 = 0;
   std::map<std::string, std::unique_ptr<gf::Plan>> plans;
+  // smoothing degree chosen by measurement for large batches, by batch configuration (see tune_degree)
+  std::map<std::string, int> cheb_tuned;
   gf::Level &fine() { return *lev.back(); }
   const gf::Level &fine() const { return *lev.back(); }
   int nlev() const { return (int)lev.size(); }

@@ -606,8 +606,9 @@ static double mass_interval_ratio(int p) {
 }
 constexpr int kPowerIters = 16;
 // Chebyshev smoothing steps before and after the coarse correction when the caller passes 0, by the
-// size of the batch (columns x unknowns of the finest level).  A large batch is bound by memory
-// traffic, and three steps gave the fewest seconds per sample (degree 2, 64^2 elements per patch,
+// size of the batch (columns x unknowns of the finest level).  A large batch solved alone has its
+// degree measured on its first solve (tune_degree, below; three is the starting point).  A large
+// batch is bound by memory traffic, and three steps gave the fewest seconds per sample (degree 2, 64^2 elements per patch,
 // 2,624 systems: 1016 samples/s against 981 with four, 874 with five and 881 with nine; degree 3,
 // 256^2, 1,952 systems: 66.5 against 60.1 with four and 56.7 with nine).  A small batch is bound by
 // launch latency -- every CG iteration is some seventy kernel launches -- and a high degree on the
@@ -1244,12 +1245,92 @@ static void drop_graphs_of(gf_context *ctx, const gf_space *sp) {
 // one host synchronisation per chunk.  Converged column tiles exit at the top of every kernel, so the
 // iterations of a chunk after convergence cost only their launches.  Instantiated graphs are kept in
 // the context, keyed by everything their launches take as arguments, and reused by later calls.
+// Smoothing degree of a large batch solved alone (more than kSmallBatchWork columns x unknowns, the
+// caller leaving the degree to the library): on its first solve every candidate degree runs
+// kTuneIters CG iterations from the batch's own right-hand side, timed with HIP events; the residual
+// reduction of each column over them predicts its iteration count at the requested tolerance
+// (geometric rate), and the degree with the least predicted time (time per iteration x the largest
+// predicted count) is kept for the space and the batch configuration (shifts, width, precision,
+// tolerance, load), so later calls with the same batch reuse it.  The right-hand side is restored
+// before the solve proper.  Small batches are bound by launch latency and concurrent batches share
+// the GPU: they keep the fixed degrees of prepare().
+constexpr int kTuneDegrees[] = {2, 3, 4, 5};
+constexpr int kTuneIters = 3;
+
+static void tune_degree(hipStream_t s, BatchSolve &b) {
+  const SolveSpec &sp0 = b.spec;
+  const Level &F = b.sp->fine();
+  if (!sp0.cheb_auto || sp0.mass_shift || sp0.precond != GF_PRECOND_VCYCLE || b.sp->nlev() < 2 ||
+      b.concurrent > 1 || sp0.kind != GF_APPLY_STENCIL || !sp0.plan ||
+      (double)sp0.ncols * F.N < kSmallBatchWork)
+    return;
+  std::ostringstream key;
+  key.precision(17);
+  key << b.w->ldb << "," << sp0.ncols << "," << sp0.prec << "," << sp0.rtol << "," << sp0.rough_load << ","
+      << sp0.smooth_load << "," << plan_key(sp0.plan->sig) << "|";
+  for (int c = 0; c < sp0.ncols; ++c) key << sp0.col_node[c] << ",";
+  auto it = b.sp->cheb_tuned.find(key.str());
+  if (it == b.sp->cheb_tuned.end()) {
+    const int ldb = b.w->ldb;
+    const size_t nr = (size_t)F.R * ldb;
+    DBuf<double> r0;
+    r0.alloc(nr);
+    HIPCHK(hipMemcpyAsync(r0.p, b.w->r.p, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const int flags0 = b.spec.flags;
+    b.spec.flags &= ~GF_FLAG_TIME_APPLY;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = kDefaultCheb;
+    double best_cost = 1e300;
+    std::vector<ColState> cs(ldb);
+    for (int deg : kTuneDegrees) {
+      b.spec.cheb = deg;
+      b.spec.cheb_auto = false;
+      HIPCHK(hipMemcpyAsync(b.w->r.p, r0.p, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+      b.prepare(s);
+      b.start(s);
+      HIPCHK(hipEventRecord(e0, s));
+      for (int k = 0; k < kTuneIters; ++k) b.iterate(s, nullptr, nullptr);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      HIPCHK(hipMemcpy(cs.data(), b.w->cs.p, ldb * sizeof(ColState), hipMemcpyDeviceToHost));
+      double nmax = kTuneIters;
+      for (int c = 0; c < sp0.ncols; ++c) {
+        if (!(cs[c].bb > 0.0)) continue;
+        const double q = cs[c].rr / cs[c].bb;  // |r_k|^2 / |b|^2 after k iterations
+        const int k = std::max(1, cs[c].it);
+        if (cs[c].done) continue;  // converged inside the trial
+        const double n = (q > 0.0 && q < 1.0) ? k * std::log(sp0.rtol * sp0.rtol) / std::log(q) : 1e9;
+        nmax = std::max(nmax, n);
+      }
+      const double cost = ms / kTuneIters * nmax;
+      if (std::getenv("GF_TUNE_LOG"))
+        std::fprintf(stderr, "degree tune p=%d lev=%d cols=%d deg=%d: %.3f ms per iteration, %.1f iterations\n",
+                     b.sp->p, b.sp->j, sp0.ncols, deg, ms / kTuneIters, nmax);
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = deg;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipMemcpyAsync(b.w->r.p, r0.p, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    b.spec.flags = flags0;
+    it = b.sp->cheb_tuned.emplace(key.str(), best).first;
+  }
+  b.spec.cheb = it->second;
+  b.spec.cheb_auto = false;
+}
+
 static void solve_all(gf_context *ctx, std::vector<BatchSolve *> &items, bool use_graph) {
   hipStream_t s = ctx->stream;
-  for (auto *it : items) {
-    it->concurrent = (int)items.size();
-    it->prepare(s);
-  }
+  for (auto *it : items) it->concurrent = (int)items.size();
+  for (auto *it : items) tune_degree(s, *it);
+  for (auto *it : items) it->prepare(s);
   for (auto *it : items) it->start(s);
   int max_iter = 0;
   for (auto *it : items) max_iter = std::max(max_iter, it->spec.max_iter);
