@@ -1246,16 +1246,14 @@ static void drop_graphs_of(gf_context *ctx, const gf_space *sp) {
 // iterations of a chunk after convergence cost only their launches.  Instantiated graphs are kept in
 // the context, keyed by everything their launches take as arguments, and reused by later calls.
 // Smoothing degree of a large batch solved alone (more than kSmallBatchWork columns x unknowns, the
-// caller leaving the degree to the library): on its first solve every candidate degree runs
-// kTuneIters CG iterations from the batch's own right-hand side, timed with HIP events; the residual
-// reduction of each column over them predicts its iteration count at the requested tolerance
-// (geometric rate), and the degree with the least predicted time (time per iteration x the largest
-// predicted count) is kept for the space and the batch configuration (shifts, width, precision,
+// caller leaving the degree to the library): on its first solve the batch is solved once with every
+// candidate degree, eagerly from its own right-hand side, and timed with HIP events to convergence;
+// the fastest degree is kept for the space and the batch configuration (shifts, width, precision,
 // tolerance, load), so later calls with the same batch reuse it.  The right-hand side is restored
-// before the solve proper.  Small batches are bound by launch latency and concurrent batches share
-// the GPU: they keep the fixed degrees of prepare().
+// before the solve proper.  (Predicting the iteration count from the residual reduction of the first
+// few iterations favoured high degrees that were slower to convergence.)  Small batches are bound
+// by launch latency and concurrent batches share the GPU: they keep the fixed degrees of prepare().
 constexpr int kTuneDegrees[] = {2, 3, 4, 5};
-constexpr int kTuneIters = 3;
 
 static void tune_degree(hipStream_t s, BatchSolve &b) {
   const SolveSpec &sp0 = b.spec;
@@ -1266,13 +1264,12 @@ static void tune_degree(hipStream_t s, BatchSolve &b) {
     return;
   std::ostringstream key;
   key.precision(17);
-  key << b.w->ldb << "," << sp0.ncols << "," << sp0.prec << "," << sp0.rtol << "," << sp0.rough_load << ","
-      << sp0.smooth_load << "," << plan_key(sp0.plan->sig) << "|";
+  key << b.w->ldb << "," << sp0.ncols << "," << sp0.prec << "," << sp0.rtol << "," << sp0.max_iter << ","
+      << sp0.rough_load << "," << sp0.smooth_load << "," << plan_key(sp0.plan->sig) << "|";
   for (int c = 0; c < sp0.ncols; ++c) key << sp0.col_node[c] << ",";
   auto it = b.sp->cheb_tuned.find(key.str());
   if (it == b.sp->cheb_tuned.end()) {
-    const int ldb = b.w->ldb;
-    const size_t nr = (size_t)F.R * ldb;
+    const size_t nr = (size_t)F.R * b.w->ldb;
     DBuf<double> r0;
     r0.alloc(nr);
     HIPCHK(hipMemcpyAsync(r0.p, b.w->r.p, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1282,36 +1279,37 @@ static void tune_degree(hipStream_t s, BatchSolve &b) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     int best = kDefaultCheb;
-    double best_cost = 1e300;
-    std::vector<ColState> cs(ldb);
+    float best_ms = 1e30f;
+    // untimed warm-up iteration: the launch-shape autotuner runs on the first use of each kernel
+    b.spec.cheb = kDefaultCheb;
+    b.spec.cheb_auto = false;
+    b.prepare(s);
+    b.start(s);
+    b.iterate(s, nullptr, nullptr);
     for (int deg : kTuneDegrees) {
       b.spec.cheb = deg;
       b.spec.cheb_auto = false;
       HIPCHK(hipMemcpyAsync(b.w->r.p, r0.p, nr * sizeof(double), hipMemcpyDeviceToDevice, s));
       b.prepare(s);
-      b.start(s);
       HIPCHK(hipEventRecord(e0, s));
-      for (int k = 0; k < kTuneIters; ++k) b.iterate(s, nullptr, nullptr);
+      b.start(s);
+      int its = 0;
+      while (its < b.spec.max_iter) {
+        b.iterate(s, nullptr, nullptr);
+        ++its;
+        b.read_active(s);
+        HIPCHK(hipStreamSynchronize(s));
+        if (b.active_tiles() == 0) break;
+      }
       HIPCHK(hipEventRecord(e1, s));
       HIPCHK(hipEventSynchronize(e1));
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      HIPCHK(hipMemcpy(cs.data(), b.w->cs.p, ldb * sizeof(ColState), hipMemcpyDeviceToHost));
-      double nmax = kTuneIters;
-      for (int c = 0; c < sp0.ncols; ++c) {
-        if (!(cs[c].bb > 0.0)) continue;
-        const double q = cs[c].rr / cs[c].bb;  // |r_k|^2 / |b|^2 after k iterations
-        const int k = std::max(1, cs[c].it);
-        if (cs[c].done) continue;  // converged inside the trial
-        const double n = (q > 0.0 && q < 1.0) ? k * std::log(sp0.rtol * sp0.rtol) / std::log(q) : 1e9;
-        nmax = std::max(nmax, n);
-      }
-      const double cost = ms / kTuneIters * nmax;
       if (std::getenv("GF_TUNE_LOG"))
-        std::fprintf(stderr, "degree tune p=%d lev=%d cols=%d deg=%d: %.3f ms per iteration, %.1f iterations\n",
-                     b.sp->p, b.sp->j, sp0.ncols, deg, ms / kTuneIters, nmax);
-      if (cost < best_cost) {
-        best_cost = cost;
+        std::fprintf(stderr, "degree tune p=%d lev=%d cols=%d deg=%d: %d iterations, %.2f ms\n", b.sp->p, b.sp->j,
+                     sp0.ncols, deg, its, ms);
+      if (ms < best_ms) {
+        best_ms = ms;
         best = deg;
       }
     }
