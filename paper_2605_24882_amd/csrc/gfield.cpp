@@ -350,7 +350,8 @@ static std::map<const gf_space *, std::unique_ptr<gf_workspaces>> &ws_registry()
 
 static size_t scratch_slots(gf_space *sp, int ldb, int ntiles) {
   size_t slots = 2 * (size_t)kMaxRowBlocks;
-  for (auto &L : sp->lev) slots = std::max(slots, (size_t)partial_slots(*L, ldb, ntiles));
+  // two sets for the smoothing step that takes two inner products
+  for (auto &L : sp->lev) slots = std::max(slots, 2 * (size_t)partial_slots(*L, ldb, ntiles));
   return slots;
 }
 
@@ -463,8 +464,9 @@ static const ApplyTune &get_tune(const Level &L, int ldb, int ntiles, const T *x
   // GF_APPLY_SHAPE="TY,TX" fixes the launch shape (reproducible profiling runs)
   if (const char *fixed = std::getenv("GF_APPLY_SHAPE")) {
     int ty = 0, tx = 0;
-    if (std::sscanf(fixed, "%d,%d", &ty, &tx) != 2 || (ty != 1 && ty != 2 && ty != 4) || tx < 1)
-      fail(GF_EINVAL, "GF_APPLY_SHAPE must be \"TY,TX\" with TY in {1,2,4} and TX >= 1");
+    // (TX below 16 would need more partial-sum slots than the workspaces hold)
+    if (std::sscanf(fixed, "%d,%d", &ty, &tx) != 2 || (ty != 1 && ty != 2 && ty != 4) || tx < 16)
+      fail(GF_EINVAL, "GF_APPLY_SHAPE must be \"TY,TX\" with TY in {1,2,4} and TX >= 16");
     best.TY = ty;
     best.TX = tx;
     return L.tune.emplace(key, best).first->second;
@@ -794,10 +796,11 @@ static int level_degree(const gf_space *sp, const SolveSpec &spec, int li) {
 // rconv when the types differ).  Pre-smoothing: Chebyshev-Jacobi from zero; coarse correction with
 // the knot-insertion restriction of the residual, recursion, prolongation; post-smoothing with the
 // same polynomial (a symmetric preconditioner).  Returns the buffer holding the result.  With
-// fin_op >= 0 the last smoothing step also reduces r . z and applies fin_op (then *fused = true).
+// fin_op >= 0 the last smoothing step also reduces r . z (and z . fin_q when fin_q is given) and
+// applies fin_op (then *fused = true).
 template <typename T, typename TR>
 static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, const TR *rsrc, T *rconv, int fin_op,
-                 bool *fused, hipStream_t s) {
+                 bool *fused, hipStream_t s, const double *fin_q = nullptr) {
   const Level &L = *sp->lev[li];
   const int ldb = w.ldb, nt = w.ntiles;
   int *act = w.active.p;
@@ -838,7 +841,8 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
     e.cf1 = cf + (size_t)k * ldb;
     e.cf2 = cf + (size_t)(deg + k) * ldb;
     if (last && fin_op >= 0) {
-      e.dot = 1;
+      e.dot = fin_q ? 2 : 1;
+      e.q2 = fin_q;
       e.op = fin_op;
       if (fused) *fused = true;
     }
@@ -846,8 +850,8 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
     if (w.slog && li + 1 == sp->nlev()) {
       HIPCHK(hipEventCreate(&ev0));
       HIPCHK(hipEventCreate(&ev1));
-      // read z, r (and z_prev), write z_out
-      const int vecs = 3 + ((k > 0 && !(dflags & 1)) ? 1 : 0);
+      // read z, r (and z_prev), write z_out; with the two inner products also the FP64 vector q
+      const int vecs = 3 + ((k > 0 && !(dflags & 1)) ? 1 : 0) + (e.dot == 2 ? (int)(sizeof(double) / sizeof(T)) : 0);
       w.slog->entries.push_back({ev0, ev1, vecs, (int)sizeof(T), w.slog->first_phase});
     }
     apply_epi<T>(L, spec.kind, za, sig, one, e, sc, w.cs.p, act, ldb, nt, spec.rtol * spec.rtol, spec.max_iter, s,
@@ -996,8 +1000,9 @@ struct BatchSolve {
     HIPCHK(hipMemsetAsync(w->x.p, 0, (size_t)F.R * ldb * sizeof(double), s));
   }
 
-  // z = B r; the FP64 V-cycle fuses r.z with fin_op into its last smoothing step
-  bool precondition(int fin_op_fp64, hipStream_t s) {
+  // z = B r.  The V-cycle fuses the reduction of fin_op into its last smoothing step: r.z in FP64
+  // (OP_RZ0, OP_BETA), r.z and z.q in mixed precision (OP_BETA_FLEX).  Returns whether it did.
+  bool precondition(int fin_op, hipStream_t s) {
     const int fi = sp->nlev() - 1;
     bool fused = false;
     if (spec.mass_shift) {  // z = D^-1 r, D = diag(M) + sigma diag(I)
@@ -1013,11 +1018,21 @@ struct BatchSolve {
         zf = bpx<float, double>(sp, *w, spec, w->r.p, w->lw[fi].r32.p, s);
       return false;
     }
-    if (!mixed())
-      zd = vcycle<double, double>(sp, *w, spec, fi, w->r.p, nullptr, fin_op_fp64, &fused, s);
-    else
+    if (!mixed()) {
+      zd = vcycle<double, double>(sp, *w, spec, fi, w->r.p, nullptr, fin_op, &fused, s);
+    } else if (fin_op == OP_BETA_FLEX && fuse_flex()) {
+      // the flexible beta's r.z and z.q from the last FP32 smoothing step (r as its FP32 copy)
+      zf = vcycle<float, double>(sp, *w, spec, fi, w->r.p, w->lw[fi].r32.p, OP_BETA_FLEX, &fused, s, w->q.p);
+    } else {
       zf = vcycle<float, double>(sp, *w, spec, fi, w->r.p, w->lw[fi].r32.p, -1, nullptr, s);
+    }
     return fused;
+  }
+
+  // whether the mixed-precision V-cycle can take the flexible beta's two inner products in its last
+  // smoothing step (stencil path on at least two levels, offsets within the kernel's 32-bit range)
+  bool fuse_flex() const {
+    return spec.kind == GF_APPLY_STENCIL && sp->nlev() > 1 && stencil_dot2_fits(sp->fine(), w->ldb);
   }
 
   void start(hipStream_t s) {
@@ -1078,10 +1093,11 @@ struct BatchSolve {
     else
       update_xr2(F, w->x.p, w->r.p, w->p.p, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, tol2(), spec.max_iter, s);
     if (mixed()) {
-      precondition(-1, s);
+      const bool fused_dot = precondition(OP_BETA_FLEX, s);
       w->fuse_q = nullptr;
-      reduce_dot2<double, float, double>(F, w->r.p, zf, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BETA_FLEX,
-                                         tol2(), spec.max_iter, nullptr, s);
+      if (!fused_dot)
+        reduce_dot2<double, float, double>(F, w->r.p, zf, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BETA_FLEX,
+                                           tol2(), spec.max_iter, nullptr, s);
       if (fuse)
         update_xp<float>(F, w->x.p, w->p.p, zf, w->cs.p, w->active0.p, ldb, nt, s);
       else
@@ -1245,23 +1261,29 @@ static void drop_graphs_of(gf_context *ctx, const gf_space *sp) {
 // one host synchronisation per chunk.  Converged column tiles exit at the top of every kernel, so the
 // iterations of a chunk after convergence cost only their launches.  Instantiated graphs are kept in
 // the context, keyed by everything their launches take as arguments, and reused by later calls.
-// Smoothing degree of a large batch solved alone (more than kSmallBatchWork columns x unknowns, the
-// caller leaving the degree to the library): on its first solve the batch is solved once with every
+// Smoothing degree of a batch solved alone with at least kTuneMinWork columns x unknowns (the caller
+// leaving the degree to the library): on its first solve the batch is solved once with every
 // candidate degree, eagerly from its own right-hand side, and timed with HIP events to convergence;
 // the fastest degree is kept for the space and the batch configuration (shifts, width, precision,
 // tolerance, load), so later calls with the same batch reuse it.  The right-hand side is restored
 // before the solve proper.  (Predicting the iteration count from the residual reduction of the first
-// few iterations favoured high degrees that were slower to convergence.)  Small batches are bound
-// by launch latency and concurrent batches share the GPU: they keep the fixed degrees of prepare().
+// few iterations favoured high degrees that were slower to convergence.)  A batch below
+// kSmallBatchWork (one column tile on a large mesh, such as a step of the integer chain) is bound by
+// latency rather than memory traffic, and its candidates reach the high degrees that cut the
+// iterations.  Smaller batches, whose solves take a few milliseconds, and concurrent batches, which
+// share the GPU, keep the fixed degrees of prepare().
 constexpr int kTuneDegrees[] = {2, 3, 4, 5};
+constexpr int kTuneDegreesSmall[] = {3, 5, 7, 9};
+constexpr double kTuneMinWork = 1e7;
 
 static void tune_degree(hipStream_t s, BatchSolve &b) {
   const SolveSpec &sp0 = b.spec;
   const Level &F = b.sp->fine();
   if (!sp0.cheb_auto || sp0.mass_shift || sp0.precond != GF_PRECOND_VCYCLE || b.sp->nlev() < 2 ||
       b.concurrent > 1 || sp0.kind != GF_APPLY_STENCIL || !sp0.plan ||
-      (double)sp0.ncols * F.N < kSmallBatchWork)
+      (double)sp0.ncols * F.N < kTuneMinWork)
     return;
+  const bool small = (double)sp0.ncols * F.N < kSmallBatchWork;
   std::ostringstream key;
   key.precision(17);
   key << b.w->ldb << "," << sp0.ncols << "," << sp0.prec << "," << sp0.rtol << "," << sp0.max_iter << ","
@@ -1286,7 +1308,9 @@ static void tune_degree(hipStream_t s, BatchSolve &b) {
     b.prepare(s);
     b.start(s);
     b.iterate(s, nullptr, nullptr);
-    for (int deg : kTuneDegrees) {
+    const std::vector<int> cand = small ? std::vector<int>(std::begin(kTuneDegreesSmall), std::end(kTuneDegreesSmall))
+                                        : std::vector<int>(std::begin(kTuneDegrees), std::end(kTuneDegrees));
+    for (int deg : cand) {
       b.spec.cheb = deg;
       b.spec.cheb_auto = false;
       HIPCHK(hipMemcpyAsync(b.w->r.p, r0.p, nr * sizeof(double), hipMemcpyDeviceToDevice, s));

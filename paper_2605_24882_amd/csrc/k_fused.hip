@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__re
   const int col = ct * CT + lane;
   const int ldb = g.ldb;
   const int grp = gb * 4 + wave;
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0;
   if (grp < g.ngroups) {
     const int k0 = gp[grp], k1 = gp[grp + 1];
     T s = 0;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__re
       const int64_t row = gr[k];
       const int64_t i = row * ldb + col;
       const bool own = (k == k0);
-      double a2 = 0.0;
+      double a2 = 0.0, a3 = 0.0;
       if (e.kind == EPI_STORE) {
         e.y[i] = s;
         if (e.dot) a2 = (double)x[i] * (double)s;
@@ -204,11 +204,18 @@ __global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__re
         const T zo = zc + dn;
         e.zout[i] = zo;
         if (e.dot) a2 = (double)rv * (double)zo;
+        if (e.dot == 2) a3 = (double)zo * e.q2[i];
       }
-      if (own) acc += a2;
+      if (own) {
+        acc += a2;
+        acc2 += a3;
+      }
     }
   }
-  if (e.dot) block_partial(acc, partial, g.nsb_apply + gb, ldb, col);
+  if (e.dot == 2)
+    block_partial2(acc, acc2, partial, g.nsb_apply + gb, (int64_t)g.nslot2 + g.nsb_apply + gb, ldb, col);
+  else if (e.dot)
+    block_partial(acc, partial, g.nsb_apply + gb, ldb, col);
 }
 
 // Per-system scalar step after a reduction: one block per column tile sums the partials of all blocks
@@ -262,13 +269,15 @@ static void launch_apply_k(const ApplyGeom &g, int algo, const T *stM, const T *
                                                                             : k_stencil<T, P, TY, KIND, DOT, SM_PAIR>;
     if (ev0)
       hipExtLaunchKernelGGL(kern, dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM, stS, x, ca, cb, e.cf1, e.cf2,
-                            e.y, e.zout, e.r, partial, active, e.dflags);
+                            e.y, e.zout, e.r, partial, active, e.dflags, e.q2);
     else
       hipLaunchKernelGGL(kern, dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, x, ca, cb, e.cf1, e.cf2, e.y, e.zout,
-                         e.r, partial, active, e.dflags);
+                         e.r, partial, active, e.dflags, e.q2);
     return;
   }
-  if constexpr (TY <= 2) {
+  if constexpr (DOT == 2) {
+    fail(GF_EUNSUPPORTED, "two inner products need the combined-stencil kernel");
+  } else if constexpr (TY <= 2) {
     if (ev0)
       hipExtLaunchKernelGGL((k_apply_fused<T, P, TY, KIND, DOT>), dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g,
                             stM, stS, x, ca, cb, e.cf1, e.cf2, e.y, e.zout, e.r, e.dM, e.dS, partial, active,
@@ -287,8 +296,16 @@ static void launch_apply_pt(const ApplyGeom &g, int algo, const T *stM, const T 
     if (e.dot) launch_apply_k<T, P, TY, EPI_STORE, 1>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
     else launch_apply_k<T, P, TY, EPI_STORE, 0>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
   } else if (e.kind == EPI_CHEB) {
-    if (e.dot) launch_apply_k<T, P, TY, EPI_CHEB, 1>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
-    else launch_apply_k<T, P, TY, EPI_CHEB, 0>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    if (e.dot == 2) {
+      if constexpr (sizeof(T) == 4)
+        launch_apply_k<T, P, TY, EPI_CHEB, 2>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+      else
+        fail(GF_EUNSUPPORTED, "two inner products in the smoothing step are an FP32 epilogue");
+    } else if (e.dot) {
+      launch_apply_k<T, P, TY, EPI_CHEB, 1>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    } else {
+      launch_apply_k<T, P, TY, EPI_CHEB, 0>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+    }
   } else {
     launch_apply_k<T, P, TY, EPI_RESID, 0>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
   }
@@ -343,6 +360,12 @@ bool stencil_offsets_fit(const Level &L, int ldb, int TY, int elem) {
   return win < lim && st < lim;
 }
 
+bool stencil_dot2_fits(const Level &L, int ldb) {
+  // every FP32 strip height, and the FP64 vector q2 read at output rows (TY + 1 patch rows at most)
+  const int64_t lim = ((int64_t)1 << 31) - 1;
+  return stencil_offsets_fit(L, ldb, 4, 4) && (int64_t)5 * L.W * ldb * 8 < lim;
+}
+
 int partial_slots(const Level &L, int ldb, int ntiles) {
   const ApplyGeom g = apply_geom(L, ldb, ntiles, 1, 16, 1);  // the most strips of any tuning candidate
   const int ngb = (L.ngroups + 3) / 4;
@@ -363,6 +386,10 @@ void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T
     algo = 0;
     g = apply_geom(L, ldb, ntiles, std::min(g.TY, 2), tune.TX, tune.NC);
   }
+  // dot 2: the second set of partial sums follows the first (strip blocks, then interface blocks)
+  g.nslot2 = g.nsb + (L.ngroups + 3) / 4;
+  if (e.dot == 2 && (algo != 1 || !stencil_dot2_fits(L, ldb)))
+    fail(GF_EUNSUPPORTED, "two inner products in the smoothing step need the combined-stencil kernel");
   switch (L.p) {
     case 1: launch_apply_p<T, 1>(g, algo, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
     case 2: launch_apply_p<T, 2>(g, algo, stM, stS, x, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
@@ -394,10 +421,12 @@ void iface_finish(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, 
   g.ngroups = L.ngroups;
   g.ngb = (L.ngroups + 3) / 4;
   g.nsb_apply = nsb_apply;
+  g.nslot2 = nsb_apply + g.ngb;
   hipLaunchKernelGGL(k_iface_finish<T>, dim3(g.ngb * ntiles), dim3(256), 0, s, g, x, e, sc.partial, cs,
                      L.grp_ptr.p, L.grp_rows.p, active, tol2, maxit);
   HIPCHK(hipGetLastError());
-  if (e.dot) finalize(nsb_apply + g.ngb, 1, e.op, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
+  if (e.dot)
+    finalize(nsb_apply + g.ngb, e.dot == 2 ? 2 : 1, e.op, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
 }
 template void iface_finish<double>(const Level &, const double *, const EpiArgs<double> &, Scratch &, ColState *,
                                    int *, int, int, int, double, int, hipStream_t);

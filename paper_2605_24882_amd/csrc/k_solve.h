@@ -123,7 +123,9 @@ enum EpiKind { EPI_STORE = 0, EPI_CHEB = 1, EPI_RESID = 2 };
 template <typename T>
 struct EpiArgs {
   int kind = EPI_STORE;
-  int dot = 0;            // accumulate x.y (STORE) or r.z_out (CHEB); the interface kernel applies `op`
+  // 1: accumulate x.y (STORE) or r.z_out (CHEB); 2 (CHEB, FP32 stencil path): r.z_out and z_out.q2 into
+  // two sets of partial sums; the interface kernel applies `op`
+  int dot = 0;
   int op = OP_STORE;
   T *y = nullptr;         // STORE: output; CHEB/RESID: patch contributions of shared rows; RESID: output
   // CHEB: new iterate, in a different buffer than the input; on entry that buffer holds the iterate
@@ -134,6 +136,7 @@ struct EpiArgs {
   // CHEB: per-system recurrence coefficients of this step, z_out = z + cf1 d + cf2 (r - A z)/D with the
   // previous direction d = z - z_prev (cf2 includes the reciprocal of the upper spectral bound)
   const T *cf1 = nullptr, *cf2 = nullptr;
+  const double *q2 = nullptr;  // CHEB with dot 2: the second vector of z_out.q2
   // CHEB: bit 0 -- the previous direction equals the input iterate (first step after a start from
   // zero: z_prev = 0, zout is not read); bit 2 -- the step has a previous direction (every step but
   // the first of a sweep; cf1 and z_prev are read only then)
@@ -149,15 +152,19 @@ struct EpiArgs {
 struct ApplyGeom {
   int W, n1, ldb, ntiles, TY, NC, nseg, TX, nyb, nstrip, nsb, q;
   int grp;  // strip blocks of one column tile dispatched back to back (1: column tile fastest)
+  int nslot2;  // first slot of the second set of partial sums (dot 2)
 };
 
 struct IfaceGeom {
   int ldb, ntiles, ngroups, ngb, nsb_apply;
+  int nslot2;  // first slot of the second set of partial sums (dot 2)
 };
 
 ApplyGeom apply_geom(const Level &L, int ldb, int ntiles, int TY, int TXmax, int NC);
 int partial_slots(const Level &L, int ldb, int ntiles);
 bool stencil_offsets_fit(const Level &L, int ldb, int TY, int elem);
+// whether the FP32 smoothing step can take the two inner products of dot 2 for every launch shape
+bool stencil_dot2_fits(const Level &L, int ldb);
 template <typename T>
 void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
                  const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,

@@ -30,6 +30,20 @@ __device__ __forceinline__ void block_partial(double acc, double *partial, int64
   if (w == 0) partial[slot * ldb + col] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
+// the same for two doubles per lane, into partial[slot0][col] and partial[slot1][col]
+__device__ __forceinline__ void block_partial2(double acc0, double acc1, double *partial, int64_t slot0,
+                                               int64_t slot1, int ldb, int col) {
+  __shared__ double red2[2][4][CT];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  red2[0][w][lane] = acc0;
+  red2[1][w][lane] = acc1;
+  __syncthreads();
+  if (w == 0) {
+    partial[slot0 * ldb + col] = red2[0][0][lane] + red2[0][1][lane] + red2[0][2][lane] + red2[0][3][lane];
+    partial[slot1 * ldb + col] = red2[1][0][lane] + red2[1][1][lane] + red2[1][2][lane] + red2[1][3][lane];
+  }
+}
+
 // ------------------------------------------------------------------ combined-stencil kernel
 // The same operator and epilogues as k_apply_fused, organised around two observations.
 //  * Every system of a column tile applies ca M + cb S with its own (ca, cb); the tiles of the solver
@@ -184,7 +198,8 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
                                                 const T *__restrict__ stS, const T *__restrict__ x,
                                                 T *__restrict__ y, T *__restrict__ zout, const T *__restrict__ r,
                                                 int m, int iy0, int x0, int x1, int64_t ct0, int lane, T *lds,
-                                                const T *sab, int slot, int nd, T a, T b, T a1, T a2, int dflags) {
+                                                const T *sab, int slot, int nd, T a, T b, T a1, T a2, int dflags,
+                                                const double *__restrict__ q2, double &acc2) {
   constexpr int S = 2 * P + 1, SS = S * S, WR = TY + 2 * P, NH = (SS + 63) / 64, NCH = (SS + 15) / 16;
   constexpr bool PAIR = MODE != SM_COMB;
   constexpr int U = (P <= 3) ? S : 1;
@@ -205,6 +220,9 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
   const __amdgpu_buffer_rsrc_t by = buf_rsrc(y + orow0 * ldb + ct0);
   const __amdgpu_buffer_rsrc_t bm = buf_rsrc(stM + orow0 * SS);
   const __amdgpu_buffer_rsrc_t bs = buf_rsrc(stS + orow0 * SS);
+  // dot 2: z_out.q2 with q2 in FP64 (offsets checked by stencil_dot2_fits)
+  __amdgpu_buffer_rsrc_t bq;
+  if constexpr (DOT == 2) bq = buf_rsrc(q2 + orow0 * ldb + ct0);
   constexpr uint32_t E = sizeof(T);
   const uint32_t colb = (uint32_t)ldb * E;                          // bytes from one row to the next
   const uint32_t vo = (uint32_t)lane * E;                           // this lane's offset in a row
@@ -293,6 +311,14 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
         zp[t] = zpn[t];
       }
       load_step(ixn);
+      // dot 2: q2 at this step's output rows, loaded now and first needed in the epilogue (no
+      // registers held across steps for it)
+      double qv[TY];
+      if constexpr (DOT == 2) {
+#pragma unroll
+        for (int t = 0; t < TY; ++t)
+          qv[t] = buf_ld(double(), bq, (uint32_t)lane * 8u, (ooff[t] + (uint32_t)ix) * (uint32_t)ldb * 8u);
+      }
       __builtin_amdgcn_wave_barrier();
       // DPP mode: chunk k of row t holds taps 16k .. 16k+15 of this lane's combined stencil in the
       // lanes of every 16-lane row
@@ -356,10 +382,18 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
           buf_st(rv[t] - Az, by, vo, so);
         } else {
           const T dp = (dflags & 4) ? ((dflags & 1) ? zc : zc - zp[t]) : T(0);
-          const T dn = a1 * dp + a2 * ((rv[t] - Az) / D);
+          // FP32: the hardware reciprocal (1 ulp) instead of the correctly rounded division, which
+          // costs some ten vector instructions per row in this loop; D is a positive diagonal
+          T jr;
+          if constexpr (sizeof(T) == 4)
+            jr = (rv[t] - Az) * __builtin_amdgcn_rcpf(D);
+          else
+            jr = (rv[t] - Az) / D;
+          const T dn = a1 * dp + a2 * jr;
           const T zo = zc + dn;
           buf_st(zo, bz, vo, so);
           if (DOT) acc += (double)rv[t] * (double)zo;
+          if constexpr (DOT == 2) acc2 += (double)zo * qv[t];
         }
       }
       if constexpr (MODE != SM_DPP && U == S) {
@@ -387,7 +421,8 @@ void k_stencil(ApplyGeom g, const T *__restrict__ stM, const T *__restrict__ stS
                                                  const T *__restrict__ cb, const T *__restrict__ cf1,
                                                  const T *__restrict__ cf2, T *__restrict__ y, T *__restrict__ zout,
                                                  const T *__restrict__ r, double *__restrict__ partial,
-                                                 const int *__restrict__ active, int dflags) {
+                                                 const int *__restrict__ active, int dflags,
+                                                 const double *__restrict__ q2) {
   constexpr int SS = (2 * P + 1) * (2 * P + 1);
   constexpr int MAXD = StencilSlots<T, P, TY>::value;
   __shared__ __attribute__((aligned(16))) T lds_all[4][TY * MAXD * SS];
@@ -410,7 +445,7 @@ void k_stencil(ApplyGeom g, const T *__restrict__ stM, const T *__restrict__ stS
   const int wave = uni(threadIdx.x >> 6);
   const int col = ct * CT + lane;
   const int strip = sb * 4 + wave;
-  double acc = 0.0;
+  double acc = 0.0, acc2 = 0.0;
   if (strip < g.nstrip) {
     const int iyb = strip % g.nyb;
     const int seg = (strip / g.nyb) % g.nseg;
@@ -447,9 +482,13 @@ void k_stencil(ApplyGeom g, const T *__restrict__ stM, const T *__restrict__ stS
       __builtin_amdgcn_wave_barrier();
     }
     acc = stencil_strip<T, P, TY, KIND, DOT, MODE>(g, stM, stS, x, y, zout, r, m, iy0, x0, x1, (int64_t)ct * CT,
-                                                   lane, lds_all[wave], sab, slot, nd, a, b, a1, a2, dflags);
+                                                   lane, lds_all[wave], sab, slot, nd, a, b, a1, a2, dflags, q2,
+                                                   acc2);
   }
-  if (DOT) block_partial(acc, partial, sb, (int)g.ldb, col);
+  if constexpr (DOT == 2)
+    block_partial2(acc, acc2, partial, sb, (int64_t)g.nslot2 + sb, (int)g.ldb, col);
+  else if (DOT)
+    block_partial(acc, partial, sb, (int)g.ldb, col);
 }
 
 }  // namespace gf
