@@ -106,7 +106,7 @@ def workload_name(cfg, km=None, kp=None):
             f"beta={beta:g} ({nint} integer solve(s) + "
             f"{(2*k+1) if km is None else f'{km+kp+1} (k = -{km}..{kp}, tolerance 1e-6)'} sinc nodes, h={h:g}); "
             f"{nsamp} samples; "
-            f"{'FP64' if prec == 0 else 'FP32 V-cycle / FP64 CG'} MG-PCG to rel. residual {rtol:g}")
+            f"{'FP64' if prec == 0 else 'FP32 V-cycle / FP64 CG (FP32 search direction)'} MG-PCG to rel. residual {rtol:g}")
 
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_24882_amd", "csrc", f) for f in ("k_fused.hip", "k_stencil.h")]
@@ -716,8 +716,9 @@ def main():
     roof = roof_entry(agg["smooth_ms"], agg["smooth_launches"], agg["smooth_bytes"],
                       f"k_stencil<{vt},p,*,EPI_CHEB,*,*> (Chebyshev smoothing step on the finest level, stencil form)",
                       "smoother")
-    roof_outer = roof_entry(agg["apply_ms"], agg["apply_launches"], agg["apply_bytes"],
-                            "k_stencil<double,p,*,EPI_STORE,dot,*> (outer CG operator, stencil form)", "outer")
+    outer_kernel = ("k_stencil<double,p,*,EPI_STORE,dot,*,float> (outer CG operator on the FP32 search direction, "
+                    "stencil form)" if prec != 0 else "k_stencil<double,p,*,EPI_STORE,dot,*> (outer CG operator, stencil form)")
+    roof_outer = roof_entry(agg["apply_ms"], agg["apply_launches"], agg["apply_bytes"], outer_kernel, "outer")
 
     out = {
         "metric": "field samples/sec at rel-L2 err <=1e-6 vs FP64 oracle; operator-apply HBM GB/s",

@@ -305,6 +305,8 @@ struct Workspace {
   // and whether every aligned group of 16 columns has one shift (see EpiArgs::nslot, rows16)
   int nslot = 0, rows16 = 0;
   DBuf<double> x, r, p, q;  // outer CG (FP64)
+  // mixed precision: the search direction stored in FP32 (see BatchSolve::p32)
+  DBuf<float> p32;
   std::vector<LevelWork> lw;
   DBuf<double> sig64, one64, zero64;
   DBuf<float> sig32, one32;
@@ -372,6 +374,7 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
   w->r.alloc(nf);
   w->p.alloc(nf);
   w->q.alloc(nf);
+  if (prec == GF_PREC_MIXED) w->p32.alloc(nf);
   w->lw.resize(sp->nlev());
   for (int li = 0; li < sp->nlev(); ++li) {
     const Level &L = *sp->lev[li];
@@ -941,6 +944,13 @@ struct BatchSolve {
 
   bool mixed() const { return spec.prec == GF_PREC_MIXED; }
   double tol2() const { return spec.rtol * spec.rtol; }
+  // Mixed precision with the V-cycle on the stencil path: the search direction p is stored in FP32.
+  // q = A p is still formed in FP64 from the stored p, and x += alpha p, r -= alpha q use that same
+  // p, so x and r stay consistent in FP64 (the attainable accuracy is unchanged); the rounding of
+  // p = z + beta p only perturbs the direction, as the FP32 preconditioner already does, which the
+  // flexible beta absorbs.  It halves the bytes of the operator's window vector and of p in the
+  // x/p update.  Decided in start() from the batch (shift groups, offsets).
+  bool p32 = false;
 
   int concurrent = 1;  // batches solved together in one call (their graph branches share the GPU)
   void prepare(hipStream_t s) {
@@ -1037,6 +1047,8 @@ struct BatchSolve {
 
   void start(hipStream_t s) {
     const Level &F = sp->fine();
+    p32 = mixed() && !spec.mass_shift && spec.kind == GF_APPLY_STENCIL && spec.precond == GF_PRECOND_VCYCLE &&
+          sp->nlev() > 1 && w->rows16 && w->p32.p && outer_p32_fits(F, w->ldb);
     // the smoothing launches of the first preconditioner application are timed with the others
     w->slog = (spec.flags & GF_FLAG_TIME_APPLY) ? &slog : nullptr;
     slog.first_phase = true;
@@ -1052,7 +1064,9 @@ struct BatchSolve {
         reduce_dot<double, double>(F, w->r.p, zd, sc, ldb, nt, w->cs.p, w->active.p, OP_RZ0, tol2(),
                                    spec.max_iter, nullptr, s);
     }
-    if (mixed())
+    if (p32)
+      convert_rows<float, float>(F, zf, w->p32.p, ldb, nt, w->active.p, s);
+    else if (mixed())
       convert_rows<float, double>(F, zf, w->p.p, ldb, nt, w->active.p, s);
     else
       convert_rows<double, double>(F, zd, w->p.p, ldb, nt, w->active.p, s);
@@ -1072,12 +1086,18 @@ struct BatchSolve {
     e.y = w->q.p;
     e.dot = 1;
     e.op = OP_ALPHA;
-    if (spec.mass_shift)
+    if (spec.mass_shift) {
       apply_epi<double>(F, GF_APPLY_STENCIL, w->p.p, w->one64.p, w->sig64.p, e, sc, w->cs.p, w->active.p, ldb, nt,
                         tol2(), spec.max_iter, s, e0, e1, F.stI.p);
-    else
+    } else if (p32) {
+      // launch shape of the FP64 operator (the tuner reads the FP64 residual as its input vector)
+      const ApplyTune &t = get_tune<double>(F, ldb, nt, w->r.p, w->sig64.p, w->one64.p, e, s);
+      apply_outer_p32(F, w->p32.p, w->sig64.p, w->one64.p, e, sc, w->cs.p, w->active.p, ldb, nt, tol2(),
+                      spec.max_iter, s, t, e0, e1);
+    } else {
       apply_epi<double>(F, spec.kind, w->p.p, w->sig64.p, w->one64.p, e, sc, w->cs.p, w->active.p, ldb, nt, tol2(),
                         spec.max_iter, s, e0, e1);
+    }
     if (spec.mass_shift) {
       // Jacobi CG of M + sigma I: residual update, z = r / D, the test and beta in one pass
       zd = w->lw[sp->nlev() - 1].z64a.p;
@@ -1098,7 +1118,9 @@ struct BatchSolve {
       if (!fused_dot)
         reduce_dot2<double, float, double>(F, w->r.p, zf, w->q.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BETA_FLEX,
                                            tol2(), spec.max_iter, nullptr, s);
-      if (fuse)
+      if (p32)
+        update_xp<float, float>(F, w->x.p, w->p32.p, zf, w->cs.p, w->active0.p, ldb, nt, s);
+      else if (fuse)
         update_xp<float>(F, w->x.p, w->p.p, zf, w->cs.p, w->active0.p, ldb, nt, s);
       else
         update_p2<float>(F, w->p.p, zf, w->cs.p, ldb, nt, w->active.p, s);
@@ -1138,11 +1160,11 @@ struct BatchSolve {
       res.apply_ms += ms;
       res.apply_launches += 1;
       res.apply_col_sum += (double)active_tiles * CT;
-      // algorithmic bytes: read x and write y for every active column of every patch row, plus the
-      // two FP64 stencils of every row
+      // algorithmic bytes: read x (FP32 when the search direction is stored so) and write y (FP64)
+      // for every active column of every patch row, plus the two FP64 stencils of every row
       const Level &F = sp->fine();
       const double rows = (double)F.npatch * F.n1 * F.n1;
-      res.apply_bytes += 2.0 * 8.0 * active_tiles * CT * rows + 2.0 * F.S * F.S * 8.0 * rows;
+      res.apply_bytes += ((p32 ? 4.0 : 8.0) + 8.0) * active_tiles * CT * rows + 2.0 * F.S * F.S * 8.0 * rows;
     }
     const Level &F = sp->fine();
     const double rows = (double)F.npatch * F.n1 * F.n1;
@@ -1221,8 +1243,8 @@ static std::string graph_key(const std::vector<BatchSolve *> &items, int chunk) 
     os << "|" << (const void *)it->sp << "," << (const void *)sp.plan << "," << (const void *)&w << "," << w.ldb
        << "," << sp.prec << "," << sp.kind << "," << sp.cheb << "," << sp.rtol << "," << sp.max_iter << ","
        << sp.flags << "," << sp.precond << "," << sp.mass_shift << "," << sp.smooth_load << "," << w.nslot << ","
-       << w.rows16 << "," << (const void *)w.x.p << "," << (const void *)w.r.p << "," << (const void *)w.p.p << ","
-       << (const void *)w.q.p << "," << (const void *)w.cs.p << "," << (const void *)w.partial.p << ","
+       << w.rows16 << "," << it->p32 << "," << (const void *)w.x.p << "," << (const void *)w.r.p << ","
+       << (const void *)w.p.p << "," << (const void *)w.p32.p << "," << (const void *)w.q.p << "," << (const void *)w.cs.p << "," << (const void *)w.partial.p << ","
        << (const void *)w.active.p << "," << (const void *)w.sig64.p;
     if (sp.plan) os << "," << (const void *)sp.plan->Ainv.p;
     for (const LevelWork &l : w.lw)

@@ -167,8 +167,8 @@ __global__ __launch_bounds__(256) void k_apply_fused(ApplyGeom g, const T *__res
 // Interface completion: sum the patch contributions of every shared unknown and run the epilogue on
 // each copy.  With e.dot the last block of a column tile adds the partials of both kernels (apply
 // blocks first, then interface blocks, in block order) and applies the per-system step e.op.
-template <typename T>
-__global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__restrict__ x, EpiArgs<T> e,
+template <typename T, typename XT = T>
+__global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const XT *__restrict__ x, EpiArgs<T> e,
                                                       double *partial, ColState *cs,
                                                       const int *__restrict__ gp, const int *__restrict__ gr,
                                                       int *active, double tol2, int maxit) {
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_iface_finish(IfaceGeom g, const T *__re
         const T rv = e.r[i];
         const T D = e.sig[col] * e.dM[row] + e.dS[row];
         const T res = (rv - s) / D;
-        const T zc = x[i];
+        const T zc = (T)x[i];
         const T dp = (e.dflags & 4) ? ((e.dflags & 1) ? zc : zc - e.zout[i]) : T(0);
         const T dn = ((e.dflags & 4) ? e.cf1[col] : T(0)) * dp + e.cf2[col] * res;
         const T zo = zc + dn;
@@ -408,9 +408,9 @@ template void apply_fused<float>(const Level &, const float *, const float *, co
                                  const float *, const EpiArgs<float> &, Scratch &, ColState *, int *, int, int, double,
                                  int, hipStream_t, const ApplyTune &, hipEvent_t, hipEvent_t);
 
-template <typename T>
-void iface_finish(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb,
-                  int ntiles, int nsb_apply, double tol2, int maxit, hipStream_t s) {
+template <typename T, typename XT>
+static void iface_finish_x(const Level &L, const XT *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active,
+                           int ldb, int ntiles, int nsb_apply, double tol2, int maxit, hipStream_t s) {
   if (L.ngroups == 0) {
     if (e.dot) fail(GF_EUNSUPPORTED, "inner product epilogue needs interface groups");
     return;
@@ -422,11 +422,57 @@ void iface_finish(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, 
   g.ngb = (L.ngroups + 3) / 4;
   g.nsb_apply = nsb_apply;
   g.nslot2 = nsb_apply + g.ngb;
-  hipLaunchKernelGGL(k_iface_finish<T>, dim3(g.ngb * ntiles), dim3(256), 0, s, g, x, e, sc.partial, cs,
+  hipLaunchKernelGGL((k_iface_finish<T, XT>), dim3(g.ngb * ntiles), dim3(256), 0, s, g, x, e, sc.partial, cs,
                      L.grp_ptr.p, L.grp_rows.p, active, tol2, maxit);
   HIPCHK(hipGetLastError());
   if (e.dot)
     finalize(nsb_apply + g.ngb, e.dot == 2 ? 2 : 1, e.op, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
+}
+
+template <typename T>
+void iface_finish(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb,
+                  int ntiles, int nsb_apply, double tol2, int maxit, hipStream_t s) {
+  iface_finish_x<T, T>(L, x, e, sc, cs, active, ldb, ntiles, nsb_apply, tol2, maxit, s);
+}
+
+// The outer CG operator of the mixed-precision solver, q = (ca M + cb S) p with p.q, on a search
+// direction stored in FP32 (FP64 stencils, arithmetic and output; each p value is widened when
+// loaded).  Shift-per-16-columns tiles (DPP mode) on the combined-stencil kernel only.
+template <int P>
+static void launch_outer_p32(const ApplyGeom &g, const double *stM, const double *stS, const float *p,
+                             const double *ca, const double *cb, const EpiArgs<double> &e, double *partial,
+                             const int *active, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  auto kern = k_stencil<double, P, 1, EPI_STORE, 1, SM_DPP, float>;
+  if constexpr (P <= 3)
+    if (g.TY == 2) kern = k_stencil<double, P, 2, EPI_STORE, 1, SM_DPP, float>;
+  if (ev0)
+    hipExtLaunchKernelGGL(kern, dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM, stS, p, ca, cb, e.cf1, e.cf2,
+                          e.y, e.zout, e.r, partial, active, e.dflags, e.q2);
+  else
+    hipLaunchKernelGGL(kern, dim3(8 * g.q), dim3(256), 0, s, g, stM, stS, p, ca, cb, e.cf1, e.cf2, e.y, e.zout, e.r,
+                       partial, active, e.dflags, e.q2);
+}
+
+bool outer_p32_fits(const Level &L, int ldb) { return stencil_offsets_fit(L, ldb, 2, (int)sizeof(double)); }
+
+void apply_outer_p32(const Level &L, const float *p, const double *ca, const double *cb, const EpiArgs<double> &e,
+                     Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2, int maxit,
+                     hipStream_t s, const ApplyTune &tune, hipEvent_t ev0, hipEvent_t ev1) {
+  if (e.kind != EPI_STORE || e.dot != 1 || !e.rows16 || tune.algo != 1 || !outer_p32_fits(L, ldb))
+    fail(GF_EUNSUPPORTED, "FP32 search direction: combined-stencil operator with p.q on 16-column shift groups");
+  ApplyGeom g = apply_geom(L, ldb, ntiles, std::min(tune.TY, 2), tune.TX, tune.NC);
+  g.nslot2 = g.nsb + (L.ngroups + 3) / 4;
+  const double *stM = L.stM.p, *stS = L.stS.p;
+  switch (L.p) {
+    case 1: launch_outer_p32<1>(g, stM, stS, p, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 2: launch_outer_p32<2>(g, stM, stS, p, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 3: launch_outer_p32<3>(g, stM, stS, p, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 4: launch_outer_p32<4>(g, stM, stS, p, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    case 5: launch_outer_p32<5>(g, stM, stS, p, ca, cb, e, sc.partial, active, s, ev0, ev1); break;
+    default: fail(GF_EUNSUPPORTED, "degree out of range");
+  }
+  HIPCHK(hipGetLastError());
+  iface_finish_x<double, float>(L, p, e, sc, cs, active, ldb, ntiles, g.nsb, tol2, maxit, s);
 }
 template void iface_finish<double>(const Level &, const double *, const EpiArgs<double> &, Scratch &, ColState *,
                                    int *, int, int, int, double, int, hipStream_t);
@@ -453,7 +499,9 @@ static RowGeom row_geom(const Level &L, int ldb) {
   g.n1 = L.n1;
   g.ldb = ldb;
   g.owner = L.owner.p;
-  g.nrb = kRowBlocks;
+  // row blocks per column tile: at least 2048 blocks in all, so that a batch of one or two tiles
+  // still keeps eight wavefronts per compute unit in flight
+  g.nrb = std::max(kRowBlocks, std::min(kMaxRowBlocks, 2048 / std::max(1, g.ntiles)));
   const int64_t need = (L.R + 15) / 16;
   if (need < g.nrb) g.nrb = (int)std::max<int64_t>(1, need);
   return g;
@@ -690,9 +738,9 @@ void jacobi_step(const Level &L, double *r, const double *q, double *z, const do
   finalize(g.nrb, 2, OP_CHECK_BETA, sc, cs, active, ldb, ntiles, tol2, maxit, nullptr, s);
 }
 
-// x += alpha p, p = z + beta p over the column tiles active when the iteration began
-template <typename TZ>
-__global__ __launch_bounds__(256) void k_update_xp(RowGeom g, double *__restrict__ x, double *__restrict__ p,
+// x += alpha p, p = z + beta p over the column tiles active when the iteration began (p stored as TP)
+template <typename TZ, typename TP>
+__global__ __launch_bounds__(256) void k_update_xp(RowGeom g, double *__restrict__ x, TP *__restrict__ p,
                                                    const TZ *__restrict__ z, const ColState *cs,
                                                    const int *active0) {
   const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
@@ -712,7 +760,7 @@ __global__ __launch_bounds__(256) void k_update_xp(RowGeom g, double *__restrict
       ok[u] = row < g.R;
       if (ok[u]) {
         const int64_t i = row * ldb + col;
-        pv[u] = p[i];
+        pv[u] = (double)p[i];
         xv[u] = x[i];
         zv[u] = (double)z[i];
       }
@@ -722,7 +770,7 @@ __global__ __launch_bounds__(256) void k_update_xp(RowGeom g, double *__restrict
       if (!ok[u]) continue;
       const int64_t i = (r0 + u * stride) * ldb + col;
       x[i] = xv[u] + al * pv[u];
-      p[i] = zv[u] + be * pv[u];
+      p[i] = (TP)(zv[u] + be * pv[u]);
     }
   }
 }
@@ -744,17 +792,19 @@ template void cheb_first_cg<float>(const Level &, double *, const double *, floa
                                    const float *, const float *, const float *, Scratch &, ColState *, int *, int *,
                                    int, int, double, int, hipStream_t);
 
-template <typename TZ>
-void update_xp(const Level &L, double *x, double *p, const TZ *z, const ColState *cs, const int *active0, int ldb,
+template <typename TZ, typename TP>
+void update_xp(const Level &L, double *x, TP *p, const TZ *z, const ColState *cs, const int *active0, int ldb,
                int ntiles, hipStream_t s) {
   const RowGeom g = row_geom(L, ldb);
-  hipLaunchKernelGGL(k_update_xp<TZ>, dim3(g.nrb * ntiles), dim3(256), 0, s, g, x, p, z, cs, active0);
+  hipLaunchKernelGGL((k_update_xp<TZ, TP>), dim3(g.nrb * ntiles), dim3(256), 0, s, g, x, p, z, cs, active0);
   HIPCHK(hipGetLastError());
 }
-template void update_xp<double>(const Level &, double *, double *, const double *, const ColState *, const int *, int,
-                                int, hipStream_t);
-template void update_xp<float>(const Level &, double *, double *, const float *, const ColState *, const int *, int,
-                               int, hipStream_t);
+template void update_xp<double, double>(const Level &, double *, double *, const double *, const ColState *,
+                                        const int *, int, int, hipStream_t);
+template void update_xp<float, double>(const Level &, double *, double *, const float *, const ColState *,
+                                       const int *, int, int, hipStream_t);
+template void update_xp<float, float>(const Level &, double *, float *, const float *, const ColState *, const int *,
+                                      int, int, hipStream_t);
 
 void update_xr2(const Level &L, double *x, double *r, const double *p, const double *q, Scratch &sc, int ldb,
                 int ntiles, ColState *cs, int *active, double tol2, int maxit, hipStream_t s) {

@@ -194,9 +194,14 @@ void cheb_first_cg(const Level &L, double *r, const double *q, T *r32, T *z, con
 void jacobi_step(const Level &L, double *r, const double *q, double *z, const double *ca, const double *dA,
                  const double *cb, const double *dB, Scratch &sc, ColState *cs, int *active, int *active0, int ldb,
                  int ntiles, double tol2, int maxit, hipStream_t s);
-template <typename TZ>
-void update_xp(const Level &L, double *x, double *p, const TZ *z, const ColState *cs, const int *active0, int ldb,
+template <typename TZ, typename TP = double>
+void update_xp(const Level &L, double *x, TP *p, const TZ *z, const ColState *cs, const int *active0, int ldb,
                int ntiles, hipStream_t s);
+// the mixed-precision outer operator on an FP32 search direction (see k_fused.hip)
+bool outer_p32_fits(const Level &L, int ldb);
+void apply_outer_p32(const Level &L, const float *p, const double *ca, const double *cb, const EpiArgs<double> &e,
+                     Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2, int maxit,
+                     hipStream_t s, const ApplyTune &tune, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 template <typename TA, typename TB>
 void reduce_dot(const Level &L, const TA *a, const TB *b, Scratch &sc, int ldb, int ntiles, ColState *cs,

@@ -187,6 +187,7 @@ template void convert_rows<float, double>(const Level &, const float *, double *
                                           hipStream_t);
 template void convert_rows<double, double>(const Level &, const double *, double *, int, int, const int *,
                                            hipStream_t);
+template void convert_rows<float, float>(const Level &, const float *, float *, int, int, const int *, hipStream_t);
 
 // power-iteration step for the spectral bound of D^-1 A: v = w / D
 struct FDivDiag {

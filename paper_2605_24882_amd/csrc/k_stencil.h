@@ -193,9 +193,9 @@ struct StencilSlots {
 
 // One strip of TY rows x [x0, x1) of one patch for one column tile (lane = system), in stencil mode
 // MODE.  Returns the lane's share of the epilogue's inner product.
-template <typename T, int P, int TY, int KIND, int DOT, int MODE>
+template <typename T, int P, int TY, int KIND, int DOT, int MODE, typename XT>
 __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__restrict__ stM,
-                                                const T *__restrict__ stS, const T *__restrict__ x,
+                                                const T *__restrict__ stS, const XT *__restrict__ x,
                                                 T *__restrict__ y, T *__restrict__ zout, const T *__restrict__ r,
                                                 int m, int iy0, int x0, int x1, int64_t ct0, int lane, T *lds,
                                                 const T *sab, int slot, int nd, T a, T b, T a1, T a2, int dflags,
@@ -226,9 +226,14 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
   constexpr uint32_t E = sizeof(T);
   const uint32_t colb = (uint32_t)ldb * E;                          // bytes from one row to the next
   const uint32_t vo = (uint32_t)lane * E;                           // this lane's offset in a row
+  // the window vector may be stored in a narrower type than the arithmetic (XT = float, T = double:
+  // the FP32 search direction of the mixed-precision CG); each value is widened once, when loaded
+  constexpr uint32_t EX = sizeof(XT);
+  const uint32_t colbx = (uint32_t)ldb * EX, vox = (uint32_t)lane * EX;
+  auto ldx = [&](uint32_t so) -> T { return (T)buf_ld(XT(), bx, vox, so); };
   uint32_t woff[WR];
 #pragma unroll
-  for (int k = 0; k < WR; ++k) woff[k] = (uint32_t)((min(iy0 + k, W - 1) - iy0) * W) * colb;
+  for (int k = 0; k < WR; ++k) woff[k] = (uint32_t)((min(iy0 + k, W - 1) - iy0) * W) * colbx;
   uint32_t ooff[TY];
 #pragma unroll
   for (int t = 0; t < TY; ++t) ooff[t] = (uint32_t)((min(iy0 + t, n1 - 1) - iy0) * W);  // in rows
@@ -243,11 +248,11 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
   for (int k = 0; k < WR; ++k) {
     if constexpr (U == S) {
 #pragma unroll
-      for (int c = 0; c < S; ++c) win[k][c] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(x0 + c) * colb);
+      for (int c = 0; c < S; ++c) win[k][c] = ldx(woff[k] + (uint32_t)(x0 + c) * colbx);
     } else {
 #pragma unroll
-      for (int c = 0; c < S - 1; ++c) win[k][c + 1] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(x0 + c) * colb);
-      nxt[k] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(x0 + 2 * P) * colb);
+      for (int c = 0; c < S - 1; ++c) win[k][c + 1] = ldx(woff[k] + (uint32_t)(x0 + c) * colbx);
+      nxt[k] = ldx(woff[k] + (uint32_t)(x0 + 2 * P) * colbx);
     }
   }
   T cmn[TY][NH], csn[TY][NH], rvn[TY], zpn[TY];
@@ -283,7 +288,7 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
 #pragma unroll
           for (int c = 0; c < S - 1; ++c) win[k][c] = win[k][c + 1];
           win[k][S - 1] = nxt[k];
-          nxt[k] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(ixn + 2 * P) * colb);
+          nxt[k] = ldx(woff[k] + (uint32_t)(ixn + 2 * P) * colbx);
         }
       }
       // stage this step's stencils (loaded during the previous step; lane l holds tap l of M_i and
@@ -344,14 +349,14 @@ __device__ __forceinline__ double stencil_strip(const ApplyGeom &g, const T *__r
         if constexpr (U == S) {
           dpp_taps<T, S, U, TY, 0, S>(ac, cc, win, u);
 #pragma unroll
-          for (int k = 0; k < WR; ++k) win[k][u % S] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(ixn + 2 * P) * colb);
+          for (int k = 0; k < WR; ++k) win[k][u % S] = ldx(woff[k] + (uint32_t)(ixn + 2 * P) * colbx);
           dpp_taps<T, S, U, TY, S, S * S>(ac, cc, win, u);
         } else {
           dpp_taps<T, S, U, TY, 0, S * S>(ac, cc, win, u);
         }
       } else if constexpr (U == S) {
 #pragma unroll
-        for (int k = 0; k < WR; ++k) nxt[k] = buf_ld(T(), bx, vo, woff[k] + (uint32_t)(ixn + 2 * P) * colb);
+        for (int k = 0; k < WR; ++k) nxt[k] = ldx(woff[k] + (uint32_t)(ixn + 2 * P) * colbx);
       }
 #pragma unroll
       for (int t = 0; t < TY; ++t) {
@@ -414,10 +419,10 @@ struct StencilWaves {
   static constexpr int value = (sizeof(T) == 8 && P == 3 && TY == 2 && KIND == EPI_STORE && MODE == SM_DPP) ? 3 : 0;
 };
 
-template <typename T, int P, int TY, int KIND, int DOT, int MODE>
+template <typename T, int P, int TY, int KIND, int DOT, int MODE, typename XT = T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StencilWaves<T, P, TY, KIND, MODE>::value)))
 void k_stencil(ApplyGeom g, const T *__restrict__ stM, const T *__restrict__ stS,
-                                                 const T *__restrict__ x, const T *__restrict__ ca,
+                                                 const XT *__restrict__ x, const T *__restrict__ ca,
                                                  const T *__restrict__ cb, const T *__restrict__ cf1,
                                                  const T *__restrict__ cf2, T *__restrict__ y, T *__restrict__ zout,
                                                  const T *__restrict__ r, double *__restrict__ partial,
@@ -481,7 +486,7 @@ void k_stencil(ApplyGeom g, const T *__restrict__ stM, const T *__restrict__ stS
       }
       __builtin_amdgcn_wave_barrier();
     }
-    acc = stencil_strip<T, P, TY, KIND, DOT, MODE>(g, stM, stS, x, y, zout, r, m, iy0, x0, x1, (int64_t)ct * CT,
+    acc = stencil_strip<T, P, TY, KIND, DOT, MODE, XT>(g, stM, stS, x, y, zout, r, m, iy0, x0, x1, (int64_t)ct * CT,
                                                    lane, lds_all[wave], sab, slot, nd, a, b, a1, a2, dflags, q2,
                                                    acc2);
   }
