@@ -317,24 +317,31 @@ __global__ __launch_bounds__(256) void k_prolong(T *zf, const T *zc, int Wf, int
   zf[i] += acc;
 }
 
-// Line-marching forms of the two transfers.  One wavefront per (patch, output row, column tile)
-// walks the input columns of its band of input rows in order: the contraction across rows is done
-// once per input column and pushed into a register window, and every output whose band ends at that
-// column is formed from the window.  Each input value is thus loaded once per output row that needs
-// it (instead of once per output value) and the loop body has no data-dependent branches.  The
+// Line-marching forms of the two transfers.  One wavefront per (patch, output row, segment of the
+// row's outputs, column tile) walks the input columns of its band of input rows in order: the
+// contraction across rows is done once per input column and pushed into a register window, and every
+// output whose band ends at that column is formed from the window.  Each input value is thus loaded
+// once per output row that needs it (instead of once per output value; a segment boundary repeats
+// the few input columns of one band) and the loop body has no data-dependent branches.  The
 // knot-insertion bands have fixed widths rw <= p+2 (restriction) and pw <= (p+3)/2 (prolongation)
 // and start at non-decreasing input indices (rs, ps).
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restrict__ r, const uint8_t *__restrict__ ownf,
                                                        int Wf, int Wc, int n1f, int n1c, int ldb,
                                                        const int *__restrict__ rs, const T *__restrict__ rcoef, int rw,
-                                                       const int *__restrict__ active, int ntiles, int np) {
+                                                       const int *__restrict__ active, int ntiles, int np, int nseg) {
   constexpr int RW = P + 2;
   const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
   const int lane = threadIdx.x;
-  const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
-  if (id >= np * n1c) return;
+  const int wid = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
+  if (wid >= np * n1c * nseg) return;
+  // segment sg of the row: outputs [c0, c1); the march starts at the first input of c0's band (the
+  // register window holds only columns of the bands it forms)
+  const int id = wid / nseg, sg = wid - id * nseg;
+  const int seglen = (n1c + nseg - 1) / nseg;
+  const int c0 = sg * seglen, c1 = min(c0 + seglen, n1c);
+  if (c0 >= c1) return;
   const int iyc = id % n1c, m = id / n1c;
   const int64_t ct0 = (int64_t)ct * CT;
   const int64_t fbase = (int64_t)m * Wf * Wf;
@@ -351,9 +358,9 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
   T tw[RW];
 #pragma unroll
   for (int l = 0; l < RW; ++l) tw[l] = 0;
-  int ixc = 0;
-  int last = rs[0] + rw - 1;  // last fine column of output ixc's band
-  for (int fx = 0; fx < n1f; ++fx) {
+  int ixc = c0;
+  int last = rs[c0] + rw - 1;  // last fine column of output ixc's band
+  for (int fx = rs[c0]; fx < n1f && ixc < c1; ++fx) {
     T t = 0;
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
@@ -364,7 +371,7 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
 #pragma unroll
     for (int l = 0; l < RW - 1; ++l) tw[l] = tw[l + 1];
     tw[RW - 1] = t;  // the window now holds fine columns fx-RW+1 .. fx
-    while (ixc < n1c && last == fx) {
+    while (ixc < c1 && last == fx) {
       T acc = 0;
 #pragma unroll
       for (int l = 0; l < RW; ++l) {
@@ -373,7 +380,7 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
       }
       (rc + (cbase + ixc) * ldb + ct0)[lane] = acc;
       ++ixc;
-      if (ixc < n1c) last = rs[ixc] + rw - 1;
+      if (ixc < c1) last = rs[ixc] + rw - 1;
     }
   }
 }
@@ -382,13 +389,18 @@ template <typename T, int P>
 __global__ __launch_bounds__(256) void k_prolong_rows(T *zf, const T *__restrict__ zc, int Wf, int Wc, int n1f, int n1c,
                                                       int ldb, const int *__restrict__ ps,
                                                       const T *__restrict__ pcoef, int pw,
-                                                      const int *__restrict__ active, int ntiles, int np) {
+                                                      const int *__restrict__ active, int ntiles, int np, int nseg) {
   constexpr int PW = (P + 3) / 2;
   const int ct = blockIdx.x % ntiles;
   if (active && !active[ct]) return;
   const int lane = threadIdx.x;
-  const int id = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
-  if (id >= np * n1f) return;
+  const int wid = wave_uniform((int)(blockIdx.x / ntiles) * 4 + threadIdx.y);
+  if (wid >= np * n1f * nseg) return;
+  // segment sg of the row: outputs [f0, f1), the march starting at the first input of f0's band
+  const int id = wid / nseg, sg = wid - id * nseg;
+  const int seglen = (n1f + nseg - 1) / nseg;
+  const int f0 = sg * seglen, f1 = min(f0 + seglen, n1f);
+  if (f0 >= f1) return;
   const int iyf = id % n1f, m = id / n1f;
   const int64_t ct0 = (int64_t)ct * CT;
   const int64_t cbase = (int64_t)m * Wc * Wc;
@@ -404,16 +416,16 @@ __global__ __launch_bounds__(256) void k_prolong_rows(T *zf, const T *__restrict
   T sw[PW];
 #pragma unroll
   for (int l = 0; l < PW; ++l) sw[l] = 0;
-  int ixf = 0;
-  int last = ps[0] + pw - 1;  // last coarse column of fine output ixf's band
-  for (int cx = 0; cx < n1c; ++cx) {
+  int ixf = f0;
+  int last = ps[f0] + pw - 1;  // last coarse column of fine output ixf's band
+  for (int cx = ps[f0]; cx < n1c && ixf < f1; ++cx) {
     T t = 0;
 #pragma unroll
     for (int k = 0; k < PW; ++k) t += wy[k] * (zc + (crow[k] + cx) * ldb + ct0)[lane];
 #pragma unroll
     for (int l = 0; l < PW - 1; ++l) sw[l] = sw[l + 1];
     sw[PW - 1] = t;
-    while (ixf < n1f && last == cx) {
+    while (ixf < f1 && last == cx) {
       T acc = 0;
 #pragma unroll
       for (int l = 0; l < PW; ++l) {
@@ -423,9 +435,16 @@ __global__ __launch_bounds__(256) void k_prolong_rows(T *zf, const T *__restrict
       T *zp = zf + (fbase + ixf) * ldb + ct0;
       zp[lane] += acc;
       ++ixf;
-      if (ixf < n1f) last = ps[ixf] + pw - 1;
+      if (ixf < f1) last = ps[ixf] + pw - 1;
     }
   }
+}
+
+// Segments per output row of the line-marching transfers: enough wavefronts (4096) for the chip when
+// the batch has few column tiles, at most eight (each segment re-marches the band of its first output)
+static int transfer_segments(int rows, int ntiles) {
+  const int64_t waves = (int64_t)rows * ntiles;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(8, (4096 + waves - 1) / std::max<int64_t>(1, waves)));
 }
 
 template <typename T>
@@ -444,9 +463,10 @@ const float *pro_coef<float>(const Level &F) { return F.pro_c32.p; }
 template <typename T, int P>
 static void launch_restrict_rows(const Level &F, const Level &C, T *rc, const T *r, int ldb, int ntiles,
                                  const int *active, hipStream_t s) {
-  const int n = F.npatch * C.n1;
+  const int nseg = transfer_segments(F.npatch * C.n1, ntiles);
+  const int n = F.npatch * C.n1 * nseg;
   hipLaunchKernelGGL((k_restrict_rows<T, P>), dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, rc, r, F.owner.p, F.W,
-                     C.W, F.n1, C.n1, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles, F.npatch);
+                     C.W, F.n1, C.n1, ldb, F.res_start.p, res_coef<T>(F), F.rw, active, ntiles, F.npatch, nseg);
 }
 
 template <typename T>
@@ -475,9 +495,10 @@ template void restrict_residual<float>(const Level &, const Level &, float *, co
 template <typename T, int P>
 static void launch_prolong_rows(const Level &F, const Level &C, T *zf, const T *zc, int ldb, int ntiles,
                                 const int *active, hipStream_t s) {
-  const int n = F.npatch * F.n1;
+  const int nseg = transfer_segments(F.npatch * F.n1, ntiles);
+  const int n = F.npatch * F.n1 * nseg;
   hipLaunchKernelGGL((k_prolong_rows<T, P>), dim3(ntiles * ((n + 3) / 4)), dim3(CT, 4), 0, s, zf, zc, F.W, C.W, F.n1,
-                     C.n1, ldb, F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles, F.npatch);
+                     C.n1, ldb, F.pro_start.p, pro_coef<T>(F), F.pw, active, ntiles, F.npatch, nseg);
 }
 
 template <typename T>

@@ -1,5 +1,7 @@
 """Accuracy of the settings the throughput workloads run at, and of the degrees the paper covers.
 
+  * mixed precision at a tight tolerance converges to the FP64 solution (the FP32 V-cycle and the
+    FP32 search direction change only the search directions);
   * the batching workload's finest meshes (128 x 128 elements, degrees 2 and 3, perturbed sphere) and
     the perturbed degree-3 64 x 64 mesh: FP32 V-cycle / FP64 CG at relative residual 1e-6 against the
     FP64 path at 1e-11 (itself pinned to the oracle element by element on smaller meshes), relative
@@ -68,6 +70,26 @@ def test_batching_meshes_mixed_precision(ctx, p, j, kappa):
     print(f"perturbed p={p} level={j} kappa={kappa}: mixed 1e-6 vs FP64 1e-11 rel. M-norm error {err:.3e} "
           f"({st1['max_iters']} / {st0['max_iters']} iterations)")
     assert err <= 1e-6
+
+
+def test_mixed_precision_reaches_fp64_accuracy(ctx):
+    """The mixed-precision solver (FP32 V-cycle; the flexible beta's inner products from its last FP32
+    smoothing step; the search direction stored in FP32, the operator, residual and iterate in FP64)
+    converges to the FP64 solution at a tight tolerance: the FP32 parts only shape the search
+    directions.  Also against the same solver through the sum-factorised operator, where neither the
+    fused products nor the FP32 direction are used."""
+    sp = g.Space(ctx, g.Geometry(ctx, False), 3, 6)
+    z = torch.from_numpy(inputs.noise_vectors([2, 3], sp.noise_length)).cuda()
+    b = sp.white_noise(z)
+    kw = dict(h=0.4, k_minus=20, k_plus=20, max_iter=2000, rtol=1e-12)
+    ref, st0 = sp.sample(8.0, 0.8, b, precision=0, **kw)
+    u, st1 = sp.sample(8.0, 0.8, b, precision=1, **kw)
+    v, st2 = sp.sample(8.0, 0.8, b, precision=1, apply_kind=g.GF_APPLY_SUMFACT, **kw)
+    e1, e2 = mrel(sp, u, ref), mrel(sp, v, ref)
+    print(f"p=3 level=6 rtol 1e-12: mixed vs FP64 {e1:.3e} ({st1['max_iters']} / {st0['max_iters']} iterations), "
+          f"mixed through the sum-factorised operator {e2:.3e} ({st2['max_iters']} iterations)")
+    assert e1 <= 1e-10 and e2 <= 1e-10
+    assert st1["max_iters"] <= st0["max_iters"] + 2
 
 
 def test_full_size_fp64_pin_against_sparse_lu(ctx):
