@@ -158,6 +158,16 @@ enum { GF_PROLONG = 0, GF_RESTRICT = 1 };
 gf_status gf_space_transfer(const gf_space *space, int32_t level, int32_t direction, int32_t nvec, const double *x,
                             double *y, int32_t mem);
 
+/* What the space keeps cached for later calls: multigrid plans (one per list of shifts: per-level
+ * spectral bounds and the dense coarse inverses of every node, Sec. 3.5) and workspaces (batch vectors,
+ * one per batch width, precision and use).  Both caches are bounded (1 GiB of coarse inverses, 96 GiB of
+ * workspaces per space; the environment variables GF_PLAN_CACHE_MB and GF_WORKSPACE_CACHE_MB set
+ * others): at the start of every call that uses the space, the least recently used entries are
+ * released until each fits its bound.  Any output pointer may be null.  Host memory only; GF_EINVAL
+ * for a null space. */
+gf_status gf_space_cache_info(const gf_space *space, int32_t *nplans, int64_t *plan_bytes, int32_t *nworkspaces,
+                              int64_t *workspace_bytes);
+
 /* gf_space_apply for callers that cannot allocate device memory: code under HIP graph capture,
  * tight serving loops, harnesses that forbid allocation.  The same operator, y = (sigma M + s_scale S) x
  * for nvec vectors (kind GF_APPLY_STENCIL or GF_APPLY_SUMFACT), on device arrays x, y ([nvec][N], on

@@ -200,6 +200,7 @@ struct gf_space {
   gf::DBuf<double> M0, S0;
   int N0 = 0;
   std::map<std::string, std::unique_ptr<gf::Plan>> plans;
+  uint64_t calls = 0;  // calls that used the space so far (recency of its cached plans and workspaces)
   // smoothing degree chosen by measurement for large batches, by batch configuration (see tune_degree)
   std::map<std::string, int> cheb_tuned;
   gf::Level &fine() { return *lev.back(); }

@@ -268,6 +268,7 @@ struct Plan {
   double ia_mass = 0.0;                     // (m(pi)/m(0))^2 of the 1D B-spline mass symbol
   DBuf<double> Ainv;                      // [node][N0][N0] inverses of the coarse matrices
   double setup_ms = 0.0;
+  uint64_t last = 0;                      // the space's call that used it last
 };
 
 struct LevelWork {
@@ -319,6 +320,8 @@ struct Workspace {
   DBuf<double> partial;
   DBuf<int> counter;
   std::vector<int> active_h;
+  uint64_t last = 0;   // the space's call that used it last
+  size_t bytes = 0;    // device memory it holds
   Scratch scratch() { return Scratch{partial.p, counter.p}; }
 };
 
@@ -363,8 +366,12 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
   if (!reg) reg.reset(new gf_workspaces());
   auto key = std::make_tuple(ldb, prec, slot);
   auto it = reg->m.find(key);
-  if (it != reg->m.end()) return *it->second;
+  if (it != reg->m.end()) {
+    it->second->last = sp->calls;
+    return *it->second;
+  }
   std::unique_ptr<Workspace> w(new Workspace());
+  w->last = sp->calls;
   w->ldb = ldb;
   w->ntiles = ldb / CT;
   w->prec = prec;
@@ -409,6 +416,10 @@ static Workspace &get_workspace(gf_space *sp, int ldb, int prec, int slot = 0) {
   w->one64.upload(ones, sp->ctx->stream);
   w->one32.upload(onesf, sp->ctx->stream);
   w->active_h.assign(w->ntiles, 0);
+  // the batch vectors and the partial sums (the per-column scalars are negligible)
+  w->bytes = w->x.n * 8 * 4 + w->p32.n * 4 + w->partial.n * 8;
+  for (const LevelWork &v : w->lw)
+    w->bytes += (v.r64.n + v.z64a.n + v.z64b.n + v.a64.n) * 8 + (v.r32.n + v.z32a.n + v.z32b.n + v.a32.n) * 4;
   Workspace &ref = *w;
   reg->m[key] = std::move(w);
   return ref;
@@ -639,7 +650,10 @@ static std::string plan_key(const std::vector<double> &sig) {
 static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
   const std::string key = plan_key(sig);
   auto it = sp->plans.find(key);
-  if (it != sp->plans.end()) return *it->second;
+  if (it != sp->plans.end()) {
+    it->second->last = sp->calls;
+    return *it->second;
+  }
   auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = sp->ctx->stream;
   std::unique_ptr<Plan> pl(new Plan());
@@ -706,6 +720,7 @@ static Plan &get_plan(gf_space *sp, const std::vector<double> &sig) {
   launch_coarse_inverse(Lf.p, sp->N0, nn, pl->Ainv.p, s);
   HIPCHK(hipStreamSynchronize(s));
   pl->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  pl->last = sp->calls;
   Plan &ref = *pl;
   sp->plans[key] = std::move(pl);
   return ref;
@@ -1271,6 +1286,59 @@ static void drop_graphs_of(gf_context *ctx, const gf_space *sp) {
       it = ctx->graphs.erase(it);
     } else {
       ++it;
+    }
+  }
+}
+
+// Bounds of a space's caches of plans (by the bytes of their coarse inverses) and workspaces (by the
+// bytes of their batch vectors).  At the start of every call that uses the space, the least recently
+// used entries are released until each cache fits its bound again (the ones the new call builds come
+// on top until the next call).  Nothing cached is released during a call, and no pointer into the
+// caches outlives a call: the cached graphs that use the space are dropped with them, and tapes own
+// their saved solutions.  A loop over new values of kappa (a new chain plan and node plan on every
+// call) thus keeps its device memory bounded, while repeated calls with the same batches keep theirs.
+// The environment variables GF_PLAN_CACHE_MB and GF_WORKSPACE_CACHE_MB set other bounds (MiB).
+constexpr size_t kPlanCacheBytes = (size_t)1 << 30;
+constexpr size_t kWorkspaceCacheBytes = (size_t)96 << 30;
+
+static size_t cache_bound(const char *env, size_t dflt) {
+  const char *v = std::getenv(env);
+  if (!v || !*v) return dflt;
+  char *end = nullptr;
+  const double mb = std::strtod(v, &end);
+  if (end == v || !(mb >= 0.0) || !std::isfinite(mb)) return dflt;
+  return (size_t)(mb * 1048576.0);
+}
+
+static void begin_call(gf_space *sp) {
+  ++sp->calls;
+  const size_t plan_bound = cache_bound("GF_PLAN_CACHE_MB", kPlanCacheBytes);
+  const size_t ws_bound = cache_bound("GF_WORKSPACE_CACHE_MB", kWorkspaceCacheBytes);
+  size_t pb = 0, wb = 0;
+  for (const auto &kv : sp->plans) pb += kv.second->Ainv.n * sizeof(double);
+  auto reg = ws_registry().find(sp);
+  if (reg != ws_registry().end() && reg->second)
+    for (const auto &kv : reg->second->m) wb += kv.second->bytes;
+  if (pb <= plan_bound && wb <= ws_bound) return;
+  // the work of earlier calls that reads them is finished (their results were returned) but not
+  // necessarily retired on the device
+  HIPCHK(hipStreamSynchronize(sp->ctx->stream));
+  drop_graphs_of(sp->ctx, sp);
+  while (pb > plan_bound && !sp->plans.empty()) {
+    auto lru = sp->plans.begin();
+    for (auto it = sp->plans.begin(); it != sp->plans.end(); ++it)
+      if (it->second->last < lru->second->last) lru = it;
+    pb -= lru->second->Ainv.n * sizeof(double);
+    sp->plans.erase(lru);
+  }
+  if (reg != ws_registry().end() && reg->second) {
+    auto &m = reg->second->m;
+    while (wb > ws_bound && !m.empty()) {
+      auto lru = m.begin();
+      for (auto it = m.begin(); it != m.end(); ++it)
+        if (it->second->last < lru->second->last) lru = it;
+      wb -= lru->second->bytes;
+      m.erase(lru);
     }
   }
 }
@@ -1922,6 +1990,26 @@ gf_status gf_space_transfer(const gf_space *csp, int32_t level, int32_t directio
   });
 }
 
+gf_status gf_space_cache_info(const gf_space *sp, int32_t *nplans, int64_t *plan_bytes, int32_t *nworkspaces,
+                              int64_t *workspace_bytes) {
+  return guarded([&] {
+    if (!sp) fail(GF_EINVAL, "null argument");
+    int64_t pb = 0, wb = 0;
+    for (const auto &kv : sp->plans) pb += (int64_t)(kv.second->Ainv.n * sizeof(double));
+    int32_t nw = 0;
+    auto reg = ws_registry().find(sp);
+    if (reg != ws_registry().end() && reg->second)
+      for (const auto &kv : reg->second->m) {
+        wb += (int64_t)kv.second->bytes;
+        ++nw;
+      }
+    if (nplans) *nplans = (int32_t)sp->plans.size();
+    if (plan_bytes) *plan_bytes = pb;
+    if (nworkspaces) *nworkspaces = nw;
+    if (workspace_bytes) *workspace_bytes = wb;
+  });
+}
+
 gf_status gf_white_noise(const gf_space *csp, int32_t nsamp, const double *z, double *b, int32_t mem) {
   return guarded([&] {
     gf_space *sp = const_cast<gf_space *>(csp);
@@ -2016,6 +2104,14 @@ struct SampleItem {
 static void run_items(gf_context *ctx, std::vector<SampleItem> &items, const gf_solve_opts *opts, int32_t mem,
                       gf_solve_stats *stats) {
   hipStream_t s = ctx->stream;
+  {
+    std::vector<gf_space *> seen;
+    for (auto &it : items)
+      if (std::find(seen.begin(), seen.end(), it.sp) == seen.end()) {
+        seen.push_back(it.sp);
+        begin_call(it.sp);
+      }
+  }
   SolveSpec base;
   base.prec = opts->precision;
   base.kind = opts->apply_kind;
@@ -2686,6 +2782,7 @@ gf_status gf_sqrt_mass(gf_space *sp, int32_t nsamp, const double *y, double *f, 
     const bool estimate = (lo == 0.0 && hi == 0.0);
     if (!estimate && (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi))) fail(GF_EINVAL, "need 0 < lo < hi, finite");
     HIPCHK(hipSetDevice(sp->ctx->device));
+    begin_call(sp);
     hipStream_t s = sp->ctx->stream;
     const Level &F = sp->fine();
     auto c0 = std::chrono::steady_clock::now();
@@ -2823,6 +2920,7 @@ gf_status gf_solve_shifted(gf_space *sp, int32_t nsys, const double *sigma, cons
     }
     if (distinct.size() > 4096) fail(GF_EINVAL, "at most 4096 distinct shifts per call");
     HIPCHK(hipSetDevice(sp->ctx->device));
+    begin_call(sp);
     hipStream_t s = sp->ctx->stream;
     const Level &F = sp->fine();
     double setup_ms = 0.0;
@@ -2937,6 +3035,7 @@ gf_status gf_grad_kappa(gf_tape *tape, const double *dl_du, double *dl_dkappa, i
     if (!tape || !dl_du || !dl_dkappa) fail(GF_EINVAL, "null argument");
     if (mem != GF_HOST && mem != GF_DEVICE) fail(GF_EINVAL, "mem must be GF_HOST or GF_DEVICE");
     HIPCHK(hipSetDevice(tape->sp->ctx->device));
+    begin_call(tape->sp);
     run_grad(*tape, dl_du, dl_dkappa, mem, stats);
   });
 }

@@ -92,6 +92,8 @@ _SIGS = {
     "gf_space_dofmap": (_i32, [_vp, _vp]),
     "gf_space_apply": (_i32, [_vp, _dbl, _dbl, _i32, _vp, _vp, _i32, _i32]),
     "gf_space_transfer": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _i32]),
+    "gf_space_cache_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32),
+                                   ctypes.POINTER(_i64)]),
     "gf_space_apply_noalloc": (_i32, [_vp, _dbl, _dbl, _i32, _vp, _vp, _i32]),
     "gf_white_noise": (_i32, [_vp, _i32, _vp, _vp, _i32]),
     "gf_sample": (_i32, [_vp, _dbl, _dbl, ctypes.POINTER(QuadRule), ctypes.POINTER(SolveOpts), _i32, _vp, _vp,
@@ -282,6 +284,13 @@ class Space:
         y = _alloc_like(x, (n_out,) if single else (nvec, n_out))
         _check(_lib.gf_space_transfer(self.h, level, direction, nvec, px, _ptr(y), mem))
         return y
+
+    def cache_info(self):
+        """(plans, plan bytes, workspaces, workspace bytes) the space keeps cached for later calls."""
+        n_p, b_p, n_w, b_w = _i32(), _i64(), _i32(), _i64()
+        _check(_lib.gf_space_cache_info(self.h, ctypes.byref(n_p), ctypes.byref(b_p), ctypes.byref(n_w),
+                                        ctypes.byref(b_w)))
+        return n_p.value, b_p.value, n_w.value, b_w.value
 
     def apply_noalloc(self, sigma, s_scale, x, y, kind=GF_APPLY_STENCIL):
         """y = (sigma M + s_scale S) x into the preallocated device tensor y (nvec, N), queued on the

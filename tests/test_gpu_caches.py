@@ -1,15 +1,14 @@
 """Bounded caches: the library keeps multigrid plans (one per list of shifts) and workspaces (one per
-batch width, precision and slot) for later calls, least recently used first out beyond a bound.  A
-loop over new values of kappa -- central differences, or an optimiser stepping kappa -- builds new
-plans on every call and must not grow device memory without bound."""
+batch width, precision and use) for later calls, and at the start of every call releases the least
+recently used ones beyond a bound (1 GiB of coarse inverses per space by default; GF_PLAN_CACHE_MB sets
+another, read at every call).  A loop over new values of kappa -- central differences, or an optimiser
+stepping kappa -- builds new plans on every call and must not grow device memory without bound; a plan
+released and built again gives the same field."""
 import pytest
 
 from paper_2605_24882_amd import inputs
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(
-    reason="the cache bound this tests is taken out: with it, one GPU run ended in a host segmentation fault "
-           "inside gf_sample_batch (test_c3_mixed_precision_batch_error) whose cause was found neither by "
-           "reading the code nor in a host-only AddressSanitizer replay of the call sequence")]
+pytestmark = pytest.mark.gpu
 
 g = pytest.importorskip("paper_2605_24882_amd.gfield")
 torch = pytest.importorskip("torch")
@@ -21,26 +20,34 @@ def ctx():
     return g.Context(0)
 
 
-def test_device_memory_flat_over_varying_kappa(ctx):
+def test_plan_cache_bounded_over_varying_kappa(ctx, monkeypatch):
+    bound = 200 << 20
+    monkeypatch.setenv("GF_PLAN_CACHE_MB", "200")
     # one-level space: the coarse solve is the dense inverse of every node's matrix on this level
-    # (488 unknowns, 1.9 MB per node, 80 MB per call's plans), so a cache that kept every plan would
-    # grow by that much per call
+    # (488 unknowns, 1.9 MB per node: 41 nodes and one chain shift, about 80 MB of plans per call), so
+    # a cache that kept every plan would grow by that much per call
     sp = g.Space(ctx, g.Geometry(ctx, False), 2, 3, mg_levels=1)
     z = torch.from_numpy(inputs.noise_vectors([0, 1], sp.noise_length)).cuda()
     b = sp.white_noise(z)
-    free = []
-    fields = []
-    for i in range(24):
+    per_call, free, fields = [], [], []
+    for i in range(10):
         kappa = 1.0 + 0.25 * i
+        before = sp.cache_info()[1]
         u, st = sp.sample(kappa, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-8)
         torch.cuda.synchronize()
+        nplans, pbytes, nws, wbytes = sp.cache_info()
+        per_call.append(max(0, pbytes - before))
         free.append(torch.cuda.mem_get_info()[0])
-        if i in (0, 23):
+        # the bound holds at the start of every call; the plans a call builds come on top until the next
+        assert pbytes <= bound + max(per_call) + (1 << 20), (i, nplans, pbytes)
+        if i == 0:
             fields.append(u.clone())
-    late = free[8:]
-    growth = max(late) - min(late)
-    print(f"device memory over calls 8..23: spread {growth / 2**20:.1f} MiB")
-    assert growth < 32 * 2**20, [f / 2**20 for f in free]
-    # a plan evicted and built again gives the same field
+    late = free[5:]
+    spread = max(late) - min(late)
+    print(f"plans per call up to {max(per_call) / 2**20:.1f} MiB; cached after 10 calls {pbytes / 2**20:.0f} MiB "
+          f"({nplans} plans); device memory over calls 5..9: spread {spread / 2**20:.1f} MiB")
+    assert nplans < 20  # the loop built 20 plans
+    assert spread < 2 * max(per_call)
+    # the first kappa's plans were released: built again, they give the same field
     u0, _ = sp.sample(1.0, 1.6, b, h=0.4, k_minus=20, k_plus=20, rtol=1e-8)
     assert torch.equal(u0, fields[0])
