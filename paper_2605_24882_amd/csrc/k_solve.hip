@@ -360,14 +360,28 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
   for (int l = 0; l < RW; ++l) tw[l] = 0;
   int ixc = c0;
   int last = rs[c0] + rw - 1;  // last fine column of output ixc's band
-  for (int fx = rs[c0]; fx < n1f && ixc < c1; ++fx) {
-    T t = 0;
+  // the input column's values and weights (0 for copies that are not the owner: one contribution per
+  // unknown), loaded one column ahead of their use
+  T cv[RW], cw[RW];
+  const int fxs = rs[c0];
+#pragma unroll
+  for (int k = 0; k < RW; ++k) {
+    const int64_t rf = frow[k] + fxs;
+    cv[k] = (r + rf * ldb + ct0)[lane];
+    cw[k] = ownf[rf] ? wy[k] : T(0);
+  }
+  for (int fx = fxs; fx < n1f && ixc < c1; ++fx) {
+    const int fxn = min(fx + 1, n1f - 1);
+    T nv[RW], nw[RW];
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
-      const int64_t rf = frow[k] + fx;
-      const T w = ownf[rf] ? wy[k] : T(0);  // one contribution per unknown: owner copies only
-      t += w * (r + rf * ldb + ct0)[lane];
+      const int64_t rf = frow[k] + fxn;
+      nv[k] = (r + rf * ldb + ct0)[lane];
+      nw[k] = ownf[rf] ? wy[k] : T(0);
     }
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < RW; ++k) t += cw[k] * cv[k];
 #pragma unroll
     for (int l = 0; l < RW - 1; ++l) tw[l] = tw[l + 1];
     tw[RW - 1] = t;  // the window now holds fine columns fx-RW+1 .. fx
@@ -381,6 +395,11 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
       (rc + (cbase + ixc) * ldb + ct0)[lane] = acc;
       ++ixc;
       if (ixc < c1) last = rs[ixc] + rw - 1;
+    }
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+      cv[k] = nv[k];
+      cw[k] = nw[k];
     }
   }
 }
@@ -418,10 +437,22 @@ __global__ __launch_bounds__(256) void k_prolong_rows(T *zf, const T *__restrict
   for (int l = 0; l < PW; ++l) sw[l] = 0;
   int ixf = f0;
   int last = ps[f0] + pw - 1;  // last coarse column of fine output ixf's band
-  for (int cx = ps[f0]; cx < n1c && ixf < f1; ++cx) {
+  // loaded ahead of their use: the coarse values of the next input column, and the fine values of the
+  // next two outputs (each is read before an earlier output is stored; they are different entries)
+  const int cxs = ps[f0];
+  T cv[PW];
+#pragma unroll
+  for (int k = 0; k < PW; ++k) cv[k] = (zc + (crow[k] + cxs) * ldb + ct0)[lane];
+  T z0 = (zf + (fbase + ixf) * ldb + ct0)[lane];
+  T z1 = (zf + (fbase + min(ixf + 1, f1 - 1)) * ldb + ct0)[lane];
+  for (int cx = cxs; cx < n1c && ixf < f1; ++cx) {
+    const int cxn = min(cx + 1, n1c - 1);
+    T nv[PW];
+#pragma unroll
+    for (int k = 0; k < PW; ++k) nv[k] = (zc + (crow[k] + cxn) * ldb + ct0)[lane];
     T t = 0;
 #pragma unroll
-    for (int k = 0; k < PW; ++k) t += wy[k] * (zc + (crow[k] + cx) * ldb + ct0)[lane];
+    for (int k = 0; k < PW; ++k) t += wy[k] * cv[k];
 #pragma unroll
     for (int l = 0; l < PW - 1; ++l) sw[l] = sw[l + 1];
     sw[PW - 1] = t;
@@ -432,11 +463,15 @@ __global__ __launch_bounds__(256) void k_prolong_rows(T *zf, const T *__restrict
         const int j = l - (PW - pw);
         if (j >= 0) acc += pcoef[ixf * pw + j] * sw[l];
       }
-      T *zp = zf + (fbase + ixf) * ldb + ct0;
-      zp[lane] += acc;
+      const T z2 = (zf + (fbase + min(ixf + 2, f1 - 1)) * ldb + ct0)[lane];
+      (zf + (fbase + ixf) * ldb + ct0)[lane] = z0 + acc;
+      z0 = z1;
+      z1 = z2;
       ++ixf;
       if (ixf < f1) last = ps[ixf] + pw - 1;
     }
+#pragma unroll
+    for (int k = 0; k < PW; ++k) cv[k] = nv[k];
   }
 }
 
