@@ -360,28 +360,14 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
   for (int l = 0; l < RW; ++l) tw[l] = 0;
   int ixc = c0;
   int last = rs[c0] + rw - 1;  // last fine column of output ixc's band
-  // the input column's values and weights (0 for copies that are not the owner: one contribution per
-  // unknown), loaded one column ahead of their use
-  T cv[RW], cw[RW];
-  const int fxs = rs[c0];
-#pragma unroll
-  for (int k = 0; k < RW; ++k) {
-    const int64_t rf = frow[k] + fxs;
-    cv[k] = (r + rf * ldb + ct0)[lane];
-    cw[k] = ownf[rf] ? wy[k] : T(0);
-  }
-  for (int fx = fxs; fx < n1f && ixc < c1; ++fx) {
-    const int fxn = min(fx + 1, n1f - 1);
-    T nv[RW], nw[RW];
-#pragma unroll
-    for (int k = 0; k < RW; ++k) {
-      const int64_t rf = frow[k] + fxn;
-      nv[k] = (r + rf * ldb + ct0)[lane];
-      nw[k] = ownf[rf] ? wy[k] : T(0);
-    }
+  for (int fx = rs[c0]; fx < n1f && ixc < c1; ++fx) {
     T t = 0;
 #pragma unroll
-    for (int k = 0; k < RW; ++k) t += cw[k] * cv[k];
+    for (int k = 0; k < RW; ++k) {
+      const int64_t rf = frow[k] + fx;
+      const T w = ownf[rf] ? wy[k] : T(0);  // one contribution per unknown: owner copies only
+      t += w * (r + rf * ldb + ct0)[lane];
+    }
 #pragma unroll
     for (int l = 0; l < RW - 1; ++l) tw[l] = tw[l + 1];
     tw[RW - 1] = t;  // the window now holds fine columns fx-RW+1 .. fx
@@ -395,11 +381,6 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
       (rc + (cbase + ixc) * ldb + ct0)[lane] = acc;
       ++ixc;
       if (ixc < c1) last = rs[ixc] + rw - 1;
-    }
-#pragma unroll
-    for (int k = 0; k < RW; ++k) {
-      cv[k] = nv[k];
-      cw[k] = nw[k];
     }
   }
 }
