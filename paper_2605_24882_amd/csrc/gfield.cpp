@@ -550,6 +550,75 @@ static const ApplyTune &get_tune(const Level &L, int ldb, int ntiles, const T *x
   return L.tune.emplace(key, best).first->second;
 }
 
+// Launch shape of the mixed-precision outer operator on the FP32 search direction (apply_outer_p32):
+// strips of two or four rows (a four-row strip reads 2.5 window rows per output row instead of 4, at
+// two waves per SIMD instead of three), 32 or 64 columns, timed on first use per level and column
+// stride on scratch vectors, partial sums and per-column states (the solver's are not touched).
+static const ApplyTune &get_tune_p32(const Level &L, int ldb, int ntiles, const double *ca, const double *cb,
+                                     const EpiArgs<double> &ecall, hipStream_t s) {
+  const auto key = std::make_tuple(12, ldb, (int)EPI_STORE, 2);
+  auto it = L.tune.find(key);
+  if (it != L.tune.end()) return it->second;
+  ApplyTune best;
+  best.TY = 2;
+  best.TX = 64;
+  if (const char *fixed = std::getenv("GF_APPLY_SHAPE")) {
+    int ty = 0, tx = 0;
+    if (std::sscanf(fixed, "%d,%d", &ty, &tx) != 2 || (ty != 1 && ty != 2 && ty != 4) || tx < 16)
+      fail(GF_EINVAL, "GF_APPLY_SHAPE must be \"TY,TX\" with TY in {1,2,4} and TX >= 16");
+    best.TY = std::min(ty, 2);  // the FP64 strip height of the fixed shape
+    best.TX = tx;
+    return L.tune.emplace(key, best).first->second;
+  }
+  if (g_autotune && L.n1 >= 8) {
+    const size_t n = (size_t)L.R * ldb;
+    DBuf<double> ty_, part;
+    DBuf<float> tp;
+    DBuf<ColState> tcs;
+    ty_.alloc(n);
+    tp.alloc(n);
+    part.alloc((size_t)2 * partial_slots(L, ldb, ntiles) * ldb);
+    tcs.alloc(ldb);
+    EpiArgs<double> e = ecall;
+    e.y = ty_.p;
+    e.dot = 1;
+    e.op = OP_ALPHA;  // into the scratch states
+    Scratch sc{part.p, nullptr};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_us = 1e30f;
+    for (int tyc : {2, 4}) {
+      if (tyc == 4 && L.p > 3) continue;
+      for (int tx : {32, 64}) {
+        if (tx > 2 * L.n1 && tx != 32) continue;
+        ApplyTune t;
+        t.TY = tyc;
+        t.TX = tx;
+        apply_outer_p32(L, tp.p, ca, cb, e, sc, tcs.p, nullptr, ldb, ntiles, 0.0, 0, s, t);
+        HIPCHK(hipEventRecord(e0, s));
+        for (int k = 0; k < 3; ++k) apply_outer_p32(L, tp.p, ca, cb, e, sc, tcs.p, nullptr, ldb, ntiles, 0.0, 0, s, t);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const float us = ms * 1e3f / 3.f;
+        if (std::getenv("GF_TUNE_LOG"))
+          std::fprintf(stderr, "tune p=%d lev=%d outer on FP32 direction ldb=%d TY=%d TX=%d: %.1f us\n", L.p, L.lev,
+                       ldb, tyc, tx, us);
+        if (us < best_us) {
+          best_us = us;
+          best = t;
+          best.us = us;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  return L.tune.emplace(key, best).first->second;
+}
+
 // One operator application with epilogue e: the fused stencil kernel, or the sum-factorised
 // kernel followed by the interface sum and the epilogue over all rows.
 template <typename T>
@@ -1105,8 +1174,7 @@ struct BatchSolve {
       apply_epi<double>(F, GF_APPLY_STENCIL, w->p.p, w->one64.p, w->sig64.p, e, sc, w->cs.p, w->active.p, ldb, nt,
                         tol2(), spec.max_iter, s, e0, e1, F.stI.p);
     } else if (p32) {
-      // launch shape of the FP64 operator (the tuner reads the FP64 residual as its input vector)
-      const ApplyTune &t = get_tune<double>(F, ldb, nt, w->r.p, w->sig64.p, w->one64.p, e, s);
+      const ApplyTune &t = get_tune_p32(F, ldb, nt, w->sig64.p, w->one64.p, e, s);
       apply_outer_p32(F, w->p32.p, w->sig64.p, w->one64.p, e, sc, w->cs.p, w->active.p, ldb, nt, tol2(),
                       spec.max_iter, s, t, e0, e1);
     } else {

@@ -443,8 +443,10 @@ static void launch_outer_p32(const ApplyGeom &g, const double *stM, const double
                              const double *ca, const double *cb, const EpiArgs<double> &e, double *partial,
                              const int *active, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
   auto kern = k_stencil<double, P, 1, EPI_STORE, 1, SM_DPP, float>;
-  if constexpr (P <= 3)
+  if constexpr (P <= 3) {
     if (g.TY == 2) kern = k_stencil<double, P, 2, EPI_STORE, 1, SM_DPP, float>;
+    if (g.TY == 4) kern = k_stencil<double, P, 4, EPI_STORE, 1, SM_DPP, float>;
+  }
   if (ev0)
     hipExtLaunchKernelGGL(kern, dim3(8 * g.q), dim3(256), 0, s, ev0, ev1, 0, g, stM, stS, p, ca, cb, e.cf1, e.cf2,
                           e.y, e.zout, e.r, partial, active, e.dflags, e.q2);
@@ -453,14 +455,16 @@ static void launch_outer_p32(const ApplyGeom &g, const double *stM, const double
                        partial, active, e.dflags, e.q2);
 }
 
-bool outer_p32_fits(const Level &L, int ldb) { return stencil_offsets_fit(L, ldb, 2, (int)sizeof(double)); }
+bool outer_p32_fits(const Level &L, int ldb) { return stencil_offsets_fit(L, ldb, 4, (int)sizeof(double)); }
 
 void apply_outer_p32(const Level &L, const float *p, const double *ca, const double *cb, const EpiArgs<double> &e,
                      Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2, int maxit,
                      hipStream_t s, const ApplyTune &tune, hipEvent_t ev0, hipEvent_t ev1) {
   if (e.kind != EPI_STORE || e.dot != 1 || !e.rows16 || tune.algo != 1 || !outer_p32_fits(L, ldb))
     fail(GF_EUNSUPPORTED, "FP32 search direction: combined-stencil operator with p.q on 16-column shift groups");
-  ApplyGeom g = apply_geom(L, ldb, ntiles, std::min(tune.TY, 2), tune.TX, tune.NC);
+  // four-row strips too: the window of FP32 values takes the registers of an FP64 one (each value is
+  // widened when loaded), so two waves per SIMD hold it; the caller's tuner picks the strip height
+  ApplyGeom g = apply_geom(L, ldb, ntiles, tune.TY, tune.TX, tune.NC);
   g.nslot2 = g.nsb + (L.ngroups + 3) / 4;
   const double *stM = L.stM.p, *stS = L.stS.p;
   switch (L.p) {
