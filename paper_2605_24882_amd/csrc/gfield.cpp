@@ -488,7 +488,7 @@ static const ApplyTune &get_tune(const Level &L, int ldb, int ntiles, const T *x
   if (g_autotune && L.n1 >= 8) {
     std::vector<ApplyTune> cand;
     for (int ty : {1, 2, 4}) {
-      if (ty == 4 && (sizeof(T) != 4 || L.p > 3)) continue;
+      if (ty == 4 && L.p > 3) continue;
       if (ty > 1 && L.p >= 4) continue;
       for (int tx : {32, 64}) {
         if (tx > 2 * L.n1 && tx != 32) continue;

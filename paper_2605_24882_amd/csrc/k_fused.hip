@@ -311,8 +311,8 @@ static void launch_apply_pt(const ApplyGeom &g, int algo, const T *stM, const T 
   }
 }
 
-// four rows per strip only for float and degrees up to 3 (the window of a double strip would not fit
-// the registers), and only in the combined-stencil kernel
+// four rows per strip only for degrees up to 3 (an FP64 strip of four rows holds its window at one or
+// two waves per SIMD; the tuner keeps it only where that pays), and only in the combined-stencil kernel
 template <typename T, int P>
 static void launch_apply_p(const ApplyGeom &g, int algo, const T *stM, const T *stS, const T *x, const T *ca,
                            const T *cb, const EpiArgs<T> &e, double *partial, const int *active, hipStream_t s,
@@ -322,11 +322,9 @@ static void launch_apply_p(const ApplyGeom &g, int algo, const T *stM, const T *
       launch_apply_pt<T, P, 2>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
       return;
     }
-    if constexpr (sizeof(T) == 4) {
-      if (g.TY == 4) {
-        launch_apply_pt<T, P, 4>(g, 1, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
-        return;
-      }
+    if (g.TY == 4) {
+      launch_apply_pt<T, P, 4>(g, 1, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
+      return;
     }
   }
   launch_apply_pt<T, P, 1>(g, algo, stM, stS, x, ca, cb, e, partial, active, s, ev0, ev1);
@@ -376,9 +374,7 @@ template <typename T>
 void apply_fused(const Level &L, const T *stM, const T *stS, const T *x, const T *ca, const T *cb,
                  const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb, int ntiles, double tol2,
                  int maxit, hipStream_t s, const ApplyTune &tune, hipEvent_t ev0, hipEvent_t ev1) {
-  // four-row strips exist for FP32 only (the FP64 window would not fit the registers)
-  const int ty = (sizeof(T) == 8 && tune.TY > 2) ? 2 : tune.TY;
-  ApplyGeom g = apply_geom(L, ldb, ntiles, ty, tune.TX, tune.NC);
+  ApplyGeom g = apply_geom(L, ldb, ntiles, tune.TY, tune.TX, tune.NC);
   g.grp = std::max(1, std::min(tune.grp, g.nsb));
   int algo = tune.algo;
   if (algo == 1 && !stencil_offsets_fit(L, ldb, g.TY, (int)sizeof(T))) {
