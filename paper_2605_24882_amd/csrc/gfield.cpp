@@ -566,7 +566,7 @@ static const ApplyTune &get_tune_p32(const Level &L, int ldb, int ntiles, const 
     int ty = 0, tx = 0;
     if (std::sscanf(fixed, "%d,%d", &ty, &tx) != 2 || (ty != 1 && ty != 2 && ty != 4) || tx < 16)
       fail(GF_EINVAL, "GF_APPLY_SHAPE must be \"TY,TX\" with TY in {1,2,4} and TX >= 16");
-    best.TY = std::min(ty, 2);  // the FP64 strip height of the fixed shape
+    best.TY = ty;
     best.TX = tx;
     return L.tune.emplace(key, best).first->second;
   }
