@@ -499,8 +499,9 @@ static RowGeom row_geom(const Level &L, int ldb) {
   g.n1 = L.n1;
   g.ldb = ldb;
   g.owner = L.owner.p;
-  // row blocks per column tile: at least 2048 blocks in all, so that a batch of one or two tiles
-  // still keeps eight wavefronts per compute unit in flight
+  // row blocks per column tile: 256, or up to 1024 for a batch of fewer than eight tiles (about 2048
+  // blocks in all), so that a batch of one or two tiles still keeps several wavefronts per compute
+  // unit in flight
   g.nrb = std::max(kRowBlocks, std::min(kMaxRowBlocks, 2048 / std::max(1, g.ntiles)));
   const int64_t need = (L.R + 15) / 16;
   if (need < g.nrb) g.nrb = (int)std::max<int64_t>(1, need);
