@@ -355,18 +355,36 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
     frow[k] = fbase + (int64_t)(min(fy0 + k, n1f - 1) + P) * Wf + P;
   }
   const int64_t cbase = (int64_t)m * Wc * Wc + (int64_t)(iyc + P) * Wc + P;
+  // one contribution per unknown: only owner copies count.  Every unknown off the patch boundary is
+  // its own owner, so the owner flags are read only on boundary rows and columns.
+  bool brow = false;
+#pragma unroll
+  for (int k = 0; k < RW; ++k) {
+    const int fy = min(fy0 + k, n1f - 1);
+    brow = brow || (k < rw && (fy == 0 || fy == n1f - 1));
+  }
   T tw[RW];
 #pragma unroll
   for (int l = 0; l < RW; ++l) tw[l] = 0;
   int ixc = c0;
   int last = rs[c0] + rw - 1;  // last fine column of output ixc's band
-  for (int fx = rs[c0]; fx < n1f && ixc < c1; ++fx) {
-    T t = 0;
+  // the input column's values, loaded one column ahead of their use
+  T cv[RW];
+  const int fxs = rs[c0];
 #pragma unroll
-    for (int k = 0; k < RW; ++k) {
-      const int64_t rf = frow[k] + fx;
-      const T w = ownf[rf] ? wy[k] : T(0);  // one contribution per unknown: owner copies only
-      t += w * (r + rf * ldb + ct0)[lane];
+  for (int k = 0; k < RW; ++k) cv[k] = (r + (frow[k] + fxs) * ldb + ct0)[lane];
+  for (int fx = fxs; fx < n1f && ixc < c1; ++fx) {
+    const int fxn = min(fx + 1, n1f - 1);
+    T nv[RW];
+#pragma unroll
+    for (int k = 0; k < RW; ++k) nv[k] = (r + (frow[k] + fxn) * ldb + ct0)[lane];
+    T t = 0;
+    if (brow || fx == 0 || fx == n1f - 1) {
+#pragma unroll
+      for (int k = 0; k < RW; ++k) t += (ownf[frow[k] + fx] ? wy[k] : T(0)) * cv[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < RW; ++k) t += wy[k] * cv[k];
     }
 #pragma unroll
     for (int l = 0; l < RW - 1; ++l) tw[l] = tw[l + 1];
@@ -382,6 +400,8 @@ __global__ __launch_bounds__(256) void k_restrict_rows(T *rc, const T *__restric
       ++ixc;
       if (ixc < c1) last = rs[ixc] + rw - 1;
     }
+#pragma unroll
+    for (int k = 0; k < RW; ++k) cv[k] = nv[k];
   }
 }
 
