@@ -1094,8 +1094,9 @@ struct BatchSolve {
     HIPCHK(hipMemsetAsync(w->x.p, 0, (size_t)F.R * ldb * sizeof(double), s));
   }
 
-  // z = B r.  The V-cycle fuses the reduction of fin_op into its last smoothing step: r.z in FP64
-  // (OP_RZ0, OP_BETA), r.z and z.q in mixed precision (OP_BETA_FLEX).  Returns whether it did.
+  // z = B r.  The V-cycle fuses the reduction of fin_op into its last smoothing step: r.z (OP_RZ0,
+  // OP_BETA; in mixed precision with r as its FP32 copy), r.z and z.q in mixed precision
+  // (OP_BETA_FLEX).  Returns whether it did.
   bool precondition(int fin_op, hipStream_t s) {
     const int fi = sp->nlev() - 1;
     bool fused = false;
@@ -1117,6 +1118,9 @@ struct BatchSolve {
     } else if (fin_op == OP_BETA_FLEX && fuse_flex()) {
       // the flexible beta's r.z and z.q from the last FP32 smoothing step (r as its FP32 copy)
       zf = vcycle<float, double>(sp, *w, spec, fi, w->r.p, w->lw[fi].r32.p, OP_BETA_FLEX, &fused, s, w->q.p);
+    } else if (fin_op == OP_RZ0 && fuse_flex()) {
+      // the first r.z the same way (the flexible beta divides by it)
+      zf = vcycle<float, double>(sp, *w, spec, fi, w->r.p, w->lw[fi].r32.p, OP_RZ0, &fused, s);
     } else {
       zf = vcycle<float, double>(sp, *w, spec, fi, w->r.p, w->lw[fi].r32.p, -1, nullptr, s);
     }
