@@ -145,6 +145,22 @@ def test_sample_eager_matches_graph(ctx):
     assert s1["host_syncs"] == s3["host_syncs"] < s2["host_syncs"], (s1["host_syncs"], s2["host_syncs"])
 
 
+def test_mixed_sample_eager_matches_graph(ctx):
+    """The same for the mixed-precision solver with 16 samples per node, the layout that stores the
+    search direction in FP32 and takes the flexible beta's products in the last smoothing step: graph
+    and eager loops, and a rerun, give bitwise identical fields."""
+    sp, d = space(ctx, 2, 3), disc(2, 3)
+    b = noise.load(d, inputs.noise_vectors(list(range(20, 36)), inputs.noise_length(2, 3)))
+    kw = dict(h=0.4, k_minus=12, k_plus=12, rtol=1e-10, precision=1)
+    u1, s1 = sp.sample(3.0, 1.6, b, **kw)
+    u2, s2 = sp.sample(3.0, 1.6, b, flags=g.GF_FLAG_NO_GRAPH, **kw)
+    u3, s3 = sp.sample(3.0, 1.6, b, **kw)
+    assert s1["max_iters"] == s2["max_iters"] == s3["max_iters"]
+    assert np.array_equal(u1, u2) and np.array_equal(u1, u3)
+    ref = _oracle_u(d, 3.0, 1.6, 0.4, 12, b)
+    assert mrel(d, u1, ref) <= 1e-8
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_sample_sumfact_operator(ctx, prec):
     """The whole solver through the matrix-free sum-factorised apply (its epilogue runs over the rows
