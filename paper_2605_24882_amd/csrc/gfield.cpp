@@ -315,6 +315,9 @@ struct Workspace {
   // outer-CG fusion: while set, the finest level's first smoothing step also performs r -= alpha q
   // (q = fuse_q) and the convergence test, and records the tiles active before it in active0
   const double *fuse_q = nullptr;
+  // while set, the finest level's first smoothing step of the V-cycle also reduces |r|^2 of its input
+  // (the reference of the convergence test, at the start of a solve)
+  bool fuse_bb = false;
   DBuf<int> active0;
   DBuf<ColState> cs;
   DBuf<double> partial;
@@ -955,7 +958,11 @@ static T *vcycle(gf_space *sp, Workspace &w, const SolveSpec &spec, int li, cons
       fused_first = true;
     }
   }
-  if (!fused_first) cheb_first<T, TR>(L, rsrc, rconv, za, dM, dS, sig, cf + (size_t)deg * ldb, ldb, nt, act, s);
+  if (!fused_first) {
+    const bool bb = w.fuse_bb && li + 1 == sp->nlev() && std::is_same<TR, double>::value;
+    cheb_first<T, TR>(L, rsrc, rconv, za, dM, dS, sig, cf + (size_t)deg * ldb, ldb, nt, act, s, bb ? &sc : nullptr,
+                      bb ? w.cs.p : nullptr);
+  }
   for (int k = 1; k < deg; ++k) smooth(k, false, k == 1 ? 1 : 0);
   // residual, restriction, coarse correction, prolongation
   {
@@ -1142,9 +1149,14 @@ struct BatchSolve {
     slog.first_phase = true;
     const int ldb = w->ldb, nt = w->ntiles;
     Scratch sc = w->scratch();
-    reduce_dot<double, double>(F, w->r.p, w->r.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BB, tol2(), spec.max_iter,
-                               nullptr, s);
-    if (!precondition(OP_RZ0, s)) {
+    // |b|^2: taken by the V-cycle's first finest-level step where there is one, else a reduction pass
+    w->fuse_bb = spec.precond == GF_PRECOND_VCYCLE && !spec.mass_shift && sp->nlev() > 1;
+    if (!w->fuse_bb)
+      reduce_dot<double, double>(F, w->r.p, w->r.p, sc, ldb, nt, w->cs.p, w->active.p, OP_BB, tol2(),
+                                 spec.max_iter, nullptr, s);
+    const bool fused_rz0 = precondition(OP_RZ0, s);
+    w->fuse_bb = false;
+    if (!fused_rz0) {
       if (mixed())
         reduce_dot<double, float>(F, w->r.p, zf, sc, ldb, nt, w->cs.p, w->active.p, OP_RZ0, tol2(), spec.max_iter,
                                   nullptr, s);

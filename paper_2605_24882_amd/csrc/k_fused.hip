@@ -588,7 +588,8 @@ template <typename T, typename TR>
 __global__ __launch_bounds__(256) void k_cheb_first(RowGeom g, const TR *__restrict__ r, T *__restrict__ r32,
                                                     T *__restrict__ z, const T *__restrict__ dM,
                                                     const T *__restrict__ dS, const T *__restrict__ sig,
-                                                    const T *__restrict__ cf2, const int *active) {
+                                                    const T *__restrict__ cf2, const int *active,
+                                                    double *partial) {
   const int ct = blockIdx.x % g.ntiles, rb = blockIdx.x / g.ntiles;
   if (active && !active[ct]) return;
   const int lane = threadIdx.x & 63;
@@ -597,25 +598,29 @@ __global__ __launch_bounds__(256) void k_cheb_first(RowGeom g, const TR *__restr
   const int ldb = g.ldb;
   const T sg = sig[col], sc = cf2[col];
   const int64_t stride = (int64_t)g.nrb * 4;
+  double acc = 0.0;  // with partial: |r|^2 over the owned unknowns, in the input's precision
   for (int64_t r0 = (int64_t)rb * 4 + wave; r0 < g.R; r0 += 4 * stride) {
-    T rv[4];
+    TR rd[4];
     bool ok[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t row = r0 + u * stride;
       ok[u] = row < g.R;
-      if (ok[u]) rv[u] = (T)r[row * ldb + col];
+      if (ok[u]) rd[u] = r[row * ldb + col];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (!ok[u]) continue;
       const int64_t row = r0 + u * stride;
       const int64_t i = row * ldb + col;
-      const T v = sc * rv[u] / (sg * dM[row] + dS[row]);
-      if (r32) r32[i] = rv[u];
+      const T rv = (T)rd[u];
+      const T v = sc * rv / (sg * dM[row] + dS[row]);
+      if (r32) r32[i] = rv;
       z[i] = v;
+      if (partial && g.owner[row]) acc += (double)rd[u] * (double)rd[u];
     }
   }
+  if (partial) block_partial(acc, partial, rb, ldb, col);
 }
 
 // The outer CG's residual update fused with the first Chebyshev step of the finest level: r -= alpha q
@@ -830,21 +835,23 @@ template void update_p2<float>(const Level &, double *, const float *, const Col
 
 template <typename T, typename TR>
 void cheb_first(const Level &L, const TR *r, T *r32, T *z, const T *dM, const T *dS, const T *sig,
-                const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s) {
+                const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s, Scratch *bb, ColState *cs) {
   const RowGeom g = row_geom(L, ldb);
   hipLaunchKernelGGL((k_cheb_first<T, TR>), dim3(g.nrb * ntiles), dim3(256), 0, s, g, r, r32, z, dM, dS, sig,
-                     cf2, active);
+                     cf2, active, bb ? bb->partial : nullptr);
   HIPCHK(hipGetLastError());
+  // |r|^2 of the right-hand side: the reference of the convergence test
+  if (bb) finalize(g.nrb, 1, OP_BB, *bb, cs, const_cast<int *>(active), ldb, ntiles, 0.0, 0, nullptr, s);
 }
 template void cheb_first<double, double>(const Level &, const double *, double *, double *, const double *,
                                          const double *, const double *, const double *, int, int, const int *,
-                                         hipStream_t);
+                                         hipStream_t, Scratch *, ColState *);
 template void cheb_first<float, float>(const Level &, const float *, float *, float *, const float *,
                                        const float *, const float *, const float *, int, int, const int *,
-                                       hipStream_t);
+                                       hipStream_t, Scratch *, ColState *);
 template void cheb_first<float, double>(const Level &, const double *, float *, float *, const float *,
                                         const float *, const float *, const float *, int, int, const int *,
-                                        hipStream_t);
+                                        hipStream_t, Scratch *, ColState *);
 
 }  // namespace gf
 

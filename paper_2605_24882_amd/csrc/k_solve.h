@@ -182,8 +182,10 @@ template <typename T>
 void epi_rows(const Level &L, const T *x, const EpiArgs<T> &e, Scratch &sc, ColState *cs, int *active, int ldb,
               int ntiles, double tol2, int maxit, hipStream_t s);
 template <typename T, typename TR>
+// (with bb: also |r|^2 over the owned unknowns into bb's partial sums, finalised as OP_BB into cs)
 void cheb_first(const Level &L, const TR *r, T *r32, T *z, const T *dM, const T *dS, const T *sig,
-                const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s);
+                const T *cf2, int ldb, int ntiles, const int *active, hipStream_t s, Scratch *bb = nullptr,
+                ColState *cs = nullptr);
 
 template <typename T>
 void cheb_first_cg(const Level &L, double *r, const double *q, T *r32, T *z, const T *dM, const T *dS, const T *sig,
